@@ -1,0 +1,120 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only draws random numbers and lays them out; it holds none of the
+renderer's arithmetic (no projection, no compositing, no activation). Every
+array is float32 because that is the precision the renderer receives; the
+oracle widens them to float64 itself.
+
+Workload shapes follow the synthetic stand-ins for the paper's scenes
+(Sec. 5: an indoor room a few metres across, a fixed receiver or transmitter,
+tens of subcarriers around 2.4 GHz, up to ~1e5 Gaussians):
+
+* means uniform in a 10 x 10 x 3 m box [-5,5] x [-5,5] x [0,3], z up, the
+  receiver at the floor centre (0, 0, 0);
+* log-scales N(-1.5, 0.5) per axis;
+* quaternions uniform on the unit 3-sphere (normalised N(0, I4)), stored
+  (w, x, y, z);
+* opacity logits N(0, 1);
+* one scalar RSS attribute per Gaussian, U(0, 1).
+
+Layout: Gaussian parameters are structure-of-arrays, ``mean[3][n]``,
+``log_scale[3][n]``, ``quat[4][n]``, ``opacity_logit[n]``; attributes are
+``attr[n][F]`` (real) or ``attr[n][F][2]`` (complex, interleaved re/im).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BOX_LO = np.array([-5.0, -5.0, 0.0])
+BOX_HI = np.array([5.0, 5.0, 3.0])
+
+SEED_SCENE = 0
+SEED_QUERIES = 1
+SEED_PERTURB = 2
+SEED_GT_SCENE = 3
+
+
+def scene(n: int, seed: int = SEED_SCENE, lo=BOX_LO, hi=BOX_HI,
+          log_scale_mean: float = -1.5, log_scale_sd: float = 0.5) -> dict:
+    """Random Gaussians: SoA float32 arrays (see module docstring)."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    mean = (lo[:, None] + (hi - lo)[:, None] * rng.random((3, n))).astype(np.float32)
+    log_scale = rng.normal(log_scale_mean, log_scale_sd, size=(3, n)).astype(np.float32)
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    quat = q.astype(np.float32)
+    opacity_logit = rng.normal(0.0, 1.0, size=n).astype(np.float32)
+    return {"mean": np.ascontiguousarray(mean), "log_scale": np.ascontiguousarray(log_scale),
+            "quat": np.ascontiguousarray(quat), "opacity_logit": opacity_logit}
+
+
+def rss_attrs(n: int, seed: int = SEED_SCENE + 100) -> np.ndarray:
+    """One real attribute per Gaussian, U(0, 1): float32 [n, 1]."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n, 1)).astype(np.float32)
+
+
+def channel_attrs(n: int, f: int, complex_: bool, seed: int = SEED_SCENE + 200,
+                  scale: float = 1.0) -> np.ndarray:
+    """F channels per Gaussian. Real: U(0,1) [n, F]; complex: unit-disk-ish
+    N(0, 0.5) re/im interleaved [n, F, 2]."""
+    rng = np.random.default_rng(seed)
+    if complex_:
+        return (scale * rng.normal(0.0, 0.5, size=(n, f, 2))).astype(np.float32)
+    return (scale * rng.random((n, f))).astype(np.float32)
+
+
+def points(b: int, seed: int = SEED_QUERIES, lo=BOX_LO, hi=BOX_HI) -> np.ndarray:
+    """b positions uniform in the box: float32 [b, 3]."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return (lo + (hi - lo) * rng.random((b, 3))).astype(np.float32)
+
+
+def subset(n: int, k: int, seed: int) -> np.ndarray:
+    """k distinct Gaussian indices out of n, sorted: int64 [k]."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=k, replace=False))
+
+
+def perturbation(n: int, seed: int = SEED_PERTURB) -> dict:
+    """Additive perturbation draws used to build a target scene: means
+    +N(0, 0.05 m), log-scales +N(0, 0.1), logits +N(0, 0.3), attributes
+    +N(0, 0.05). Returned as raw draws; the caller adds them."""
+    rng = np.random.default_rng(seed)
+    return {"mean": rng.normal(0.0, 0.05, size=(3, n)).astype(np.float32),
+            "log_scale": rng.normal(0.0, 0.1, size=(3, n)).astype(np.float32),
+            "opacity_logit": rng.normal(0.0, 0.3, size=n).astype(np.float32),
+            "attr_sd": 0.05,
+            "rng": rng}
+
+
+def embeddings(n: int, dim: int = 32, seed: int = SEED_SCENE + 300, sd: float = 0.1) -> np.ndarray:
+    """Per-Gaussian embedding N(0, sd^2 I): float32 [n, dim]."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, sd, size=(n, dim)).astype(np.float32)
+
+
+def mlp_init(sizes, seed: int = SEED_SCENE + 400, gain: float = 1.0) -> list:
+    """He-style normal init for a stack of linear layers: list of
+    (W [out, in] float32, b [out] float32)."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        w = rng.normal(0.0, gain * np.sqrt(2.0 / fan_in), size=(fan_out, fan_in)).astype(np.float32)
+        b = np.zeros(fan_out, dtype=np.float32)
+        layers.append((w, b))
+    return layers
+
+
+def uniform(shape, lo: float, hi: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return (lo + (hi - lo) * rng.random(shape)).astype(np.float32)
+
+
+def normal(shape, sd: float, seed: int, mean: float = 0.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.normal(mean, sd, size=shape).astype(np.float32)
