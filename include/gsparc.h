@@ -1,0 +1,164 @@
+/*
+ * gsparc.h -- C ABI of the MI355X hemispherical RF Gaussian-splatting renderer.
+ *
+ * The library renders, for each query (a receiver position, optionally a
+ * transmitter position), the directional spectrum of N anisotropic 3D
+ * Gaussians on a receiver-centred equirectangular azimuth x elevation grid:
+ *
+ *   render(gaussians, attrs, rx, grid, channels) -> spectrum[F][H][W]
+ *
+ * following the paper's problem statement (Sec. 3.3), the projection and
+ * projected covariance of Sec. 4.2 and the compositing rule Eq. (3).  The
+ * spectrum-to-channel map (spatial mean, Eq. (2)) and the losses of
+ * Eq. (4) are separate calls.
+ *
+ * Conventions for every call
+ *  - Pointers are DEVICE pointers unless a comment marks them (host).  The
+ *    caller allocates and owns every buffer; the library never allocates
+ *    device memory inside these calls and keeps no pointer after a call
+ *    returns, except that the workspace carries state from a forward call to
+ *    the matching backward call.
+ *  - Calls are asynchronous and ordered on `stream` (a hipStream_t passed as
+ *    void*; NULL is the default stream).  They return once the work is
+ *    enqueued.  Host-side argument errors return at once and enqueue nothing.
+ *  - Conditions only the device can see (pair-buffer overflow, non-finite
+ *    inputs) are recorded in the workspace's per-query flags and read back
+ *    with gs_read_flags(); when a query's overflow flag is set its output is
+ *    undefined.
+ *  - No call synchronises the stream except gs_read_flags().  Calls are not
+ *    thread-safe on one workspace.
+ *
+ * Data layout (FP32 unless stated)
+ *  - Gaussian parameters are structure-of-arrays over n Gaussians:
+ *      mean[3][n] (m), log_scale[3][n], quat[4][n] (w, x, y, z; need not be
+ *      normalised), opacity_logit[n].
+ *    Activations are applied inside the library: scale = exp(log_scale),
+ *    rotation from quat/|quat|, opacity = sigmoid(opacity_logit) (Sec. 3.2).
+ *  - Attributes: attr[q][n][F][c], c = 2 (interleaved re, im) when complex,
+ *    else 1; query q starts at attr + q * query_stride (floats); a stride of
+ *    0 shares one attribute set between all queries.
+ *  - Spectrum: out[q][F][H][W][c].  Row 0 is the horizon, row H-1 touches the
+ *    zenith; column 0 starts at azimuth -pi.  Pixel centres are at
+ *    (col + 1/2, row + 1/2).
+ */
+#ifndef GSPARC_H
+#define GSPARC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARG = 1, /* a NULL pointer, a non-positive size, a bad tile shape */
+    GS_ERR_WORKSPACE = 2,   /* workspace NULL, misaligned (256 B) or smaller than required */
+    GS_ERR_CAPACITY = 3,    /* a size exceeds what the library supports */
+    GS_ERR_HIP = 4,         /* a HIP runtime call failed (launch, copy, sync) */
+    GS_ERR_NONFINITE = 5    /* reserved for callers checking gs_flags */
+} gs_status;
+
+/* N Gaussians, structure of arrays (see file header). */
+typedef struct {
+    int32_t n;
+    const float* mean;          /* [3][n] */
+    const float* log_scale;     /* [3][n] */
+    const float* quat;          /* [4][n], (w, x, y, z) */
+    const float* opacity_logit; /* [n] */
+} gs_scene;
+
+/* Per-Gaussian channel values (the emission s_i of Eq. (3)). */
+typedef struct {
+    int32_t n_chan;       /* F >= 1 */
+    int32_t is_complex;   /* 0: real, 1: complex interleaved (re, im) */
+    const float* data;    /* [n_queries or 1][n][F][c] */
+    int64_t query_stride; /* floats between queries; 0 = shared */
+} gs_attrs;
+
+/* Queries: receiver (grid centre) and optional transmitter positions. */
+typedef struct {
+    int32_t count;   /* number of queries B >= 1 */
+    const float* rx; /* [B][3] device */
+    const float* tx; /* [B][3] device, or NULL (then tx = rx) */
+} gs_queries;
+
+/* Hemispherical grid.  `view` is V of Sec. 4.2, row-major: t = V (mu - rx),
+ * azimuth atan2(t_x, t_z), elevation asin(t_y / |t|).  The default maps world
+ * (x, y, z), z up, to (y, z, x). */
+typedef struct {
+    int32_t H, W;           /* rows (elevation 0..pi/2), columns (azimuth 2 pi) */
+    int32_t tile_h, tile_w; /* tile_h * tile_w in {64, 128, 256, 512, 1024} */
+    double view[9];         /* (host value) */
+} gs_grid;
+
+/* Renderer parameters; gs_default_params() fills the defaults. */
+typedef struct {
+    float alpha_min;   /* a pair with alpha < alpha_min is skipped (1/255) */
+    float alpha_max;   /* alpha = min(alpha_max, opacity * G) (0.99) */
+    float T_min;       /* stop before a Gaussian that would take T below T_min (1e-4) */
+    float dilation;    /* added to both diagonal entries of Sigma', px^2 (0.3) */
+    float r_near;      /* Gaussians nearer than this to the receiver are dropped, m (0.2) */
+    float atten_power; /* attenuation 1 / max(d, r_near)^p (2) */
+    int32_t atten_ref; /* d measured to: 0 the receiver, 1 the transmitter (0) */
+    float margin;      /* support-rectangle margin, px (1e-3) */
+    int64_t pair_capacity; /* (Gaussian, tile) pairs per query; 0 = n * min(tiles, 64) + 4096 */
+    int32_t chan_group;    /* channel floats per blend workgroup, 0 = automatic */
+    int32_t reserved;
+} gs_params;
+
+/* Per-query device-side results, read with gs_read_flags(). */
+typedef struct {
+    uint32_t n_visible;  /* Gaussians that survived culling */
+    uint32_t n_pairs;    /* (Gaussian, tile) pairs requested */
+    uint32_t overflow;   /* 1 if n_pairs > pair_capacity (output undefined) */
+    uint32_t n_invalid;  /* Gaussians dropped for non-finite or degenerate values */
+} gs_flags;
+
+/* Byte offsets of the workspace sub-buffers for query 0 and the per-query
+ * stride of each (for inspection and tests). */
+typedef struct {
+    size_t total;
+    size_t flags, rec, rect, status, tinfo, order, keys, pair_keys, pair_list, ranges;
+    size_t T_final, n_last, n_contrib;
+    size_t flags_stride, rec_stride, rect_stride, status_stride, tinfo_stride, order_stride,
+        keys_stride, pair_keys_stride, pair_list_stride, ranges_stride, pix_stride;
+    int64_t pair_capacity;
+    int32_t tiles_x, tiles_y;
+} gs_layout;
+
+void gs_default_params(gs_params* p);
+/* Fills H, W, 16x16 tiles and the default view. */
+void gs_default_grid(gs_grid* g, int32_t H, int32_t W);
+const char* gs_status_string(gs_status s);
+
+/* Workspace size and layout for n Gaussians, B queries, a grid and params. */
+gs_status gs_workspace_layout(int32_t n, int32_t n_queries, const gs_grid* grid,
+                              const gs_params* prm, gs_layout* out);
+
+/*
+ * Forward render (Sec. 4.2, Eq. (3)) of every query.
+ *  spectrum: [B][F][H][W][c], fully written.
+ *  workspace: >= gs_layout.total bytes, 256-byte aligned, caller-owned.  It
+ *  keeps the per-pixel final transmittance and stop positions, the sorted
+ *  tile lists and the projected records for gs_render_backward().
+ * Steps enqueued: projection + culling, depth sort, tiles-touched scan,
+ * (tile, depth) pair emission, pair sort, tile ranges, tile blending.
+ */
+gs_status gs_render_forward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
+                            const gs_grid* grid, const gs_params* prm, float* spectrum,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Copies the per-query flags of the last forward call into `out` (host,
+ * [B] entries).  Synchronises `stream`.
+ */
+gs_status gs_read_flags(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries,
+                        const gs_grid* grid, const gs_params* prm, gs_flags* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSPARC_H */

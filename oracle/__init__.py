@@ -90,8 +90,10 @@ def _p(a):
 def params(**kw) -> np.ndarray:
     d = dict(DEFAULTS)
     d.update(kw)
-    return np.array([d["alpha_min"], d["alpha_max"], d["T_min"], d["dilation"], d["r_near"],
-                     d["atten_power"], float(d["atten_ref"]), d["margin"]], dtype=np.float64)
+    # the renderer's parameters are single-precision numbers: use the same values
+    v = np.array([d["alpha_min"], d["alpha_max"], d["T_min"], d["dilation"], d["r_near"],
+                  d["atten_power"], float(d["atten_ref"]), d["margin"]], dtype=np.float64)
+    return v.astype(np.float32).astype(np.float64)
 
 
 def _f32(a):

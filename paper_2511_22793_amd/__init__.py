@@ -1,0 +1,5 @@
+"""MI355X-native hemispherical RF Gaussian-splatting renderer (GSpaRC's hot
+path): projection onto a receiver-centred equirectangular grid, tile binning
+with a (tile, depth) radix sort, and front-to-back compositing, as hand-written
+HIP kernels for gfx950 behind the C ABI of include/gsparc.h."""
+from .render import Grid, Params, Workspace, forward, layout  # noqa: F401

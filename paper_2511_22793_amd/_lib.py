@@ -1,0 +1,102 @@
+"""ctypes declarations of the C ABI in include/gsparc.h and the library loader.
+
+The product path has no fallback: if libgsparc.so is missing or fails to load,
+``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsparc.so")
+
+c_f32 = ctypes.c_float
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_u32 = ctypes.c_uint32
+c_sz = ctypes.c_size_t
+c_p = ctypes.c_void_p
+
+GS_OK, GS_ERR_INVALID_ARG, GS_ERR_WORKSPACE, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_NONFINITE = range(6)
+
+
+class GsScene(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("mean", c_p), ("log_scale", c_p), ("quat", c_p), ("opacity_logit", c_p)]
+
+
+class GsAttrs(ctypes.Structure):
+    _fields_ = [("n_chan", c_i32), ("is_complex", c_i32), ("data", c_p), ("query_stride", c_i64)]
+
+
+class GsQueries(ctypes.Structure):
+    _fields_ = [("count", c_i32), ("rx", c_p), ("tx", c_p)]
+
+
+class GsGrid(ctypes.Structure):
+    _fields_ = [("H", c_i32), ("W", c_i32), ("tile_h", c_i32), ("tile_w", c_i32), ("view", ctypes.c_double * 9)]
+
+
+class GsParams(ctypes.Structure):
+    _fields_ = [("alpha_min", c_f32), ("alpha_max", c_f32), ("T_min", c_f32), ("dilation", c_f32),
+                ("r_near", c_f32), ("atten_power", c_f32), ("atten_ref", c_i32), ("margin", c_f32),
+                ("pair_capacity", c_i64), ("chan_group", c_i32), ("reserved", c_i32)]
+
+
+class GsFlags(ctypes.Structure):
+    _fields_ = [("n_visible", c_u32), ("n_pairs", c_u32), ("overflow", c_u32), ("n_invalid", c_u32)]
+
+
+_LAYOUT_FIELDS = ["total", "flags", "rec", "rect", "status", "tinfo", "order", "keys", "pair_keys", "pair_list",
+                  "ranges", "T_final", "n_last", "n_contrib", "flags_stride", "rec_stride", "rect_stride",
+                  "status_stride", "tinfo_stride", "order_stride", "keys_stride", "pair_keys_stride",
+                  "pair_list_stride", "ranges_stride", "pix_stride"]
+
+
+class GsLayout(ctypes.Structure):
+    _fields_ = [(f, c_sz) for f in _LAYOUT_FIELDS] + [("pair_capacity", c_i64), ("tiles_x", c_i32),
+                                                        ("tiles_y", c_i32)]
+
+
+# every symbol declared in include/gsparc.h, with (restype, argtypes)
+SIGNATURES = {
+    "gs_default_params": (None, [ctypes.POINTER(GsParams)]),
+    "gs_default_grid": (None, [ctypes.POINTER(GsGrid), c_i32, c_i32]),
+    "gs_status_string": (ctypes.c_char_p, [c_i32]),
+    "gs_workspace_layout": (c_i32, [c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
+                                    ctypes.POINTER(GsLayout)]),
+    "gs_render_forward": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
+                                  ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p]),
+    "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
+                              ctypes.POINTER(GsFlags), c_p]),
+}
+
+_lib = None
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().gs_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__("%s: %s (status %d)" % (what, msg, status))
+
+
+def lib():
+    """Loads libgsparc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgsparc.so is not built (run python -m paper_2511_22793_amd.build); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != GS_OK:
+        raise GsError(status, what)

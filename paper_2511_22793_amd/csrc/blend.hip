@@ -1,0 +1,146 @@
+// Front-to-back compositing of the per-tile depth-ordered lists (Eq. (3),
+// Sec. 4.2; the per-pixel loop of Algorithm 1).  One workgroup per
+// (tile, channel group, query), one thread per pixel.  Batches of the
+// tile's list are staged in LDS; every thread walks the batch in order:
+//   dx, dy      pixel-centre offset, azimuth wrapped into [-W/2, W/2)  (FP64)
+//   q           conic quadratic form                                  (FP64)
+//   G           exp(-q/2) via v_exp_f32                               (FP32)
+//   alpha       min(alpha_max, opacity G); skip when alpha < alpha_min
+//   stop        before the Gaussian that would take T below T_min
+//   out_f      += T alpha a_i v_{i,f} for the group's channels        (FP32)
+// The whole workgroup leaves the list once every pixel has stopped.
+// The attribute row of the current Gaussian is wave-uniform and is read
+// through scalar loads.
+#include "common.h"
+
+namespace gs {
+
+constexpr double LOG2E = 1.4426950408889634;
+
+template <int CG>
+__global__ __launch_bounds__(256) void k_blend(
+    const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
+    const uint2* __restrict__ ranges, size_t s_ranges, const float* __restrict__ attr, int64_t a_stride,
+    int Fc, int C, int H, int W, int tw, int th, int TX, float amin, float amax, float tmin,
+    float* __restrict__ out, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
+    uint32_t* __restrict__ n_contrib, size_t s_pix)
+{
+    const int tile = blockIdx.x, cg = blockIdx.y, q = blockIdx.z;
+    const int nthr = tw * th;
+    const int txi = tile % TX, tyi = tile / TX;
+    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+    const int col = txi * tw + lx, row = tyi * th + ly;
+    const bool inside = col < W && row < H;
+    const uint2 rg = ranges[q * s_ranges + tile];
+    const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * W;
+    rec += q * s_rec;
+    plist += q * s_plist;
+    const float* A = attr + q * a_stride + cg * CG;
+
+    __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
+    __shared__ float s_sig[256], s_att[256];
+    __shared__ uint32_t s_g[256];
+
+    float T = 1.0f;
+    float acc[CG];
+#pragma unroll
+    for (int k = 0; k < CG; ++k) acc[k] = 0.0f;
+    uint32_t last = 0, cnt = 0;
+    bool done = !inside;
+
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += nthr) {
+        if (__syncthreads_count(done) == nthr) break;
+        const uint32_t i = b0 + threadIdx.x;
+        if (i < rg.y) {
+            const uint32_t g = plist[i];
+            const GRec r = rec[g];
+            s_px[threadIdx.x] = r.px;
+            s_py[threadIdx.x] = r.py;
+            s_ca[threadIdx.x] = r.ca;
+            s_cb[threadIdx.x] = r.cb;
+            s_cc[threadIdx.x] = r.cc;
+            s_sig[threadIdx.x] = r.sigma;
+            s_att[threadIdx.x] = r.att;
+            s_g[threadIdx.x] = g;
+        }
+        __syncthreads();
+        const int m = (int)min((uint32_t)nthr, rg.y - b0);
+        for (int j = 0; j < m && !done; ++j) {
+            double dx = pcx - s_px[j];
+            dx = dx >= halfW ? dx - W : (dx < -halfW ? dx + W : dx);
+            const double dy = pcy - s_py[j];
+            const double qv = s_ca[j] * dx * dx + 2.0 * s_cb[j] * dx * dy + s_cc[j] * dy * dy;
+            const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
+            const float alpha = fminf(amax, s_sig[j] * G);
+            if (alpha < amin) continue;
+            const float Tn = T * (1.0f - alpha);
+            if (Tn < tmin) {
+                done = true;
+                break;
+            }
+            const float wgt = T * alpha * s_att[j];
+            const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
+            const float* v = A + (size_t)g * Fc;
+#pragma unroll
+            for (int k = 0; k < CG; ++k) acc[k] = fmaf(wgt, v[k], acc[k]);
+            T = Tn;
+            last = b0 + j + 1 - rg.x;
+            ++cnt;
+        }
+    }
+    if (!inside) return;
+    const size_t HW = (size_t)H * W, pix = (size_t)row * W + col;
+    const int F = Fc / C;
+#pragma unroll
+    for (int k = 0; k < CG; ++k) {
+        const int ch = cg * CG + k;
+        const int f = ch / C, comp = ch - f * C;
+        out[(((size_t)q * F + f) * HW + pix) * C + comp] = acc[k];
+    }
+    if (cg == 0) {
+        T_final[q * s_pix + pix] = T;
+        n_last[q * s_pix + pix] = last;
+        n_contrib[q * s_pix + pix] = cnt;
+    }
+}
+
+template <int CG>
+static void blend_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, const gs_params& p, const Layout& L,
+                     char* ws, float* out, int C)
+{
+    hipLaunchKernelGGL(k_blend<CG>, grid, block, 0, s, (const GRec*)(ws + L.rec), L.s_rec / sizeof(GRec),
+                       (const uint32_t*)(ws + L.plist), L.s_plist / 4, (const uint2*)(ws + L.ranges),
+                       L.s_ranges / sizeof(uint2), a.data, a.query_stride, a.n_chan * C, C, L.H, L.W, L.tw, L.th,
+                       L.TX, p.alpha_min, p.alpha_max, p.T_min, out, (float*)(ws + L.T_final),
+                       (uint32_t*)(ws + L.n_last), (uint32_t*)(ws + L.n_contrib), L.s_pix / 4);
+}
+
+// Channel floats per workgroup: the largest power of two that divides F*c,
+// at most 32 (or the caller's choice when it divides F*c).
+int choose_chan_group(int Fc, int requested)
+{
+    if (requested > 0 && requested <= 32 && (requested & (requested - 1)) == 0 && Fc % requested == 0)
+        return requested;
+    int cg = 1;
+    while (cg < 32 && Fc % (cg * 2) == 0) cg *= 2;
+    return cg;
+}
+
+gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, char* ws, float* out, hipStream_t s)
+{
+    const int C = a.is_complex ? 2 : 1;
+    const int Fc = a.n_chan * C;
+    const int cg = choose_chan_group(Fc, p.chan_group);
+    dim3 grid(L.T, Fc / cg, L.nq), block(L.tw * L.th);
+    switch (cg) {
+        case 1: blend_cg<1>(grid, block, s, a, p, L, ws, out, C); break;
+        case 2: blend_cg<2>(grid, block, s, a, p, L, ws, out, C); break;
+        case 4: blend_cg<4>(grid, block, s, a, p, L, ws, out, C); break;
+        case 8: blend_cg<8>(grid, block, s, a, p, L, ws, out, C); break;
+        case 16: blend_cg<16>(grid, block, s, a, p, L, ws, out, C); break;
+        default: blend_cg<32>(grid, block, s, a, p, L, ws, out, C); break;
+    }
+    return GS_OK;
+}
+
+}  // namespace gs

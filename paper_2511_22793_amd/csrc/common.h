@@ -1,0 +1,68 @@
+// Internal declarations shared by the HIP translation units of libgsparc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsparc.h"
+
+namespace gs {
+
+// Per-Gaussian projected record read by the blend kernels (48 bytes).
+// Centre and inverse projected covariance stay in FP64: on gfx950 an FP64
+// FMA issues at the same rate as an unpacked FP32 FMA, and FP64 removes the
+// centre-rounding error that an FP32 pixel coordinate near 360 would carry.
+struct alignas(16) GRec {
+    double px, py;      // pixel-space centre
+    double ca, cb, cc;  // conic: inverse of Sigma' (a, b; b, c)
+    float sigma;        // opacity
+    float att;          // attenuation 1 / max(d, r_near)^p
+};
+static_assert(sizeof(GRec) == 48, "GRec layout");
+
+// culling status (same codes as the public documentation)
+enum : uint32_t { ST_VISIBLE = 0, ST_NEAR = 1, ST_FAINT = 2, ST_OFFGRID = 3, ST_INVALID = 4 };
+
+// per-query flag words
+enum : int { FL_NVIS = 0, FL_PAIRS = 1, FL_OVERFLOW = 2, FL_INVALID = 3, FL_PUSED = 4, FL_WORDS = 16 };
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per sort workgroup
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+
+// Byte layout of the caller's workspace (all sub-buffers 256-byte aligned,
+// each an array over queries with the given stride).
+struct Layout {
+    int n, nq, H, W, tw, th, TX, TY, T;
+    int64_t cap;          // pair capacity per query
+    int rank_bits;        // bits of the depth rank inside a pair key
+    int tile_bits;        // bits of the tile id inside a pair key
+    int pair_passes;      // radix passes over pair keys
+    int sort_blocks;      // max sort workgroups for n keys
+    int pair_blocks;      // max sort workgroups for cap keys
+    size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;
+    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib;
+    size_t s_flags, s_rec, s_rect, s_status, s_tinfo, s_keys, s_partial, s_pkeys, s_plist, s_ranges,
+        s_counts, s_totals, s_pix;
+    size_t total;
+};
+
+gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* p, Layout* L);
+
+// kernel launchers (stream-ordered, no synchronisation)
+void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_t v, hipStream_t s);
+void launch_project(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,
+                    const Layout& L, char* ws, hipStream_t s);
+void launch_depth_sort(const Layout& L, char* ws, hipStream_t s);
+void launch_binning(const Layout& L, char* ws, hipStream_t s);
+gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, char* ws, float* out,
+                       hipStream_t s);
+
+}  // namespace gs
+
+#define GS_CHECK_LAUNCH()                                  \
+    do {                                                   \
+        if (hipGetLastError() != hipSuccess) return GS_ERR_HIP; \
+    } while (0)

@@ -1,0 +1,375 @@
+// Depth ordering and tile binning (the "directional sorting" of the method:
+// Gaussians are binned to tiles and each tile's list is ordered by distance
+// to the receiver, Sec. 4.2 and the per-pixel loop of Algorithm 1).
+//
+// 1. depth sort: stable LSD radix sort of the FP32 distance keys (index
+//    order breaks ties), 8-bit digits, one pass = count + scan + scatter;
+// 2. tiles-touched scan: exclusive prefix sum of the tile counts in depth
+//    order, giving each Gaussian's first pair slot and the pair total;
+// 3. pair emission: key = tile << rank_bits | depth_rank, unique per pair;
+// 4. pair sort: the same radix sort over the used key bits;
+// 5. tile ranges: [start, end) of each tile in the sorted pair array, and
+//    the Gaussian id of every sorted pair.
+// Every query of a batch is an independent segment (blockIdx.y).
+#include "common.h"
+
+namespace gs {
+
+__global__ void k_fill_u32(uint32_t* p, size_t count, size_t q_stride, uint32_t v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[blockIdx.y * q_stride + i] = v;
+}
+
+void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_t v, hipStream_t s)
+{
+    if (count == 0) return;
+    dim3 grid((unsigned)((count + 255) / 256), nq);
+    hipLaunchKernelGGL(k_fill_u32, grid, dim3(256), 0, s, p, count, q_stride, v);
+}
+
+__device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int q)
+{
+    return n_dev ? n_dev[q * n_stride] : n_fixed;
+}
+
+// Per-workgroup digit histogram; counts laid out [digit][block] per query.
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
+    const uint32_t* __restrict__ keys, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
+    uint32_t n_fixed, int shift, uint32_t* __restrict__ counts, size_t s_counts, int max_blocks)
+{
+    const int q = blockIdx.y;
+    const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
+    const uint32_t base = blockIdx.x * SORT_TILE;
+    if (base >= n) return;
+    __shared__ uint32_t hist[RADIX];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    keys += q * s_keys;
+#pragma unroll 4
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
+        if (e < n) atomicAdd(&hist[(keys[e] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    counts[q * s_counts + (size_t)threadIdx.x * max_blocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Exclusive scan over blocks for one digit (one workgroup per digit and
+// query); writes the digit total to totals[digit].
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ counts, size_t s_counts,
+                                                   uint32_t* __restrict__ totals, size_t s_totals,
+                                                   const uint32_t* __restrict__ n_dev, size_t n_stride,
+                                                   uint32_t n_fixed, int max_blocks)
+{
+    const int d = blockIdx.x, q = blockIdx.y;
+    const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
+    const int nb = (int)((n + SORT_TILE - 1) / SORT_TILE);
+    uint32_t* row = counts + q * s_counts + (size_t)d * max_blocks;
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? row[b] : 0u;
+        // inclusive wave scan
+        uint32_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t wbase = carry;
+        for (int k = 0; k < w; ++k) wbase += wsum[k];
+        if (b < nb) row[b] = wbase + x - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry = wbase + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[q * s_totals + d] = carry;
+}
+
+// Stable scatter.  Wave w of the workgroup owns keys [w*1024, (w+1)*1024) of
+// the block, consumed as 16 rounds of 64 consecutive keys.  A key's rank is
+// (digit base) + (same digit in earlier blocks) + (in earlier waves) +
+// (in earlier rounds of this wave) + (lanes below it with the same digit in
+// this round, from an 8-ballot match mask).
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
+    uint32_t n_fixed, int shift, const uint32_t* __restrict__ counts, size_t s_counts,
+    const uint32_t* __restrict__ totals, size_t s_totals, int max_blocks)
+{
+    const int q = blockIdx.y;
+    const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
+    const uint32_t base = blockIdx.x * SORT_TILE;
+    if (base >= n) return;
+    __shared__ uint32_t s_goff[RADIX];
+    __shared__ uint32_t s_wcnt[4][RADIX];
+    __shared__ uint32_t s_wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    kin += q * s_keys;
+    kout += q * s_keys;
+    if (vin) {
+        vin += q * s_keys;
+        vout += q * s_keys;
+    }
+    // digit bases: exclusive scan of the totals over digits
+    {
+        const uint32_t t = totals[q * s_totals + tid];
+        uint32_t x = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_wsum[w] = x;
+        __syncthreads();
+        uint32_t wb = 0;
+        for (int k = 0; k < w; ++k) wb += s_wsum[k];
+        s_goff[tid] = wb + x - t + counts[q * s_counts + (size_t)tid * max_blocks + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_wcnt[k][tid] = 0;
+    }
+    __syncthreads();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t key[SORT_ITEMS], val[SORT_ITEMS], pos[SORT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+        const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
+        const bool valid = e < n;
+        key[j] = valid ? kin[e] : 0u;
+        val[j] = (valid && vin) ? vin[e] : 0u;
+        const uint32_t dig = (key[j] >> shift) & (RADIX - 1);
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
+            const unsigned long long bb = __ballot((dig >> b) & 1u);
+            m &= ((dig >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t r = (uint32_t)__popcll(m & lt);
+        const uint32_t c = s_wcnt[w][dig];
+        pos[j] = c + r;
+        // the highest lane of each digit group advances the wave's counter
+        const bool leader = valid && ((m >> lane) == 1ull);
+        __builtin_amdgcn_wave_barrier();
+        if (leader) s_wcnt[w][dig] = c + r + 1;
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t c = s_wcnt[k][tid];
+            s_wcnt[k][tid] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+        const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
+        if (e < n) {
+            const uint32_t dig = (key[j] >> shift) & (RADIX - 1);
+            const uint32_t dst = s_goff[dig] + s_wcnt[w][dig] + pos[j];
+            if (dst < n) {  // always true when the counts are consistent
+                kout[dst] = key[j];
+                if (vout) vout[dst] = val[j];
+            }
+        }
+    }
+}
+
+// Sorts `passes` digits starting at bit 0; returns the buffer index (0 = a,
+// 1 = b) that holds the result.
+static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, size_t s_keys,
+                      const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int passes, int blocks,
+                      const Layout& L, char* ws, hipStream_t s)
+{
+    uint32_t* counts = (uint32_t*)(ws + L.counts);
+    uint32_t* totals = (uint32_t*)(ws + L.totals);
+    const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
+    const int maxb = L.pair_blocks > L.sort_blocks ? L.pair_blocks : L.sort_blocks;
+    uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * RADIX_BITS;
+        hipLaunchKernelGGL(k_sort_count, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, s_keys, n_dev,
+                           n_stride, n_fixed, shift, counts, sc, maxb);
+        hipLaunchKernelGGL(k_sort_scan, dim3(RADIX, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev,
+                           n_stride, n_fixed, maxb);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, vin, kout, vout,
+                           s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, maxb);
+        uint32_t* t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    return passes & 1;
+}
+
+void launch_depth_sort(const Layout& L, char* ws, hipStream_t s)
+{
+    // keys a -> ... -> a after 4 passes (even), values follow
+    radix_sort((uint32_t*)(ws + L.keys_a), (uint32_t*)(ws + L.keys_b), (uint32_t*)(ws + L.vals_a),
+               (uint32_t*)(ws + L.vals_b), L.s_keys / 4, nullptr, 0, (uint32_t)L.n, 4, L.sort_blocks, L, ws, s);
+}
+
+// ---- tiles-touched scan and pair emission -------------------------------
+
+__device__ __forceinline__ uint32_t ntiles_at(const uint32_t* order, const uint4* tinfo, uint32_t k, uint32_t nvis)
+{
+    return k < nvis ? tinfo[order[k]].w : 0u;
+}
+
+// Sum of tile counts of each SORT_TILE chunk of the depth order.
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ order, size_t s_order,
+                                                     const uint4* __restrict__ tinfo, size_t s_tinfo,
+                                                     const uint32_t* __restrict__ flags, size_t s_flags,
+                                                     uint32_t* __restrict__ partial, size_t s_partial)
+{
+    const int q = blockIdx.y;
+    const uint32_t nvis = flags[q * s_flags + FL_NVIS];
+    const uint32_t base = blockIdx.x * SORT_TILE;
+    order += q * s_order;
+    tinfo += q * s_tinfo;
+    uint32_t sum = 0;
+    if (base < nvis)
+        for (int i = 0; i < SORT_ITEMS; ++i) sum += ntiles_at(order, tinfo, base + i * 256 + threadIdx.x, nvis);
+    __shared__ uint32_t red[4];
+    // wave reduction then workgroup
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[q * s_partial + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Exclusive scan of the chunk sums; records the pair count and overflow.
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ partial, size_t s_partial, int nchunks,
+                                                  uint32_t* __restrict__ flags, size_t s_flags, int64_t cap)
+{
+    const int q = blockIdx.x;
+    partial += q * s_partial;
+    flags += q * s_flags;
+    __shared__ unsigned long long s_run;
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        for (int c = 0; c < nchunks; ++c) {
+            const uint32_t v = partial[c];
+            partial[c] = (uint32_t)run;
+            run += v;
+        }
+        s_run = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long P = s_run;
+        flags[FL_PAIRS] = (uint32_t)(P > 0xFFFFFFFFull ? 0xFFFFFFFFull : P);
+        flags[FL_OVERFLOW] = P > (unsigned long long)cap ? 1u : 0u;
+        flags[FL_PUSED] = (uint32_t)(P > (unsigned long long)cap ? (unsigned long long)cap : P);
+    }
+}
+
+// Emits the pair keys of each Gaussian in depth order.  Thread t of chunk c
+// owns depth ranks c*SORT_TILE + t*SORT_ITEMS + [0, SORT_ITEMS).
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, size_t s_order,
+                                              const uint4* __restrict__ tinfo, size_t s_tinfo,
+                                              const uint32_t* __restrict__ flags, size_t s_flags,
+                                              const uint32_t* __restrict__ partial, size_t s_partial,
+                                              uint32_t* __restrict__ pkeys, size_t s_pkeys, int64_t cap,
+                                              int TX, int rank_bits)
+{
+    const int q = blockIdx.y;
+    const uint32_t nvis = flags[q * s_flags + FL_NVIS];
+    const uint32_t base = blockIdx.x * SORT_TILE;
+    if (base >= nvis) return;
+    order += q * s_order;
+    tinfo += q * s_tinfo;
+    pkeys += q * s_pkeys;
+    const uint32_t k0 = base + threadIdx.x * SORT_ITEMS;
+    uint32_t sum = 0;
+    for (int i = 0; i < SORT_ITEMS; ++i) sum += ntiles_at(order, tinfo, k0 + i, nvis);
+    // exclusive workgroup scan of the per-thread sums
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __shared__ uint32_t wsum[4];
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t off = partial[q * s_partial + blockIdx.x] + x - sum;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        const uint32_t k = k0 + i;
+        if (k >= nvis) break;
+        const uint4 ti = tinfo[order[k]];
+        const int xa0 = ti.x & 0xFFFF, xa1 = ti.x >> 16, xb0 = ti.y & 0xFFFF, xb1 = ti.y >> 16;
+        const int ty0 = ti.z & 0xFFFF, ty1 = ti.z >> 16;
+        for (int ty = ty0; ty <= ty1; ++ty) {
+            for (int tx = xa0; tx <= xa1; ++tx, ++off)
+                if ((int64_t)off < cap) pkeys[off] = ((uint32_t)(ty * TX + tx) << rank_bits) | k;
+            for (int tx = xb0; tx <= xb1; ++tx, ++off)
+                if ((int64_t)off < cap) pkeys[off] = ((uint32_t)(ty * TX + tx) << rank_bits) | k;
+        }
+    }
+}
+
+// Tile ranges from the sorted pair keys; also resolves each pair's Gaussian.
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pkeys, size_t s_pkeys,
+                                                const uint32_t* __restrict__ order, size_t s_order,
+                                                const uint32_t* __restrict__ flags, size_t s_flags,
+                                                uint32_t* __restrict__ plist, size_t s_plist,
+                                                uint2* __restrict__ ranges, size_t s_ranges, int rank_bits,
+                                                uint32_t T)
+{
+    const int q = blockIdx.y;
+    const uint32_t P = flags[q * s_flags + FL_PUSED];
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    pkeys += q * s_pkeys;
+    ranges += q * s_ranges;
+    const uint32_t key = pkeys[p];
+    const uint32_t t = key >> rank_bits;
+    plist[q * s_plist + p] = order[q * s_order + (key & ((1u << rank_bits) - 1u))];
+    const uint32_t prev = p > 0 ? (pkeys[p - 1] >> rank_bits) : 0xFFFFFFFFu;
+    if (t >= T || (p > 0 && prev >= T)) return;  // never taken for keys written by k_emit
+    if (t != prev) {
+        ranges[t].x = p;
+        if (p > 0) ranges[prev].y = p;
+    }
+    if (p == P - 1) ranges[t].y = P;
+}
+
+void launch_binning(const Layout& L, char* ws, hipStream_t s)
+{
+    const uint32_t* order = (const uint32_t*)(ws + L.vals_a);
+    const uint4* tinfo = (const uint4*)(ws + L.tinfo);
+    uint32_t* flags = (uint32_t*)(ws + L.flags);
+    uint32_t* partial = (uint32_t*)(ws + L.partial);
+    const size_t so = L.s_keys / 4, sti = L.s_tinfo / sizeof(uint4), sf = L.s_flags / 4, sp = L.s_partial / 4;
+    const int nchunks = (L.n + SORT_TILE - 1) / SORT_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf,
+                       partial, sp);
+    hipLaunchKernelGGL(k_scan_top, dim3(L.nq), dim3(256), 0, s, partial, sp, nchunks, flags, sf, L.cap);
+    uint32_t* pa = (uint32_t*)(ws + L.pkeys_a);
+    uint32_t* pb = (uint32_t*)(ws + L.pkeys_b);
+    const size_t spk = L.s_pkeys / 4;
+    hipLaunchKernelGGL(k_emit, dim3(nchunks, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf, partial, sp,
+                       pa, spk, L.cap, L.TX, L.rank_bits);
+    const int which = radix_sort(pa, pb, nullptr, nullptr, spk, flags + FL_PUSED, sf, 0, L.pair_passes,
+                                 L.pair_blocks, L, ws, s);
+    uint32_t* sorted = which ? pb : pa;
+    uint2* ranges = (uint2*)(ws + L.ranges);
+    launch_fill_u32((uint32_t*)ranges, (size_t)L.T * 2, L.s_ranges / 4, L.nq, 0u, s);
+    dim3 grid((unsigned)((L.cap + 255) / 256), L.nq);
+    hipLaunchKernelGGL(k_ranges, grid, dim3(256), 0, s, sorted, spk, order, so, flags, sf,
+                       (uint32_t*)(ws + L.plist), L.s_plist / 4, ranges, L.s_ranges / sizeof(uint2), L.rank_bits,
+                       (uint32_t)L.T);
+}
+
+}  // namespace gs

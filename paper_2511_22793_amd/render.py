@@ -1,0 +1,166 @@
+"""Python binding of the renderer: argument marshalling around the C ABI.
+
+Every step runs in the HIP library; PyTorch only provides device memory and
+the current stream.  Shapes follow include/gsparc.h:
+  scene     dict of float32 CUDA tensors mean [3,n], log_scale [3,n],
+            quat [4,n], opacity_logit [n]
+  attr      [n,F] / [n,F,2] (shared by all queries) or [B,n,F] / [B,n,F,2]
+  rx, tx    [B,3] float32 CUDA tensors (tx may be None)
+  output    [B,F,H,W] (real) or [B,F,H,W,2] (complex, re/im interleaved)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+from ._lib import GsAttrs, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
+
+DEFAULT_VIEW = (0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0)
+
+
+@dataclass
+class Params:
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    dilation: float = 0.3
+    r_near: float = 0.2
+    atten_power: float = 2.0
+    atten_ref: int = 0
+    margin: float = 1e-3
+    pair_capacity: int = 0
+    chan_group: int = 0
+
+    def c(self) -> GsParams:
+        return GsParams(self.alpha_min, self.alpha_max, self.T_min, self.dilation, self.r_near, self.atten_power,
+                        int(self.atten_ref), self.margin, int(self.pair_capacity), int(self.chan_group), 0)
+
+
+@dataclass
+class Grid:
+    H: int = 90
+    W: int = 360
+    tile_h: int = 16
+    tile_w: int = 16
+    view: tuple = field(default=DEFAULT_VIEW)
+
+    def c(self) -> GsGrid:
+        g = GsGrid()
+        g.H, g.W, g.tile_h, g.tile_w = self.H, self.W, self.tile_h, self.tile_w
+        for k in range(9):
+            g.view[k] = float(self.view[k])
+        return g
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_f32(name, t, shape=None):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+def layout(n: int, n_queries: int, grid: Grid, params: Params) -> GsLayout:
+    L = GsLayout()
+    g, p = grid.c(), params.c()
+    check(lib().gs_workspace_layout(n, n_queries, ctypes.byref(g), ctypes.byref(p), ctypes.byref(L)),
+          "gs_workspace_layout")
+    return L
+
+
+class Workspace:
+    """Caller-owned device workspace of one (n, B, grid, params) shape."""
+
+    def __init__(self, n: int, n_queries: int, grid: Grid, params: Params, device=None):
+        self.n, self.nq, self.grid, self.params = n, n_queries, grid, params
+        self.layout = layout(n, n_queries, grid, params)
+        self.buf = torch.empty(self.layout.total + 256, dtype=torch.uint8, device=device or "cuda")
+        base = self.buf.data_ptr()
+        self.offset = (-base) % 256
+        self.ptr = base + self.offset
+        self.nbytes = self.layout.total
+
+    def fits(self, n, n_queries, grid, params):
+        return (n, n_queries, grid, params) == (self.n, self.nq, self.grid, self.params)
+
+    def view(self, field_name: str, q: int, count: int, dtype=torch.int32) -> torch.Tensor:
+        """Device tensor over `count` elements of a sub-buffer of query q."""
+        L = self.layout
+        off = getattr(L, field_name) + q * getattr(L, _STRIDE[field_name])
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        b = self.buf[self.offset + off:self.offset + off + count * itemsize]
+        return b.view(dtype)
+
+    def flags(self, stream=None):
+        out = (GsFlags * self.nq)()
+        g, p = self.grid.c(), self.params.c()
+        st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        check(lib().gs_read_flags(ctypes.c_void_p(self.ptr), self.nbytes, self.n, self.nq, ctypes.byref(g),
+                                  ctypes.byref(p), out, ctypes.c_void_p(st)), "gs_read_flags")
+        return [dict(n_visible=f.n_visible, n_pairs=f.n_pairs, overflow=f.overflow, n_invalid=f.n_invalid)
+                for f in out]
+
+
+_STRIDE = {"flags": "flags_stride", "rec": "rec_stride", "rect": "rect_stride", "status": "status_stride",
+           "tinfo": "tinfo_stride", "order": "order_stride", "keys": "keys_stride",
+           "pair_keys": "pair_keys_stride", "pair_list": "pair_list_stride", "ranges": "ranges_stride",
+           "T_final": "pix_stride", "n_last": "pix_stride", "n_contrib": "pix_stride"}
+
+
+def _scene_c(scene: dict) -> GsScene:
+    n = scene["opacity_logit"].shape[0]
+    _check_f32("mean", scene["mean"], (3, n))
+    _check_f32("log_scale", scene["log_scale"], (3, n))
+    _check_f32("quat", scene["quat"], (4, n))
+    _check_f32("opacity_logit", scene["opacity_logit"], (n,))
+    return GsScene(n, _ptr(scene["mean"]), _ptr(scene["log_scale"]), _ptr(scene["quat"]),
+                   _ptr(scene["opacity_logit"]))
+
+
+def _attrs_c(attr: torch.Tensor, n: int, B: int, is_complex: bool) -> GsAttrs:
+    _check_f32("attr", attr)
+    per_query = attr.dim() == (4 if is_complex else 3)
+    shape = attr.shape[1:] if per_query else attr.shape
+    if shape[0] != n or (is_complex and shape[-1] != 2):
+        raise ValueError("attr shape %s does not match n=%d complex=%s" % (tuple(attr.shape), n, is_complex))
+    if per_query and attr.shape[0] != B:
+        raise ValueError("attr has %d query slices, expected %d" % (attr.shape[0], B))
+    F = shape[1]
+    stride = attr[0].numel() if per_query else 0
+    return GsAttrs(F, int(is_complex), _ptr(attr), stride)
+
+
+def forward(scene: dict, attr: torch.Tensor, rx: torch.Tensor, tx: Optional[torch.Tensor] = None,
+            grid: Grid = Grid(), params: Params = Params(), is_complex: bool = False,
+            workspace: Optional[Workspace] = None, out: Optional[torch.Tensor] = None):
+    """Renders B queries; returns (spectrum, workspace)."""
+    sc = _scene_c(scene)
+    n = sc.n
+    _check_f32("rx", rx)
+    B = rx.shape[0]
+    if rx.shape != (B, 3):
+        raise ValueError("rx must be [B,3]")
+    if tx is not None:
+        _check_f32("tx", tx, (B, 3))
+    a = _attrs_c(attr, n, B, is_complex)
+    F = a.n_chan
+    shape = (B, F, grid.H, grid.W, 2) if is_complex else (B, F, grid.H, grid.W)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=rx.device)
+    else:
+        _check_f32("out", out, shape)
+    if workspace is None or not workspace.fits(n, B, grid, params):
+        workspace = Workspace(n, B, grid, params, device=rx.device)
+    q = GsQueries(B, _ptr(rx), _ptr(tx))
+    g, p = grid.c(), params.c()
+    stream = torch.cuda.current_stream(rx.device).cuda_stream
+    check(lib().gs_render_forward(ctypes.byref(sc), ctypes.byref(a), ctypes.byref(q), ctypes.byref(g),
+                                  ctypes.byref(p), _ptr(out), ctypes.c_void_p(workspace.ptr), workspace.nbytes,
+                                  ctypes.c_void_p(stream)), "gs_render_forward")
+    return out, workspace

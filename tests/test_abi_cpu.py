@@ -1,0 +1,136 @@
+"""The C-ABI library loads on a machine without a GPU, exports every symbol
+that include/gsparc.h declares, and rejects bad arguments on the host before
+enqueuing anything (no device call is made by these tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_22793_amd import _lib
+from paper_2511_22793_amd._lib import GsAttrs, GsGrid, GsLayout, GsParams, GsQueries, GsScene
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gsparc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(gs_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = _lib.lib()
+    names = declared_symbols()
+    assert len(names) >= 6
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in _lib.SIGNATURES, "binding missing for %s" % name
+
+
+def grid(H=90, W=360, th=16, tw=16):
+    g = GsGrid()
+    _lib.lib().gs_default_grid(ctypes.byref(g), H, W)
+    g.tile_h, g.tile_w = th, tw
+    return g
+
+
+def params(**kw):
+    p = GsParams()
+    _lib.lib().gs_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_defaults():
+    p = params()
+    assert p.alpha_min == pytest.approx(1 / 255) and p.alpha_max == pytest.approx(0.99)
+    assert p.T_min == pytest.approx(1e-4) and p.dilation == pytest.approx(0.3) and p.r_near == pytest.approx(0.2)
+    g = grid()
+    assert list(g.view) == [0, 1, 0, 0, 0, 1, 1, 0, 0] and (g.tile_h, g.tile_w) == (16, 16)
+
+
+@pytest.mark.parametrize("n,B,H,W", [(2048, 1, 90, 360), (100_000, 64, 90, 360), (300_000, 4, 180, 720)])
+def test_layout(n, B, H, W):
+    out = GsLayout()
+    st = _lib.lib().gs_workspace_layout(n, B, ctypes.byref(grid(H, W)), ctypes.byref(params()), ctypes.byref(out))
+    assert st == _lib.GS_OK
+    assert out.tiles_x == (W + 15) // 16 and out.tiles_y == (H + 15) // 16
+    assert out.total % 256 == 0 and out.total > n * B * 48
+    T = out.tiles_x * out.tiles_y
+    assert out.pair_capacity == n * min(T, 64) + 4096
+    for f in ("flags", "rec", "rect", "order", "pair_list", "ranges", "T_final"):
+        assert getattr(out, f) % 256 == 0
+
+
+@pytest.mark.parametrize("bad", [dict(n=0), dict(B=0), dict(th=10, tw=10), dict(th=32, tw=32), dict(H=0)])
+def test_layout_rejects(bad):
+    a = dict(n=100, B=1, H=90, W=360, th=16, tw=16)
+    a.update(bad)
+    out = GsLayout()
+    st = _lib.lib().gs_workspace_layout(a["n"], a["B"], ctypes.byref(grid(a["H"], a["W"], a["th"], a["tw"])),
+                                        ctypes.byref(params()), ctypes.byref(out))
+    assert st == _lib.GS_ERR_INVALID_ARG
+
+
+def test_layout_rejects_key_overflow():
+    # depth rank bits + tile bits must fit a 32-bit pair key
+    out = GsLayout()
+    st = _lib.lib().gs_workspace_layout(1 << 28, 1, ctypes.byref(grid(2048, 4096)), ctypes.byref(params()),
+                                        ctypes.byref(out))
+    assert st == _lib.GS_ERR_CAPACITY
+
+
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def _forward(scene, attrs, queries, g, p, out, ws, nbytes):
+    return _lib.lib().gs_render_forward(scene, attrs, queries, g, p, out, ws, nbytes, None)
+
+
+def _valid_args(n=100):
+    sc = GsScene(n, FAKE, FAKE, FAKE, FAKE)
+    at = GsAttrs(1, 0, FAKE, 0)
+    q = GsQueries(1, FAKE, None)
+    return sc, at, q
+
+
+def test_forward_rejects_null_and_bad_sizes_on_host():
+    sc, at, q = _valid_args()
+    g, p = grid(), params()
+    L = _lib.lib()
+    assert _forward(None, ctypes.byref(at), ctypes.byref(q), ctypes.byref(g), ctypes.byref(p), FAKE, FAKE, 1) == \
+        _lib.GS_ERR_INVALID_ARG
+    bad = GsScene(100, None, FAKE, FAKE, FAKE)
+    assert _forward(ctypes.byref(bad), ctypes.byref(at), ctypes.byref(q), ctypes.byref(g), ctypes.byref(p), FAKE,
+                    FAKE, 1) == _lib.GS_ERR_INVALID_ARG
+    bad_at = GsAttrs(0, 0, FAKE, 0)
+    assert _forward(ctypes.byref(sc), ctypes.byref(bad_at), ctypes.byref(q), ctypes.byref(g), ctypes.byref(p),
+                    FAKE, FAKE, 1) == _lib.GS_ERR_INVALID_ARG
+    bad_q = GsQueries(0, FAKE, None)
+    assert _forward(ctypes.byref(sc), ctypes.byref(at), ctypes.byref(bad_q), ctypes.byref(g), ctypes.byref(p),
+                    FAKE, FAKE, 1) == _lib.GS_ERR_INVALID_ARG
+    bad_p = params(alpha_max=1.5)
+    assert _forward(ctypes.byref(sc), ctypes.byref(at), ctypes.byref(q), ctypes.byref(g), ctypes.byref(bad_p),
+                    FAKE, FAKE, 1) == _lib.GS_ERR_INVALID_ARG
+    assert L.gs_status_string(_lib.GS_ERR_WORKSPACE)
+
+
+def test_forward_rejects_small_or_misaligned_workspace_on_host():
+    sc, at, q = _valid_args()
+    g, p = grid(), params()
+    out = GsLayout()
+    assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(out)) == 0
+    args = (ctypes.byref(sc), ctypes.byref(at), ctypes.byref(q), ctypes.byref(g), ctypes.byref(p), FAKE)
+    assert _forward(*args, FAKE, out.total - 1) == _lib.GS_ERR_WORKSPACE
+    assert _forward(*args, ctypes.c_void_p(0x10010), out.total) == _lib.GS_ERR_WORKSPACE
+    assert _forward(*args, None, out.total) == _lib.GS_ERR_WORKSPACE
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libgsparc.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.lib()

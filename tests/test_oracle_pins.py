@@ -234,14 +234,15 @@ def test_three_gaussians_by_hand():
 
 
 def test_stop_rule_excludes_the_crossing_gaussian():
-    # opaque stack: alpha = 0.99 each; T: 1 -> 0.01 -> 1e-4 (not below) -> 1e-6 (stop)
+    # opaque stack: alpha = 0.99 each; T: 1 -> 0.01 -> ~1e-4 -> ~1e-6; the Gaussian that
+    # would take T below T_min is not added
     col, row = 50, 10
     az, el = _centre_direction(col, row)
     sc = concat(*[one_gaussian(direction(az, el, r), log_s=(-1.0,) * 3, logit=9.0) for r in (1.0, 2.0, 3.0, 4.0)])
-    prm = oracle.params(atten_power=0.0, T_min=1e-4 * (1 - 1e-9))
+    prm = oracle.params(atten_power=0.0, T_min=0.9e-4)
     res = oracle.render(sc, np.ones((4, 1), np.float32), [0, 0, 0], H, W, prm=prm)
     assert res["n_contrib"][row, col] == 2
-    prm = oracle.params(atten_power=0.0, T_min=1e-4 * (1 + 1e-9))
+    prm = oracle.params(atten_power=0.0, T_min=1.1e-4)
     res = oracle.render(sc, np.ones((4, 1), np.float32), [0, 0, 0], H, W, prm=prm)
     assert res["n_contrib"][row, col] == 1
 
