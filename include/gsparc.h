@@ -89,7 +89,7 @@ typedef struct {
  * (x, y, z), z up, to (y, z, x). */
 typedef struct {
     int32_t H, W;           /* rows (elevation 0..pi/2), columns (azimuth 2 pi) */
-    int32_t tile_h, tile_w; /* tile_h * tile_w in {64, 128, 256, 512, 1024} */
+    int32_t tile_h, tile_w; /* tile_h * tile_w in {64, 128, 256} */
     double view[9];         /* (host value) */
 } gs_grid;
 
@@ -149,6 +149,26 @@ gs_status gs_workspace_layout(int32_t n, int32_t n_queries, const gs_grid* grid,
 gs_status gs_render_forward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
                             const gs_grid* grid, const gs_params* prm, float* spectrum,
                             void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * The two halves of gs_render_forward():
+ *  gs_render_prepare: projection + culling, depth sort, tiles-touched scan,
+ *    pair emission, pair sort and tile ranges for every query, into the
+ *    workspace.
+ *  gs_render_blend: compositing (Eq. (3)) of `n_sets` attribute sets over the
+ *    prepared workspace.  n_sets == queries prepared: set q uses query q's
+ *    geometry.  One prepared query and n_sets > 1: every set shares query 0's
+ *    geometry (a fixed receiver seen by many transmitters whose effect is in
+ *    the attributes); this requires atten_ref == 0.  `attrs->query_stride`
+ *    then steps between sets.  spectrum: [n_sets][F][H][W][c].  The
+ *    per-pixel state (T_final, stop position) is per prepared query.
+ *  `n_queries` must equal the count passed to gs_render_prepare().
+ */
+gs_status gs_render_prepare(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
+                            const gs_params* prm, void* workspace, size_t ws_bytes, void* stream);
+gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, int32_t n_sets,
+                          const gs_grid* grid, const gs_params* prm, float* spectrum, void* workspace,
+                          size_t ws_bytes, void* stream);
 
 /*
  * Copies the per-query flags of the last forward call into `out` (host,

@@ -2,4 +2,4 @@
 path): projection onto a receiver-centred equirectangular grid, tile binning
 with a (tile, depth) radix sort, and front-to-back compositing, as hand-written
 HIP kernels for gfx950 behind the C ABI of include/gsparc.h."""
-from .render import Grid, Params, Workspace, forward, layout  # noqa: F401
+from .render import Grid, Params, Workspace, blend, forward, layout, prepare  # noqa: F401

@@ -67,6 +67,10 @@ SIGNATURES = {
                                     ctypes.POINTER(GsLayout)]),
     "gs_render_forward": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
                                   ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p]),
+    "gs_render_prepare": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsQueries), ctypes.POINTER(GsGrid),
+                                  ctypes.POINTER(GsParams), c_p, c_sz, c_p]),
+    "gs_render_blend": (c_i32, [ctypes.POINTER(GsAttrs), c_i32, c_i32, c_i32, ctypes.POINTER(GsGrid),
+                                ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
                               ctypes.POINTER(GsFlags), c_p]),
 }

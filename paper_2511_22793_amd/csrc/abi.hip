@@ -31,7 +31,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->TX = (g->W + g->tile_w - 1) / g->tile_w;
     L->TY = (g->H + g->tile_h - 1) / g->tile_h;
     L->T = L->TX * L->TY;
-    if (L->TX > 0xFFFF || L->TY > 0xFFFF) return GS_ERR_CAPACITY;
+    if (L->TX > 0xFFFF || L->TY > 0xFFFF || L->T >= (1 << 22)) return GS_ERR_CAPACITY;
     int64_t cap = p->pair_capacity;
     if (cap <= 0) cap = (int64_t)n * (L->T < 64 ? L->T : 64) + 4096;
     if (cap > 0x7FFFFFFFll) return GS_ERR_CAPACITY;
@@ -39,7 +39,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->rank_bits = bits_for((uint64_t)(n - 1));
     L->tile_bits = bits_for((uint64_t)(L->T - 1));
     if (L->rank_bits + L->tile_bits > 32) return GS_ERR_CAPACITY;
-    L->pair_passes = (L->rank_bits + L->tile_bits + RADIX_BITS - 1) / RADIX_BITS;
+    L->pair_passes = (L->tile_bits + RADIX_BITS - 1) / RADIX_BITS;
     L->sort_blocks = (n + SORT_TILE - 1) / SORT_TILE;
     L->pair_blocks = (int)((cap + SORT_TILE - 1) / SORT_TILE);
     const int maxb = L->sort_blocks > L->pair_blocks ? L->sort_blocks : L->pair_blocks;
@@ -52,7 +52,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_status = align256((size_t)n * 4);
     L->s_tinfo = align256((size_t)n * 16);
     L->s_keys = align256((size_t)n * 4);
-    L->s_partial = align256((size_t)L->sort_blocks * 4);
+    L->s_partial = align256((size_t)((n + 63) / 64) * 4);
     L->s_pkeys = align256((size_t)cap * 4);
     L->s_plist = align256((size_t)cap * 4);
     L->s_ranges = align256((size_t)L->T * 8);
@@ -195,6 +195,15 @@ static gs_status check_forward(const gs_scene* sc, const gs_attrs* a, const gs_q
     return GS_OK;
 }
 
+static void enqueue_prepare(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
+                            const gs_params* prm, const Layout& L, char* ws, hipStream_t s)
+{
+    launch_fill_u32((uint32_t*)(ws + L.flags), FL_WORDS, L.s_flags / 4, L.nq, 0u, s);
+    launch_project(*scene, *queries, *grid, *prm, L, ws, s);
+    launch_depth_sort(L, ws, s);
+    launch_binning(L, ws, s);
+}
+
 gs_status gs_render_forward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
                             const gs_grid* grid, const gs_params* prm, float* spectrum, void* workspace,
                             size_t ws_bytes, void* stream)
@@ -205,11 +214,44 @@ gs_status gs_render_forward(const gs_scene* scene, const gs_attrs* attrs, const 
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)workspace;
     (void)hipGetLastError();  // clear a stale error so that GS_CHECK_LAUNCH reports ours
-    launch_fill_u32((uint32_t*)(ws + L.flags), FL_WORDS, L.s_flags / 4, L.nq, 0u, s);
-    launch_project(*scene, *queries, *grid, *prm, L, ws, s);
-    launch_depth_sort(L, ws, s);
-    launch_binning(L, ws, s);
-    st = launch_blend(*attrs, *prm, L, ws, spectrum, s);
+    enqueue_prepare(scene, queries, grid, prm, L, ws, s);
+    st = launch_blend(*attrs, *prm, L, L.nq, ws, spectrum, s);
+    if (st != GS_OK) return st;
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+gs_status gs_render_prepare(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
+                            const gs_params* prm, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!scene || !queries || !grid || !prm) return GS_ERR_INVALID_ARG;
+    gs_attrs dummy = {1, 0, (const float*)workspace, 0};
+    Layout L;
+    gs_status st = check_forward(scene, &dummy, queries, grid, prm, (const float*)workspace, workspace, ws_bytes, &L);
+    if (st != GS_OK) return st;
+    (void)hipGetLastError();
+    enqueue_prepare(scene, queries, grid, prm, L, (char*)workspace, (hipStream_t)stream);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, int32_t n_sets,
+                          const gs_grid* grid, const gs_params* prm, float* spectrum, void* workspace,
+                          size_t ws_bytes, void* stream)
+{
+    if (!attrs || !attrs->data || attrs->n_chan < 1 || attrs->query_stride < 0 || !spectrum || !grid || !prm)
+        return GS_ERR_INVALID_ARG;
+    if (attrs->is_complex != 0 && attrs->is_complex != 1) return GS_ERR_INVALID_ARG;
+    if ((int64_t)attrs->n_chan * (attrs->is_complex ? 2 : 1) > 65536) return GS_ERR_CAPACITY;
+    if (n_sets < 1 || n_queries < 1) return GS_ERR_INVALID_ARG;
+    if (n_sets != n_queries && !(n_queries == 1 && prm->atten_ref == 0)) return GS_ERR_INVALID_ARG;
+    if (n_sets > 65535) return GS_ERR_CAPACITY;
+    Layout L;
+    gs_status st = make_layout(n, n_queries, grid, prm, &L);
+    if (st != GS_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255) || ws_bytes < L.total) return GS_ERR_WORKSPACE;
+    (void)hipGetLastError();
+    st = launch_blend(*attrs, *prm, L, n_sets, (char*)workspace, spectrum, (hipStream_t)stream);
     if (st != GS_OK) return st;
     GS_CHECK_LAUNCH();
     return GS_OK;

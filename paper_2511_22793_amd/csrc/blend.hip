@@ -23,9 +23,10 @@ __global__ __launch_bounds__(256) void k_blend(
     const uint2* __restrict__ ranges, size_t s_ranges, const float* __restrict__ attr, int64_t a_stride,
     int Fc, int C, int H, int W, int tw, int th, int TX, float amin, float amax, float tmin,
     float* __restrict__ out, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
-    uint32_t* __restrict__ n_contrib, size_t s_pix)
+    uint32_t* __restrict__ n_contrib, size_t s_pix, int shared_geo)
 {
-    const int tile = blockIdx.x, cg = blockIdx.y, q = blockIdx.z;
+    const int tile = blockIdx.x, cg = blockIdx.y, set = blockIdx.z;
+    const int q = shared_geo ? 0 : set;  // geometry query
     const int nthr = tw * th;
     const int txi = tile % TX, tyi = tile / TX;
     const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_blend(
     const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * W;
     rec += q * s_rec;
     plist += q * s_plist;
-    const float* A = attr + q * a_stride + cg * CG;
+    const float* A = attr + set * a_stride + cg * CG;
 
     __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
     __shared__ float s_sig[256], s_att[256];
@@ -66,26 +67,31 @@ __global__ __launch_bounds__(256) void k_blend(
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, rg.y - b0);
         for (int j = 0; j < m && !done; ++j) {
+            // the attribute row is wave-uniform: issue its scalar loads first
+            // so that the alpha evaluation below hides their latency
+            const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
+            const float* vp = A + (size_t)g * Fc;
+            float v[CG];
+#pragma unroll
+            for (int k = 0; k < CG; ++k) v[k] = vp[k];
             double dx = pcx - s_px[j];
-            dx = dx >= halfW ? dx - W : (dx < -halfW ? dx + W : dx);
+            dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
             const double dy = pcy - s_py[j];
             const double qv = s_ca[j] * dx * dx + 2.0 * s_cb[j] * dx * dy + s_cc[j] * dy * dy;
             const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
             const float alpha = fminf(amax, s_sig[j] * G);
-            if (alpha < amin) continue;
             const float Tn = T * (1.0f - alpha);
-            if (Tn < tmin) {
-                done = true;
-                break;
-            }
-            const float wgt = T * alpha * s_att[j];
-            const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
-            const float* v = A + (size_t)g * Fc;
+            const bool stop = alpha >= amin && Tn < tmin;
+            const bool take = alpha >= amin && !stop;
+            done = stop;
+            // branch-free update (one basic block, so the row loads issue
+            // first): a skipped pair adds zero and keeps T
+            const float wgt = take ? T * alpha * s_att[j] : 0.0f;
 #pragma unroll
             for (int k = 0; k < CG; ++k) acc[k] = fmaf(wgt, v[k], acc[k]);
-            T = Tn;
-            last = b0 + j + 1 - rg.x;
-            ++cnt;
+            T = take ? Tn : T;
+            last = take ? b0 + j + 1 - rg.x : last;
+            cnt += take ? 1u : 0u;
         }
     }
     if (!inside) return;
@@ -95,9 +101,9 @@ __global__ __launch_bounds__(256) void k_blend(
     for (int k = 0; k < CG; ++k) {
         const int ch = cg * CG + k;
         const int f = ch / C, comp = ch - f * C;
-        out[(((size_t)q * F + f) * HW + pix) * C + comp] = acc[k];
+        out[(((size_t)set * F + f) * HW + pix) * C + comp] = acc[k];
     }
-    if (cg == 0) {
+    if (cg == 0 && set == q) {
         T_final[q * s_pix + pix] = T;
         n_last[q * s_pix + pix] = last;
         n_contrib[q * s_pix + pix] = cnt;
@@ -106,39 +112,43 @@ __global__ __launch_bounds__(256) void k_blend(
 
 template <int CG>
 static void blend_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, const gs_params& p, const Layout& L,
-                     char* ws, float* out, int C)
+                     char* ws, float* out, int C, int shared_geo)
 {
     hipLaunchKernelGGL(k_blend<CG>, grid, block, 0, s, (const GRec*)(ws + L.rec), L.s_rec / sizeof(GRec),
                        (const uint32_t*)(ws + L.plist), L.s_plist / 4, (const uint2*)(ws + L.ranges),
                        L.s_ranges / sizeof(uint2), a.data, a.query_stride, a.n_chan * C, C, L.H, L.W, L.tw, L.th,
                        L.TX, p.alpha_min, p.alpha_max, p.T_min, out, (float*)(ws + L.T_final),
-                       (uint32_t*)(ws + L.n_last), (uint32_t*)(ws + L.n_contrib), L.s_pix / 4);
+                       (uint32_t*)(ws + L.n_last), (uint32_t*)(ws + L.n_contrib), L.s_pix / 4, shared_geo);
 }
 
 // Channel floats per workgroup: the largest power of two that divides F*c,
-// at most 32 (or the caller's choice when it divides F*c).
+// at most 32, or the caller's choice (a power of two up to 64 dividing F*c).
 int choose_chan_group(int Fc, int requested)
 {
-    if (requested > 0 && requested <= 32 && (requested & (requested - 1)) == 0 && Fc % requested == 0)
+    if (requested > 0 && requested <= 64 && (requested & (requested - 1)) == 0 && Fc % requested == 0)
         return requested;
     int cg = 1;
     while (cg < 32 && Fc % (cg * 2) == 0) cg *= 2;
     return cg;
 }
 
-gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, char* ws, float* out, hipStream_t s)
+gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
+                       hipStream_t s)
 {
     const int C = a.is_complex ? 2 : 1;
     const int Fc = a.n_chan * C;
     const int cg = choose_chan_group(Fc, p.chan_group);
-    dim3 grid(L.T, Fc / cg, L.nq), block(L.tw * L.th);
+    if (Fc / cg > 65535) return GS_ERR_CAPACITY;
+    const int shared = (L.nq == 1 && n_sets > 1) ? 1 : 0;
+    dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
     switch (cg) {
-        case 1: blend_cg<1>(grid, block, s, a, p, L, ws, out, C); break;
-        case 2: blend_cg<2>(grid, block, s, a, p, L, ws, out, C); break;
-        case 4: blend_cg<4>(grid, block, s, a, p, L, ws, out, C); break;
-        case 8: blend_cg<8>(grid, block, s, a, p, L, ws, out, C); break;
-        case 16: blend_cg<16>(grid, block, s, a, p, L, ws, out, C); break;
-        default: blend_cg<32>(grid, block, s, a, p, L, ws, out, C); break;
+        case 1: blend_cg<1>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        case 2: blend_cg<2>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        case 4: blend_cg<4>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        case 8: blend_cg<8>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        case 16: blend_cg<16>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        case 32: blend_cg<32>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        default: blend_cg<64>(grid, block, s, a, p, L, ws, out, C, shared); break;
     }
     return GS_OK;
 }

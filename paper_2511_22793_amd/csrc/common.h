@@ -27,7 +27,7 @@ enum : uint32_t { ST_VISIBLE = 0, ST_NEAR = 1, ST_FAINT = 2, ST_OFFGRID = 3, ST_
 enum : int { FL_NVIS = 0, FL_PAIRS = 1, FL_OVERFLOW = 2, FL_INVALID = 3, FL_PUSED = 4, FL_WORDS = 16 };
 
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
+constexpr int SORT_ITEMS = 8;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per sort workgroup
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
@@ -57,7 +57,7 @@ void launch_project(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, 
                     const Layout& L, char* ws, hipStream_t s);
 void launch_depth_sort(const Layout& L, char* ws, hipStream_t s);
 void launch_binning(const Layout& L, char* ws, hipStream_t s);
-gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, char* ws, float* out,
+gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
                        hipStream_t s);
 
 }  // namespace gs

@@ -7,7 +7,8 @@
 // 2. tiles-touched scan: exclusive prefix sum of the tile counts in depth
 //    order, giving each Gaussian's first pair slot and the pair total;
 // 3. pair emission: key = tile << rank_bits | depth_rank, unique per pair;
-// 4. pair sort: the same radix sort over the used key bits;
+// 4. pair sort: the same radix sort over the tile digits only (pairs are
+//    emitted in depth order, so a stable sort by tile completes the order);
 // 5. tile ranges: [start, end) of each tile in the sorted pair array, and
 //    the Gaussian id of every sorted pair.
 // Every query of a batch is an independent segment (blockIdx.y).
@@ -46,10 +47,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
     hist[threadIdx.x] = 0;
     __syncthreads();
     keys += q * s_keys;
-#pragma unroll 4
+    uint32_t kv[SORT_ITEMS];
+#pragma unroll
     for (int i = 0; i < SORT_ITEMS; ++i) {
         const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
-        if (e < n) atomicAdd(&hist[(keys[e] >> shift) & (RADIX - 1)], 1u);
+        kv[i] = e < n ? keys[e] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
+        if (e < n) atomicAdd(&hist[(kv[i] >> shift) & (RADIX - 1)], 1u);
     }
     __syncthreads();
     counts[q * s_counts + (size_t)threadIdx.x * max_blocks + blockIdx.x] = hist[threadIdx.x];
@@ -138,12 +145,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t key[SORT_ITEMS], val[SORT_ITEMS], pos[SORT_ITEMS];
+    // issue every load before the rank chain so that they overlap
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+        const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
+        key[j] = e < n ? kin[e] : 0u;
+        val[j] = (e < n && vin) ? vin[e] : 0u;
+    }
 #pragma unroll
     for (int j = 0; j < SORT_ITEMS; ++j) {
         const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
         const bool valid = e < n;
-        key[j] = valid ? kin[e] : 0u;
-        val[j] = (valid && vin) ? vin[e] : 0u;
         const uint32_t dig = (key[j] >> shift) & (RADIX - 1);
         unsigned long long m = __ballot(valid);
 #pragma unroll
@@ -188,8 +200,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
 // Sorts `passes` digits starting at bit 0; returns the buffer index (0 = a,
 // 1 = b) that holds the result.
 static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, size_t s_keys,
-                      const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int passes, int blocks,
-                      const Layout& L, char* ws, hipStream_t s)
+                      const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int first_bit, int passes,
+                      int blocks, const Layout& L, char* ws, hipStream_t s)
 {
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* totals = (uint32_t*)(ws + L.totals);
@@ -197,7 +209,7 @@ static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, si
     const int maxb = L.pair_blocks > L.sort_blocks ? L.pair_blocks : L.sort_blocks;
     uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
-        const int shift = p * RADIX_BITS;
+        const int shift = first_bit + p * RADIX_BITS;
         hipLaunchKernelGGL(k_sort_count, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, s_keys, n_dev,
                            n_stride, n_fixed, shift, counts, sc, maxb);
         hipLaunchKernelGGL(k_sort_scan, dim3(RADIX, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev,
@@ -214,108 +226,137 @@ void launch_depth_sort(const Layout& L, char* ws, hipStream_t s)
 {
     // keys a -> ... -> a after 4 passes (even), values follow
     radix_sort((uint32_t*)(ws + L.keys_a), (uint32_t*)(ws + L.keys_b), (uint32_t*)(ws + L.vals_a),
-               (uint32_t*)(ws + L.vals_b), L.s_keys / 4, nullptr, 0, (uint32_t)L.n, 4, L.sort_blocks, L, ws, s);
+               (uint32_t*)(ws + L.vals_b), L.s_keys / 4, nullptr, 0, (uint32_t)L.n, 0, 4, L.sort_blocks, L, ws, s);
 }
 
 // ---- tiles-touched scan and pair emission -------------------------------
+// Scan granularity: EMIT_RANKS consecutive depth ranks per workgroup.
+constexpr int EMIT_RANKS = 64;
 
 __device__ __forceinline__ uint32_t ntiles_at(const uint32_t* order, const uint4* tinfo, uint32_t k, uint32_t nvis)
 {
     return k < nvis ? tinfo[order[k]].w : 0u;
 }
 
-// Sum of tile counts of each SORT_TILE chunk of the depth order.
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ order, size_t s_order,
-                                                     const uint4* __restrict__ tinfo, size_t s_tinfo,
-                                                     const uint32_t* __restrict__ flags, size_t s_flags,
-                                                     uint32_t* __restrict__ partial, size_t s_partial)
+// Exclusive scan within a 256-thread workgroup; returns the prefix of v.
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* wsum)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int k = 0; k < w; ++k) base += wsum[k];
+    return base + x - v;
+}
+
+// Sum of the tile counts of each EMIT_RANKS block of the depth order (one
+// wave per block).
+__global__ __launch_bounds__(64) void k_scan_reduce(const uint32_t* __restrict__ order, size_t s_order,
+                                                    const uint4* __restrict__ tinfo, size_t s_tinfo,
+                                                    const uint32_t* __restrict__ flags, size_t s_flags,
+                                                    uint32_t* __restrict__ partial, size_t s_partial)
 {
     const int q = blockIdx.y;
     const uint32_t nvis = flags[q * s_flags + FL_NVIS];
-    const uint32_t base = blockIdx.x * SORT_TILE;
-    order += q * s_order;
-    tinfo += q * s_tinfo;
-    uint32_t sum = 0;
-    if (base < nvis)
-        for (int i = 0; i < SORT_ITEMS; ++i) sum += ntiles_at(order, tinfo, base + i * 256 + threadIdx.x, nvis);
-    __shared__ uint32_t red[4];
-    // wave reduction then workgroup
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[q * s_partial + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    const uint32_t k = blockIdx.x * EMIT_RANKS + threadIdx.x;
+    uint32_t v = ntiles_at(order + q * s_order, tinfo + q * s_tinfo, k, nvis);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x == 0) partial[q * s_partial + blockIdx.x] = v;
 }
 
-// Exclusive scan of the chunk sums; records the pair count and overflow.
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ partial, size_t s_partial, int nchunks,
+// Exclusive scan of the block sums; records the pair count and overflow.
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ partial, size_t s_partial, int nblocks,
                                                   uint32_t* __restrict__ flags, size_t s_flags, int64_t cap)
 {
     const int q = blockIdx.x;
     partial += q * s_partial;
     flags += q * s_flags;
-    __shared__ unsigned long long s_run;
-    if (threadIdx.x == 0) {
-        unsigned long long run = 0;
-        for (int c = 0; c < nchunks; ++c) {
-            const uint32_t v = partial[c];
-            partial[c] = (uint32_t)run;
-            run += v;
-        }
-        s_run = run;
-    }
+    __shared__ uint32_t wsum[4];
+    __shared__ unsigned long long carry;
+    if (threadIdx.x == 0) carry = 0;
     __syncthreads();
+    for (int b0 = 0; b0 < nblocks; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const uint32_t v = b < nblocks ? partial[b] : 0u;
+        const uint32_t ex = block_exclusive_scan_256(v, wsum);
+        const unsigned long long c = carry;
+        if (b < nblocks) partial[b] = (uint32_t)(c + ex);
+        __syncthreads();
+        if (threadIdx.x == 255) carry = c + ex + v;
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        const unsigned long long P = s_run;
+        const unsigned long long P = carry;
         flags[FL_PAIRS] = (uint32_t)(P > 0xFFFFFFFFull ? 0xFFFFFFFFull : P);
         flags[FL_OVERFLOW] = P > (unsigned long long)cap ? 1u : 0u;
         flags[FL_PUSED] = (uint32_t)(P > (unsigned long long)cap ? (unsigned long long)cap : P);
     }
 }
 
-// Emits the pair keys of each Gaussian in depth order.  Thread t of chunk c
-// owns depth ranks c*SORT_TILE + t*SORT_ITEMS + [0, SORT_ITEMS).
+// Emits the pair keys in depth order.  A workgroup owns 64 consecutive
+// ranks; their pairs are spread over its 256 lanes (pair p belongs to the
+// last rank whose first pair slot is <= p; each lane walks forward through
+// the 64 prefix offsets as its p grows by 256), so the stores stay coalesced
+// and the work balanced however unequal the tile counts are.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, size_t s_order,
-                                              const uint4* __restrict__ tinfo, size_t s_tinfo,
-                                              const uint32_t* __restrict__ flags, size_t s_flags,
-                                              const uint32_t* __restrict__ partial, size_t s_partial,
-                                              uint32_t* __restrict__ pkeys, size_t s_pkeys, int64_t cap,
-                                              int TX, int rank_bits)
+                                             const uint4* __restrict__ tinfo, size_t s_tinfo,
+                                             const uint32_t* __restrict__ flags, size_t s_flags,
+                                             const uint32_t* __restrict__ partial, size_t s_partial,
+                                             uint32_t* __restrict__ pkeys, size_t s_pkeys, int64_t cap,
+                                             int TX, int rank_bits)
 {
     const int q = blockIdx.y;
     const uint32_t nvis = flags[q * s_flags + FL_NVIS];
-    const uint32_t base = blockIdx.x * SORT_TILE;
+    const uint32_t base = blockIdx.x * EMIT_RANKS;
     if (base >= nvis) return;
     order += q * s_order;
     tinfo += q * s_tinfo;
     pkeys += q * s_pkeys;
-    const uint32_t k0 = base + threadIdx.x * SORT_ITEMS;
-    uint32_t sum = 0;
-    for (int i = 0; i < SORT_ITEMS; ++i) sum += ntiles_at(order, tinfo, k0 + i, nvis);
-    // exclusive workgroup scan of the per-thread sums
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = sum;
+    __shared__ uint4 s_ti[EMIT_RANKS];
+    __shared__ uint32_t s_start[EMIT_RANKS + 1];
+    __shared__ uint32_t s_total;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        const uint32_t k = base + lane;
+        const uint4 ti = k < nvis ? tinfo[order[k]] : make_uint4(0, 0, 0, 0);
+        uint32_t x = ti.w;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    __shared__ uint32_t wsum[4];
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    uint32_t off = partial[q * s_partial + blockIdx.x] + x - sum;
-    for (int k = 0; k < w; ++k) off += wsum[k];
-    for (int i = 0; i < SORT_ITEMS; ++i) {
-        const uint32_t k = k0 + i;
-        if (k >= nvis) break;
-        const uint4 ti = tinfo[order[k]];
-        const int xa0 = ti.x & 0xFFFF, xa1 = ti.x >> 16, xb0 = ti.y & 0xFFFF, xb1 = ti.y >> 16;
-        const int ty0 = ti.z & 0xFFFF, ty1 = ti.z >> 16;
-        for (int ty = ty0; ty <= ty1; ++ty) {
-            for (int tx = xa0; tx <= xa1; ++tx, ++off)
-                if ((int64_t)off < cap) pkeys[off] = ((uint32_t)(ty * TX + tx) << rank_bits) | k;
-            for (int tx = xb0; tx <= xb1; ++tx, ++off)
-                if ((int64_t)off < cap) pkeys[off] = ((uint32_t)(ty * TX + tx) << rank_bits) | k;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
+        s_ti[lane] = ti;
+        s_start[lane] = x - ti.w;
+        if (lane == 63) {
+            s_start[EMIT_RANKS] = 0xFFFFFFFFu;  // sentinel
+            s_total = x;
+        }
+    }
+    const uint32_t o0 = partial[q * s_partial + blockIdx.x];
+    __syncthreads();
+    const uint32_t total = s_total;
+    int j = 0;  // largest j with s_start[j] <= p; only moves forward as p grows
+    for (uint32_t p = threadIdx.x; p < total; p += 256) {
+        while (s_start[j + 1] <= p) ++j;
+        const uint4 t = s_ti[j];
+        const uint32_t e = p - s_start[j];
+        const int xa0 = t.x & 0xFFFF, xa1 = t.x >> 16, xb0 = t.y & 0xFFFF, xb1 = t.y >> 16;
+        const int ty0 = t.z & 0xFFFF;
+        const int na = xa1 - xa0 + 1, nb = xb1 >= xb0 ? xb1 - xb0 + 1 : 0, ncols = na + nb;
+        // row = e / ncols: (e + 0.5) / ncols is at least 0.5/ncols from an
+        // integer and the float product's error is below that while
+        // e < 2^22 (the layout caps the tile count there)
+        const int r = (int)(((float)e + 0.5f) * (1.0f / (float)ncols));
+        const int c = (int)e - r * ncols;
+        const int tx = c < na ? xa0 + c : xb0 + (c - na);
+        const uint32_t dst = o0 + p;
+        if ((int64_t)dst < cap) pkeys[dst] = ((uint32_t)((ty0 + r) * TX + tx) << rank_bits) | (base + j);
     }
 }
 
@@ -329,20 +370,20 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pke
 {
     const int q = blockIdx.y;
     const uint32_t P = flags[q * s_flags + FL_PUSED];
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
     pkeys += q * s_pkeys;
     ranges += q * s_ranges;
-    const uint32_t key = pkeys[p];
-    const uint32_t t = key >> rank_bits;
-    plist[q * s_plist + p] = order[q * s_order + (key & ((1u << rank_bits) - 1u))];
-    const uint32_t prev = p > 0 ? (pkeys[p - 1] >> rank_bits) : 0xFFFFFFFFu;
-    if (t >= T || (p > 0 && prev >= T)) return;  // never taken for keys written by k_emit
-    if (t != prev) {
-        ranges[t].x = p;
-        if (p > 0) ranges[prev].y = p;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const uint32_t key = pkeys[p];
+        const uint32_t t = key >> rank_bits;
+        plist[q * s_plist + p] = order[q * s_order + (key & ((1u << rank_bits) - 1u))];
+        const uint32_t prev = p > 0 ? (pkeys[p - 1] >> rank_bits) : 0xFFFFFFFFu;
+        if (t >= T || (p > 0 && prev >= T)) continue;  // never taken for keys written by k_emit
+        if (t != prev) {
+            ranges[t].x = p;
+            if (p > 0) ranges[prev].y = p;
+        }
+        if (p == P - 1) ranges[t].y = P;
     }
-    if (p == P - 1) ranges[t].y = P;
 }
 
 void launch_binning(const Layout& L, char* ws, hipStream_t s)
@@ -352,21 +393,24 @@ void launch_binning(const Layout& L, char* ws, hipStream_t s)
     uint32_t* flags = (uint32_t*)(ws + L.flags);
     uint32_t* partial = (uint32_t*)(ws + L.partial);
     const size_t so = L.s_keys / 4, sti = L.s_tinfo / sizeof(uint4), sf = L.s_flags / 4, sp = L.s_partial / 4;
-    const int nchunks = (L.n + SORT_TILE - 1) / SORT_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf,
+    const int nblk = (L.n + EMIT_RANKS - 1) / EMIT_RANKS;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk, L.nq), dim3(64), 0, s, order, so, tinfo, sti, flags, sf,
                        partial, sp);
-    hipLaunchKernelGGL(k_scan_top, dim3(L.nq), dim3(256), 0, s, partial, sp, nchunks, flags, sf, L.cap);
+    hipLaunchKernelGGL(k_scan_top, dim3(L.nq), dim3(256), 0, s, partial, sp, nblk, flags, sf, L.cap);
     uint32_t* pa = (uint32_t*)(ws + L.pkeys_a);
     uint32_t* pb = (uint32_t*)(ws + L.pkeys_b);
     const size_t spk = L.s_pkeys / 4;
-    hipLaunchKernelGGL(k_emit, dim3(nchunks, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf, partial, sp,
+    hipLaunchKernelGGL(k_emit, dim3(nblk, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf, partial, sp,
                        pa, spk, L.cap, L.TX, L.rank_bits);
-    const int which = radix_sort(pa, pb, nullptr, nullptr, spk, flags + FL_PUSED, sf, 0, L.pair_passes,
-                                 L.pair_blocks, L, ws, s);
+    // pairs are emitted in depth-rank order, so a stable sort on the tile
+    // digits alone yields (tile, depth) order
+    const int which = radix_sort(pa, pb, nullptr, nullptr, spk, flags + FL_PUSED, sf, 0, L.rank_bits,
+                                 L.pair_passes, L.pair_blocks, L, ws, s);
     uint32_t* sorted = which ? pb : pa;
     uint2* ranges = (uint2*)(ws + L.ranges);
     launch_fill_u32((uint32_t*)ranges, (size_t)L.T * 2, L.s_ranges / 4, L.nq, 0u, s);
-    dim3 grid((unsigned)((L.cap + 255) / 256), L.nq);
+    const int64_t rblocks = (L.cap + 255) / 256;
+    dim3 grid((unsigned)(rblocks < 1024 ? rblocks : 1024), L.nq);
     hipLaunchKernelGGL(k_ranges, grid, dim3(256), 0, s, sorted, spk, order, so, flags, sf,
                        (uint32_t*)(ws + L.plist), L.s_plist / 4, ranges, L.s_ranges / sizeof(uint2), L.rank_bits,
                        (uint32_t)L.T);

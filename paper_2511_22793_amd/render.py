@@ -164,3 +164,46 @@ def forward(scene: dict, attr: torch.Tensor, rx: torch.Tensor, tx: Optional[torc
                                   ctypes.byref(p), _ptr(out), ctypes.c_void_p(workspace.ptr), workspace.nbytes,
                                   ctypes.c_void_p(stream)), "gs_render_forward")
     return out, workspace
+
+
+def prepare(scene: dict, rx: torch.Tensor, tx: Optional[torch.Tensor] = None, grid: Grid = Grid(),
+            params: Params = Params(), workspace: Optional[Workspace] = None) -> Workspace:
+    """Projection, depth sort and tile binning of B queries into a workspace."""
+    sc = _scene_c(scene)
+    _check_f32("rx", rx)
+    B = rx.shape[0]
+    if tx is not None:
+        _check_f32("tx", tx, (B, 3))
+    if workspace is None or not workspace.fits(sc.n, B, grid, params):
+        workspace = Workspace(sc.n, B, grid, params, device=rx.device)
+    q = GsQueries(B, _ptr(rx), _ptr(tx))
+    g, p = grid.c(), params.c()
+    stream = torch.cuda.current_stream(rx.device).cuda_stream
+    check(lib().gs_render_prepare(ctypes.byref(sc), ctypes.byref(q), ctypes.byref(g), ctypes.byref(p),
+                                  ctypes.c_void_p(workspace.ptr), workspace.nbytes, ctypes.c_void_p(stream)),
+          "gs_render_prepare")
+    return workspace
+
+
+def blend(workspace: Workspace, attr: torch.Tensor, n_sets: Optional[int] = None, is_complex: bool = False,
+          out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Compositing over a prepared workspace.  attr: [n_sets, n, F(,2)] (or
+    [n, F(,2)] with n_sets = 1 per prepared query)."""
+    _check_f32("attr", attr)
+    n, B = workspace.n, workspace.nq
+    per_set = attr.dim() == (4 if is_complex else 3)
+    S = attr.shape[0] if per_set else B
+    if n_sets is not None and n_sets != S:
+        raise ValueError("n_sets %d does not match attr" % n_sets)
+    a = _attrs_c(attr, n, S, is_complex)
+    shape = (S, a.n_chan, workspace.grid.H, workspace.grid.W) + ((2,) if is_complex else ())
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=attr.device)
+    else:
+        _check_f32("out", out, shape)
+    g, p = workspace.grid.c(), workspace.params.c()
+    stream = torch.cuda.current_stream(attr.device).cuda_stream
+    check(lib().gs_render_blend(ctypes.byref(a), n, B, S, ctypes.byref(g), ctypes.byref(p), _ptr(out),
+                                ctypes.c_void_p(workspace.ptr), workspace.nbytes, ctypes.c_void_p(stream)),
+          "gs_render_blend")
+    return out
