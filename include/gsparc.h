@@ -171,6 +171,45 @@ gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, i
                           size_t ws_bytes, void* stream);
 
 /*
+ * Backward of gs_render_forward() / gs_render_prepare() + gs_render_blend()
+ * (Eq. (3) differentiated; Sec. 4.2 projection differentiated), for the
+ * workspace state that call left.  Arguments repeat the forward's (same
+ * scene, attrs, queries, n_sets, grid, params) plus:
+ *  spectrum    the forward output [S][F][H][W][c]
+ *  d_spectrum  dL/dspectrum, same layout
+ * Outputs (overwritten, not accumulated):
+ *  d_mean [3][n], d_log_scale [3][n], d_quat [4][n], d_opacity_logit [n]:
+ *    gradients with respect to the raw parameters, summed over all queries;
+ *  d_attr: layout of attrs (one slice when attrs->query_stride == 0, then
+ *    summed over sets; else [S][n][F][c]).
+ * Per pixel the list is re-walked front to back up to the forward's stop
+ * position, recomputing alpha and the transmittance.  Discrete decisions
+ * (alpha >= alpha_min, the stop, the alpha_max clamp) are those of the
+ * forward; a clamped alpha passes no gradient to opacity or footprint.
+ * Float atomics make the summation order, and so the last bits, vary
+ * between runs.
+ */
+gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
+                             int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
+                             const float* d_spectrum, float* d_mean, float* d_log_scale, float* d_quat,
+                             float* d_opacity_logit, float* d_attr, void* workspace, size_t ws_bytes,
+                             void* stream);
+
+/*
+ * Training loss on spectra (Eq. (2) spatial mean, Eq. (4) channel loss).
+ * For each of n_sets spectra zhat [F][H][W][c] and targets z (same layout):
+ *   h^_f = (1/HW) sum_p zhat_f,p      (coherent mean; re, im separately)
+ *   L_b  = (1/(F H W)) sum |zhat - z|^2 + lambda_ch sum_f |h^_f - h_f|^2
+ * with h_f the spatial mean of the target.  Writes loss[b] = L_b (device,
+ * [n_sets]), h_hat [n_sets][F][c] and d_spectrum = dL/dzhat for
+ * L = (1/n_sets) sum_b L_b.  scratch: >= n_sets*F*c*3 floats, 256-byte
+ * aligned, caller-owned.
+ */
+gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                           int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
+                           float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes, void* stream);
+
+/*
  * Copies the per-query flags of the last forward call into `out` (host,
  * [B] entries).  Synchronises `stream`.
  */

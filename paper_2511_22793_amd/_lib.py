@@ -71,6 +71,11 @@ SIGNATURES = {
                                   ctypes.POINTER(GsParams), c_p, c_sz, c_p]),
     "gs_render_blend": (c_i32, [ctypes.POINTER(GsAttrs), c_i32, c_i32, c_i32, ctypes.POINTER(GsGrid),
                                 ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p]),
+    "gs_render_backward": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
+                                   c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p, c_p, c_p,
+                                   c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
+                                 c_p]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
                               ctypes.POINTER(GsFlags), c_p]),
 }

@@ -1,0 +1,109 @@
+// Spectrum-to-channel map and training loss (Eq. (2), Eq. (4)).
+//
+// For each set b and channel f (re and im separately when complex):
+//   h^_bf = (1/HW) sum_p zhat_bfp                  (coherent spatial mean)
+//   L_b   = (1/(F H W)) sum_{f,p} |zhat - z|^2 + lambda sum_f |h^_bf - h_bf|^2
+//   L     = (1/B) sum_b L_b
+// with h_bf the spatial mean of the target spectrum.  The gradient is
+//   dL/dzhat = (1/B) [2 (zhat - z) / (F H W) + lambda 2 (h^ - h) / (H W)].
+// Two passes: a reduction per (set, channel component) into FP32
+// accumulators (workgroup partial sums, then atomics), then the elementwise
+// gradient.  Both passes stream the spectra once.
+#include "common.h"
+
+namespace gs {
+
+// acc layout per set: [Fc][3] = (sum zhat, sum z, sum (zhat - z)^2)
+__global__ __launch_bounds__(256) void k_loss_reduce(const float* __restrict__ zhat, const float* __restrict__ z,
+                                                     int Fc, int C, size_t HW, float* __restrict__ acc)
+{
+    const int b = blockIdx.z, f = blockIdx.y;  // f indexes complex channels (F)
+    const size_t F = Fc / C;
+    const size_t base = ((size_t)b * F + f) * HW * C;
+    float s[2] = {0, 0}, t[2] = {0, 0}, e = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < HW; i += (size_t)gridDim.x * 256) {
+        for (int c = 0; c < C; ++c) {
+            const float a = zhat[base + i * C + c], y = z[base + i * C + c];
+            s[c] += a;
+            t[c] += y;
+            e += (a - y) * (a - y);
+        }
+    }
+    __shared__ float red[5][4];
+    float vals[5] = {s[0], s[1], t[0], t[1], e};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        float v = vals[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int k = threadIdx.x;
+        const float v = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+        float* a = acc + ((size_t)b * Fc + (size_t)f * C) * 3;
+        if (k < 2 && k < C) unsafeAtomicAdd(a + k * 3 + 0, v);
+        else if (k >= 2 && k < 4 && k - 2 < C) unsafeAtomicAdd(a + (k - 2) * 3 + 1, v);
+        else if (k == 4) unsafeAtomicAdd(a + 2, v);  // squared error summed over components
+    }
+}
+
+__global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ zhat, const float* __restrict__ z,
+                                                   int B, int Fc, int C, size_t HW, float lambda,
+                                                   const float* __restrict__ acc, float* __restrict__ dz,
+                                                   float* __restrict__ hhat, float* __restrict__ loss)
+{
+    const int b = blockIdx.z, f = blockIdx.y;
+    const size_t F = Fc / C;
+    const size_t base = ((size_t)b * F + f) * HW * C;
+    const float* a = acc + ((size_t)b * Fc + (size_t)f * C) * 3;
+    const float inv_hw = 1.0f / (float)HW;
+    const float k1 = 2.0f / ((float)F * (float)HW * (float)B);
+    float gmean[2];
+    for (int c = 0; c < C; ++c) gmean[c] = lambda * 2.0f * (a[c * 3] - a[c * 3 + 1]) * inv_hw * inv_hw / (float)B;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < HW; i += (size_t)gridDim.x * 256)
+        for (int c = 0; c < C; ++c) {
+            const size_t k = base + i * C + c;
+            dz[k] = k1 * (zhat[k] - z[k]) + gmean[c];
+        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float Lf = a[2] / ((float)F * (float)HW);
+        for (int c = 0; c < C; ++c) {
+            const float hd = (a[c * 3] - a[c * 3 + 1]) * inv_hw;
+            hhat[((size_t)b * Fc + (size_t)f * C) + c] = a[c * 3] * inv_hw;
+            Lf += lambda * hd * hd;
+        }
+        unsafeAtomicAdd(loss + b, Lf);
+    }
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                                      int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
+                                      float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes,
+                                      void* stream)
+{
+    if (!spectrum || !target || !loss || !h_hat || !d_spectrum || n_sets < 1 || n_chan < 1 || H < 1 || W < 1 ||
+        (is_complex != 0 && is_complex != 1) || !(lambda_ch >= 0.0f))
+        return GS_ERR_INVALID_ARG;
+    if (n_chan > 65535 || n_sets > 65535) return GS_ERR_CAPACITY;
+    const int C = is_complex ? 2 : 1;
+    const int Fc = n_chan * C;
+    const size_t need = (size_t)n_sets * Fc * 3 * sizeof(float);
+    if (!scratch || scratch_bytes < need || ((uintptr_t)scratch & 255)) return GS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    const size_t HW = (size_t)H * W;
+    launch_fill_u32((uint32_t*)scratch, (size_t)n_sets * Fc * 3, 0, 1, 0u, s);
+    launch_fill_u32((uint32_t*)loss, (size_t)n_sets, 0, 1, 0u, s);
+    const unsigned gx = (unsigned)((HW + 255) / 256 < 64 ? (HW + 255) / 256 : 64);
+    dim3 grid(gx, n_chan, n_sets);
+    hipLaunchKernelGGL(k_loss_reduce, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+    hipLaunchKernelGGL(k_loss_grad, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW, lambda_ch,
+                       (const float*)scratch, d_spectrum, h_hat, loss);
+    if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
+    return GS_OK;
+}

@@ -207,3 +207,53 @@ def blend(workspace: Workspace, attr: torch.Tensor, n_sets: Optional[int] = None
                                 ctypes.c_void_p(workspace.ptr), workspace.nbytes, ctypes.c_void_p(stream)),
           "gs_render_blend")
     return out
+
+
+def backward(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Tensor, spectrum: torch.Tensor,
+             d_spectrum: torch.Tensor, tx: Optional[torch.Tensor] = None, is_complex: bool = False,
+             n_sets: Optional[int] = None) -> dict:
+    """Gradients of a forward (or prepare + blend) call that used `workspace`.
+    Returns d_mean, d_log_scale, d_quat, d_opacity_logit, d_attr."""
+    sc = _scene_c(scene)
+    n = sc.n
+    B = rx.shape[0]
+    per_set = attr.dim() == (4 if is_complex else 3)
+    S = n_sets if n_sets is not None else (attr.shape[0] if per_set else B)
+    a = _attrs_c(attr, n, S, is_complex)
+    _check_f32("spectrum", spectrum)
+    _check_f32("d_spectrum", d_spectrum, tuple(spectrum.shape))
+    dev = rx.device
+    g = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+         "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev),
+         "d_attr": torch.empty_like(attr)}
+    q = GsQueries(B, _ptr(rx), _ptr(tx))
+    gr, p = workspace.grid.c(), workspace.params.c()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_render_backward(ctypes.byref(sc), ctypes.byref(a), ctypes.byref(q), S, ctypes.byref(gr),
+                                   ctypes.byref(p), _ptr(spectrum), _ptr(d_spectrum), _ptr(g["d_mean"]),
+                                   _ptr(g["d_log_scale"]), _ptr(g["d_quat"]), _ptr(g["d_opacity_logit"]),
+                                   _ptr(g["d_attr"]), ctypes.c_void_p(workspace.ptr), workspace.nbytes,
+                                   ctypes.c_void_p(stream)), "gs_render_backward")
+    return g
+
+
+def loss_spectrum(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, lambda_ch: float = 1.0):
+    """Spectrum L2 + Eq. (4) on the spatial means.  spectrum, target:
+    [B,F,H,W(,2)].  Returns (loss per set [B], h_hat [B,F(,2)], d_spectrum)
+    with d_spectrum the gradient of the mean over sets."""
+    _check_f32("spectrum", spectrum)
+    _check_f32("target", target, tuple(spectrum.shape))
+    B, F, H, W = spectrum.shape[:4]
+    C = 2 if is_complex else 1
+    dev = spectrum.device
+    loss = torch.empty(B, device=dev)
+    hhat = torch.empty((B, F, 2) if is_complex else (B, F), device=dev)
+    d = torch.empty_like(spectrum)
+    scratch = torch.empty(B * F * C * 3 * 4 + 256, dtype=torch.uint8, device=dev)
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_loss_spectrum(_ptr(spectrum), _ptr(target), B, F, int(is_complex), H, W, float(lambda_ch),
+                                 _ptr(loss), _ptr(hhat), _ptr(d), ctypes.c_void_p(base + off),
+                                 scratch.numel() - off, ctypes.c_void_p(stream)), "gs_loss_spectrum")
+    return loss, hhat, d
