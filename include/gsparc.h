@@ -209,6 +209,96 @@ gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n
                            int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
                            float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes, void* stream);
 
+/* ---- attribute network (shared form of the emission predictor, Eq. (1)) ----
+ * Per (set s, Gaussian g):  h1 = relu(W1 [e_g, gamma(tx_s), 0] + b1),
+ * h2 = relu(W2 h1 + b2), o = W3 h2 + b3, A_f = sigmoid(o_f - ln d),
+ * phi_f = o_{64+f}, attr = A e^{j phi}, d = max(|tx_s - mu_g|, r_near);
+ * gamma = Fourier features (u, sin 2^k pi u, cos 2^k pi u), k = 0..7, u the
+ * transmitter scaled to [-1, 1] by the box.  Shapes fixed: embedding 32,
+ * input padded to 96, hidden 64, 64 complex subcarriers.  Weights are BF16
+ * ([out][in] row-major), biases FP32; products run on BF16 matrix cores with
+ * FP32 accumulation. */
+typedef struct {
+    const uint16_t* W1; /* bf16 [64][96] */
+    const float* b1;    /* [64] */
+    const uint16_t* W2; /* bf16 [64][64] */
+    const float* b2;    /* [64] */
+    const uint16_t* W3; /* bf16 [128][64]: rows 0..63 amplitudes, 64..127 phases */
+    const float* b3;    /* [128] */
+    float box_lo[3], box_hi[3]; /* (host values) encoding box */
+    float r_near;               /* distance floor of the log-distance bias, m */
+} gs_mlp;
+
+/* Rows to evaluate: for set s, the Gaussians list[s*list_stride + i],
+ * i < count[count_stride ? s : 0] (device count, so the list can come from a
+ * device-side pass).  row_cap: rows per set the saved-activation buffers
+ * hold (>= every count).  grid_x: workgroups per set (0 = 256). */
+typedef struct {
+    int32_t n_sets;
+    const float* tx;        /* [S][3] */
+    const uint32_t* list;   /* Gaussian indices */
+    int64_t list_stride;
+    const uint32_t* count;
+    int32_t count_stride;
+    int64_t row_cap;
+    int32_t grid_x;
+} gs_mlp_rows;
+
+/* Caller-owned scratch of the network calls.  For inference only cb is
+ * needed (save_* may be NULL); training needs every buffer. */
+typedef struct {
+    float* cb;           /* [S][64] per-set first-layer bias */
+    uint16_t* genc;      /* [S][64] bf16 encodings (training) */
+    uint16_t* save_h1;   /* [S][row_cap][64] bf16 */
+    uint16_t* save_h2;   /* [S][row_cap][64] bf16 */
+    uint16_t* save_do;   /* [S][row_cap][128] bf16 */
+    uint16_t* save_dz2;  /* [S][row_cap][64] bf16 */
+    uint16_t* save_dz1;  /* [S][row_cap][64] bf16 */
+    float* dc;           /* [S][64] */
+    uint16_t* wT;        /* 32*64 + 64*64 + 64*128 bf16 transposed weights */
+    float* partial;      /* n_partial * 8192 floats */
+    int32_t n_partial;   /* split-K workgroups of the weight gradients */
+} gs_mlp_state;
+
+typedef struct {
+    float *dW1, *db1, *dW2, *db2, *dW3, *db3; /* FP32, shapes of the weights */
+    float* dE;                                /* [n][32] */
+} gs_mlp_grads;
+
+/* Z1 = E W1[:, :32]^T: the query-independent part of the first layer.
+ * E: bf16 [n][32]; Z1: FP32 [n][64]. */
+gs_status gs_mlp_embed(const gs_mlp* net, const uint16_t* E, int32_t n, float* Z1, void* stream);
+/* Attributes of the listed rows into attr[s * attr_stride + g*128 ...]
+ * ([S][n][64][2] for attr_stride = n*128); other rows untouched.  With
+ * st->save_h1/save_h2 set, keeps the activations for gs_mlp_backward(). */
+gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, int32_t n,
+                         const gs_mlp_rows* rows, float* attr, int64_t attr_stride, gs_mlp_state* st,
+                         void* stream);
+/* Gradients of sum(d_attr * attr) over the listed rows (same rows as the
+ * forward that saved the activations).  All outputs overwritten. */
+gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mean, int32_t n,
+                          const gs_mlp_rows* rows, const float* d_attr, int64_t attr_stride,
+                          gs_mlp_state* st, gs_mlp_grads* grads, void* stream);
+/* One 16x16x32 BF16 matrix-core product C = A B (A [16][32], B [32][16]
+ * bf16 row-major, C [16][16] FP32): checks the operand layout. */
+gs_status gs_mfma_probe(const uint16_t* A, const uint16_t* B, float* C, void* stream);
+
+/* ---- fused Adam over parameter segments (Kingma and Ba) ----
+ * For each segment: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); when shadow is
+ * set, shadow = bf16(p).  Segments are described on the host. */
+typedef struct {
+    float* p;
+    const float* g;
+    float* m;
+    float* v;
+    uint16_t* shadow; /* optional bf16 copy of p */
+    int64_t count;
+    float lr;
+} gs_adam_segment;
+gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, int32_t step, float beta1,
+                       float beta2, float eps, void* stream);
+
 /*
  * Copies the per-query flags of the last forward call into `out` (host,
  * [B] entries).  Synchronises `stream`.

@@ -47,6 +47,30 @@ class GsFlags(ctypes.Structure):
     _fields_ = [("n_visible", c_u32), ("n_pairs", c_u32), ("overflow", c_u32), ("n_invalid", c_u32)]
 
 
+class GsMlp(ctypes.Structure):
+    _fields_ = [("W1", c_p), ("b1", c_p), ("W2", c_p), ("b2", c_p), ("W3", c_p), ("b3", c_p),
+                ("box_lo", c_f32 * 3), ("box_hi", c_f32 * 3), ("r_near", c_f32)]
+
+
+class GsMlpRows(ctypes.Structure):
+    _fields_ = [("n_sets", c_i32), ("tx", c_p), ("list", c_p), ("list_stride", c_i64), ("count", c_p),
+                ("count_stride", c_i32), ("row_cap", c_i64), ("grid_x", c_i32)]
+
+
+class GsMlpState(ctypes.Structure):
+    _fields_ = [("cb", c_p), ("genc", c_p), ("save_h1", c_p), ("save_h2", c_p), ("save_do", c_p),
+                ("save_dz2", c_p), ("save_dz1", c_p), ("dc", c_p), ("wT", c_p), ("partial", c_p),
+                ("n_partial", c_i32)]
+
+
+class GsMlpGrads(ctypes.Structure):
+    _fields_ = [("dW1", c_p), ("db1", c_p), ("dW2", c_p), ("db2", c_p), ("dW3", c_p), ("db3", c_p), ("dE", c_p)]
+
+
+class GsAdamSegment(ctypes.Structure):
+    _fields_ = [("p", c_p), ("g", c_p), ("m", c_p), ("v", c_p), ("shadow", c_p), ("count", c_i64), ("lr", c_f32)]
+
+
 _LAYOUT_FIELDS = ["total", "flags", "rec", "rect", "status", "tinfo", "order", "keys", "pair_keys", "pair_list",
                   "ranges", "T_final", "n_last", "n_contrib", "flags_stride", "rec_stride", "rect_stride",
                   "status_stride", "tinfo_stride", "order_stride", "keys_stride", "pair_keys_stride",
@@ -76,6 +100,13 @@ SIGNATURES = {
                                    c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
                                  c_p]),
+    "gs_mlp_embed": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_i32, c_p, c_p]),
+    "gs_mlp_forward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
+                               ctypes.POINTER(GsMlpState), c_p]),
+    "gs_mlp_backward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
+                                ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
+    "gs_mfma_probe": (c_i32, [c_p, c_p, c_p, c_p]),
+    "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
                               ctypes.POINTER(GsFlags), c_p]),
 }

@@ -1,0 +1,74 @@
+// Fused Adam (Kingma and Ba) over several parameter segments in one launch;
+// segments that feed the BF16 matrix cores also refresh their BF16 copy.
+#include "common.h"
+
+namespace gs {
+
+constexpr int ADAM_MAX_SEGS = 16;
+
+struct AdamSegs {
+    float* p[ADAM_MAX_SEGS];
+    const float* g[ADAM_MAX_SEGS];
+    float* m[ADAM_MAX_SEGS];
+    float* v[ADAM_MAX_SEGS];
+    uint16_t* sh[ADAM_MAX_SEGS];
+    int64_t start[ADAM_MAX_SEGS + 1];  // prefix of counts
+    float lr[ADAM_MAX_SEGS];
+    int nseg;
+};
+
+__device__ __forceinline__ uint16_t f2bf_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_adam(AdamSegs S, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t total = S.start[S.nseg];
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        int k = 0;
+        while (e >= S.start[k + 1]) ++k;
+        const int64_t i = e - S.start[k];
+        const float g = S.g[k][i];
+        const float m = b1 * S.m[k][i] + (1.0f - b1) * g;
+        const float v = b2 * S.v[k][i] + (1.0f - b2) * g * g;
+        S.m[k][i] = m;
+        S.v[k][i] = v;
+        const float p = S.p[k][i] - S.lr[k] * (m / c1) / (sqrtf(v / c2) + eps);
+        S.p[k][i] = p;
+        if (S.sh[k]) S.sh[k][i] = f2bf_rne(p);
+    }
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" gs_status gs_adam_step(const gs_adam_segment* segs, int32_t n_segs, int32_t step, float beta1,
+                                  float beta2, float eps, void* stream)
+{
+    if (!segs || n_segs < 1 || n_segs > ADAM_MAX_SEGS || step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return GS_ERR_INVALID_ARG;
+    AdamSegs S{};
+    S.nseg = n_segs;
+    int64_t total = 0;
+    for (int k = 0; k < n_segs; ++k) {
+        const gs_adam_segment& a = segs[k];
+        if (!a.p || !a.g || !a.m || !a.v || a.count < 0) return GS_ERR_INVALID_ARG;
+        S.p[k] = a.p; S.g[k] = a.g; S.m[k] = a.m; S.v[k] = a.v; S.sh[k] = a.shadow; S.lr[k] = a.lr;
+        S.start[k] = total;
+        total += a.count;
+    }
+    S.start[n_segs] = total;
+    if (total == 0) return GS_OK;
+    const double c1 = 1.0 - pow((double)beta1, step), c2 = 1.0 - pow((double)beta2, step);
+    (void)hipGetLastError();
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, (hipStream_t)stream,
+                       S, beta1, beta2, eps, (float)c1, (float)c2);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}

@@ -1,0 +1,631 @@
+// Attribute network on the BF16 matrix cores of gfx950
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// Per (set s, Gaussian g) row, a shared form of the emission predictor of
+// Eq. (1):
+//   h1 = relu(Z1[g] + c[s])          Z1 = E W1e^T (query-independent),
+//                                    c[s] = b1 + W1t gamma(tx_s)
+//   h2 = relu(W2 h1 + b2)
+//   o  = W3 h2 + b3                  (64 amplitudes, 64 phases)
+//   A_f = sigmoid(o_f - ln d_sg), phi_f = o_{64+f},  attr = A e^{j phi}
+// with d_sg = max(|tx_s - mu_g|, r_near).  Rows come from a list of
+// Gaussians (e.g. those that reach some pixel) shared by all sets or one
+// list per set.
+//
+// MFMA 16x16x32 operand layout (lane l of a wave):
+//   A (16 x 32): row l%16, k = 8*(l/16) .. +7   (8 bf16)
+//   B (32 x 16): col l%16, k = 8*(l/16) .. +7   (8 bf16)
+//   C (16 x 16): col l%16, rows 4*(l/16) .. +3  (4 floats)
+#include "common.h"
+#include "mlp.h"
+
+namespace gs {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint16_t f2bf(float x)  // round to nearest even
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40);  // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p)  // 16-byte aligned
+{
+    const uint4 v = *(const uint4*)p;
+    bf16x8 r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+}
+
+// ---- layout probe: C = A B for one 16x16x32 tile (A, B row-major bf16) ----
+__global__ void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* C)
+{
+    const int l = threadIdx.x;
+    uint16_t a[8], b[8];
+    for (int j = 0; j < 8; ++j) {
+        a[j] = A[(l % 16) * 32 + 8 * (l / 16) + j];
+        b[j] = B[(8 * (l / 16) + j) * 16 + (l % 16)];
+    }
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, a, 16);
+    __builtin_memcpy(&bv, b, 16);
+    f32x4 c = {0, 0, 0, 0};
+    c = mfma(av, bv, c);
+    for (int i = 0; i < 4; ++i) C[(4 * (l / 16) + i) * 16 + (l % 16)] = c[i];
+}
+
+// ---- Z1 = E W1e^T, one wave per 16 Gaussians -----------------------------
+__global__ __launch_bounds__(256) void k_mlp_embed(const uint16_t* __restrict__ E, int n,
+                                                   const uint16_t* __restrict__ W1, float* __restrict__ Z1)
+{
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r0 = tile * 16;
+    if (r0 >= n) return;
+    const int row = r0 + (lane & 15);
+    bf16x8 a = {};
+    if (row < n) a = load8(E + (size_t)row * MLP_EMB + 8 * (lane >> 4));
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const bf16x8 b = load8(W1 + (size_t)(nt * 16 + (lane & 15)) * MLP_IN + 8 * (lane >> 4));
+        f32x4 c = {0, 0, 0, 0};
+        c = mfma(a, b, c);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = r0 + 4 * (lane >> 4) + i;
+            if (rr < n) Z1[(size_t)rr * MLP_HID + nt * 16 + (lane & 15)] = c[i];
+        }
+    }
+}
+
+// ---- c[s] = b1 + W1t bf16(gamma(tx_s)) -----------------------------------
+__global__ __launch_bounds__(64) void k_mlp_bias(const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                 const float* __restrict__ tx, float lo0, float lo1, float lo2,
+                                                 float hi0, float hi1, float hi2, float* __restrict__ cb,
+                                                 uint16_t* __restrict__ genc)
+{
+    const int s = blockIdx.x, j = threadIdx.x;
+    __shared__ float g[MLP_ENC];
+    if (j < 3) {
+        const float lo = j == 0 ? lo0 : (j == 1 ? lo1 : lo2), hi = j == 0 ? hi0 : (j == 1 ? hi1 : hi2);
+        const double u = 2.0 * ((double)tx[3 * s + j] - lo) / ((double)hi - lo) - 1.0;
+        g[j] = bf2f(f2bf((float)u));
+        for (int k = 0; k < MLP_BANDS; ++k) {
+            const double a = ldexp(M_PI, k) * u;
+            g[3 + 6 * k + j] = bf2f(f2bf((float)sin(a)));
+            g[6 + 6 * k + j] = bf2f(f2bf((float)cos(a)));
+        }
+    }
+    __syncthreads();
+    float acc = b1[j];
+    for (int k = 0; k < MLP_ENC; ++k) acc = fmaf(bf2f(W1[(size_t)j * MLP_IN + MLP_EMB + k]), g[k], acc);
+    cb[s * MLP_HID + j] = acc;
+    if (genc)
+        for (int k = j; k < MLP_ENC; k += 64) genc[s * MLP_ENC_PAD + k] = f2bf(g[k]);
+}
+
+// one wave's 16 rows: h1 (bf16, LDS) -> h2 (bf16, LDS) -> o (C layout)
+struct RowTile {
+    int g[16];
+};
+
+__device__ __forceinline__ void layer_mfma(const uint16_t* __restrict__ act /*LDS [16][64]*/,
+                                           const uint16_t* __restrict__ W /*[N][64] bf16*/, int ntiles,
+                                           f32x4* acc, int lane)
+{
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) {
+        if (nt < ntiles) {
+            f32x4 c = {0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                const bf16x8 a = load8(act + (lane & 15) * MLP_HID + kc * 32 + 8 * (lane >> 4));
+                const bf16x8 b = load8(W + (size_t)(nt * 16 + (lane & 15)) * MLP_HID + kc * 32 + 8 * (lane >> 4));
+                c = mfma(a, b, c);
+            }
+            acc[nt] = c;
+        }
+    }
+}
+
+// Loads h1 = relu(Z1[g] + c[s]) for the wave's 16 rows into LDS (bf16).
+__device__ __forceinline__ void load_h1(const float* __restrict__ Z1, const float* __restrict__ cs, const int* rows,
+                                        uint16_t* h1s, int lane)
+{
+    const int r = lane & 15, c0 = (lane >> 4) * 16;
+    const int g = rows[r];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float v = 0.0f;
+        if (g >= 0) v = fmaxf(Z1[(size_t)g * MLP_HID + c0 + j] + cs[c0 + j], 0.0f);
+        h1s[r * MLP_HID + c0 + j] = f2bf(v);
+    }
+}
+
+// C layout (16 x 64 as 4 tiles) + bias -> relu -> bf16 -> LDS [16][64]
+__device__ __forceinline__ void store_hidden(const f32x4* acc, const float* __restrict__ b, uint16_t* hs,
+                                             int lane)
+{
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int col = nt * 16 + (lane & 15), row = 4 * (lane >> 4) + i;
+            hs[row * MLP_HID + col] = f2bf(fmaxf(acc[nt][i] + b[col], 0.0f));
+        }
+}
+
+// rows of a set: list entries [0, count); list shared (stride 0) or per set
+__device__ __forceinline__ int row_gauss(const uint32_t* list, uint32_t count, int i)
+{
+    return i < (int)count ? (int)list[i] : -1;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
+{
+    const int s = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t* list = A.list + (size_t)s * A.list_stride;
+    const uint32_t count = A.count[A.count_stride ? s : 0];
+    __shared__ __attribute__((aligned(16))) uint16_t s_h1[4][16 * MLP_HID];
+    __shared__ __attribute__((aligned(16))) uint16_t s_h2[4][16 * MLP_HID];
+    __shared__ int s_rows[4][16];
+    const float* cs = A.cb + s * MLP_HID;
+    const float tx0 = A.tx[3 * s], tx1 = A.tx[3 * s + 1], tx2 = A.tx[3 * s + 2];
+    for (int base = blockIdx.x * 64; base < (int)count; base += gridDim.x * 64) {
+        const int r0 = base + w * 16;
+        if (lane < 16) s_rows[w][lane] = row_gauss(list, count, r0 + lane);
+        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
+        load_h1(A.Z1, cs, s_rows[w], s_h1[w], lane);
+        __syncthreads();
+        f32x4 acc[8];
+        layer_mfma(s_h1[w], A.W2, 4, acc, lane);
+        store_hidden(acc, A.b2, s_h2[w], lane);
+        __syncthreads();
+        layer_mfma(s_h2[w], A.W3, 8, acc, lane);
+        // save activations for the backward (row-compact order r = s*cap + i)
+        if (A.save_h1) {
+            const int r = lane & 15, c0 = (lane >> 4) * 16;
+            const int i = r0 + r;
+            if (i < (int)count) {
+                uint16_t* d1 = A.save_h1 + ((size_t)s * A.row_cap + i) * MLP_HID + c0;
+                uint16_t* d2 = A.save_h2 + ((size_t)s * A.row_cap + i) * MLP_HID + c0;
+                for (int j = 0; j < 16; ++j) {
+                    d1[j] = s_h1[w][r * MLP_HID + c0 + j];
+                    d2[j] = s_h2[w][r * MLP_HID + c0 + j];
+                }
+            }
+        }
+        // epilogue: amplitude / phase -> complex attribute
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = 4 * (lane >> 4) + i;
+            const int g = s_rows[w][rr];
+            if (g < 0) continue;
+            const float e0 = A.mean[g] - tx0, e1 = A.mean[A.n + g] - tx1, e2 = A.mean[2 * A.n + g] - tx2;
+            const float d = fmaxf(sqrtf(e0 * e0 + e1 * e1 + e2 * e2), A.r_near);
+            const float lnd = logf(d);
+            float* out = A.attr + (size_t)s * A.attr_stride + (size_t)g * (2 * MLP_F);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int f = nt * 16 + (lane & 15);
+                const float oa = acc[nt][i] + A.b3[f] - lnd;
+                const float op = acc[nt + 4][i] + A.b3[MLP_F + f];
+                const float amp = 1.0f / (1.0f + expf(-oa));
+                float sn, cs_;
+                sincosf(op, &sn, &cs_);
+                *(float2*)(out + 2 * f) = make_float2(amp * cs_, amp * sn);
+            }
+        }
+    }
+}
+
+// Backward through the epilogue and the three layers for each row.  Writes
+// the rounded products' operands (d_o, dZ2, dZ1 as bf16) for the weight
+// gradients, bias sums, per-set dZ1 sums and dE (atomics).
+__global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
+{
+    const int s = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t* list = A.list + (size_t)s * A.list_stride;
+    const uint32_t count = A.count[A.count_stride ? s : 0];
+    __shared__ __attribute__((aligned(16))) uint16_t s_h2[4][16 * MLP_HID];
+    __shared__ __attribute__((aligned(16))) uint16_t s_do[4][16 * 2 * MLP_F];
+    __shared__ __attribute__((aligned(16))) uint16_t s_dz[4][16 * MLP_HID];
+    __shared__ int s_rows[4][16];
+    __shared__ float s_db3[2 * MLP_F], s_db2[MLP_HID], s_dc[MLP_HID];
+    for (int k = threadIdx.x; k < 2 * MLP_F; k += 256) s_db3[k] = 0.0f;
+    if (threadIdx.x < MLP_HID) {
+        s_db2[threadIdx.x] = 0.0f;
+        s_dc[threadIdx.x] = 0.0f;
+    }
+    const float tx0 = A.tx[3 * s], tx1 = A.tx[3 * s + 1], tx2 = A.tx[3 * s + 2];
+    __syncthreads();
+    for (int base = blockIdx.x * 64; base < (int)count; base += gridDim.x * 64) {
+        const int r0 = base + w * 16;
+        if (lane < 16) s_rows[w][lane] = row_gauss(list, count, r0 + lane);
+        __syncthreads();
+        // saved h2 of the 16 rows
+        {
+            const int r = lane & 15, c0 = (lane >> 4) * 16;
+            const int i = r0 + r;
+            for (int j = 0; j < 16; ++j)
+                s_h2[w][r * MLP_HID + c0 + j] =
+                    i < (int)count ? A.save_h2[((size_t)s * A.row_cap + i) * MLP_HID + c0 + j] : (uint16_t)0;
+        }
+        __syncthreads();
+        f32x4 acc[8];
+        layer_mfma(s_h2[w], A.W3, 8, acc, lane);  // recompute o
+        // d_o from d_attr
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = 4 * (lane >> 4) + i;
+            const int g = s_rows[w][rr];
+            float lnd = 0.0f;
+            if (g >= 0) {
+                const float e0 = A.mean[g] - tx0, e1 = A.mean[A.n + g] - tx1, e2 = A.mean[2 * A.n + g] - tx2;
+                lnd = logf(fmaxf(sqrtf(e0 * e0 + e1 * e1 + e2 * e2), A.r_near));
+            }
+            const float* dat = A.d_attr + (size_t)s * A.attr_stride + (size_t)(g < 0 ? 0 : g) * (2 * MLP_F);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int f = nt * 16 + (lane & 15);
+                float da = 0.0f, dp = 0.0f;
+                if (g >= 0) {
+                    const float oa = acc[nt][i] + A.b3[f] - lnd;
+                    const float op = acc[nt + 4][i] + A.b3[MLP_F + f];
+                    const float amp = 1.0f / (1.0f + expf(-oa));
+                    float sn, cs_;
+                    sincosf(op, &sn, &cs_);
+                    const float2 gg = *(const float2*)(dat + 2 * f);
+                    da = (gg.x * cs_ + gg.y * sn) * amp * (1.0f - amp);
+                    dp = amp * (-gg.x * sn + gg.y * cs_);
+                }
+                s_do[w][rr * 2 * MLP_F + f] = f2bf(da);
+                s_do[w][rr * 2 * MLP_F + MLP_F + f] = f2bf(dp);
+                acc[nt][i] = da;
+                acc[nt + 4][i] = dp;
+            }
+        }
+        // db3: FP32 sums of d_o
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            float v = acc[nt][0] + acc[nt][1] + acc[nt][2] + acc[nt][3];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) atomicAdd(&s_db3[nt * 16 + lane], v);
+        }
+        __syncthreads();
+        // write d_o (bf16) for the weight gradient
+        {
+            const int r = lane & 15;
+            const int i = r0 + r;
+            if (i < (int)count)
+                for (int j = (lane >> 4) * 32; j < (lane >> 4) * 32 + 32; ++j)
+                    A.save_do[((size_t)s * A.row_cap + i) * 2 * MLP_F + j] = s_do[w][r * 2 * MLP_F + j];
+        }
+        // dh2 = d_o W3  (K = 128: four 32-wide chunks; B from W3^T [64][128])
+        f32x4 dh[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 c = {0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                const bf16x8 a = load8(&s_do[w][(lane & 15) * 2 * MLP_F + kc * 32 + 8 * (lane >> 4)]);
+                const bf16x8 b = load8(A.W3T + (size_t)(nt * 16 + (lane & 15)) * 2 * MLP_F + kc * 32 + 8 * (lane >> 4));
+                c = mfma(a, b, c);
+            }
+            dh[nt] = c;
+        }
+        // dZ2 = dh2 * [h2 > 0]
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int col = nt * 16 + (lane & 15), row = 4 * (lane >> 4) + i;
+                const float m = bf2f(s_h2[w][row * MLP_HID + col]) > 0.0f ? 1.0f : 0.0f;
+                dh[nt][i] *= m;
+            }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            float v = dh[nt][0] + dh[nt][1] + dh[nt][2] + dh[nt][3];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) atomicAdd(&s_db2[nt * 16 + lane], v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                s_dz[w][(4 * (lane >> 4) + i) * MLP_HID + nt * 16 + (lane & 15)] = f2bf(dh[nt][i]);
+        __syncthreads();
+        {
+            const int r = lane & 15, c0 = (lane >> 4) * 16;
+            const int i = r0 + r;
+            if (i < (int)count)
+                for (int j = 0; j < 16; ++j)
+                    A.save_dz2[((size_t)s * A.row_cap + i) * MLP_HID + c0 + j] = s_dz[w][r * MLP_HID + c0 + j];
+        }
+        // dh1 = dZ2 W2 (B from W2^T), dZ1 = dh1 * [h1 > 0]
+        f32x4 d1[4];
+        layer_mfma(s_dz[w], A.W2T, 4, d1, lane);
+        __syncthreads();
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int col = nt * 16 + (lane & 15), row = 4 * (lane >> 4) + i;
+                const int rix = r0 + row;
+                float m = 0.0f;
+                if (rix < (int)count) m = bf2f(A.save_h1[((size_t)s * A.row_cap + rix) * MLP_HID + col]) > 0.0f;
+                d1[nt][i] *= m;
+                s_dz[w][row * MLP_HID + col] = f2bf(d1[nt][i]);
+            }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            float v = d1[nt][0] + d1[nt][1] + d1[nt][2] + d1[nt][3];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) atomicAdd(&s_dc[nt * 16 + lane], v);
+        }
+        __syncthreads();
+        {
+            const int r = lane & 15, c0 = (lane >> 4) * 16;
+            const int i = r0 + r;
+            if (i < (int)count)
+                for (int j = 0; j < 16; ++j)
+                    A.save_dz1[((size_t)s * A.row_cap + i) * MLP_HID + c0 + j] = s_dz[w][r * MLP_HID + c0 + j];
+        }
+        // dE[g] += dZ1 W1e  (B from W1e^T [32][64])
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x4 c = {0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                const bf16x8 a = load8(&s_dz[w][(lane & 15) * MLP_HID + kc * 32 + 8 * (lane >> 4)]);
+                const bf16x8 b = load8(A.W1eT + (size_t)(nt * 16 + (lane & 15)) * MLP_HID + kc * 32 + 8 * (lane >> 4));
+                c = mfma(a, b, c);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int g = s_rows[w][4 * (lane >> 4) + i];
+                if (g >= 0) unsafeAtomicAdd(A.dE + (size_t)g * MLP_EMB + nt * 16 + (lane & 15), c[i]);
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 2 * MLP_F; k += 256) unsafeAtomicAdd(A.db3 + k, s_db3[k]);
+    if (threadIdx.x < MLP_HID) {
+        unsafeAtomicAdd(A.db2 + threadIdx.x, s_db2[threadIdx.x]);
+        unsafeAtomicAdd(A.dc + s * MLP_HID + threadIdx.x, s_dc[threadIdx.x]);
+    }
+}
+
+// Split-K weight gradient C[M][N] = sum over rows r of a[r][m] b[r][n] (bf16
+// operands, FP32 accumulation).  a rows: [S][cap][M]; b rows: [S][cap][N], or
+// when b_gather is set, b = E[list[i]] ([n][N]).  Each workgroup handles K
+// blocks of 32 rows round-robin and writes its partial [M][N].
+template <int M, int N>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b,
+                                               const uint16_t* __restrict__ bgather, const uint32_t* __restrict__ list,
+                                               size_t list_stride, const uint32_t* __restrict__ count,
+                                               int count_stride, int S, size_t cap, float* __restrict__ partial)
+{
+    constexpr int MT = M / 16, NT = N / 16, TILES = MT * NT, PER_WAVE = TILES / 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ __attribute__((aligned(16))) uint16_t tA[M][40];  // [m][32 rows], padded
+    __shared__ __attribute__((aligned(16))) uint16_t tB[N][40];
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int t = 0; t < PER_WAVE; ++t) acc[t] = f32x4{0, 0, 0, 0};
+    // K blocks enumerate (set, 32-row block)
+    int kb = blockIdx.x;
+    for (int s = 0; s < S; ++s) {
+        const uint32_t cnt = count[count_stride ? s : 0];
+        const int nblk = (int)((cnt + 31) / 32);
+        const uint32_t* lst = list + (size_t)s * list_stride;
+        while (kb < nblk) {
+            // stage 32 rows transposed
+            for (int e = threadIdx.x; e < 32 * M; e += 256) {
+                const int r = e / M, m = e % M;
+                const int i = kb * 32 + r;
+                tA[m][r] = i < (int)cnt ? a[((size_t)s * cap + i) * M + m] : (uint16_t)0;
+            }
+            for (int e = threadIdx.x; e < 32 * N; e += 256) {
+                const int r = e / N, c = e % N;
+                const int i = kb * 32 + r;
+                uint16_t v = 0;
+                if (i < (int)cnt) v = bgather ? bgather[(size_t)lst[i] * N + c] : b[((size_t)s * cap + i) * N + c];
+                tB[c][r] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < PER_WAVE; ++t) {
+                const int tile = w * PER_WAVE + t;
+                const int mt = tile / NT, nt = tile % NT;
+                const bf16x8 av = load8(&tA[mt * 16 + (lane & 15)][8 * (lane >> 4)]);
+                const bf16x8 bv = load8(&tB[nt * 16 + (lane & 15)][8 * (lane >> 4)]);
+                acc[t] = mfma(av, bv, acc[t]);
+            }
+            __syncthreads();
+            kb += gridDim.x;
+        }
+        kb -= nblk;
+    }
+    float* P = partial + (size_t)blockIdx.x * M * N;
+#pragma unroll
+    for (int t = 0; t < PER_WAVE; ++t) {
+        const int tile = w * PER_WAVE + t;
+        const int mt = tile / NT, nt = tile % NT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) P[(mt * 16 + 4 * (lane >> 4) + i) * N + nt * 16 + (lane & 15)] = acc[t][i];
+    }
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ partial, int nparts, int len, float* __restrict__ out,
+                                  int out_ld, int out_col0, int ncols)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    float s = 0.0f;
+    for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * len + e];
+    const int r = e / ncols, c = e % ncols;
+    out[(size_t)r * out_ld + out_col0 + c] = s;
+}
+
+// dW1t = sum_s dc_s gamma_s^T (bf16 gamma), db1 = sum_s dc_s
+__global__ void k_mlp_bias_grad(const float* __restrict__ dc, const uint16_t* __restrict__ genc, int S,
+                                float* __restrict__ dW1, float* __restrict__ db1)
+{
+    const int j = threadIdx.x;  // hidden unit
+    for (int k = blockIdx.x; k <= MLP_ENC; k += gridDim.x) {
+        float acc = 0.0f;
+        for (int s = 0; s < S; ++s) acc += dc[s * MLP_HID + j] * (k < MLP_ENC ? bf2f(genc[s * MLP_ENC_PAD + k]) : 1.0f);
+        if (k < MLP_ENC) dW1[(size_t)j * MLP_IN + MLP_EMB + k] = acc;
+        else db1[j] = acc;
+    }
+}
+
+// bf16 transposes of the weights used as B operands in the backward
+__global__ void k_mlp_transpose(const uint16_t* __restrict__ W1, const uint16_t* __restrict__ W2,
+                                const uint16_t* __restrict__ W3, uint16_t* __restrict__ W1eT,
+                                uint16_t* __restrict__ W2T, uint16_t* __restrict__ W3T)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < MLP_EMB * MLP_HID) {  // W1eT[n][k] = W1[k][n], n < 32
+        const int n = e / MLP_HID, k = e % MLP_HID;
+        W1eT[e] = W1[(size_t)k * MLP_IN + n];
+    }
+    if (e < MLP_HID * MLP_HID) {  // W2T[n][k] = W2[k][n]
+        const int n = e / MLP_HID, k = e % MLP_HID;
+        W2T[e] = W2[(size_t)k * MLP_HID + n];
+    }
+    if (e < MLP_HID * 2 * MLP_F) {  // W3T[n][k] = W3[k][n], n < 64, k < 128
+        const int n = e / (2 * MLP_F), k = e % (2 * MLP_F);
+        W3T[e] = W3[(size_t)k * MLP_HID + n];
+    }
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+gs_status gs_mfma_probe(const uint16_t* A, const uint16_t* B, float* C, void* stream)
+{
+    if (!A || !B || !C) return GS_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, C);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+gs_status gs_mlp_embed(const gs_mlp* net, const uint16_t* E, int32_t n, float* Z1, void* stream)
+{
+    if (!net || !net->W1 || !E || !Z1 || n < 1) return GS_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    const int tiles = (n + 15) / 16;
+    hipLaunchKernelGGL(k_mlp_embed, dim3((tiles + 3) / 4), dim3(256), 0, (hipStream_t)stream, E, n, net->W1, Z1);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+static gs_status check_rows(const gs_mlp* net, const gs_mlp_rows* rows, const float* mean, int32_t n)
+{
+    if (!net || !rows || !mean || n < 1) return GS_ERR_INVALID_ARG;
+    if (!net->W1 || !net->b1 || !net->W2 || !net->b2 || !net->W3 || !net->b3) return GS_ERR_INVALID_ARG;
+    if (!rows->tx || !rows->list || !rows->count || rows->n_sets < 1 || rows->n_sets > 65535) return GS_ERR_INVALID_ARG;
+    if (rows->row_cap < 1 || !(net->r_near > 0.0f)) return GS_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!(net->box_hi[k] > net->box_lo[k])) return GS_ERR_INVALID_ARG;
+    return GS_OK;
+}
+
+gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, int32_t n, const gs_mlp_rows* rows,
+                         float* attr, int64_t attr_stride, gs_mlp_state* st, void* stream)
+{
+    gs_status e = check_rows(net, rows, mean, n);
+    if (e != GS_OK) return e;
+    if (!Z1 || !attr || !st || !st->cb || attr_stride < (int64_t)n * 2 * MLP_F) return GS_ERR_INVALID_ARG;
+    if ((st->save_h1 == nullptr) != (st->save_h2 == nullptr)) return GS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_mlp_bias, dim3(rows->n_sets), dim3(64), 0, s, net->W1, net->b1, rows->tx, net->box_lo[0],
+                       net->box_lo[1], net->box_lo[2], net->box_hi[0], net->box_hi[1], net->box_hi[2], st->cb,
+                       st->genc);
+    MlpArgs A{};
+    A.W2 = net->W2; A.b2 = net->b2; A.W3 = net->W3; A.b3 = net->b3;
+    A.Z1 = Z1; A.cb = st->cb; A.mean = mean; A.n = n; A.tx = rows->tx; A.r_near = net->r_near;
+    A.list = rows->list; A.list_stride = rows->list_stride; A.count = rows->count; A.count_stride = rows->count_stride;
+    A.row_cap = rows->row_cap; A.attr = attr; A.attr_stride = attr_stride;
+    A.save_h1 = st->save_h1; A.save_h2 = st->save_h2;
+    const int gx = rows->grid_x > 0 ? rows->grid_x : 256;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mean, int32_t n, const gs_mlp_rows* rows,
+                          const float* d_attr, int64_t attr_stride, gs_mlp_state* st, gs_mlp_grads* gr,
+                          void* stream)
+{
+    gs_status e = check_rows(net, rows, mean, n);
+    if (e != GS_OK) return e;
+    if (!E || !d_attr || !st || !gr || !st->save_h1 || !st->save_h2 || !st->save_do || !st->save_dz2 ||
+        !st->save_dz1 || !st->genc || !st->dc || !st->wT || !st->partial || st->n_partial < 1)
+        return GS_ERR_INVALID_ARG;
+    if (!gr->dW1 || !gr->db1 || !gr->dW2 || !gr->db2 || !gr->dW3 || !gr->db3 || !gr->dE) return GS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    uint16_t* W1eT = st->wT;
+    uint16_t* W2T = W1eT + MLP_EMB * MLP_HID;
+    uint16_t* W3T = W2T + MLP_HID * MLP_HID;
+    hipLaunchKernelGGL(k_mlp_transpose, dim3((MLP_HID * 2 * MLP_F + 255) / 256), dim3(256), 0, s, net->W1, net->W2,
+                       net->W3, W1eT, W2T, W3T);
+    launch_fill_u32((uint32_t*)gr->db3, 2 * MLP_F, 0, 1, 0u, s);
+    launch_fill_u32((uint32_t*)gr->db2, MLP_HID, 0, 1, 0u, s);
+    launch_fill_u32((uint32_t*)gr->dW1, (size_t)MLP_HID * MLP_IN, 0, 1, 0u, s);
+    launch_fill_u32((uint32_t*)st->dc, (size_t)rows->n_sets * MLP_HID, 0, 1, 0u, s);
+    launch_fill_u32((uint32_t*)gr->dE, (size_t)n * MLP_EMB, 0, 1, 0u, s);
+    MlpArgs A{};
+    A.W2 = net->W2; A.b2 = net->b2; A.W3 = net->W3; A.b3 = net->b3;
+    A.W2T = W2T; A.W3T = W3T; A.W1eT = W1eT;
+    A.mean = mean; A.n = n; A.tx = rows->tx; A.r_near = net->r_near;
+    A.list = rows->list; A.list_stride = rows->list_stride; A.count = rows->count; A.count_stride = rows->count_stride;
+    A.row_cap = rows->row_cap; A.d_attr = d_attr; A.attr_stride = attr_stride;
+    A.save_h1 = st->save_h1; A.save_h2 = st->save_h2; A.save_do = st->save_do; A.save_dz2 = st->save_dz2;
+    A.save_dz1 = st->save_dz1; A.db3 = gr->db3; A.db2 = gr->db2; A.dc = st->dc; A.dE = gr->dE;
+    const int gx = rows->grid_x > 0 ? rows->grid_x : 256;
+    hipLaunchKernelGGL(k_mlp_bwd_data, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
+    const int P = st->n_partial;
+    const size_t cap = (size_t)rows->row_cap;
+    // dW3 = d_o^T h2, dW2 = dZ2^T h1, dW1e = dZ1^T E
+    hipLaunchKernelGGL((k_wgrad<2 * MLP_F, MLP_HID>), dim3(P), dim3(256), 0, s, st->save_do, st->save_h2, nullptr,
+                       rows->list, rows->list_stride, rows->count, rows->count_stride, rows->n_sets, cap, st->partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((2 * MLP_F * MLP_HID + 255) / 256), dim3(256), 0, s, st->partial, P,
+                       2 * MLP_F * MLP_HID, gr->dW3, MLP_HID, 0, MLP_HID);
+    hipLaunchKernelGGL((k_wgrad<MLP_HID, MLP_HID>), dim3(P), dim3(256), 0, s, st->save_dz2, st->save_h1, nullptr,
+                       rows->list, rows->list_stride, rows->count, rows->count_stride, rows->n_sets, cap, st->partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((MLP_HID * MLP_HID + 255) / 256), dim3(256), 0, s, st->partial, P,
+                       MLP_HID * MLP_HID, gr->dW2, MLP_HID, 0, MLP_HID);
+    hipLaunchKernelGGL((k_wgrad<MLP_HID, MLP_EMB>), dim3(P), dim3(256), 0, s, st->save_dz1, nullptr, E, rows->list,
+                       rows->list_stride, rows->count, rows->count_stride, rows->n_sets, cap, st->partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((MLP_HID * MLP_EMB + 255) / 256), dim3(256), 0, s, st->partial, P,
+                       MLP_HID * MLP_EMB, gr->dW1, MLP_IN, 0, MLP_EMB);
+    hipLaunchKernelGGL(k_mlp_bias_grad, dim3(MLP_ENC + 1), dim3(MLP_HID), 0, s, st->dc, st->genc, rows->n_sets,
+                       gr->dW1, gr->db1);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+}  // extern "C"
