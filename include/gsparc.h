@@ -189,11 +189,25 @@ gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, i
  * Float atomics make the summation order, and so the last bits, vary
  * between runs.
  */
+#define GS_BWD_ATTR_GRAD_ZEROED 1 /* flags: d_attr is already zero, do not clear it */
 gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
                              int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
                              const float* d_spectrum, float* d_mean, float* d_log_scale, float* d_quat,
-                             float* d_opacity_logit, float* d_attr, void* workspace, size_t ws_bytes,
-                             void* stream);
+                             float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace,
+                             size_t ws_bytes, void* stream);
+
+/*
+ * Live set of a prepared workspace: walks every pixel's list without
+ * attributes (alpha and transmittance only, the discrete decisions of
+ * Eq. (3)) and lists, per query, the Gaussians that reach at least one pixel
+ * before it stops; no other Gaussian can change the spectrum or receive a
+ * gradient.  live_list: [n_queries][list_stride] (order unspecified),
+ * live_count: [n_queries] (device).  Also records the per-pixel state that
+ * the forward records.
+ */
+gs_status gs_render_live(int32_t n, int32_t n_queries, const gs_grid* grid, const gs_params* prm,
+                         void* workspace, size_t ws_bytes, uint32_t* live_list, int64_t list_stride,
+                         uint32_t* live_count, void* stream);
 
 /*
  * Training loss on spectra (Eq. (2) spatial mean, Eq. (4) channel loss).
@@ -275,9 +289,11 @@ gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, 
                          const gs_mlp_rows* rows, float* attr, int64_t attr_stride, gs_mlp_state* st,
                          void* stream);
 /* Gradients of sum(d_attr * attr) over the listed rows (same rows as the
- * forward that saved the activations).  All outputs overwritten. */
+ * forward that saved the activations).  All outputs overwritten.  With
+ * clear_d_attr set, the listed rows of d_attr are zeroed after use (so a
+ * buffer that only those rows ever touch stays zero between steps). */
 gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mean, int32_t n,
-                          const gs_mlp_rows* rows, const float* d_attr, int64_t attr_stride,
+                          const gs_mlp_rows* rows, float* d_attr, int64_t attr_stride, int32_t clear_d_attr,
                           gs_mlp_state* st, gs_mlp_grads* grads, void* stream);
 /* One 16x16x32 BF16 matrix-core product C = A B (A [16][32], B [32][16]
  * bf16 row-major, C [16][16] FP32): checks the operand layout. */

@@ -97,14 +97,16 @@ SIGNATURES = {
                                 ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p]),
     "gs_render_backward": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
                                    c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p, c_p, c_p,
-                                   c_p, c_p, c_p, c_p, c_sz, c_p]),
+                                   c_p, c_p, c_p, c_i32, c_p, c_sz, c_p]),
+    "gs_render_live": (c_i32, [c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_sz, c_p,
+                               c_i64, c_p, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
                                  c_p]),
     "gs_mlp_embed": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_i32, c_p, c_p]),
     "gs_mlp_forward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
                                ctypes.POINTER(GsMlpState), c_p]),
     "gs_mlp_backward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
-                                ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
+                                c_i32, ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
     "gs_mfma_probe": (c_i32, [c_p, c_p, c_p, c_p]),
     "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),

@@ -60,6 +60,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_totals = align256(RADIX * 4);
     L->s_pix = align256(HW * 4);
     L->s_g2d = align256((size_t)n * 8 * 4);
+    L->s_live = align256((size_t)n * 4);
 
     size_t off = 0;
     auto take = [&](size_t stride) {
@@ -87,6 +88,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->n_last = take(L->s_pix);
     L->n_contrib = take(L->s_pix);
     L->g2d = take(L->s_g2d);
+    L->live = take(L->s_live);
     L->total = off;
     return GS_OK;
 }
@@ -259,10 +261,27 @@ gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, i
     return GS_OK;
 }
 
+gs_status gs_render_live(int32_t n, int32_t n_queries, const gs_grid* grid, const gs_params* prm, void* workspace,
+                         size_t ws_bytes, uint32_t* live_list, int64_t list_stride, uint32_t* live_count,
+                         void* stream)
+{
+    if (!live_list || !live_count || !grid || !prm) return GS_ERR_INVALID_ARG;
+    Layout L;
+    gs_status st = make_layout(n, n_queries, grid, prm, &L);
+    if (st != GS_OK) return st;
+    if (list_stride < n && n_queries > 1) return GS_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace & 255) || ws_bytes < L.total) return GS_ERR_WORKSPACE;
+    (void)hipGetLastError();
+    launch_live(*prm, L, (char*)workspace, live_list, (size_t)list_stride, live_count, (hipStream_t)stream);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
 gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
                              int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
                              const float* d_spectrum, float* d_mean, float* d_log_scale, float* d_quat,
-                             float* d_opacity_logit, float* d_attr, void* workspace, size_t ws_bytes, void* stream)
+                             float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace, size_t ws_bytes,
+                             void* stream)
 {
     if (!d_spectrum || !d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !d_attr) return GS_ERR_INVALID_ARG;
     Layout L;
@@ -276,7 +295,7 @@ gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const
     const int C = attrs->is_complex ? 2 : 1;
     const size_t na = (size_t)(attrs->query_stride ? n_sets : 1) * scene->n * attrs->n_chan * C;
     launch_fill_u32((uint32_t*)(ws + L.g2d), (size_t)L.n * 8, L.s_g2d / 4, L.nq, 0u, s);
-    launch_fill_u32((uint32_t*)d_attr, na, 0, 1, 0u, s);
+    if (!(flags & GS_BWD_ATTR_GRAD_ZEROED)) launch_fill_u32((uint32_t*)d_attr, na, 0, 1, 0u, s);
     st = launch_blend_bwd(*attrs, *prm, L, n_sets, ws, spectrum, d_spectrum, d_attr, s);
     if (st != GS_OK) return st;
     launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);

@@ -43,9 +43,9 @@ struct Layout {
     int sort_blocks;      // max sort workgroups for n keys
     int pair_blocks;      // max sort workgroups for cap keys
     size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;
-    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d;
+    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live;
     size_t s_flags, s_rec, s_rect, s_status, s_tinfo, s_keys, s_partial, s_pkeys, s_plist, s_ranges,
-        s_counts, s_totals, s_pix, s_g2d;
+        s_counts, s_totals, s_pix, s_g2d, s_live;
     size_t total;
 };
 
@@ -59,6 +59,8 @@ void launch_depth_sort(const Layout& L, char* ws, hipStream_t s);
 void launch_binning(const Layout& L, char* ws, hipStream_t s);
 gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
                        hipStream_t s);
+void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, size_t s_list, uint32_t* count,
+                 hipStream_t s);
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                            const float* out, const float* dout, float* d_attr, hipStream_t s);
 void launch_project_bwd(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,

@@ -28,6 +28,7 @@ struct MlpArgs {
     int64_t row_cap;
     float* attr;
     const float* d_attr;
+    float* clear;  // d_attr again when consumed rows are to be zeroed
     int64_t attr_stride;
     uint16_t *save_h1, *save_h2, *save_do, *save_dz2, *save_dz1;
     float *db3, *db2, *dc, *dE;

@@ -289,6 +289,9 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
                     float sn, cs_;
                     sincosf(op, &sn, &cs_);
                     const float2 gg = *(const float2*)(dat + 2 * f);
+                    if (A.clear)
+                        *(float2*)(A.clear + (size_t)s * A.attr_stride + (size_t)g * (2 * MLP_F) + 2 * f) =
+                            make_float2(0.0f, 0.0f);
                     da = (gg.x * cs_ + gg.y * sn) * amp * (1.0f - amp);
                     dp = amp * (-gg.x * sn + gg.y * cs_);
                 }
@@ -577,8 +580,8 @@ gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, 
 }
 
 gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mean, int32_t n, const gs_mlp_rows* rows,
-                          const float* d_attr, int64_t attr_stride, gs_mlp_state* st, gs_mlp_grads* gr,
-                          void* stream)
+                          float* d_attr, int64_t attr_stride, int32_t clear_d_attr, gs_mlp_state* st,
+                          gs_mlp_grads* gr, void* stream)
 {
     gs_status e = check_rows(net, rows, mean, n);
     if (e != GS_OK) return e;
@@ -604,6 +607,7 @@ gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mea
     A.mean = mean; A.n = n; A.tx = rows->tx; A.r_near = net->r_near;
     A.list = rows->list; A.list_stride = rows->list_stride; A.count = rows->count; A.count_stride = rows->count_stride;
     A.row_cap = rows->row_cap; A.d_attr = d_attr; A.attr_stride = attr_stride;
+    A.clear = clear_d_attr ? d_attr : nullptr;
     A.save_h1 = st->save_h1; A.save_h2 = st->save_h2; A.save_do = st->save_do; A.save_dz2 = st->save_dz2;
     A.save_dz1 = st->save_dz1; A.db3 = gr->db3; A.db2 = gr->db2; A.dc = st->dc; A.dE = gr->dE;
     const int gx = rows->grid_x > 0 ? rows->grid_x : 256;

@@ -124,7 +124,7 @@ def forward(net: AttributeNet, Z1: torch.Tensor, mean: torch.Tensor, rows: Rows,
 
 
 def backward(net: AttributeNet, E_bf: torch.Tensor, mean: torch.Tensor, rows: Rows, d_attr: torch.Tensor,
-             state: State, grads: Optional[dict] = None) -> dict:
+             state: State, grads: Optional[dict] = None, clear_d_attr: bool = False) -> dict:
     n = mean.shape[1]
     dev = mean.device
     if grads is None:
@@ -136,7 +136,8 @@ def backward(net: AttributeNet, E_bf: torch.Tensor, mean: torch.Tensor, rows: Ro
                    _p(grads["b3"]), _p(grads["E"]))
     m, r, s = net.c(), rows.c(), state.c()
     check(lib().gs_mlp_backward(ctypes.byref(m), _p(E_bf), _p(mean), n, ctypes.byref(r), _p(d_attr), n * 2 * F,
-                                ctypes.byref(s), ctypes.byref(g), _stream(dev)), "gs_mlp_backward")
+                                int(clear_d_attr), ctypes.byref(s), ctypes.byref(g), _stream(dev)),
+          "gs_mlp_backward")
     return grads
 
 

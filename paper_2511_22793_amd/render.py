@@ -192,7 +192,7 @@ def blend(workspace: Workspace, attr: torch.Tensor, n_sets: Optional[int] = None
     _check_f32("attr", attr)
     n, B = workspace.n, workspace.nq
     per_set = attr.dim() == (4 if is_complex else 3)
-    S = attr.shape[0] if per_set else B
+    S = attr.shape[0] if per_set else (n_sets if n_sets is not None else B)
     if n_sets is not None and n_sets != S:
         raise ValueError("n_sets %d does not match attr" % n_sets)
     a = _attrs_c(attr, n, S, is_complex)
@@ -211,7 +211,7 @@ def blend(workspace: Workspace, attr: torch.Tensor, n_sets: Optional[int] = None
 
 def backward(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Tensor, spectrum: torch.Tensor,
              d_spectrum: torch.Tensor, tx: Optional[torch.Tensor] = None, is_complex: bool = False,
-             n_sets: Optional[int] = None) -> dict:
+             n_sets: Optional[int] = None, d_attr: Optional[torch.Tensor] = None, out: Optional[dict] = None) -> dict:
     """Gradients of a forward (or prepare + blend) call that used `workspace`.
     Returns d_mean, d_log_scale, d_quat, d_opacity_logit, d_attr."""
     sc = _scene_c(scene)
@@ -223,18 +223,38 @@ def backward(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Te
     _check_f32("spectrum", spectrum)
     _check_f32("d_spectrum", d_spectrum, tuple(spectrum.shape))
     dev = rx.device
-    g = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
-         "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev),
-         "d_attr": torch.empty_like(attr)}
+    g = out if out is not None else {
+        "d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+        "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+    # a caller-provided d_attr must be all zero: it is accumulated into, not cleared
+    flags = 1 if d_attr is not None else 0
+    g["d_attr"] = d_attr if d_attr is not None else torch.empty_like(attr)
     q = GsQueries(B, _ptr(rx), _ptr(tx))
     gr, p = workspace.grid.c(), workspace.params.c()
     stream = torch.cuda.current_stream(dev).cuda_stream
     check(lib().gs_render_backward(ctypes.byref(sc), ctypes.byref(a), ctypes.byref(q), S, ctypes.byref(gr),
                                    ctypes.byref(p), _ptr(spectrum), _ptr(d_spectrum), _ptr(g["d_mean"]),
                                    _ptr(g["d_log_scale"]), _ptr(g["d_quat"]), _ptr(g["d_opacity_logit"]),
-                                   _ptr(g["d_attr"]), ctypes.c_void_p(workspace.ptr), workspace.nbytes,
+                                   _ptr(g["d_attr"]), flags, ctypes.c_void_p(workspace.ptr), workspace.nbytes,
                                    ctypes.c_void_p(stream)), "gs_render_backward")
     return g
+
+
+def live(workspace: Workspace, lst: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None):
+    """Gaussians reaching some pixel, per prepared query: (list [B, n] int32
+    (valid prefix of length count[b]), count [B] int32 on the device)."""
+    n, B = workspace.n, workspace.nq
+    dev = workspace.buf.device
+    if lst is None:
+        lst = torch.empty(B, n, dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.empty(B, dtype=torch.int32, device=dev)
+    g, p = workspace.grid.c(), workspace.params.c()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_render_live(n, B, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(workspace.ptr),
+                               workspace.nbytes, _ptr(lst), n, _ptr(count), ctypes.c_void_p(stream)),
+          "gs_render_live")
+    return lst, count
 
 
 def loss_spectrum(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, lambda_ch: float = 1.0):

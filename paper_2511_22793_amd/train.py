@@ -1,0 +1,167 @@
+"""Training step of the learned-attribute renderer (Algorithm 1's loop with a
+shared attribute network, a fixed receiver and a batch of transmitters).
+
+One step, all on the device with no host synchronisation:
+  prepare (projection, depth sort, tile binning) for the receiver
+  live pass: Gaussians that reach some pixel
+  network forward for (transmitter, live Gaussian) rows -> attributes
+  blend of the batch's attribute sets over the shared geometry -> spectra
+  loss (spectrum L2 + Eq. (4) on the Eq. (2) mean) -> dL/dspectrum
+  blend + projection backward -> Gaussian-parameter and attribute gradients
+  network backward -> weight, bias and embedding gradients
+  fused Adam over every parameter group (Table 2 learning rates; the
+  position rate decays exponentially)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import mlp as gm
+from .render import Grid, Params, Workspace, backward, blend, live, loss_spectrum, prepare
+
+F = gm.F
+
+
+@dataclass
+class Rates:
+    position: float = 1.6e-4
+    position_final: float = 1.6e-7
+    opacity: float = 0.0055
+    scaling: float = 0.005
+    rotation: float = 0.001
+    mlp: float = 0.005
+    embedding: float = 0.005
+
+
+class LearnedScene:
+    """Gaussian geometry, per-Gaussian embeddings and the attribute network,
+    with Adam state, for batches of `batch` transmitters seen from `rx`."""
+
+    def __init__(self, scene: dict, embeddings: np.ndarray, weights: dict, rx, batch: int, box_lo, box_hi,
+                 grid: Grid = Grid(), params: Params = Params(), rates: Rates = Rates(), total_steps: int = 1000,
+                 train_geometry: bool = True, lambda_ch: float = 1.0, device="cuda"):
+        dev = torch.device(device)
+        self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
+        self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
+        self.n = n = scene["opacity_logit"].shape[0]
+        self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
+        self.E = torch.tensor(np.asarray(embeddings, np.float32), device=dev)
+        self.E_bf = torch.from_numpy(gm.bf16_bits(embeddings).view(np.int16)).to(dev)
+        self.net = gm.AttributeNet(weights, box_lo, box_hi, params.r_near, device=dev)
+        self.rx = torch.tensor(np.asarray(rx, np.float32).reshape(1, 3), device=dev)
+        self.ws = Workspace(n, 1, grid, params, device=dev)
+        # attribute rows never written stay zero (the blend multiplies them by 0)
+        self.attr = torch.zeros(batch, n, F, 2, device=dev)
+        self.d_attr = torch.zeros(batch, n, F, 2, device=dev)
+        self.spec = torch.empty(batch, F, grid.H, grid.W, 2, device=dev)
+        self.live_list = torch.empty(1, n, dtype=torch.int32, device=dev)
+        self.live_count = torch.empty(1, dtype=torch.int32, device=dev)
+        self.state = gm.State(batch, n, training=True, device=dev)
+        self.Z1 = torch.empty(n, gm.HID, device=dev)
+        self.ggrads = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+                       "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+        self.mgrads = None
+        self.moments = {}
+        self.step_count = 0
+
+    def _rows(self, tx):
+        return gm.Rows(tx, self.live_list[0], self.live_count, row_cap=self.n)
+
+    def render(self, tx: torch.Tensor, keep: bool = False) -> torch.Tensor:
+        """Spectra [B, F, H, W, 2] for transmitters tx [B, 3] (B = batch)."""
+        sc = self.g
+        prepare(sc, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
+        live(self.ws, self.live_list, self.live_count)
+        gm.embed(self.net, self.E_bf, self.Z1)
+        gm.forward(self.net, self.Z1, sc["mean"], self._rows(tx), self.attr, self.state)
+        blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
+        return self.spec
+
+    def _moment(self, key, like):
+        if key not in self.moments:
+            self.moments[key] = (torch.zeros_like(like), torch.zeros_like(like))
+        return self.moments[key]
+
+    def position_lr(self):
+        t = min(self.step_count / max(self.total_steps - 1, 1), 1.0)
+        r = self.rates
+        return math.exp((1 - t) * math.log(r.position) + t * math.log(r.position_final))
+
+    def train_step(self, tx: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+        """One step on transmitters tx [B,3] with target spectra [B,F,H,W,2];
+        returns the per-set losses (device tensor, before the update)."""
+        sc = self.g
+        spec = self.render(tx, keep=True)
+        loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
+        backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
+                 d_attr=self.d_attr, out=self.ggrads)
+        self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
+                                  self.mgrads, clear_d_attr=True)
+        self.step_count += 1
+        r = self.rates
+        segs = []
+        for k, lr, sh in (("W1", r.mlp, self.net.bf["W1"]), ("b1", r.mlp, None), ("W2", r.mlp, self.net.bf["W2"]),
+                          ("b2", r.mlp, None), ("W3", r.mlp, self.net.bf["W3"]), ("b3", r.mlp, None)):
+            m, v = self._moment(k, self.net.w[k])
+            segs.append((self.net.w[k], self.mgrads[k], m, v, sh, lr))
+        m, v = self._moment("E", self.E)
+        segs.append((self.E, self.mgrads["E"], m, v, self.E_bf, r.embedding))
+        if self.train_geometry:
+            for k, lr in (("mean", self.position_lr()), ("log_scale", r.scaling), ("quat", r.rotation),
+                          ("opacity_logit", r.opacity)):
+                m, v = self._moment(k, sc[k])
+                segs.append((sc[k], self.ggrads["d_" + k], m, v, None, lr))
+        gm.adam_step(segs, self.step_count)
+        return loss
+
+
+class FixedAttributeScene:
+    """The comparison without the network: one learned complex attribute
+    vector per Gaussian, shared by every transmitter (geometry fixed)."""
+
+    def __init__(self, scene: dict, rx, batch: int, grid: Grid = Grid(), params: Params = Params(), lr: float = 0.005,
+                 lambda_ch: float = 1.0, device="cuda"):
+        dev = torch.device(device)
+        self.dev, self.grid, self.params, self.lr, self.B, self.lambda_ch = dev, grid, params, lr, batch, lambda_ch
+        self.n = n = scene["opacity_logit"].shape[0]
+        self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
+        self.rx = torch.tensor(np.asarray(rx, np.float32).reshape(1, 3), device=dev)
+        self.attr = torch.zeros(n, F, 2, device=dev)
+        self.m = torch.zeros_like(self.attr)
+        self.v = torch.zeros_like(self.attr)
+        self.ws = Workspace(n, 1, grid, params, device=dev)
+        self.spec = torch.empty(batch, F, grid.H, grid.W, 2, device=dev)
+        self.step_count = 0
+
+    def render(self, tx=None) -> torch.Tensor:
+        prepare(self.g, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
+        # one attribute set (stride 0) blended B times
+        return blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
+
+    def train_step(self, tx, target) -> torch.Tensor:
+        spec = self.render()
+        loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
+        # shared attributes: the backward sums the attribute gradient over sets
+        g = backward(self.ws, self.g, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B)
+        self.step_count += 1
+        gm.adam_step([(self.attr, g["d_attr"], self.m, self.v, None, self.lr)], self.step_count)
+        return loss
+
+
+def ground_truth_attributes(scene: dict, rho: np.ndarray, tx: np.ndarray, r_near: float = 0.2,
+                            f_c: float = 2.4e9, df: float = 312.5e3, nf: int = F) -> np.ndarray:
+    """Synthetic transmitter-dependent emissions: Gaussian reflectivity rho_i
+    times the baseband delay phase and free-space loss of the transmitter leg,
+    c_i[k] = rho_i exp(-j 2 pi (f_k - f_c) d_i / c0) / max(d_i, r_near),
+    f_k = f_c + (k - (nf-1)/2) df.  Returns [S, n, nf, 2] float32."""
+    c0 = 299_792_458.0
+    m = np.asarray(scene["mean"], np.float64).T
+    d = np.linalg.norm(m[None] - np.asarray(tx, np.float64)[:, None], axis=-1)      # [S, n]
+    fk = (np.arange(nf) - (nf - 1) / 2.0) * df
+    ph = -2.0 * np.pi * fk[None, None, :] * d[..., None] / c0
+    a = np.asarray(rho, np.float64)[None, :, None] / np.maximum(d, r_near)[..., None]
+    return np.stack([a * np.cos(ph), a * np.sin(ph)], -1).astype(np.float32)
