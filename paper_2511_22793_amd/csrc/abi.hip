@@ -61,6 +61,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_pix = align256(HW * 4);
     L->s_g2d = align256((size_t)n * 8 * 4);
     L->s_live = align256((size_t)n * 4);
+    L->s_gacc = align256((size_t)cap * 8 * 4);
 
     size_t off = 0;
     auto take = [&](size_t stride) {
@@ -89,6 +90,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->n_contrib = take(L->s_pix);
     L->g2d = take(L->s_g2d);
     L->live = take(L->s_live);
+    L->gacc = take(L->s_gacc);
     L->total = off;
     return GS_OK;
 }
@@ -295,6 +297,9 @@ gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const
     const int C = attrs->is_complex ? 2 : 1;
     const size_t na = (size_t)(attrs->query_stride ? n_sets : 1) * scene->n * attrs->n_chan * C;
     launch_fill_u32((uint32_t*)(ws + L.g2d), (size_t)L.n * 8, L.s_g2d / 4, L.nq, 0u, s);
+    // the per-pair accumulator over the used pairs (the fold clears it again)
+    launch_fill_dev((uint32_t*)(ws + L.gacc), (size_t)L.cap * 8, L.s_gacc / 4, L.nq,
+                    (const uint32_t*)(ws + L.flags) + FL_PUSED, L.s_flags / 4, 8u, s);
     if (!(flags & GS_BWD_ATTR_GRAD_ZEROED)) launch_fill_u32((uint32_t*)d_attr, na, 0, 1, 0u, s);
     st = launch_blend_bwd(*attrs, *prm, L, n_sets, ws, spectrum, d_spectrum, d_attr, s);
     if (st != GS_OK) return st;

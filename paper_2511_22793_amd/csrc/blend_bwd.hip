@@ -14,8 +14,13 @@
 // form q the gradient reaches the pixel-space centre and the conic.
 //
 // Per list entry the per-pixel terms are summed over the wave by a
-// butterfly reduce-scatter (every lane ends with one summed value) and
-// added to the per-Gaussian accumulators with one vector atomic.
+// butterfly reduce-scatter (every lane ends with one summed value), the
+// four waves are combined in LDS, and each batch of entries is flushed once
+// per workgroup: attribute gradients by atomics, geometric terms into a
+// per-pair accumulator (only the workgroups of one tile share an address)
+// that a second pass folds into the per-Gaussian sums.  The nearest
+// Gaussians cover every tile, so per-wave atomics would serialise on a few
+// addresses.
 #include "common.h"
 
 namespace gs {
@@ -24,28 +29,33 @@ constexpr double LOG2E_B = 1.4426950408889634;
 
 // Butterfly reduce-scatter of V values over the 64 lanes of a wave.  On
 // return x[0] of lane l holds the wave total of value (l >> (6 - log2 V)).
+// Each stage exchanges half of the remaining values with the lane at xor
+// distance M; all sizes are compile-time so the arrays stay in registers.
+template <int V, int M>
+__device__ __forceinline__ void reduce_scatter_step(float* x, int lane)
+{
+    if constexpr (M >= 1) {
+        if constexpr (V > 1) {
+            constexpr int half = V / 2;
+            const bool up = (lane & M) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const float send = up ? x[i] : x[i + half];
+                const float keep = up ? x[i + half] : x[i];
+                x[i] = keep + __shfl_xor(send, M, 64);
+            }
+            reduce_scatter_step<half, M / 2>(x, lane);
+        } else {
+            x[0] += __shfl_xor(x[0], M, 64);
+            reduce_scatter_step<1, M / 2>(x, lane);
+        }
+    }
+}
+
 template <int V>
 __device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
 {
-    int n = V;
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        if (n > 1) {
-            const int half = n >> 1;
-            const bool up = (lane & m) != 0;
-#pragma unroll
-            for (int i = 0; i < V / 2; ++i) {
-                if (i < half) {
-                    const float send = up ? x[i] : x[i + half];
-                    const float keep = up ? x[i + half] : x[i];
-                    x[i] = keep + __shfl_xor(send, m, 64);
-                }
-            }
-            n = half;
-        } else {
-            x[0] += __shfl_xor(x[0], m, 64);
-        }
-    }
+    reduce_scatter_step<V, 32>(x, lane);
 }
 
 template <int CG>
@@ -54,7 +64,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     const uint2* __restrict__ ranges, size_t s_ranges, const float* __restrict__ attr, int64_t a_stride,
     int Fc, int C, int H, int W, int tw, int th, int TX, float amin, float amax,
     const float* __restrict__ out, const float* __restrict__ dout, const uint32_t* __restrict__ n_last, size_t s_pix,
-    float* __restrict__ g2d, size_t s_g2d, float* __restrict__ d_attr, int64_t da_stride, int shared_geo)
+    float* __restrict__ gacc, size_t s_gacc, float* __restrict__ d_attr, int64_t da_stride, int shared_geo)
 {
     const int tile = blockIdx.x, cg = blockIdx.y, set = blockIdx.z;
     const int q = shared_geo ? 0 : set;
@@ -68,7 +78,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * W;
     rec += q * s_rec;
     plist += q * s_plist;
-    g2d += q * s_g2d;
+    gacc += q * s_gacc;
     const float* A = attr + set * a_stride + cg * CG;
     float* dA = d_attr + set * da_stride + cg * CG;
     const size_t HW = (size_t)H * W, pix = inside ? (size_t)row * W + col : 0;
@@ -90,6 +100,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
     __shared__ float s_sig[256], s_att[256];
     __shared__ uint32_t s_g[256];
+    // per-entry sums over the workgroup's pixels, flushed once per batch
+    __shared__ float s_ad[256][CG];
+    __shared__ float s_geo[256][8];
 
     float T = 1.0f, P = 0.0f;
     // the walk of this workgroup ends at the largest stop position of its pixels
@@ -99,6 +112,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     if (stop) atomicMax(&s_maxstop, stop);
     __syncthreads();
     const uint32_t end = rg.x + s_maxstop;
+    constexpr int shA = CG >= 64 ? 0 : (CG == 32 ? 1 : (CG == 16 ? 2 : (CG == 8 ? 3 : (CG == 4 ? 4 : (CG == 2 ? 5 : 6)))));
 
     for (uint32_t b0 = rg.x; b0 < end; b0 += nthr) {
         __syncthreads();
@@ -115,6 +129,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
             s_att[threadIdx.x] = r.att;
             s_g[threadIdx.x] = g;
         }
+        for (int e = threadIdx.x; e < 256 * CG; e += nthr) s_ad[e / CG][e % CG] = 0.0f;
+        for (int e = threadIdx.x; e < 256 * 8; e += nthr) s_geo[e / 8][e % 8] = 0.0f;
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, end - b0);
         for (int j = 0; j < m; ++j) {
@@ -154,8 +170,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
                 geo[2] = dq * (float)(dx * dx);                     // d/dA
                 geo[3] = dq * (float)(2.0 * dx * dy);               // d/dB
                 geo[4] = dq * (float)(dy * dy);                     // d/dC
-                geo[5] = dsg * G;                             // d/dsigma
-                geo[6] = Ta * gv;                             // d/da
+                geo[5] = dsg * G;                                   // d/dsigma
+                geo[6] = Ta * gv;                                   // d/da
                 geo[7] = 0.0f;
                 T = T * (1.0f - alpha);
                 P = Pn;
@@ -165,9 +181,40 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
             }
             wave_reduce_scatter<CG>(red, lane);
             wave_reduce_scatter<8>(geo, lane);
-            constexpr int shA = CG >= 64 ? 0 : (CG == 32 ? 1 : (CG == 16 ? 2 : (CG == 8 ? 3 : (CG == 4 ? 4 : (CG == 2 ? 5 : 6)))));
-            if ((lane & ((1 << shA) - 1)) == 0) unsafeAtomicAdd(dA + (size_t)g * Fc + (lane >> shA), red[0]);
-            if ((lane & 7) == 0) unsafeAtomicAdd(g2d + (size_t)g * 8 + (lane >> 3), geo[0]);
+            if ((lane & ((1 << shA) - 1)) == 0) atomicAdd(&s_ad[j][lane >> shA], red[0]);
+            if ((lane & 7) == 0) atomicAdd(&s_geo[j][lane >> 3], geo[0]);
+        }
+        __syncthreads();
+        // flush: attribute gradients (one atomic per entry and channel per
+        // workgroup), geometric terms into the per-pair accumulator
+        for (int e = threadIdx.x; e < m * CG; e += nthr) {
+            const int j = e / CG, k = e % CG;
+            const float val = s_ad[j][k];
+            if (val != 0.0f) unsafeAtomicAdd(dA + (size_t)s_g[j] * Fc + k, val);
+        }
+        for (int e = threadIdx.x; e < m * 8; e += nthr) {
+            const int j = e / 8, k = e % 8;
+            const float val = s_geo[j][k];
+            if (val != 0.0f) unsafeAtomicAdd(gacc + (size_t)(b0 + j) * 8 + k, val);
+        }
+    }
+}
+
+// Folds the per-pair geometric sums into the per-Gaussian accumulators and
+// clears the pair accumulator for the next call.
+__global__ __launch_bounds__(256) void k_geo_fold(float* __restrict__ gacc, size_t s_gacc,
+                                                  const uint32_t* __restrict__ plist, size_t s_plist,
+                                                  const uint32_t* __restrict__ flags, size_t s_flags,
+                                                  float* __restrict__ g2d, size_t s_g2d)
+{
+    const int q = blockIdx.y;
+    const uint32_t P = flags[q * s_flags + FL_PUSED];
+    gacc += q * s_gacc;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < P * 8u; e += gridDim.x * blockDim.x) {
+        const float v = gacc[e];
+        if (v != 0.0f) {
+            gacc[e] = 0.0f;
+            unsafeAtomicAdd(g2d + q * s_g2d + (size_t)plist[q * s_plist + e / 8] * 8 + (e & 7), v);
         }
     }
 }
@@ -180,7 +227,7 @@ static void bwd_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, cons
                        (const uint32_t*)(ws + L.plist), L.s_plist / 4, (const uint2*)(ws + L.ranges),
                        L.s_ranges / sizeof(uint2), a.data, a.query_stride, a.n_chan * C, C, L.H, L.W, L.tw, L.th,
                        L.TX, p.alpha_min, p.alpha_max, out, dout, (const uint32_t*)(ws + L.n_last), L.s_pix / 4,
-                       (float*)(ws + L.g2d), L.s_g2d / 4, d_attr, da_stride, shared);
+                       (float*)(ws + L.gacc), L.s_gacc / 4, d_attr, da_stride, shared);
 }
 
 int choose_chan_group(int Fc, int requested);
@@ -204,6 +251,10 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
         case 16: bwd_cg<16>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
         default: bwd_cg<32>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
     }
+    const int64_t fb = (L.cap * 8 + 255) / 256;
+    hipLaunchKernelGGL(k_geo_fold, dim3((unsigned)(fb < 2048 ? fb : 2048), L.nq), dim3(256), 0, s,
+                       (float*)(ws + L.gacc), L.s_gacc / 4, (const uint32_t*)(ws + L.plist), L.s_plist / 4,
+                       (const uint32_t*)(ws + L.flags), L.s_flags / 4, (float*)(ws + L.g2d), L.s_g2d / 4);
     return GS_OK;
 }
 

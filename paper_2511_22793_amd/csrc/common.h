@@ -43,9 +43,9 @@ struct Layout {
     int sort_blocks;      // max sort workgroups for n keys
     int pair_blocks;      // max sort workgroups for cap keys
     size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;
-    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live;
+    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live, gacc;
     size_t s_flags, s_rec, s_rect, s_status, s_tinfo, s_keys, s_partial, s_pkeys, s_plist, s_ranges,
-        s_counts, s_totals, s_pix, s_g2d, s_live;
+        s_counts, s_totals, s_pix, s_g2d, s_live, s_gacc;
     size_t total;
 };
 
@@ -53,6 +53,9 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
 
 // kernel launchers (stream-ordered, no synchronisation)
 void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_t v, hipStream_t s);
+// fills [0, per_query * n_dev[q]) of each query, n_dev read on the device
+void launch_fill_dev(uint32_t* p, size_t max_count, size_t q_stride, int nq, const uint32_t* n_dev, size_t n_stride,
+                     uint32_t per_query, hipStream_t s);
 void launch_project(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,
                     const Layout& L, char* ws, hipStream_t s);
 void launch_depth_sort(const Layout& L, char* ws, hipStream_t s);

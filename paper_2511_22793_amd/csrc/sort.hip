@@ -29,6 +29,21 @@ void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_
     hipLaunchKernelGGL(k_fill_u32, grid, dim3(256), 0, s, p, count, q_stride, v);
 }
 
+__global__ void k_fill_dev(uint32_t* p, size_t q_stride, const uint32_t* n_dev, size_t n_stride, uint32_t mult)
+{
+    const size_t n = (size_t)n_dev[blockIdx.y * n_stride] * mult;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[blockIdx.y * q_stride + i] = 0u;
+}
+
+void launch_fill_dev(uint32_t* p, size_t max_count, size_t q_stride, int nq, const uint32_t* n_dev, size_t n_stride,
+                     uint32_t per_query, hipStream_t s)
+{
+    const size_t blocks = (max_count + 255) / 256;
+    dim3 grid((unsigned)(blocks < 2048 ? (blocks ? blocks : 1) : 2048), nq);
+    hipLaunchKernelGGL(k_fill_dev, grid, dim3(256), 0, s, p, q_stride, n_dev, n_stride, per_query);
+}
+
 __device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int q)
 {
     return n_dev ? n_dev[q * n_stride] : n_fixed;

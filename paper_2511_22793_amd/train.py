@@ -37,6 +37,18 @@ class Rates:
     embedding: float = 0.005
 
 
+def init_weights(seed: int = 0) -> dict:
+    """He-normal initial weights in [out, in] layout (W1 [64, 96] with zero
+    columns beyond the 83 inputs), zero biases."""
+    rng = np.random.default_rng(seed)
+    fan1 = gm.EMB + gm.ENC
+    W1 = np.zeros((gm.HID, gm.IN_PAD))
+    W1[:, :fan1] = rng.normal(0, np.sqrt(2.0 / fan1), size=(gm.HID, fan1))
+    return {"W1": W1, "b1": np.zeros(gm.HID),
+            "W2": rng.normal(0, np.sqrt(2.0 / gm.HID), size=(gm.HID, gm.HID)), "b2": np.zeros(gm.HID),
+            "W3": rng.normal(0, np.sqrt(2.0 / gm.HID), size=(2 * F, gm.HID)), "b3": np.zeros(2 * F)}
+
+
 class LearnedScene:
     """Gaussian geometry, per-Gaussian embeddings and the attribute network,
     with Adam state, for batches of `batch` transmitters seen from `rx`."""
@@ -91,16 +103,30 @@ class LearnedScene:
         r = self.rates
         return math.exp((1 - t) * math.log(r.position) + t * math.log(r.position_final))
 
-    def train_step(self, tx: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    def train_step(self, tx: torch.Tensor, target: torch.Tensor, marks=None) -> torch.Tensor:
         """One step on transmitters tx [B,3] with target spectra [B,F,H,W,2];
-        returns the per-set losses (device tensor, before the update)."""
+        returns the per-set losses (device tensor, before the update).
+        marks: optional callable(name) invoked between stages (timing)."""
+        mark = marks or (lambda name: None)
         sc = self.g
-        spec = self.render(tx, keep=True)
+        mark("start")
+        prepare(sc, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
+        mark("prepare")
+        live(self.ws, self.live_list, self.live_count)
+        mark("live")
+        gm.embed(self.net, self.E_bf, self.Z1)
+        gm.forward(self.net, self.Z1, sc["mean"], self._rows(tx), self.attr, self.state)
+        mark("mlp_fwd")
+        spec = blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
+        mark("blend")
         loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
+        mark("loss")
         backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
                  d_attr=self.d_attr, out=self.ggrads)
+        mark("render_bwd")
         self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
                                   self.mgrads, clear_d_attr=True)
+        mark("mlp_bwd")
         self.step_count += 1
         r = self.rates
         segs = []
@@ -116,6 +142,7 @@ class LearnedScene:
                 m, v = self._moment(k, sc[k])
                 segs.append((sc[k], self.ggrads["d_" + k], m, v, None, lr))
         gm.adam_step(segs, self.step_count)
+        mark("adam")
         return loss
 
 
