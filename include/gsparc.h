@@ -105,8 +105,14 @@ typedef struct {
     float margin;      /* support-rectangle margin, px (1e-3) */
     int64_t pair_capacity; /* (Gaussian, tile) pairs per query; 0 = n * min(tiles, 64) + 4096 */
     int32_t chan_group;    /* channel floats per blend workgroup, 0 = automatic */
-    int32_t reserved;
+    int32_t options;       /* GS_OPT_* bits (0) */
 } gs_params;
+
+/* options: the workspace holds only what the forward needs (no per-pair
+ * gradient accumulators, no live-set buffers); gs_render_backward() and
+ * gs_render_live() then reject it.  For serving, where the pair
+ * accumulators would otherwise be the largest part of the workspace. */
+#define GS_OPT_FORWARD_ONLY 1
 
 /* Per-query device-side results, read with gs_read_flags(). */
 typedef struct {
@@ -314,6 +320,64 @@ typedef struct {
 } gs_adam_segment;
 gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, int32_t step, float beta1,
                        float beta2, float eps, void* stream);
+
+/*
+ * Batched serving: many queries over several scenes of uneven size, grid,
+ * tile shape and channel count in one persistent blend launch.
+ *
+ * A job is one scene with a group of queries (receiver positions; n_sets =
+ * queries.count, set q seen from query q) and its own grid, params, output
+ * and workspace, exactly as for gs_render_forward() (GS_OPT_FORWARD_ONLY is
+ * allowed and saves memory).  gs_batch_run() enqueues, for job 0, 1, ...:
+ * the prepare steps of gs_render_prepare(), then one persistent blend kernel
+ * whose workgroups pull (job, query, channel group, tile) items from a device
+ * counter in job order, so the job order is the service order.  Spectra and
+ * workspace state are those that gs_render_forward() leaves for the same
+ * job, bit for bit.
+ *
+ *  gs_batch_plan_bytes(n_jobs): size of the plan buffer (device, 256-byte
+ *    aligned, caller-owned).
+ *  gs_batch_plan: validates the jobs (host array), writes the job table into
+ *    the plan buffer and fills *info (host).  Synchronises `stream` (the
+ *    table is copied from host memory).  Call again whenever any job field
+ *    changes; the plan holds device pointers of the jobs' buffers.
+ *  gs_batch_run: enqueues the batch for a plan made from the same jobs.
+ *    Enqueues kernels only (no copies, no memset, no allocation, no host
+ *    synchronisation), so it can be captured into a HIP graph and replayed.
+ *    workgroups: persistent workgroups (> 0; info->workgroups fills the
+ *    device at the kernel's occupancy).  timestamps: NULL, or a device array
+ *    of info->n_queries + 2 uint64 values written as device wall-clock ticks
+ *    (gs_wall_clock_khz()): [0] batch start (before the first prepare),
+ *    [1 + k] completion of the k-th query's spectrum (queries numbered job
+ *    by job), [n_queries + 1] batch end.
+ *  Concurrent runs of one plan race on its work counter.
+ */
+typedef struct {
+    gs_scene scene;
+    gs_attrs attrs;
+    gs_queries queries;
+    gs_grid grid;
+    gs_params params;
+    float* spectrum;        /* [queries.count][F][H][W][c] */
+    void* workspace;        /* >= gs_workspace_layout(...).total bytes */
+    size_t workspace_bytes;
+} gs_batch_job;
+
+typedef struct {
+    int64_t items;       /* blend work items of the batch */
+    int32_t n_queries;   /* queries over all jobs */
+    int32_t block;       /* threads per workgroup: the largest tile's pixels */
+    int32_t workgroups;  /* workgroups that fill the device at full occupancy */
+    int32_t reserved;
+} gs_batch_info;
+
+size_t gs_batch_plan_bytes(int32_t n_jobs);
+gs_status gs_batch_plan(const gs_batch_job* jobs, int32_t n_jobs, void* plan, size_t plan_bytes,
+                        gs_batch_info* info, void* stream);
+gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, size_t plan_bytes,
+                       int32_t workgroups, uint64_t* timestamps, void* stream);
+/* Device wall-clock rate (kHz) of the current device, for the timestamps. */
+gs_status gs_wall_clock_khz(int32_t* khz);
 
 /*
  * Copies the per-query flags of the last forward call into `out` (host,

@@ -40,7 +40,9 @@ class GsGrid(ctypes.Structure):
 class GsParams(ctypes.Structure):
     _fields_ = [("alpha_min", c_f32), ("alpha_max", c_f32), ("T_min", c_f32), ("dilation", c_f32),
                 ("r_near", c_f32), ("atten_power", c_f32), ("atten_ref", c_i32), ("margin", c_f32),
-                ("pair_capacity", c_i64), ("chan_group", c_i32), ("reserved", c_i32)]
+                ("pair_capacity", c_i64), ("chan_group", c_i32), ("options", c_i32)]
+
+GS_OPT_FORWARD_ONLY = 1
 
 
 class GsFlags(ctypes.Structure):
@@ -69,6 +71,16 @@ class GsMlpGrads(ctypes.Structure):
 
 class GsAdamSegment(ctypes.Structure):
     _fields_ = [("p", c_p), ("g", c_p), ("m", c_p), ("v", c_p), ("shadow", c_p), ("count", c_i64), ("lr", c_f32)]
+
+
+class GsBatchJob(ctypes.Structure):
+    _fields_ = [("scene", GsScene), ("attrs", GsAttrs), ("queries", GsQueries), ("grid", GsGrid),
+                ("params", GsParams), ("spectrum", c_p), ("workspace", c_p), ("workspace_bytes", c_sz)]
+
+
+class GsBatchInfo(ctypes.Structure):
+    _fields_ = [("items", c_i64), ("n_queries", c_i32), ("block", c_i32), ("workgroups", c_i32),
+                ("reserved", c_i32)]
 
 
 _LAYOUT_FIELDS = ["total", "flags", "rec", "rect", "status", "tinfo", "order", "keys", "pair_keys", "pair_list",
@@ -109,6 +121,10 @@ SIGNATURES = {
                                 c_i32, ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
     "gs_mfma_probe": (c_i32, [c_p, c_p, c_p, c_p]),
     "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p]),
+    "gs_batch_plan_bytes": (c_sz, [c_i32]),
+    "gs_batch_plan": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, ctypes.POINTER(GsBatchInfo), c_p]),
+    "gs_batch_run": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, c_i32, c_p, c_p]),
+    "gs_wall_clock_khz": (c_i32, [ctypes.POINTER(c_i32)]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
                               ctypes.POINTER(GsFlags), c_p]),
 }

@@ -6,8 +6,6 @@
 
 namespace gs {
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 static int bits_for(uint64_t v)  // bits needed to hold values 0..v
 {
     int b = 1;
@@ -18,6 +16,7 @@ static int bits_for(uint64_t v)  // bits needed to hold values 0..v
 gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* p, Layout* L)
 {
     if (n < 1 || nq < 1 || !g || !p) return GS_ERR_INVALID_ARG;
+    if (p->options & ~GS_OPT_FORWARD_ONLY) return GS_ERR_INVALID_ARG;
     if (g->H < 1 || g->W < 2 || g->tile_h < 1 || g->tile_w < 1) return GS_ERR_INVALID_ARG;
     const int nthr = g->tile_h * g->tile_w;
     if (nthr != 64 && nthr != 128 && nthr != 256) return GS_ERR_INVALID_ARG;
@@ -59,9 +58,10 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_counts = align256((size_t)maxb * RADIX * 4);
     L->s_totals = align256(RADIX * 4);
     L->s_pix = align256(HW * 4);
-    L->s_g2d = align256((size_t)n * 8 * 4);
-    L->s_live = align256((size_t)n * 4);
-    L->s_gacc = align256((size_t)cap * 8 * 4);
+    const bool fwd_only = (p->options & GS_OPT_FORWARD_ONLY) != 0;
+    L->s_g2d = fwd_only ? 0 : align256((size_t)n * 8 * 4);
+    L->s_live = fwd_only ? 0 : align256((size_t)n * 4);
+    L->s_gacc = fwd_only ? 0 : align256((size_t)cap * 8 * 4);
 
     size_t off = 0;
     auto take = [&](size_t stride) {
@@ -93,6 +93,35 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->gacc = take(L->s_gacc);
     L->total = off;
     return GS_OK;
+}
+
+gs_status check_forward(const gs_scene* sc, const gs_attrs* a, const gs_queries* qs, const gs_grid* g,
+                               const gs_params* p, const float* spectrum, const void* ws, size_t ws_bytes,
+                               Layout* L)
+{
+    if (!sc || !a || !qs || !g || !p || !spectrum) return GS_ERR_INVALID_ARG;
+    if (!sc->mean || !sc->log_scale || !sc->quat || !sc->opacity_logit || sc->n < 1) return GS_ERR_INVALID_ARG;
+    if (!a->data || a->n_chan < 1 || a->query_stride < 0 || (a->is_complex != 0 && a->is_complex != 1))
+        return GS_ERR_INVALID_ARG;
+    if ((int64_t)a->n_chan * (a->is_complex ? 2 : 1) > 65536) return GS_ERR_CAPACITY;
+    if (!qs->rx || qs->count < 1) return GS_ERR_INVALID_ARG;
+    if (!(p->alpha_min > 0.0f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.0f) || !(p->T_min >= 0.0f) ||
+        !(p->T_min < 1.0f) || !(p->dilation >= 0.0f) || !(p->r_near >= 0.0f) || !(p->margin >= 0.0f) ||
+        !(p->atten_power >= 0.0f) || (p->atten_ref != 0 && p->atten_ref != 1))
+        return GS_ERR_INVALID_ARG;
+    const gs_status st = make_layout(sc->n, qs->count, g, p, L);
+    if (st != GS_OK) return st;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L->total) return GS_ERR_WORKSPACE;
+    return GS_OK;
+}
+
+void enqueue_prepare(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
+                            const gs_params* prm, const Layout& L, char* ws, hipStream_t s)
+{
+    launch_fill_u32((uint32_t*)(ws + L.flags), FL_WORDS, L.s_flags / 4, L.nq, 0u, s);
+    launch_project(*scene, *queries, *grid, *prm, L, ws, s);
+    launch_depth_sort(L, ws, s);
+    launch_binning(L, ws, s);
 }
 
 }  // namespace gs
@@ -181,35 +210,6 @@ gs_status gs_workspace_layout(int32_t n, int32_t n_queries, const gs_grid* grid,
     return GS_OK;
 }
 
-static gs_status check_forward(const gs_scene* sc, const gs_attrs* a, const gs_queries* qs, const gs_grid* g,
-                               const gs_params* p, const float* spectrum, const void* ws, size_t ws_bytes,
-                               Layout* L)
-{
-    if (!sc || !a || !qs || !g || !p || !spectrum) return GS_ERR_INVALID_ARG;
-    if (!sc->mean || !sc->log_scale || !sc->quat || !sc->opacity_logit || sc->n < 1) return GS_ERR_INVALID_ARG;
-    if (!a->data || a->n_chan < 1 || a->query_stride < 0 || (a->is_complex != 0 && a->is_complex != 1))
-        return GS_ERR_INVALID_ARG;
-    if ((int64_t)a->n_chan * (a->is_complex ? 2 : 1) > 65536) return GS_ERR_CAPACITY;
-    if (!qs->rx || qs->count < 1) return GS_ERR_INVALID_ARG;
-    if (!(p->alpha_min > 0.0f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.0f) || !(p->T_min >= 0.0f) ||
-        !(p->T_min < 1.0f) || !(p->dilation >= 0.0f) || !(p->r_near >= 0.0f) || !(p->margin >= 0.0f) ||
-        !(p->atten_power >= 0.0f) || (p->atten_ref != 0 && p->atten_ref != 1))
-        return GS_ERR_INVALID_ARG;
-    const gs_status st = make_layout(sc->n, qs->count, g, p, L);
-    if (st != GS_OK) return st;
-    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L->total) return GS_ERR_WORKSPACE;
-    return GS_OK;
-}
-
-static void enqueue_prepare(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
-                            const gs_params* prm, const Layout& L, char* ws, hipStream_t s)
-{
-    launch_fill_u32((uint32_t*)(ws + L.flags), FL_WORDS, L.s_flags / 4, L.nq, 0u, s);
-    launch_project(*scene, *queries, *grid, *prm, L, ws, s);
-    launch_depth_sort(L, ws, s);
-    launch_binning(L, ws, s);
-}
-
 gs_status gs_render_forward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
                             const gs_grid* grid, const gs_params* prm, float* spectrum, void* workspace,
                             size_t ws_bytes, void* stream)
@@ -268,6 +268,7 @@ gs_status gs_render_live(int32_t n, int32_t n_queries, const gs_grid* grid, cons
                          void* stream)
 {
     if (!live_list || !live_count || !grid || !prm) return GS_ERR_INVALID_ARG;
+    if (prm->options & GS_OPT_FORWARD_ONLY) return GS_ERR_INVALID_ARG;
     Layout L;
     gs_status st = make_layout(n, n_queries, grid, prm, &L);
     if (st != GS_OK) return st;
@@ -286,6 +287,7 @@ gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const
                              void* stream)
 {
     if (!d_spectrum || !d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !d_attr) return GS_ERR_INVALID_ARG;
+    if (prm && (prm->options & GS_OPT_FORWARD_ONLY)) return GS_ERR_INVALID_ARG;
     Layout L;
     gs_status st = check_forward(scene, attrs, queries, grid, prm, spectrum, workspace, ws_bytes, &L);
     if (st != GS_OK) return st;

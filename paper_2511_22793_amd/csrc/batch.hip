@@ -1,0 +1,124 @@
+// Batched serving: the prepare steps of every job, then one persistent
+// blend launch over all jobs' (query, channel group, tile) items.
+#include "common.h"
+
+namespace gs {
+
+constexpr size_t PLAN_HEAD = 256;  // work counter, then the job table
+
+static gs_status build_table(const gs_batch_job* jobs, int n_jobs, std::vector<BlendJob>& table, gs_batch_info* info)
+{
+    if (!jobs || n_jobs < 1 || n_jobs > (1 << 16)) return GS_ERR_INVALID_ARG;
+    table.resize(n_jobs);
+    uint64_t items = 0;
+    int64_t nq_total = 0;
+    int block = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const gs_batch_job& b = jobs[j];
+        Layout L;
+        gs_status st = check_forward(&b.scene, &b.attrs, &b.queries, &b.grid, &b.params, b.spectrum, b.workspace,
+                                     b.workspace_bytes, &L);
+        if (st != GS_OK) return st;
+        const int C = b.attrs.is_complex ? 2 : 1;
+        const int Fc = b.attrs.n_chan * C;
+        int cg = choose_chan_group(Fc, b.params.chan_group);
+        if (cg > 32) cg = 32;  // the persistent kernel carries groups up to 32
+        BlendJob J = make_blend_job(b.attrs, b.params, L, L.nq, (char*)b.workspace, b.spectrum);
+        J.cg = cg;
+        J.ncg = Fc / cg;
+        J.item_begin = (uint32_t)items;
+        J.query0 = (int)nq_total;
+        items += (uint64_t)L.T * (uint64_t)J.ncg * (uint64_t)L.nq;
+        nq_total += L.nq;
+        if (items >= 0xFFFFFFFFull || nq_total > 0x7FFFFFFF) return GS_ERR_CAPACITY;
+        block = std::max(block, L.tw * L.th);
+        table[j] = J;
+    }
+    if (info) {
+        info->items = (int64_t)items;
+        info->n_queries = (int32_t)nq_total;
+        info->block = block;
+        info->workgroups = 0;
+        info->reserved = 0;
+    }
+    return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+size_t gs_batch_plan_bytes(int32_t n_jobs)
+{
+    if (n_jobs < 1) return 0;
+    return PLAN_HEAD + align256((size_t)n_jobs * sizeof(BlendJob));
+}
+
+gs_status gs_batch_plan(const gs_batch_job* jobs, int32_t n_jobs, void* plan, size_t plan_bytes, gs_batch_info* info,
+                        void* stream)
+{
+    if (!info) return GS_ERR_INVALID_ARG;
+    std::vector<BlendJob> table;
+    gs_status st = build_table(jobs, n_jobs, table, info);
+    if (st != GS_OK) return st;
+    if (!plan || ((uintptr_t)plan & 255) || plan_bytes < gs_batch_plan_bytes(n_jobs)) return GS_ERR_WORKSPACE;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return GS_ERR_HIP;
+    if (persist_occupancy(info->block, &per_cu) != hipSuccess) return GS_ERR_HIP;
+    info->workgroups = std::max(1, cus * std::max(1, per_cu));
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync((char*)plan + PLAN_HEAD, table.data(), table.size() * sizeof(BlendJob),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return GS_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GS_ERR_HIP;
+    return GS_OK;
+}
+
+gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, size_t plan_bytes, int32_t workgroups,
+                       uint64_t* timestamps, void* stream)
+{
+    std::vector<BlendJob> table;
+    gs_batch_info info;
+    gs_status st = build_table(jobs, n_jobs, table, &info);
+    if (st != GS_OK) return st;
+    if (!plan || ((uintptr_t)plan & 255) || plan_bytes < gs_batch_plan_bytes(n_jobs)) return GS_ERR_WORKSPACE;
+    if (workgroups < 1 || workgroups > (1 << 20)) return GS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    uint32_t* counter = (uint32_t*)plan;
+    unsigned long long* ts = (unsigned long long*)timestamps;
+    launch_fill_u32(counter, 1, 0, 1, 0u, s);
+    if (ts) {
+        launch_fill_u32((uint32_t*)ts, 2 * ((size_t)info.n_queries + 2), 0, 1, 0u, s);
+        launch_stamp(ts, s);
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        const gs_batch_job& b = jobs[j];
+        Layout L;
+        st = make_layout(b.scene.n, b.queries.count, &b.grid, &b.params, &L);
+        if (st != GS_OK) return st;
+        enqueue_prepare(&b.scene, &b.queries, &b.grid, &b.params, L, (char*)b.workspace, s);
+    }
+    launch_blend_persist((const BlendJob*)((char*)plan + PLAN_HEAD), n_jobs, (uint32_t)info.items, counter,
+                         ts ? ts + 1 : nullptr, workgroups, info.block, s);
+    if (ts) launch_stamp(ts + 1 + info.n_queries, s);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+gs_status gs_wall_clock_khz(int32_t* khz)
+{
+    if (!khz) return GS_ERR_INVALID_ARG;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return GS_ERR_HIP;
+    *khz = v;
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -17,30 +17,34 @@ namespace gs {
 
 constexpr double LOG2E = 1.4426950408889634;
 
-template <int CG>
-__global__ __launch_bounds__(256) void k_blend(
-    const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
-    const uint2* __restrict__ ranges, size_t s_ranges, const float* __restrict__ attr, int64_t a_stride,
-    int Fc, int C, int H, int W, int tw, int th, int TX, float amin, float amax, float tmin,
-    float* __restrict__ out, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
-    uint32_t* __restrict__ n_contrib, size_t s_pix, int shared_geo)
-{
-    const int tile = blockIdx.x, cg = blockIdx.y, set = blockIdx.z;
-    const int q = shared_geo ? 0 : set;  // geometry query
-    const int nthr = tw * th;
-    const int txi = tile % TX, tyi = tile / TX;
-    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
-    const int col = txi * tw + lx, row = tyi * th + ly;
-    const bool inside = col < W && row < H;
-    const uint2 rg = ranges[q * s_ranges + tile];
-    const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * W;
-    rec += q * s_rec;
-    plist += q * s_plist;
-    const float* A = attr + set * a_stride + cg * CG;
+// LDS batch of one tile's list (declared once per kernel, so that the
+// channel-group instantiations of one kernel share it).
+struct BlendLds {
+    double px[256], py[256], ca[256], cb[256], cc[256];
+    float sig[256], att[256];
+    uint32_t g[256];
+};
 
-    __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
-    __shared__ float s_sig[256], s_att[256];
-    __shared__ uint32_t s_g[256];
+// One (tile, channel group, set) of a blend job; every thread of the
+// workgroup must call it (it synchronises).  Threads beyond the tile's pixel
+// count idle.
+template <int CG>
+__device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int tile, int cg, int set)
+{
+    const int q = J.shared_geo ? 0 : set;  // geometry query
+    const int nthr = J.tw * J.th;
+    const int txi = tile % J.TX, tyi = tile / J.TX;
+    const int lx = threadIdx.x % J.tw, ly = threadIdx.x / J.tw;
+    const int col = txi * J.tw + lx, row = tyi * J.th + ly;
+    const bool inside = (int)threadIdx.x < nthr && col < J.W && row < J.H;
+    const uint2 rg = J.ranges[q * J.s_ranges + tile];
+    const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * J.W;
+    const double Wd = (double)J.W;
+    const GRec* rec = J.rec + q * J.s_rec;
+    const uint32_t* plist = J.plist + q * J.s_plist;
+    const int Fc = J.Fc;
+    const float* A = J.attr + set * J.a_stride + cg * CG;
+    const float amin = J.amin, amax = J.amax, tmin = J.tmin;
 
     float T = 1.0f;
     float acc[CG];
@@ -50,43 +54,43 @@ __global__ __launch_bounds__(256) void k_blend(
     bool done = !inside;
 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += nthr) {
-        if (__syncthreads_count(done) == nthr) break;
+        if (__syncthreads_count(done) == (int)blockDim.x) break;
         const uint32_t i = b0 + threadIdx.x;
-        if (i < rg.y) {
+        if ((int)threadIdx.x < nthr && i < rg.y) {
             const uint32_t g = plist[i];
             const GRec r = rec[g];
-            s_px[threadIdx.x] = r.px;
-            s_py[threadIdx.x] = r.py;
-            s_ca[threadIdx.x] = r.ca;
-            s_cb[threadIdx.x] = r.cb;
-            s_cc[threadIdx.x] = r.cc;
-            s_sig[threadIdx.x] = r.sigma;
-            s_att[threadIdx.x] = r.att;
-            s_g[threadIdx.x] = g;
+            S.px[threadIdx.x] = r.px;
+            S.py[threadIdx.x] = r.py;
+            S.ca[threadIdx.x] = r.ca;
+            S.cb[threadIdx.x] = r.cb;
+            S.cc[threadIdx.x] = r.cc;
+            S.sig[threadIdx.x] = r.sigma;
+            S.att[threadIdx.x] = r.att;
+            S.g[threadIdx.x] = g;
         }
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, rg.y - b0);
         for (int j = 0; j < m && !done; ++j) {
             // the attribute row is wave-uniform: issue its scalar loads first
             // so that the alpha evaluation below hides their latency
-            const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
+            const uint32_t g = __builtin_amdgcn_readfirstlane(S.g[j]);
             const float* vp = A + (size_t)g * Fc;
             float v[CG];
 #pragma unroll
             for (int k = 0; k < CG; ++k) v[k] = vp[k];
-            double dx = pcx - s_px[j];
-            dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
-            const double dy = pcy - s_py[j];
-            const double qv = s_ca[j] * dx * dx + 2.0 * s_cb[j] * dx * dy + s_cc[j] * dy * dy;
+            double dx = pcx - S.px[j];
+            dx += dx >= halfW ? -Wd : (dx < -halfW ? Wd : 0.0);
+            const double dy = pcy - S.py[j];
+            const double qv = S.ca[j] * dx * dx + 2.0 * S.cb[j] * dx * dy + S.cc[j] * dy * dy;
             const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
-            const float alpha = fminf(amax, s_sig[j] * G);
+            const float alpha = fminf(amax, S.sig[j] * G);
             const float Tn = T * (1.0f - alpha);
             const bool stop = alpha >= amin && Tn < tmin;
             const bool take = alpha >= amin && !stop;
             done = stop;
             // branch-free update (one basic block, so the row loads issue
             // first): a skipped pair adds zero and keeps T
-            const float wgt = take ? T * alpha * s_att[j] : 0.0f;
+            const float wgt = take ? T * alpha * S.att[j] : 0.0f;
 #pragma unroll
             for (int k = 0; k < CG; ++k) acc[k] = fmaf(wgt, v[k], acc[k]);
             T = take ? Tn : T;
@@ -94,20 +98,81 @@ __global__ __launch_bounds__(256) void k_blend(
             cnt += take ? 1u : 0u;
         }
     }
+    __syncthreads();  // the LDS batch may be reused by the caller's next item
     if (!inside) return;
-    const size_t HW = (size_t)H * W, pix = (size_t)row * W + col;
-    const int F = Fc / C;
+    const size_t HW = (size_t)J.H * J.W, pix = (size_t)row * J.W + col;
+    const int F = Fc / J.C;
 #pragma unroll
     for (int k = 0; k < CG; ++k) {
         const int ch = cg * CG + k;
-        const int f = ch / C, comp = ch - f * C;
-        out[(((size_t)set * F + f) * HW + pix) * C + comp] = acc[k];
+        const int f = ch / J.C, comp = ch - f * J.C;
+        J.out[(((size_t)set * F + f) * HW + pix) * J.C + comp] = acc[k];
     }
-    if (cg == 0 && set == q) {
-        T_final[q * s_pix + pix] = T;
-        n_last[q * s_pix + pix] = last;
-        n_contrib[q * s_pix + pix] = cnt;
+    if (cg == 0 && set == q && J.T_final) {
+        J.T_final[q * J.s_pix + pix] = T;
+        J.n_last[q * J.s_pix + pix] = last;
+        J.n_contrib[q * J.s_pix + pix] = cnt;
     }
+}
+
+template <int CG>
+__global__ __launch_bounds__(256) void k_blend(BlendJob J)
+{
+    __shared__ BlendLds S;
+    blend_tile<CG>(J, S, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Persistent blend over a table of jobs (scenes of any size, grid, tile
+// shape and channel count): each workgroup takes (job, tile, channel group,
+// set) items from a device counter until none are left -- every workgroup
+// exits once the counter passes the total -- and stamps the completion time
+// of the item's query.  Items are numbered job by job, then set by set, then
+// channel group, then tile, so a query's items are contiguous and the job
+// order is the service order.
+__global__ __launch_bounds__(256) void k_blend_persist(const BlendJob* __restrict__ jobs, int njobs, uint32_t total,
+                                                       uint32_t* counter, unsigned long long* done_ts)
+{
+    __shared__ BlendLds S;
+    __shared__ uint32_t s_item;
+    __shared__ int s_job;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t item = atomicAdd(counter, 1u);
+            int lo = 0, hi = njobs - 1;  // last job with item_begin <= item
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (jobs[mid].item_begin <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            s_item = item;
+            s_job = lo;
+        }
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        const int j = __builtin_amdgcn_readfirstlane(s_job);
+        __syncthreads();
+        if (item >= total) break;
+        const BlendJob& J = jobs[j];
+        const uint32_t local = item - J.item_begin;
+        const int tile = (int)(local % (uint32_t)J.T);
+        const uint32_t rest = local / (uint32_t)J.T;
+        const int cg = (int)(rest % (uint32_t)J.ncg);
+        const int set = (int)(rest / (uint32_t)J.ncg);
+        switch (J.cg) {
+            case 1: blend_tile<1>(J, S, tile, cg, set); break;
+            case 2: blend_tile<2>(J, S, tile, cg, set); break;
+            case 4: blend_tile<4>(J, S, tile, cg, set); break;
+            case 8: blend_tile<8>(J, S, tile, cg, set); break;
+            case 16: blend_tile<16>(J, S, tile, cg, set); break;
+            default: blend_tile<32>(J, S, tile, cg, set); break;
+        }
+        if (threadIdx.x == 0 && done_ts) atomicMax(&done_ts[J.query0 + set], (unsigned long long)wall_clock64());
+    }
+}
+
+__global__ void k_stamp(unsigned long long* ts)
+{
+    if (threadIdx.x == 0) *ts = (unsigned long long)wall_clock64();
 }
 
 // Geometry-only walk: marks every Gaussian that reaches at least one pixel
@@ -208,15 +273,37 @@ void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, 
                        s_list, count);
 }
 
-template <int CG>
-static void blend_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, const gs_params& p, const Layout& L,
-                     char* ws, float* out, int C, int shared_geo)
+BlendJob make_blend_job(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out)
 {
-    hipLaunchKernelGGL(k_blend<CG>, grid, block, 0, s, (const GRec*)(ws + L.rec), L.s_rec / sizeof(GRec),
-                       (const uint32_t*)(ws + L.plist), L.s_plist / 4, (const uint2*)(ws + L.ranges),
-                       L.s_ranges / sizeof(uint2), a.data, a.query_stride, a.n_chan * C, C, L.H, L.W, L.tw, L.th,
-                       L.TX, p.alpha_min, p.alpha_max, p.T_min, out, (float*)(ws + L.T_final),
-                       (uint32_t*)(ws + L.n_last), (uint32_t*)(ws + L.n_contrib), L.s_pix / 4, shared_geo);
+    const int C = a.is_complex ? 2 : 1;
+    BlendJob J{};
+    J.rec = (const GRec*)(ws + L.rec);
+    J.s_rec = L.s_rec / sizeof(GRec);
+    J.plist = (const uint32_t*)(ws + L.plist);
+    J.s_plist = L.s_plist / 4;
+    J.ranges = (const uint2*)(ws + L.ranges);
+    J.s_ranges = L.s_ranges / sizeof(uint2);
+    J.attr = a.data;
+    J.a_stride = a.query_stride;
+    J.Fc = a.n_chan * C;
+    J.C = C;
+    J.H = L.H;
+    J.W = L.W;
+    J.tw = L.tw;
+    J.th = L.th;
+    J.TX = L.TX;
+    J.T = L.T;
+    J.nsets = n_sets;
+    J.shared_geo = (L.nq == 1 && n_sets > 1) ? 1 : 0;
+    J.amin = p.alpha_min;
+    J.amax = p.alpha_max;
+    J.tmin = p.T_min;
+    J.out = out;
+    J.T_final = (float*)(ws + L.T_final);
+    J.n_last = (uint32_t*)(ws + L.n_last);
+    J.n_contrib = (uint32_t*)(ws + L.n_contrib);
+    J.s_pix = L.s_pix / 4;
+    return J;
 }
 
 // Channel floats per workgroup: the largest power of two that divides F*c,
@@ -237,18 +324,33 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
     const int Fc = a.n_chan * C;
     const int cg = choose_chan_group(Fc, p.chan_group);
     if (Fc / cg > 65535) return GS_ERR_CAPACITY;
-    const int shared = (L.nq == 1 && n_sets > 1) ? 1 : 0;
+    BlendJob J = make_blend_job(a, p, L, n_sets, ws, out);
+    J.cg = cg;
+    J.ncg = Fc / cg;
     dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
     switch (cg) {
-        case 1: blend_cg<1>(grid, block, s, a, p, L, ws, out, C, shared); break;
-        case 2: blend_cg<2>(grid, block, s, a, p, L, ws, out, C, shared); break;
-        case 4: blend_cg<4>(grid, block, s, a, p, L, ws, out, C, shared); break;
-        case 8: blend_cg<8>(grid, block, s, a, p, L, ws, out, C, shared); break;
-        case 16: blend_cg<16>(grid, block, s, a, p, L, ws, out, C, shared); break;
-        case 32: blend_cg<32>(grid, block, s, a, p, L, ws, out, C, shared); break;
-        default: blend_cg<64>(grid, block, s, a, p, L, ws, out, C, shared); break;
+        case 1: hipLaunchKernelGGL(k_blend<1>, grid, block, 0, s, J); break;
+        case 2: hipLaunchKernelGGL(k_blend<2>, grid, block, 0, s, J); break;
+        case 4: hipLaunchKernelGGL(k_blend<4>, grid, block, 0, s, J); break;
+        case 8: hipLaunchKernelGGL(k_blend<8>, grid, block, 0, s, J); break;
+        case 16: hipLaunchKernelGGL(k_blend<16>, grid, block, 0, s, J); break;
+        case 32: hipLaunchKernelGGL(k_blend<32>, grid, block, 0, s, J); break;
+        default: hipLaunchKernelGGL(k_blend<64>, grid, block, 0, s, J); break;
     }
     return GS_OK;
 }
+
+void launch_blend_persist(const BlendJob* jobs, int njobs, uint32_t total, uint32_t* counter,
+                          unsigned long long* done_ts, int workgroups, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_blend_persist, dim3(workgroups), dim3(block), 0, s, jobs, njobs, total, counter, done_ts);
+}
+
+hipError_t persist_occupancy(int block, int* per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_blend_persist, block, 0);
+}
+
+void launch_stamp(unsigned long long* ts, hipStream_t s) { hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, ts); }
 
 }  // namespace gs

@@ -230,8 +230,6 @@ static void bwd_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, cons
                        (float*)(ws + L.gacc), L.s_gacc / 4, d_attr, da_stride, shared);
 }
 
-int choose_chan_group(int Fc, int requested);
-
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                            const float* out, const float* dout, float* d_attr, hipStream_t s)
 {

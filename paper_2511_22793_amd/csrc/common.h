@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "../../include/gsparc.h"
 
 namespace gs {
@@ -25,6 +28,27 @@ enum : uint32_t { ST_VISIBLE = 0, ST_NEAR = 1, ST_FAINT = 2, ST_OFFGRID = 3, ST_
 
 // per-query flag words
 enum : int { FL_NVIS = 0, FL_PAIRS = 1, FL_OVERFLOW = 2, FL_INVALID = 3, FL_PUSED = 4, FL_WORDS = 16 };
+
+// One blend job: a prepared workspace, its attribute sets and output.
+struct BlendJob {
+    const GRec* rec;
+    size_t s_rec;
+    const uint32_t* plist;
+    size_t s_plist;
+    const uint2* ranges;
+    size_t s_ranges;
+    const float* attr;
+    int64_t a_stride;
+    int Fc, C, H, W, tw, th, TX, T, cg, ncg, nsets, shared_geo;
+    float amin, amax, tmin;
+    float* out;
+    float* T_final;
+    uint32_t* n_last;
+    uint32_t* n_contrib;
+    size_t s_pix;
+    uint32_t item_begin;  // first work item of this job in a persistent launch
+    int query0;           // index of the job's first query in the batch
+};
 
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 8;
@@ -49,6 +73,7 @@ struct Layout {
     size_t total;
 };
 
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* p, Layout* L);
 
 // kernel launchers (stream-ordered, no synchronisation)
@@ -64,6 +89,16 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
                        hipStream_t s);
 void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, size_t s_list, uint32_t* count,
                  hipStream_t s);
+gs_status check_forward(const gs_scene* sc, const gs_attrs* a, const gs_queries* qs, const gs_grid* g,
+                        const gs_params* p, const float* spectrum, const void* ws, size_t ws_bytes, Layout* L);
+void enqueue_prepare(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid, const gs_params* prm,
+                     const Layout& L, char* ws, hipStream_t s);
+int choose_chan_group(int Fc, int requested);
+BlendJob make_blend_job(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out);
+void launch_blend_persist(const BlendJob* jobs, int njobs, uint32_t total, uint32_t* counter,
+                          unsigned long long* done_ts, int workgroups, int block, hipStream_t s);
+void launch_stamp(unsigned long long* ts, hipStream_t s);
+hipError_t persist_occupancy(int block, int* per_cu);
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                            const float* out, const float* dout, float* d_attr, hipStream_t s);
 void launch_project_bwd(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,

@@ -16,7 +16,7 @@ from typing import Optional
 
 import torch
 
-from ._lib import GsAttrs, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
+from ._lib import GS_OPT_FORWARD_ONLY, GsAttrs, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
 
 DEFAULT_VIEW = (0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0)
 
@@ -33,10 +33,12 @@ class Params:
     margin: float = 1e-3
     pair_capacity: int = 0
     chan_group: int = 0
+    forward_only: bool = False
 
     def c(self) -> GsParams:
         return GsParams(self.alpha_min, self.alpha_max, self.T_min, self.dilation, self.r_near, self.atten_power,
-                        int(self.atten_ref), self.margin, int(self.pair_capacity), int(self.chan_group), 0)
+                        int(self.atten_ref), self.margin, int(self.pair_capacity), int(self.chan_group),
+                        GS_OPT_FORWARD_ONLY if self.forward_only else 0)
 
 
 @dataclass

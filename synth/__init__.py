@@ -32,6 +32,7 @@ SEED_SCENE = 0
 SEED_QUERIES = 1
 SEED_PERTURB = 2
 SEED_GT_SCENE = 3
+SEED_SERVING = 4
 
 
 def scene(n: int, seed: int = SEED_SCENE, lo=BOX_LO, hi=BOX_HI,
@@ -118,3 +119,42 @@ def uniform(shape, lo: float, hi: float, seed: int) -> np.ndarray:
 def normal(shape, sd: float, seed: int, mean: float = 0.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.normal(mean, sd, size=shape).astype(np.float32)
+
+
+def serving_mix(n_queries: int = 256, n_scenes: int = 8, sizes=(10_000, 30_000, 80_000, 150_000, 200_000),
+                grids=((90, 360), (180, 720)), chans=(1, 16, 64), seed: int = SEED_SERVING) -> list:
+    """An uneven serving batch: n_scenes scenes whose Gaussian count, grid
+    (1 or 0.5 degree) and channel count are drawn uniformly from the given
+    sets, and n_queries receivers each assigned to a uniformly drawn scene
+    (every scene keeps at least one).  One channel is a real RSS value, more
+    are complex subcarriers.  Returns one dict per scene: n, H, W, F,
+    complex, n_queries, scene_seed, query_seed, attr_seed."""
+    rng = np.random.default_rng(seed)
+    n = rng.choice(np.asarray(sizes), size=n_scenes)
+    g = rng.integers(0, len(grids), size=n_scenes)
+    f = rng.choice(np.asarray(chans), size=n_scenes)
+    owner = rng.integers(0, n_scenes, size=n_queries)
+    counts = np.bincount(owner, minlength=n_scenes)
+    for s_ in range(n_scenes):  # move a query from the largest group to an empty one
+        if counts[s_] == 0:
+            counts[np.argmax(counts)] -= 1
+            counts[s_] = 1
+    out = []
+    for s_ in range(n_scenes):
+        H, W = grids[g[s_]]
+        out.append({"n": int(n[s_]), "H": int(H), "W": int(W), "F": int(f[s_]), "complex": bool(f[s_] > 1),
+                    "n_queries": int(counts[s_]), "scene_seed": seed * 1000 + s_,
+                    "query_seed": seed * 1000 + 100 + s_, "attr_seed": seed * 1000 + 200 + s_})
+    return out
+
+
+def serving_arrays(mix: list, n_scale: float = 1.0) -> list:
+    """Host arrays of a serving mix: per scene (scene, attr, rx, complex, H,
+    W), the scene recipe of the other workloads with n scaled by n_scale,
+    shared attributes and receivers uniform in the room."""
+    out = []
+    for m in mix:
+        n = max(1, int(round(m["n"] * n_scale)))
+        out.append((scene(n, seed=m["scene_seed"]), channel_attrs(n, m["F"], m["complex"], seed=m["attr_seed"]),
+                    points(m["n_queries"], seed=m["query_seed"]), m["complex"], m["H"], m["W"]))
+    return out

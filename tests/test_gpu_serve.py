@@ -1,0 +1,164 @@
+"""Batched serving on the GPU: one persistent blend launch over scenes of
+uneven size, grid, tile shape and channel count reproduces the per-query
+renderer bit for bit (and so the oracle), replays of its graph capture
+reproduce the eager run, and the autotuner's choices keep that identity."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2511_22793_amd as gs
+import synth
+from gpu_util import GATE, check_parity
+from paper_2511_22793_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+# (tile_h, tile_w, chan_group) per job: every workgroup class and several groups
+VARIANTS = [(16, 16, 0), (8, 32, 8), (8, 8, 4), (16, 8, 16), (32, 8, 2)]
+
+
+def small_jobs(seed=9, n_scenes=4, n_queries=10, variants=True):
+    mix = synth.serving_mix(n_queries=n_queries, n_scenes=n_scenes, sizes=(700, 1500, 3000),
+                            grids=((45, 180), (90, 360)), chans=(1, 4, 16), seed=seed)
+    jobs = serve.make_jobs(synth.serving_arrays(mix))
+    if variants:
+        for i, j in enumerate(jobs):
+            th, tw, cg = VARIANTS[i % len(VARIANTS)]
+            j.grid = gs.Grid(j.grid.H, j.grid.W, th, tw)
+            j.params = gs.Params(forward_only=True, chan_group=cg)
+    return mix, jobs
+
+
+def single(job):
+    out, ws = gs.forward(job.scene, job.attr, job.rx, grid=job.grid, params=job.params, is_complex=job.is_complex)
+    return out, ws
+
+
+def pixel_state(ws, q, H, W):
+    return [ws.view(f, q, H * W, torch.int32).clone() for f in ("T_final", "n_last", "n_contrib")]
+
+
+def assert_batch_equals_single(batch):
+    for i, job in enumerate(batch.jobs):
+        ref, ws = single(job)
+        torch.cuda.synchronize()
+        assert torch.equal(batch.spectra[i], ref), "job %d (%s)" % (i, job.signature())
+        for q in range(job.B):
+            a = pixel_state(batch.workspaces[i], q, job.grid.H, job.grid.W)
+            b = pixel_state(ws, q, job.grid.H, job.grid.W)
+            for x, y in zip(a, b):
+                assert torch.equal(x, y), "job %d query %d pixel state" % (i, q)
+
+
+def check_timestamps(batch):
+    ts = batch.timestamps.cpu().numpy()
+    assert ts[0] > 0 and np.all(ts[1:-1] >= ts[0]) and np.all(ts[1:-1] <= ts[-1])
+    lat = batch.latencies_ms()
+    assert 0 < lat["p50"] <= lat["p99"] <= lat["makespan"]
+    return lat
+
+
+def test_batch_matches_single_query_forward():
+    _, jobs = small_jobs()
+    batch = serve.Batch(jobs)
+    assert batch.info.block == 256 and batch.n_queries == 10
+    batch.run()
+    torch.cuda.synchronize()
+    assert_batch_equals_single(batch)
+    check_timestamps(batch)
+    for fl in batch.flags():
+        assert all(f["overflow"] == 0 for f in fl)
+
+
+def test_batched_spectra_match_oracle():
+    mix, jobs = small_jobs(seed=11, n_scenes=3, n_queries=6)
+    batch = serve.Batch(jobs)
+    batch.run()
+    torch.cuda.synchronize()
+    arrs = synth.serving_arrays(mix)
+    for i, (sc, attr, rx, cplx, H, W) in enumerate(arrs):
+        got = batch.spectra[i][0].cpu().double().numpy()
+        if cplx:
+            got = got[..., 0] + 1j * got[..., 1]
+        ref = oracle.render(sc, attr, rx[0], H, W)
+        check_parity(got, ref, "job %d" % i)
+
+
+def test_single_workgroup_and_one_class():
+    # one persistent workgroup drains the whole queue; 64-thread workgroups
+    _, jobs = small_jobs(seed=13, n_scenes=2, n_queries=3, variants=False)
+    for j in jobs:
+        j.grid = gs.Grid(j.grid.H, j.grid.W, 8, 8)
+    batch = serve.Batch(jobs, workgroups=1)
+    assert batch.info.block == 64
+    batch.run()
+    torch.cuda.synchronize()
+    assert_batch_equals_single(batch)
+
+
+def test_graph_replay_matches_eager():
+    _, jobs = small_jobs(seed=17)
+    batch = serve.Batch(jobs)
+    batch.run()
+    torch.cuda.synchronize()
+    eager = [s.clone() for s in batch.spectra]
+    batch.capture()
+    _, other = small_jobs(seed=19, n_scenes=2, n_queries=3)
+    for r in range(3):
+        for s in batch.spectra:
+            s.zero_()
+        single(other[r % 2])  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        batch.replay()
+        torch.cuda.synchronize()
+        for i, s in enumerate(batch.spectra):
+            assert torch.equal(s, eager[i]), "replay %d job %d" % (r, i)
+        check_timestamps(batch)
+
+
+def test_autotuner_choices_and_cache(tmp_path):
+    _, jobs = small_jobs(seed=23, n_scenes=3, n_queries=6, variants=False)
+    path = str(tmp_path / "tune.json")
+    tuner = serve.Autotuner(path=path, probe=2, reps=1)
+    batch = tuner.tune(jobs)
+    cache = json.load(open(path))
+    assert set(cache) == {j.signature() for j in jobs}
+    blk = tuner.choice["block"]
+    for j in batch.jobs:
+        assert j.grid.tile_h * j.grid.tile_w == blk
+    est = [cache[j.signature()][str(blk)]["ms_per_query"] * j.B for j in batch.jobs]
+    assert est == sorted(est)  # shortest job first
+    batch.run()
+    torch.cuda.synchronize()
+    assert_batch_equals_single(batch)
+    again = serve.Autotuner(path=path, probe=2, reps=1)
+    again.tune(jobs, tune_workgroups=False)
+    assert again.log == []  # every signature came from the cache
+
+
+def test_full_size_serving_mix_sampled():
+    # the 256-query, 8-scene uneven mix at full size; the oracle computes a
+    # seeded sample of pixels of one receiver per scene
+    mix = synth.serving_mix()
+    arrs = synth.serving_arrays(mix)
+    jobs = serve.make_jobs(arrs)
+    batch = serve.Batch(jobs)
+    batch.run()
+    torch.cuda.synchronize()
+    check_timestamps(batch)
+    rng = np.random.default_rng(29)
+    for i, (sc, attr, rx, cplx, H, W) in enumerate(arrs):
+        assert all(f["overflow"] == 0 for f in batch.flags()[i])
+        q = int(rng.integers(0, rx.shape[0]))
+        pix = np.sort(rng.choice(H * W, size=48, replace=False)).astype(np.int32)
+        ref = oracle.render(sc, attr, rx[q], H, W, pixels=pix)
+        r, c = pix // W, pix % W
+        got = batch.spectra[i][q].cpu().double().numpy()
+        if cplx:
+            got = got[..., 0] + 1j * got[..., 1]
+        err = oracle.parity_error(got[:, r, c], ref["out"][:, r, c], ref["absacc"][:, r, c])
+        ok = ~ref["ambig"][r, c]
+        assert float(err[:, ok].max()) <= GATE, "scene %d (%s)" % (i, jobs[i].signature())
