@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-mix", action="store_true")
+    ap.add_argument("--mix-only", action="store_true", help="run only the uneven serving mix (for profiling)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON) for the serving mix")
     return ap.parse_args()
 
 
@@ -69,6 +72,9 @@ def main():
     from paper_2511_22793_amd import train
 
     dev = torch.device("cuda:0")
+    if args.mix_only:
+        print(json.dumps({"serving_mix": serving_mix(args, gs, dev)}), flush=True)
+        return
     n, B, SB, F, H, W = args.n, args.batch, args.serve_batch, args.channels, args.H, args.W
     assert F == train.F, "the attribute network has 64 complex outputs"
     grid = gs.Grid(H, W)
@@ -170,6 +176,8 @@ def main():
                        "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_F32_TFLOPS, 4), "traffic": None,
                        "launch_ms": round(ms, 4),
                        "work": {"pairs_evaluated_per_set": n_eval, "contributions_per_set": n_contrib, "sets": B}}
+    if not args.no_mix:
+        res["serving_mix"] = serving_mix(args, gs, dev)
     if not args.no_plain:
         res["plain"] = plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, box_lo, box_hi, dev)
         res["plain"]["speedup_training"] = round(res["value"] / res["plain"]["training_spectra_per_s"], 3)
@@ -177,6 +185,72 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(gt, rho, tx_all, H, W, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def serving_mix(args, gs, dev):
+    """256 receivers over 8 scenes of uneven size (10k-200k Gaussians), grid
+    (90x360 / 180x720) and channel count (1 real, 16 or 64 complex), with
+    fixed attributes: autotuned, captured once as a graph and replayed.
+    Per-query latency = completion of its spectrum - batch start (device
+    clock), over every timed replay; against one gs_render_forward per
+    query, back to back."""
+    import torch
+    import synth
+    from paper_2511_22793_amd import serve
+    mix = synth.serving_mix()
+    jobs = serve.make_jobs(synth.serving_arrays(mix), device=dev)
+    t = time.perf_counter()
+    tuner = serve.Autotuner(path=args.tune_cache)
+    batch = tuner.tune(jobs)
+    tune_s = time.perf_counter() - t
+    batch.capture()
+    for _ in range(args.warmup):
+        batch.replay()
+    torch.cuda.synchronize()
+    lat, spans = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, min(args.steps, 10))
+    total_ms = 0.0
+    for _ in range(reps):
+        e0.record()
+        batch.replay()
+        e1.record()
+        e1.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        L = batch.latencies_ms()
+        lat.append(L["per_query"])
+        spans.append(L["makespan"])
+    lat = np.concatenate(lat)
+    ms_batch = total_ms / reps
+    # plain: one forward per query, each on its own scene, back to back
+    # (a workspace and an output per scene, reused by its queries in turn)
+    singles = []
+    for i, j in enumerate(batch.jobs):
+        ws = gs.Workspace(j.n, 1, gs.Grid(j.grid.H, j.grid.W), gs.Params(forward_only=True), device=dev)
+        o = torch.empty((1,) + tuple(batch.spectra[i].shape[1:]), device=dev)
+        for q in range(j.B):
+            singles.append((j, j.rx[q:q + 1].contiguous(), ws, o))
+
+    def run_plain():
+        for j, rx, ws, o in singles:
+            gs.forward(j.scene, j.attr, rx, grid=ws.grid, params=ws.params, is_complex=j.is_complex, workspace=ws,
+                       out=o)
+    run_plain()
+    torch.cuda.synchronize()
+    e0.record()
+    run_plain()
+    e1.record()
+    e1.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    nq = batch.n_queries
+    return {"queries": nq, "scenes": [j.signature() for j in batch.jobs],
+            "tuned": {"block": tuner.choice["block"], "workgroups": tuner.choice.get("workgroups"),
+                      "tiles_and_groups": [list(x[1:]) for x in tuner.choice["jobs"]], "tune_s": round(tune_s, 2)},
+            "ms_per_batch": round(ms_batch, 4), "makespan_ms_device": round(float(np.mean(spans)), 4),
+            "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "queries_per_s": round(nq / (ms_batch / 1e3), 2), "replays": reps,
+            "plain_ms_per_batch": round(ms_plain, 4), "plain_queries_per_s": round(nq / (ms_plain / 1e3), 2),
+            "speedup_vs_plain": round(ms_plain / ms_batch, 3)}
 
 
 def plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, box_lo, box_hi, dev):

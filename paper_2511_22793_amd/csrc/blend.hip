@@ -17,6 +17,15 @@ namespace gs {
 
 constexpr double LOG2E = 1.4426950408889634;
 
+// Attribute rows are read-only for the whole launch: reading them through a
+// constant-address-space pointer lets the wave-uniform row go through the
+// scalar cache (s_load) whatever the kernel stores elsewhere.
+typedef __attribute__((address_space(4))) const float CFloat;
+// The other buffers are global memory; naming the address space keeps the
+// persistent kernel (which reads its pointers from a table) off flat
+// instructions.
+#define GLOBAL_AS __attribute__((address_space(1)))
+
 // LDS batch of one tile's list (declared once per kernel, so that the
 // channel-group instantiations of one kernel share it).
 struct BlendLds {
@@ -28,8 +37,15 @@ struct BlendLds {
 // One (tile, channel group, set) of a blend job; every thread of the
 // workgroup must call it (it synchronises).  Threads beyond the tile's pixel
 // count idle.
+// The buffers are passed as restrict parameters so that, once inlined, the
+// attribute rows are known not to alias the stores and load through the
+// scalar cache.
 template <int CG>
-__device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int tile, int cg, int set)
+__device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, int tile, int cg, int set,
+                                                const GRec* __restrict__ rec, const uint32_t* __restrict__ plist,
+                                                const uint2* __restrict__ ranges, const float* __restrict__ attr,
+                                                float* __restrict__ out, float* __restrict__ T_final,
+                                                uint32_t* __restrict__ n_last, uint32_t* __restrict__ n_contrib)
 {
     const int q = J.shared_geo ? 0 : set;  // geometry query
     const int nthr = J.tw * J.th;
@@ -37,13 +53,18 @@ __device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int t
     const int lx = threadIdx.x % J.tw, ly = threadIdx.x / J.tw;
     const int col = txi * J.tw + lx, row = tyi * J.th + ly;
     const bool inside = (int)threadIdx.x < nthr && col < J.W && row < J.H;
-    const uint2 rg = J.ranges[q * J.s_ranges + tile];
+    uint2 rg;
+    {
+        const unsigned long long r = ((const GLOBAL_AS unsigned long long*)ranges)[q * J.s_ranges + tile];
+        rg.x = (uint32_t)r;
+        rg.y = (uint32_t)(r >> 32);
+    }
     const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * J.W;
     const double Wd = (double)J.W;
-    const GRec* rec = J.rec + q * J.s_rec;
-    const uint32_t* plist = J.plist + q * J.s_plist;
+    rec += q * J.s_rec;
+    plist += q * J.s_plist;
     const int Fc = J.Fc;
-    const float* A = J.attr + set * J.a_stride + cg * CG;
+    const float* A = attr + set * J.a_stride + cg * CG;
     const float amin = J.amin, amax = J.amax, tmin = J.tmin;
 
     float T = 1.0f;
@@ -57,8 +78,8 @@ __device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int t
         if (__syncthreads_count(done) == (int)blockDim.x) break;
         const uint32_t i = b0 + threadIdx.x;
         if ((int)threadIdx.x < nthr && i < rg.y) {
-            const uint32_t g = plist[i];
-            const GRec r = rec[g];
+            const uint32_t g = ((const GLOBAL_AS uint32_t*)plist)[i];
+            const GLOBAL_AS GRec& r = ((const GLOBAL_AS GRec*)rec)[g];
             S.px[threadIdx.x] = r.px;
             S.py[threadIdx.x] = r.py;
             S.ca[threadIdx.x] = r.ca;
@@ -74,7 +95,7 @@ __device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int t
             // the attribute row is wave-uniform: issue its scalar loads first
             // so that the alpha evaluation below hides their latency
             const uint32_t g = __builtin_amdgcn_readfirstlane(S.g[j]);
-            const float* vp = A + (size_t)g * Fc;
+            const CFloat* vp = (const CFloat*)(A + (size_t)g * Fc);
             float v[CG];
 #pragma unroll
             for (int k = 0; k < CG; ++k) v[k] = vp[k];
@@ -106,20 +127,32 @@ __device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int t
     for (int k = 0; k < CG; ++k) {
         const int ch = cg * CG + k;
         const int f = ch / J.C, comp = ch - f * J.C;
-        J.out[(((size_t)set * F + f) * HW + pix) * J.C + comp] = acc[k];
+        ((GLOBAL_AS float*)out)[(((size_t)set * F + f) * HW + pix) * J.C + comp] = acc[k];
     }
-    if (cg == 0 && set == q && J.T_final) {
-        J.T_final[q * J.s_pix + pix] = T;
-        J.n_last[q * J.s_pix + pix] = last;
-        J.n_contrib[q * J.s_pix + pix] = cnt;
+    if (cg == 0 && set == q && T_final) {
+        ((GLOBAL_AS float*)T_final)[q * J.s_pix + pix] = T;
+        ((GLOBAL_AS uint32_t*)n_last)[q * J.s_pix + pix] = last;
+        ((GLOBAL_AS uint32_t*)n_contrib)[q * J.s_pix + pix] = cnt;
     }
 }
 
 template <int CG>
-__global__ __launch_bounds__(256) void k_blend(BlendJob J)
+__device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int tile, int cg, int set)
+{
+    blend_tile_impl<CG>(J, S, tile, cg, set, J.rec, J.plist, J.ranges, J.attr, J.out, J.T_final, J.n_last,
+                        J.n_contrib);
+}
+
+template <int CG>
+__global__ __launch_bounds__(256) void k_blend(BlendJob J, const GRec* __restrict__ rec,
+                                               const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
+                                               const float* __restrict__ attr, float* __restrict__ out,
+                                               float* __restrict__ T_final, uint32_t* __restrict__ n_last,
+                                               uint32_t* __restrict__ n_contrib)
 {
     __shared__ BlendLds S;
-    blend_tile<CG>(J, S, blockIdx.x, blockIdx.y, blockIdx.z);
+    blend_tile_impl<CG>(J, S, blockIdx.x, blockIdx.y, blockIdx.z, rec, plist, ranges, attr, out, T_final, n_last,
+                        n_contrib);
 }
 
 // Persistent blend over a table of jobs (scenes of any size, grid, tile
@@ -328,15 +361,17 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
     J.cg = cg;
     J.ncg = Fc / cg;
     dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
+#define ARGS J.rec, J.plist, J.ranges, J.attr, J.out, J.T_final, J.n_last, J.n_contrib
     switch (cg) {
-        case 1: hipLaunchKernelGGL(k_blend<1>, grid, block, 0, s, J); break;
-        case 2: hipLaunchKernelGGL(k_blend<2>, grid, block, 0, s, J); break;
-        case 4: hipLaunchKernelGGL(k_blend<4>, grid, block, 0, s, J); break;
-        case 8: hipLaunchKernelGGL(k_blend<8>, grid, block, 0, s, J); break;
-        case 16: hipLaunchKernelGGL(k_blend<16>, grid, block, 0, s, J); break;
-        case 32: hipLaunchKernelGGL(k_blend<32>, grid, block, 0, s, J); break;
-        default: hipLaunchKernelGGL(k_blend<64>, grid, block, 0, s, J); break;
+        case 1: hipLaunchKernelGGL(k_blend<1>, grid, block, 0, s, J, ARGS); break;
+        case 2: hipLaunchKernelGGL(k_blend<2>, grid, block, 0, s, J, ARGS); break;
+        case 4: hipLaunchKernelGGL(k_blend<4>, grid, block, 0, s, J, ARGS); break;
+        case 8: hipLaunchKernelGGL(k_blend<8>, grid, block, 0, s, J, ARGS); break;
+        case 16: hipLaunchKernelGGL(k_blend<16>, grid, block, 0, s, J, ARGS); break;
+        case 32: hipLaunchKernelGGL(k_blend<32>, grid, block, 0, s, J, ARGS); break;
+        default: hipLaunchKernelGGL(k_blend<64>, grid, block, 0, s, J, ARGS); break;
     }
+#undef ARGS
     return GS_OK;
 }
 

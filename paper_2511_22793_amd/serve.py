@@ -145,7 +145,7 @@ class Batch:
 
 
 TILE_SHAPES = {256: ((16, 16), (8, 32), (32, 8)), 128: ((8, 16), (16, 8)), 64: ((8, 8),)}
-CHAN_GROUPS = (4, 8, 16, 32)
+CHAN_GROUPS = (8, 16, 32)
 
 
 def _time(fn, reps: int) -> float:
@@ -195,7 +195,7 @@ class Autotuner:
             return self.cache[key]
         probe = job.head(self.probe)
         fc = job.F * (2 if job.is_complex else 1)
-        groups = [c for c in CHAN_GROUPS if fc % c == 0] or [1]
+        groups = [c for c in CHAN_GROUPS if fc % c == 0] or [fc & -fc if fc & -fc <= 32 else 32]
         res = {}
         for block, shapes in TILE_SHAPES.items():
             best = None
