@@ -58,6 +58,11 @@ __device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
     reduce_scatter_step<V, 32>(x, lane);
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Entries per matrix-core step of the attribute gradient (MFMA path).
+constexpr int BWD_SUB = 16;
+
 template <int CG>
 __global__ __launch_bounds__(256) void k_blend_bwd(
     const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
@@ -66,6 +71,12 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     const float* __restrict__ out, const float* __restrict__ dout, const uint32_t* __restrict__ n_last, size_t s_pix,
     float* __restrict__ gacc, size_t s_gacc, float* __restrict__ d_attr, int64_t da_stride, int shared_geo)
 {
+    // CG >= 16: the attribute gradient of a run of BWD_SUB entries,
+    // dA[e][f] = sum_p w[p][e] g[p][f], is a 16 x CG x 64 product per wave
+    // on the FP32 matrix cores (v_mfma_f32_16x16x4_f32); w goes through LDS.
+    // Smaller groups reduce over the wave with the butterfly.
+    constexpr bool MFMA = CG >= 16;
+    constexpr int NB = MFMA ? CG / 16 : 1;
     const int tile = blockIdx.x, cg = blockIdx.y, set = blockIdx.z;
     const int q = shared_geo ? 0 : set;
     const int nthr = tw * th;
@@ -73,7 +84,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
     const int col = txi * tw + lx, row = tyi * th + ly;
     const bool inside = col < W && row < H;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint2 rg = ranges[q * s_ranges + tile];
     const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * W;
     rec += q * s_rec;
@@ -97,12 +108,33 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     }
     const uint32_t stop = inside ? n_last[q * s_pix + pix] : 0u;
 
+    // MFMA B operands: for K-step s the lane holds g of pixel 4s + lane/16 of
+    // its wave, channel nb*16 + lane%16
+    float gB[MFMA ? 16 : 1][NB];
+    if constexpr (MFMA) {
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int t = wave * 64 + 4 * st + (lane >> 4);
+            const int pc = txi * tw + t % tw, pr = tyi * th + t / tw;
+            const bool in = t < nthr && pc < W && pr < H;
+            const size_t pp = in ? (size_t)pr * W + pc : 0;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int ch = cg * CG + nb * 16 + (lane & 15);
+                const int f = ch / C, comp = ch - f * C;
+                gB[st][nb] = in ? dout[(((size_t)set * F + f) * HW + pp) * C + comp] : 0.0f;
+            }
+        }
+    }
+
     __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
     __shared__ float s_sig[256], s_att[256];
     __shared__ uint32_t s_g[256];
     // per-entry sums over the workgroup's pixels, flushed once per batch
     __shared__ float s_ad[256][CG];
     __shared__ float s_geo[256][8];
+    // per-wave pixel weights of the current run of entries (row padded)
+    __shared__ float s_w[MFMA ? 4 : 1][MFMA ? BWD_SUB : 1][65];
 
     float T = 1.0f, P = 0.0f;
     // the walk of this workgroup ends at the largest stop position of its pixels
@@ -133,56 +165,95 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
         for (int e = threadIdx.x; e < 256 * 8; e += nthr) s_geo[e / 8][e % 8] = 0.0f;
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, end - b0);
-        for (int j = 0; j < m; ++j) {
-            const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
-            const float* vp = A + (size_t)g * Fc;
-            float v[CG];
+        for (int j0 = 0; j0 < m; j0 += (MFMA ? BWD_SUB : m)) {
+            const int jn = MFMA ? min(BWD_SUB, m - j0) : m;
+            for (int jj = 0; jj < (MFMA ? BWD_SUB : jn); ++jj) {
+                const int j = j0 + jj;
+                float w = 0.0f;
+                if (jj < jn) {
+                    const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
+                    const float* vp = A + (size_t)g * Fc;
+                    float v[CG];
 #pragma unroll
-            for (int k = 0; k < CG; ++k) v[k] = vp[k];
-            double dx = pcx - s_px[j];
-            dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
-            const double dy = pcy - s_py[j];
-            const double ca = s_ca[j], cb = s_cb[j], cc = s_cc[j];
-            const double qv = ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy;
-            const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E_B * qv));
-            const float sig = s_sig[j], att = s_att[j];
-            const float sg = sig * G;
-            const float alpha = fminf(amax, sg);
-            const bool take = (b0 + j - rg.x) < stop && alpha >= amin;
-            if (__ballot(take) == 0ull) continue;  // wave-uniform skip
-            float gv = 0.0f;
+                    for (int k = 0; k < CG; ++k) v[k] = vp[k];
+                    double dx = pcx - s_px[j];
+                    dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
+                    const double dy = pcy - s_py[j];
+                    const double ca = s_ca[j], cb = s_cb[j], cc = s_cc[j];
+                    const double qv = ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy;
+                    const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E_B * qv));
+                    const float sig = s_sig[j], att = s_att[j];
+                    const float sg = sig * G;
+                    const float alpha = fminf(amax, sg);
+                    const bool take = (b0 + j - rg.x) < stop && alpha >= amin;
+                    if (__ballot(take) != 0ull) {  // else the whole wave skips the entry
+                        float gv = 0.0f;
 #pragma unroll
-            for (int k = 0; k < CG; ++k) gv = fmaf(gch[k], v[k], gv);
-            const float cA = att * gv;
-            const float Ta = T * alpha;
-            const float Pn = P + Ta * cA;
-            const float dalpha = T * cA - (D - Pn) / (1.0f - alpha);
-            const float dsg = sg < amax ? dalpha : 0.0f;  // clamp passes nothing
-            const float dq = -0.5f * dsg * sig * G;
-            float red[CG];
-            const float w = take ? Ta * att : 0.0f;
+                        for (int k = 0; k < CG; ++k) gv = fmaf(gch[k], v[k], gv);
+                        const float cA = att * gv;
+                        const float Ta = T * alpha;
+                        const float Pn = P + Ta * cA;
+                        const float dalpha = T * cA - (D - Pn) / (1.0f - alpha);
+                        const float dsg = sg < amax ? dalpha : 0.0f;  // clamp passes nothing
+                        const float dq = -0.5f * dsg * sig * G;
+                        w = take ? Ta * att : 0.0f;
+                        float geo[8];
+                        if (take) {
+                            geo[0] = dq * (float)(-2.0 * (ca * dx + cb * dy));  // d/dpx
+                            geo[1] = dq * (float)(-2.0 * (cb * dx + cc * dy));  // d/dpy
+                            geo[2] = dq * (float)(dx * dx);                     // d/dA
+                            geo[3] = dq * (float)(2.0 * dx * dy);               // d/dB
+                            geo[4] = dq * (float)(dy * dy);                     // d/dC
+                            geo[5] = dsg * G;                                   // d/dsigma
+                            geo[6] = Ta * gv;                                   // d/da
+                            geo[7] = 0.0f;
+                            T = T * (1.0f - alpha);
+                            P = Pn;
+                        } else {
 #pragma unroll
-            for (int k = 0; k < CG; ++k) red[k] = w * gch[k];
-            float geo[8];
-            if (take) {
-                geo[0] = dq * (float)(-2.0 * (ca * dx + cb * dy));  // d/dpx
-                geo[1] = dq * (float)(-2.0 * (cb * dx + cc * dy));  // d/dpy
-                geo[2] = dq * (float)(dx * dx);                     // d/dA
-                geo[3] = dq * (float)(2.0 * dx * dy);               // d/dB
-                geo[4] = dq * (float)(dy * dy);                     // d/dC
-                geo[5] = dsg * G;                                   // d/dsigma
-                geo[6] = Ta * gv;                                   // d/da
-                geo[7] = 0.0f;
-                T = T * (1.0f - alpha);
-                P = Pn;
-            } else {
+                            for (int k = 0; k < 8; ++k) geo[k] = 0.0f;
+                        }
+                        wave_reduce_scatter<8>(geo, lane);
+                        if ((lane & 7) == 0) atomicAdd(&s_geo[j][lane >> 3], geo[0]);
+                        if constexpr (!MFMA) {
+                            float red[CG];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) geo[k] = 0.0f;
+                            for (int k = 0; k < CG; ++k) red[k] = w * gch[k];
+                            wave_reduce_scatter<CG>(red, lane);
+                            if ((lane & ((1 << shA) - 1)) == 0) atomicAdd(&s_ad[j][lane >> shA], red[0]);
+                        }
+                    }
+                }
+                if constexpr (MFMA) s_w[wave][jj][lane] = w;
             }
-            wave_reduce_scatter<CG>(red, lane);
-            wave_reduce_scatter<8>(geo, lane);
-            if ((lane & ((1 << shA) - 1)) == 0) atomicAdd(&s_ad[j][lane >> shA], red[0]);
-            if ((lane & 7) == 0) atomicAdd(&s_geo[j][lane >> 3], geo[0]);
+            if constexpr (MFMA) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                f32x4 acc[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    const float a = s_w[wave][lane & 15][4 * st + (lane >> 4)];
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gB[st][nb], acc[nb], 0, 0, 0);
+                }
+                // lane holds entries 4*(lane/16) + r, channel nb*16 + lane%16
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = 4 * (lane >> 4) + r;
+                    if (e < jn) {
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            if (acc[nb][r] != 0.0f) atomicAdd(&s_ad[j0 + e][nb * 16 + (lane & 15)], acc[nb][r]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
         __syncthreads();
         // flush: attribute gradients (one atomic per entry and channel per

@@ -13,21 +13,46 @@
 
 namespace gs {
 
+// One (set, channel) slice is HW*C contiguous floats; with C = 2 the even
+// positions are real parts and the odd ones imaginary parts.  Slices whose
+// length is a multiple of 4 (and 16-byte aligned spectra) are streamed as
+// float4, so that component c of element x, y, z, w is 0, 1, 0, 1 (C = 2) or
+// always 0 (C = 1).
 // acc layout per set: [Fc][3] = (sum zhat, sum z, sum (zhat - z)^2)
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_loss_reduce(const float* __restrict__ zhat, const float* __restrict__ z,
                                                      int Fc, int C, size_t HW, float* __restrict__ acc)
 {
     const int b = blockIdx.z, f = blockIdx.y;  // f indexes complex channels (F)
     const size_t F = Fc / C;
-    const size_t base = ((size_t)b * F + f) * HW * C;
+    const size_t n = HW * C, base = ((size_t)b * F + f) * n;
     float s[2] = {0, 0}, t[2] = {0, 0}, e = 0.0f;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < HW; i += (size_t)gridDim.x * 256) {
-        for (int c = 0; c < C; ++c) {
-            const float a = zhat[base + i * C + c], y = z[base + i * C + c];
-            s[c] += a;
-            t[c] += y;
-            e += (a - y) * (a - y);
+    const size_t nv = VEC ? n / 4 : 0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    if (VEC) {
+        const float4* a4 = (const float4*)(zhat + base);
+        const float4* y4 = (const float4*)(z + base);
+        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
+            const float4 a = a4[i], y = y4[i];
+            s[0] += a.x + a.z;
+            s[1] += a.y + a.w;
+            t[0] += y.x + y.z;
+            t[1] += y.y + y.w;
+            const float d0 = a.x - y.x, d1 = a.y - y.y, d2 = a.z - y.z, d3 = a.w - y.w;
+            e += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
         }
+        if (C == 1) {
+            s[0] += s[1];
+            t[0] += t[1];
+            s[1] = t[1] = 0.0f;
+        }
+    }
+    for (size_t k = nv * 4 + (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) {
+        const float a = zhat[base + k], y = z[base + k];
+        const int c = (int)(k % C);
+        s[c] += a;
+        t[c] += y;
+        e += (a - y) * (a - y);
     }
     __shared__ float red[5][4];
     float vals[5] = {s[0], s[1], t[0], t[1], e};
@@ -48,6 +73,7 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const float* __restrict__ z
     }
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ zhat, const float* __restrict__ z,
                                                    int B, int Fc, int C, size_t HW, float lambda,
                                                    const float* __restrict__ acc, float* __restrict__ dz,
@@ -55,17 +81,27 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ zha
 {
     const int b = blockIdx.z, f = blockIdx.y;
     const size_t F = Fc / C;
-    const size_t base = ((size_t)b * F + f) * HW * C;
+    const size_t n = HW * C, base = ((size_t)b * F + f) * n;
     const float* a = acc + ((size_t)b * Fc + (size_t)f * C) * 3;
     const float inv_hw = 1.0f / (float)HW;
     const float k1 = 2.0f / ((float)F * (float)HW * (float)B);
-    float gmean[2];
+    float gmean[2] = {0.0f, 0.0f};
     for (int c = 0; c < C; ++c) gmean[c] = lambda * 2.0f * (a[c * 3] - a[c * 3 + 1]) * inv_hw * inv_hw / (float)B;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < HW; i += (size_t)gridDim.x * 256)
-        for (int c = 0; c < C; ++c) {
-            const size_t k = base + i * C + c;
-            dz[k] = k1 * (zhat[k] - z[k]) + gmean[c];
+    const float g1 = C == 2 ? gmean[1] : gmean[0];
+    const size_t nv = VEC ? n / 4 : 0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    if (VEC) {
+        const float4* a4 = (const float4*)(zhat + base);
+        const float4* y4 = (const float4*)(z + base);
+        float4* d4 = (float4*)(dz + base);
+        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
+            const float4 x = a4[i], y = y4[i];
+            d4[i] = make_float4(k1 * (x.x - y.x) + gmean[0], k1 * (x.y - y.y) + g1, k1 * (x.z - y.z) + gmean[0],
+                                k1 * (x.w - y.w) + g1);
         }
+    }
+    for (size_t k = nv * 4 + (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride)
+        dz[base + k] = k1 * (zhat[base + k] - z[base + k]) + gmean[k % C];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         float Lf = a[2] / ((float)F * (float)HW);
         for (int c = 0; c < C; ++c) {
@@ -99,11 +135,19 @@ extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target
     const size_t HW = (size_t)H * W;
     launch_fill_u32((uint32_t*)scratch, (size_t)n_sets * Fc * 3, 0, 1, 0u, s);
     launch_fill_u32((uint32_t*)loss, (size_t)n_sets, 0, 1, 0u, s);
-    const unsigned gx = (unsigned)((HW + 255) / 256 < 64 ? (HW + 255) / 256 : 64);
+    const bool vec = (HW * C) % 4 == 0 && (((uintptr_t)spectrum | (uintptr_t)target | (uintptr_t)d_spectrum) & 15) == 0;
+    const size_t per = vec ? HW * C / 4 : HW * C;  // items of one slice
+    const unsigned gx = (unsigned)((per + 255) / 256 < 32 ? (per + 255) / 256 : 32);
     dim3 grid(gx, n_chan, n_sets);
-    hipLaunchKernelGGL(k_loss_reduce, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
-    hipLaunchKernelGGL(k_loss_grad, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW, lambda_ch,
-                       (const float*)scratch, d_spectrum, h_hat, loss);
+    if (vec) {
+        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+        hipLaunchKernelGGL(k_loss_grad<true>, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW, lambda_ch,
+                           (const float*)scratch, d_spectrum, h_hat, loss);
+    } else {
+        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+        hipLaunchKernelGGL(k_loss_grad<false>, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW,
+                           lambda_ch, (const float*)scratch, d_spectrum, h_hat, loss);
+    }
     if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
     return GS_OK;
 }

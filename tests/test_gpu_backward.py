@@ -153,9 +153,11 @@ def test_autograd_function_matches_direct_backward():
     compare(a.grad.cpu().numpy(), ref["attr"], "attr")
 
 
-@pytest.mark.parametrize("cplx,lam", [(True, 1.0), (False, 0.5)])
-def test_loss_kernel_matches_definition(cplx, lam):
-    B, F, H, W = 3, 4, 90, 360
+@pytest.mark.parametrize("cplx,lam,H,W", [(True, 1.0, 90, 360), (False, 0.5, 90, 360), (True, 1.0, 7, 9),
+                                           (False, 0.5, 7, 9), (True, 0.5, 5, 6)])
+def test_loss_kernel_matches_definition(cplx, lam, H, W):
+    # 90x360 streams float4; 7x9 slices are not a multiple of 4 floats (scalar path)
+    B, F = 3, 4
     rng = np.random.default_rng(15)
     shape = (B, F, H, W, 2) if cplx else (B, F, H, W)
     zh = rng.normal(size=shape).astype(np.float32)
@@ -169,7 +171,9 @@ def test_loss_kernel_matches_definition(cplx, lam):
     assert np.allclose(hh.cpu().numpy(), hmean, atol=1e-6)
     # gradient of mean_b L_b by its definition
     gdef = (2 * (zh64 - z64) / (F * H * W) + lam * 2 * (hmean - tmean)[:, :, None, None] / (H * W)) / B
-    assert np.allclose(d.cpu().numpy(), gdef, rtol=1e-4, atol=1e-12)
+    # the two FP32 terms can cancel: absolute tolerance scaled by the terms
+    terms = np.abs(2 * (zh64 - z64) / (F * H * W) / B).max() + np.abs(lam * 2 * (hmean - tmean) / (H * W) / B).max()
+    assert np.allclose(d.cpu().numpy(), gdef, rtol=1e-4, atol=1e-6 * terms)
 
 
 @pytest.mark.slow
