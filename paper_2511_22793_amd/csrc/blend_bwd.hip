@@ -27,6 +27,9 @@ namespace gs {
 
 constexpr double LOG2E_B = 1.4426950408889634;
 
+// read-only attribute rows through the scalar/constant path where uniform
+typedef __attribute__((address_space(4))) const float CFloatB;
+
 // Butterfly reduce-scatter of V values over the 64 lanes of a wave.  On
 // return x[0] of lane l holds the wave total of value (l >> (6 - log2 V)).
 // Each stage exchanges half of the remaining values with the lane at xor
@@ -58,13 +61,55 @@ __device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
     reduce_scatter_step<V, 32>(x, lane);
 }
 
+// The same reduce-scatter for 8 values without the LDS crossbar: lane
+// halves and quarter rows are exchanged with v_permlane32_swap /
+// v_permlane16_swap (each swap also moves the partner's half, so one add
+// completes a stage), the xor-8 stage and the final sum over 8 lanes use
+// DPP row rotations and quad permutations.  Lane l ends with the wave
+// total of value l >> 3 in x[0].
+__device__ __forceinline__ float dpp_f(float v, int ctrl_sel)
+{
+    const int iv = __float_as_int(v);
+    int r;
+    switch (ctrl_sel) {
+        case 0: r = __builtin_amdgcn_update_dpp(iv, iv, 0x128, 0xF, 0xF, false); break;  // row_ror:8
+        case 1: r = __builtin_amdgcn_update_dpp(iv, iv, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+        case 2: r = __builtin_amdgcn_update_dpp(iv, iv, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+        default: r = __builtin_amdgcn_update_dpp(iv, iv, 0x141, 0xF, 0xF, false); break; // row_half_mirror
+    }
+    return __int_as_float(r);
+}
+
+__device__ __forceinline__ void wave_reduce_scatter8(float* x, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i + 4]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[i + 2]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const float t0 = x[0] + dpp_f(x[0], 0), t1 = x[1] + dpp_f(x[1], 0);
+    float v = (lane & 8) ? t1 : t0;
+    v += dpp_f(v, 1);
+    v += dpp_f(v, 2);
+    v += dpp_f(v, 3);
+    x[0] = v;
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Entries per matrix-core step of the attribute gradient (MFMA path).
+// Entries per matrix-core step of the attribute gradient (MFMA path), and
+// entries staged in LDS per batch (a small batch keeps the LDS footprint,
+// and so the occupancy, reasonable).
 constexpr int BWD_SUB = 16;
+constexpr int BWD_BATCH = 64;
 
 template <int CG>
-__global__ __launch_bounds__(256) void k_blend_bwd(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_bwd(
     const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
     const uint2* __restrict__ ranges, size_t s_ranges, const float* __restrict__ attr, int64_t a_stride,
     int Fc, int C, int H, int W, int tw, int th, int TX, float amin, float amax,
@@ -108,10 +153,28 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     }
     const uint32_t stop = inside ? n_last[q * s_pix + pix] : 0u;
 
-    // MFMA B operands: for K-step s the lane holds g of pixel 4s + lane/16 of
-    // its wave, channel nb*16 + lane%16
+    // MFMA operands held for the whole kernel:
+    //  gB (attribute gradient, B = g[pixel][channel]): for K-step s the lane
+    //    holds g of pixel 4s + lane/16 of its wave, channel nb*16 + lane%16;
+    //  gT (gv = v . g per entry and pixel, B = g^T[channel][pixel]): for
+    //    K-step k and pixel block pb the lane holds g of pixel 16 pb + lane%16,
+    //    channel 4k + lane/16.
     float gB[MFMA ? 16 : 1][NB];
+    float gT[MFMA ? 4 : 1][MFMA ? CG / 4 : 1];
     if constexpr (MFMA) {
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            const int t = wave * 64 + 16 * pb + (lane & 15);
+            const int pc = txi * tw + t % tw, pr = tyi * th + t / tw;
+            const bool in = t < nthr && pc < W && pr < H;
+            const size_t pp = in ? (size_t)pr * W + pc : 0;
+#pragma unroll
+            for (int k = 0; k < CG / 4; ++k) {
+                const int ch = cg * CG + 4 * k + (lane >> 4);
+                const int f = ch / C, comp = ch - f * C;
+                gT[pb][k] = in ? dout[(((size_t)set * F + f) * HW + pp) * C + comp] : 0.0f;
+            }
+        }
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
             const int t = wave * 64 + 4 * st + (lane >> 4);
@@ -127,13 +190,14 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
         }
     }
 
-    __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
-    __shared__ float s_sig[256], s_att[256];
-    __shared__ uint32_t s_g[256];
+    __shared__ double s_px[BWD_BATCH], s_py[BWD_BATCH], s_ca[BWD_BATCH], s_cb[BWD_BATCH], s_cc[BWD_BATCH];
+    __shared__ float s_sig[BWD_BATCH], s_att[BWD_BATCH];
+    __shared__ uint32_t s_g[BWD_BATCH];
     // per-entry sums over the workgroup's pixels, flushed once per batch
-    __shared__ float s_ad[256][CG];
-    __shared__ float s_geo[256][8];
-    // per-wave pixel weights of the current run of entries (row padded)
+    __shared__ float s_ad[BWD_BATCH][CG];
+    __shared__ float s_geo[BWD_BATCH][8];
+    // per wave, for the current run of entries: gv = v . g from the matrix
+    // cores, replaced entry by entry by the pixel weight w (rows padded)
     __shared__ float s_w[MFMA ? 4 : 1][MFMA ? BWD_SUB : 1][65];
 
     float T = 1.0f, P = 0.0f;
@@ -144,12 +208,17 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     if (stop) atomicMax(&s_maxstop, stop);
     __syncthreads();
     const uint32_t end = rg.x + s_maxstop;
+    // a wave stops walking at the largest stop position of its own pixels
+    uint32_t wstop = stop;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wstop = max(wstop, (uint32_t)__shfl_xor((int)wstop, o, 64));
+    const uint32_t wend = rg.x + wstop;
     constexpr int shA = CG >= 64 ? 0 : (CG == 32 ? 1 : (CG == 16 ? 2 : (CG == 8 ? 3 : (CG == 4 ? 4 : (CG == 2 ? 5 : 6)))));
 
-    for (uint32_t b0 = rg.x; b0 < end; b0 += nthr) {
+    for (uint32_t b0 = rg.x; b0 < end; b0 += BWD_BATCH) {
         __syncthreads();
         const uint32_t i = b0 + threadIdx.x;
-        if (i < end) {
+        if (threadIdx.x < BWD_BATCH && i < end) {
             const uint32_t g = plist[i];
             const GRec r = rec[g];
             s_px[threadIdx.x] = r.px;
@@ -161,21 +230,43 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
             s_att[threadIdx.x] = r.att;
             s_g[threadIdx.x] = g;
         }
-        for (int e = threadIdx.x; e < 256 * CG; e += nthr) s_ad[e / CG][e % CG] = 0.0f;
-        for (int e = threadIdx.x; e < 256 * 8; e += nthr) s_geo[e / 8][e % 8] = 0.0f;
+        for (int e = threadIdx.x; e < BWD_BATCH * CG; e += nthr) s_ad[e / CG][e % CG] = 0.0f;
+        for (int e = threadIdx.x; e < BWD_BATCH * 8; e += nthr) s_geo[e / 8][e % 8] = 0.0f;
         __syncthreads();
-        const int m = (int)min((uint32_t)nthr, end - b0);
+        const int m = (int)min((uint32_t)BWD_BATCH, end - b0);
         for (int j0 = 0; j0 < m; j0 += (MFMA ? BWD_SUB : m)) {
+            if (b0 + j0 >= wend) break;  // wave-uniform: nothing left for this wave
             const int jn = MFMA ? min(BWD_SUB, m - j0) : m;
+            if constexpr (MFMA) {
+                // gv[e][p] = sum_f v[e][f] g[p][f]: A = v rows of the run
+                // (lane: entry lane%16, channel 4k + lane/16), B = gT
+                const int e = lane & 15;
+                const bool ev = e < jn;
+                const CFloatB* vr = (const CFloatB*)(A + (size_t)(ev ? s_g[j0 + e] : 0u) * Fc) + (lane >> 4);
+                float va[CG / 4];
+#pragma unroll
+                for (int k = 0; k < CG / 4; ++k) va[k] = ev ? vr[4 * k] : 0.0f;
+                f32x4 gv4[4];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) {
+                    gv4[pb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int k = 0; k < CG / 4; ++k)
+                        gv4[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(va[k], gT[pb][k], gv4[pb], 0, 0, 0);
+                }
+                // lane holds entries 4*(lane/16) + r of pixel 16 pb + lane%16
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) s_w[wave][4 * (lane >> 4) + r][16 * pb + (lane & 15)] = gv4[pb][r];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
             for (int jj = 0; jj < (MFMA ? BWD_SUB : jn); ++jj) {
                 const int j = j0 + jj;
                 float w = 0.0f;
-                if (jj < jn) {
-                    const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
-                    const float* vp = A + (size_t)g * Fc;
-                    float v[CG];
-#pragma unroll
-                    for (int k = 0; k < CG; ++k) v[k] = vp[k];
+                if (jj < jn && b0 + j < wend) {
                     double dx = pcx - s_px[j];
                     dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
                     const double dy = pcy - s_py[j];
@@ -188,12 +279,19 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
                     const bool take = (b0 + j - rg.x) < stop && alpha >= amin;
                     if (__ballot(take) != 0ull) {  // else the whole wave skips the entry
                         float gv = 0.0f;
+                        if constexpr (MFMA) {
+                            gv = s_w[wave][jj][lane];
+                        } else {
+                            const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
+                            const float* vp = A + (size_t)g * Fc;
 #pragma unroll
-                        for (int k = 0; k < CG; ++k) gv = fmaf(gch[k], v[k], gv);
+                            for (int k = 0; k < CG; ++k) gv = fmaf(gch[k], vp[k], gv);
+                        }
                         const float cA = att * gv;
                         const float Ta = T * alpha;
                         const float Pn = P + Ta * cA;
-                        const float dalpha = T * cA - (D - Pn) / (1.0f - alpha);
+                        // alpha <= alpha_max < 1; a one-ulp reciprocal is ample here
+                        const float dalpha = T * cA - (D - Pn) * __builtin_amdgcn_rcpf(1.0f - alpha);
                         const float dsg = sg < amax ? dalpha : 0.0f;  // clamp passes nothing
                         const float dq = -0.5f * dsg * sig * G;
                         w = take ? Ta * att : 0.0f;
@@ -213,7 +311,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
 #pragma unroll
                             for (int k = 0; k < 8; ++k) geo[k] = 0.0f;
                         }
-                        wave_reduce_scatter<8>(geo, lane);
+                        wave_reduce_scatter8(geo, lane);
                         if ((lane & 7) == 0) atomicAdd(&s_geo[j][lane >> 3], geo[0]);
                         if constexpr (!MFMA) {
                             float red[CG];
