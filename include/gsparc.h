@@ -203,6 +203,25 @@ gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const
                              size_t ws_bytes, void* stream);
 
 /*
+ * gs_render_backward() for the loss of gs_loss_spectrum() without reading a
+ * stored gradient: dL/dzhat = scale (zhat - z) + mean_grad[s][f*c + comp] is
+ * formed inside the kernel from the forward output and the target (for the
+ * loss of gs_loss_spectrum(), scale = 2 / (F H W n_sets) and mean_grad comes
+ * from gs_loss_spectrum_stats()), which saves a full pass over the spectra.
+ * lg is a host struct of device pointers; other arguments as above.
+ */
+typedef struct {
+    const float* target;    /* z, layout of the spectrum */
+    const float* mean_grad; /* [n_sets][F*c] */
+    float scale;
+} gs_l2_grad;
+gs_status gs_render_backward_l2(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
+                                int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
+                                const gs_l2_grad* lg, float* d_mean, float* d_log_scale, float* d_quat,
+                                float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace,
+                                size_t ws_bytes, void* stream);
+
+/*
  * Live set of a prepared workspace: walks every pixel's list without
  * attributes (alpha and transmittance only, the discrete decisions of
  * Eq. (3)) and lists, per query, the Gaussians that reach at least one pixel
@@ -228,6 +247,16 @@ gs_status gs_render_live(int32_t n, int32_t n_queries, const gs_grid* grid, cons
 gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
                            int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
                            float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes, void* stream);
+
+/*
+ * The loss of gs_loss_spectrum() without the elementwise gradient, for
+ * gs_render_backward_l2(): writes loss [n_sets], h_hat [n_sets][F][c] and
+ * mean_grad [n_sets][F*c] = lambda_ch 2 (h^ - h) / (H W) / n_sets, the
+ * channel-mean part of dL/dzhat (same arguments and scratch otherwise).
+ */
+gs_status gs_loss_spectrum_stats(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                                 int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
+                                 float* h_hat, float* mean_grad, void* scratch, size_t scratch_bytes, void* stream);
 
 /* ---- attribute network (shared form of the emission predictor, Eq. (1)) ----
  * Per (set s, Gaussian g):  h1 = relu(W1 [e_g, gamma(tx_s), 0] + b1),

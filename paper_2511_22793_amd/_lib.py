@@ -73,6 +73,10 @@ class GsAdamSegment(ctypes.Structure):
     _fields_ = [("p", c_p), ("g", c_p), ("m", c_p), ("v", c_p), ("shadow", c_p), ("count", c_i64), ("lr", c_f32)]
 
 
+class GsL2Grad(ctypes.Structure):
+    _fields_ = [("target", c_p), ("mean_grad", c_p), ("scale", c_f32)]
+
+
 class GsBatchJob(ctypes.Structure):
     _fields_ = [("scene", GsScene), ("attrs", GsAttrs), ("queries", GsQueries), ("grid", GsGrid),
                 ("params", GsParams), ("spectrum", c_p), ("workspace", c_p), ("workspace_bytes", c_sz)]
@@ -110,6 +114,11 @@ SIGNATURES = {
     "gs_render_backward": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
                                    c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p, c_p, c_p,
                                    c_p, c_p, c_p, c_i32, c_p, c_sz, c_p]),
+    "gs_render_backward_l2": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
+                                      c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p,
+                                      ctypes.POINTER(GsL2Grad), c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz, c_p]),
+    "gs_loss_spectrum_stats": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
+                                       c_p]),
     "gs_render_live": (c_i32, [c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_sz, c_p,
                                c_i64, c_p, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,

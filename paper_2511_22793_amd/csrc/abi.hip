@@ -280,13 +280,13 @@ gs_status gs_render_live(int32_t n, int32_t n_queries, const gs_grid* grid, cons
     return GS_OK;
 }
 
-gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
-                             int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
-                             const float* d_spectrum, float* d_mean, float* d_log_scale, float* d_quat,
-                             float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace, size_t ws_bytes,
-                             void* stream)
+static gs_status render_backward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
+                                 int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
+                                 const BwdUpstream& up, float* d_mean, float* d_log_scale, float* d_quat,
+                                 float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace,
+                                 size_t ws_bytes, void* stream)
 {
-    if (!d_spectrum || !d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !d_attr) return GS_ERR_INVALID_ARG;
+    if (!d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !d_attr) return GS_ERR_INVALID_ARG;
     if (prm && (prm->options & GS_OPT_FORWARD_ONLY)) return GS_ERR_INVALID_ARG;
     Layout L;
     gs_status st = check_forward(scene, attrs, queries, grid, prm, spectrum, workspace, ws_bytes, &L);
@@ -303,11 +303,35 @@ gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const
     launch_fill_dev((uint32_t*)(ws + L.gacc), (size_t)L.cap * 8, L.s_gacc / 4, L.nq,
                     (const uint32_t*)(ws + L.flags) + FL_PUSED, L.s_flags / 4, 8u, s);
     if (!(flags & GS_BWD_ATTR_GRAD_ZEROED)) launch_fill_u32((uint32_t*)d_attr, na, 0, 1, 0u, s);
-    st = launch_blend_bwd(*attrs, *prm, L, n_sets, ws, spectrum, d_spectrum, d_attr, s);
+    st = launch_blend_bwd(*attrs, *prm, L, n_sets, ws, spectrum, up, d_attr, s);
     if (st != GS_OK) return st;
     launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);
     GS_CHECK_LAUNCH();
     return GS_OK;
+}
+
+gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
+                             int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
+                             const float* d_spectrum, float* d_mean, float* d_log_scale, float* d_quat,
+                             float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace, size_t ws_bytes,
+                             void* stream)
+{
+    if (!d_spectrum) return GS_ERR_INVALID_ARG;
+    const BwdUpstream up{d_spectrum, nullptr, nullptr, 0.0f};
+    return render_backward(scene, attrs, queries, n_sets, grid, prm, spectrum, up, d_mean, d_log_scale, d_quat,
+                           d_opacity_logit, d_attr, flags, workspace, ws_bytes, stream);
+}
+
+gs_status gs_render_backward_l2(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries,
+                                int32_t n_sets, const gs_grid* grid, const gs_params* prm, const float* spectrum,
+                                const gs_l2_grad* lg, float* d_mean, float* d_log_scale, float* d_quat,
+                                float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace,
+                                size_t ws_bytes, void* stream)
+{
+    if (!lg || !lg->target || !lg->mean_grad || !(lg->scale == lg->scale)) return GS_ERR_INVALID_ARG;
+    const BwdUpstream up{nullptr, lg->target, lg->mean_grad, lg->scale};
+    return render_backward(scene, attrs, queries, n_sets, grid, prm, spectrum, up, d_mean, d_log_scale, d_quat,
+                           d_opacity_logit, d_attr, flags, workspace, ws_bytes, stream);
 }
 
 gs_status gs_read_flags(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries, const gs_grid* grid,

@@ -113,9 +113,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
     const uint2* __restrict__ ranges, size_t s_ranges, const float* __restrict__ attr, int64_t a_stride,
     int Fc, int C, int H, int W, int tw, int th, int TX, float amin, float amax,
-    const float* __restrict__ out, const float* __restrict__ dout, const uint32_t* __restrict__ n_last, size_t s_pix,
+    const float* __restrict__ out, const float* __restrict__ dout, const float* __restrict__ tgt,
+    const float* __restrict__ mgrad, float gscale, const uint32_t* __restrict__ n_last, size_t s_pix,
     float* __restrict__ gacc, size_t s_gacc, float* __restrict__ d_attr, int64_t da_stride, int shared_geo)
 {
+    // dL/dout of the element at idx (channel component ch): read, or, for the
+    // spectrum L2 + channel-mean loss, formed from the output and the target
+    auto upstream = [&](size_t idx, int ch) -> float {
+        return tgt ? gscale * (out[idx] - tgt[idx]) + mgrad[(size_t)blockIdx.z * Fc + ch] : dout[idx];
+    };
     // CG >= 16: the attribute gradient of a run of BWD_SUB entries,
     // dA[e][f] = sum_p w[p][e] g[p][f], is a 16 x CG x 64 product per wave
     // on the FP32 matrix cores (v_mfma_f32_16x16x4_f32); w goes through LDS.
@@ -148,7 +154,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int ch = cg * CG + k;
         const int f = ch / C, comp = ch - f * C;
         const size_t idx = (((size_t)set * F + f) * HW + pix) * C + comp;
-        gch[k] = inside ? dout[idx] : 0.0f;
+        gch[k] = inside ? upstream(idx, ch) : 0.0f;
         D += inside ? gch[k] * out[idx] : 0.0f;
     }
     const uint32_t stop = inside ? n_last[q * s_pix + pix] : 0u;
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int k = 0; k < CG / 4; ++k) {
                 const int ch = cg * CG + 4 * k + (lane >> 4);
                 const int f = ch / C, comp = ch - f * C;
-                gT[pb][k] = in ? dout[(((size_t)set * F + f) * HW + pp) * C + comp] : 0.0f;
+                gT[pb][k] = in ? upstream((((size_t)set * F + f) * HW + pp) * C + comp, ch) : 0.0f;
             }
         }
 #pragma unroll
@@ -185,13 +191,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int nb = 0; nb < NB; ++nb) {
                 const int ch = cg * CG + nb * 16 + (lane & 15);
                 const int f = ch / C, comp = ch - f * C;
-                gB[st][nb] = in ? dout[(((size_t)set * F + f) * HW + pp) * C + comp] : 0.0f;
+                gB[st][nb] = in ? upstream((((size_t)set * F + f) * HW + pp) * C + comp, ch) : 0.0f;
             }
         }
     }
 
     __shared__ double s_px[BWD_BATCH], s_py[BWD_BATCH], s_ca[BWD_BATCH], s_cb[BWD_BATCH], s_cc[BWD_BATCH];
     __shared__ float s_sig[BWD_BATCH], s_att[BWD_BATCH];
+    __shared__ float s_caf[BWD_BATCH], s_cbf[BWD_BATCH], s_ccf[BWD_BATCH];
     __shared__ uint32_t s_g[BWD_BATCH];
     // per-entry sums over the workgroup's pixels, flushed once per batch
     __shared__ float s_ad[BWD_BATCH][CG];
@@ -226,6 +233,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             s_ca[threadIdx.x] = r.ca;
             s_cb[threadIdx.x] = r.cb;
             s_cc[threadIdx.x] = r.cc;
+            s_caf[threadIdx.x] = (float)r.ca;
+            s_cbf[threadIdx.x] = (float)r.cb;
+            s_ccf[threadIdx.x] = (float)r.cc;
             s_sig[threadIdx.x] = r.sigma;
             s_att[threadIdx.x] = r.att;
             s_g[threadIdx.x] = g;
@@ -297,11 +307,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         w = take ? Ta * att : 0.0f;
                         float geo[8];
                         if (take) {
-                            geo[0] = dq * (float)(-2.0 * (ca * dx + cb * dy));  // d/dpx
-                            geo[1] = dq * (float)(-2.0 * (cb * dx + cc * dy));  // d/dpy
-                            geo[2] = dq * (float)(dx * dx);                     // d/dA
-                            geo[3] = dq * (float)(2.0 * dx * dy);               // d/dB
-                            geo[4] = dq * (float)(dy * dy);                     // d/dC
+                            // gradient factors in FP32 from the exact offsets
+                            const float dxf = (float)dx, dyf = (float)dy;
+                            const float dq2 = -2.0f * dq;
+                            geo[0] = dq2 * fmaf(s_caf[j], dxf, s_cbf[j] * dyf);  // d/dpx
+                            geo[1] = dq2 * fmaf(s_cbf[j], dxf, s_ccf[j] * dyf);  // d/dpy
+                            geo[2] = dq * (dxf * dxf);                           // d/dA
+                            geo[3] = dq * (2.0f * dxf * dyf);                    // d/dB
+                            geo[4] = dq * (dyf * dyf);                           // d/dC
                             geo[5] = dsg * G;                                   // d/dsigma
                             geo[6] = Ta * gv;                                   // d/da
                             geo[7] = 0.0f;
@@ -390,17 +403,18 @@ __global__ __launch_bounds__(256) void k_geo_fold(float* __restrict__ gacc, size
 
 template <int CG>
 static void bwd_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, const gs_params& p, const Layout& L,
-                   char* ws, const float* out, const float* dout, float* d_attr, int64_t da_stride, int C, int shared)
+                   char* ws, const float* out, const BwdUpstream& up, float* d_attr, int64_t da_stride, int C, int shared)
 {
     hipLaunchKernelGGL(k_blend_bwd<CG>, grid, block, 0, s, (const GRec*)(ws + L.rec), L.s_rec / sizeof(GRec),
                        (const uint32_t*)(ws + L.plist), L.s_plist / 4, (const uint2*)(ws + L.ranges),
                        L.s_ranges / sizeof(uint2), a.data, a.query_stride, a.n_chan * C, C, L.H, L.W, L.tw, L.th,
-                       L.TX, p.alpha_min, p.alpha_max, out, dout, (const uint32_t*)(ws + L.n_last), L.s_pix / 4,
+                       L.TX, p.alpha_min, p.alpha_max, out, up.dout, up.target, up.mean_grad, up.scale,
+                       (const uint32_t*)(ws + L.n_last), L.s_pix / 4,
                        (float*)(ws + L.gacc), L.s_gacc / 4, d_attr, da_stride, shared);
 }
 
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
-                           const float* out, const float* dout, float* d_attr, hipStream_t s)
+                           const float* out, const BwdUpstream& up, float* d_attr, hipStream_t s)
 {
     const int C = a.is_complex ? 2 : 1;
     const int Fc = a.n_chan * C;
@@ -411,12 +425,12 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
     dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
     const int64_t das = a.query_stride;  // d_attr mirrors the attribute layout
     switch (cg) {
-        case 1: bwd_cg<1>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
-        case 2: bwd_cg<2>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
-        case 4: bwd_cg<4>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
-        case 8: bwd_cg<8>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
-        case 16: bwd_cg<16>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
-        default: bwd_cg<32>(grid, block, s, a, p, L, ws, out, dout, d_attr, das, C, shared); break;
+        case 1: bwd_cg<1>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
+        case 2: bwd_cg<2>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
+        case 4: bwd_cg<4>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
+        case 8: bwd_cg<8>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
+        case 16: bwd_cg<16>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
+        default: bwd_cg<32>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
     }
     const int64_t fb = (L.cap * 8 + 255) / 256;
     hipLaunchKernelGGL(k_geo_fold, dim3((unsigned)(fb < 2048 ? fb : 2048), L.nq), dim3(256), 0, s,

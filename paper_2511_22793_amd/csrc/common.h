@@ -99,8 +99,16 @@ void launch_blend_persist(const BlendJob* jobs, int njobs, uint32_t total, uint3
                           unsigned long long* done_ts, int workgroups, int block, hipStream_t s);
 void launch_stamp(unsigned long long* ts, hipStream_t s);
 hipError_t persist_occupancy(int block, int* per_cu);
+// Upstream gradient of the backward: dout, or (target, mean_grad, scale)
+// for the fused spectrum L2 + channel-mean loss.
+struct BwdUpstream {
+    const float* dout;
+    const float* target;
+    const float* mean_grad;
+    float scale;
+};
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
-                           const float* out, const float* dout, float* d_attr, hipStream_t s);
+                           const float* out, const BwdUpstream& up, float* d_attr, hipStream_t s);
 void launch_project_bwd(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,
                         const Layout& L, char* ws, float* d_mean, float* d_log_scale, float* d_quat, float* d_opac,
                         hipStream_t s);

@@ -113,9 +113,69 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ zha
     }
 }
 
+// Loss, spatial means and the channel-mean term of the gradient, without
+// the elementwise gradient: one workgroup per set, one thread per channel
+// component.  mean_grad[b][f*C + c] = lambda 2 (h^ - h) / (H W) / B.
+__global__ void k_loss_finish(int B, int Fc, int C, size_t HW, float lambda, const float* __restrict__ acc,
+                              float* __restrict__ hhat, float* __restrict__ loss, float* __restrict__ mgrad)
+{
+    const int b = blockIdx.x;
+    const float inv_hw = 1.0f / (float)HW;
+    const float F = (float)(Fc / C);
+    float Lpart = 0.0f;
+    for (int k = threadIdx.x; k < Fc; k += blockDim.x) {
+        const float* a = acc + ((size_t)b * Fc + (size_t)(k - k % C)) * 3;  // the channel's accumulators
+        const int c = k % C;
+        const float hd = (a[c * 3] - a[c * 3 + 1]) * inv_hw;
+        hhat[(size_t)b * Fc + k] = a[c * 3] * inv_hw;
+        mgrad[(size_t)b * Fc + k] = lambda * 2.0f * (a[c * 3] - a[c * 3 + 1]) * inv_hw * inv_hw / (float)B;
+        Lpart += lambda * hd * hd + (c == 0 ? a[2] / (F * (float)HW) : 0.0f);
+    }
+    for (int o = 32; o > 0; o >>= 1) Lpart += __shfl_xor(Lpart, o, 64);
+    __shared__ float red[16];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = Lpart;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += red[w];
+        loss[b] = t;
+    }
+}
+
 }  // namespace gs
 
 using namespace gs;
+
+extern "C" gs_status gs_loss_spectrum_stats(const float* spectrum, const float* target, int32_t n_sets,
+                                            int32_t n_chan, int32_t is_complex, int32_t H, int32_t W,
+                                            float lambda_ch, float* loss, float* h_hat, float* mean_grad,
+                                            void* scratch, size_t scratch_bytes, void* stream)
+{
+    if (!spectrum || !target || !loss || !h_hat || !mean_grad || n_sets < 1 || n_chan < 1 || H < 1 || W < 1 ||
+        (is_complex != 0 && is_complex != 1) || !(lambda_ch >= 0.0f))
+        return GS_ERR_INVALID_ARG;
+    if (n_chan > 65535 || n_sets > 65535) return GS_ERR_CAPACITY;
+    const int C = is_complex ? 2 : 1;
+    const int Fc = n_chan * C;
+    const size_t need = (size_t)n_sets * Fc * 3 * sizeof(float);
+    if (!scratch || scratch_bytes < need || ((uintptr_t)scratch & 255)) return GS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    const size_t HW = (size_t)H * W;
+    launch_fill_u32((uint32_t*)scratch, (size_t)n_sets * Fc * 3, 0, 1, 0u, s);
+    const bool vec = (HW * C) % 4 == 0 && (((uintptr_t)spectrum | (uintptr_t)target) & 15) == 0;
+    const size_t per = vec ? HW * C / 4 : HW * C;
+    const unsigned gx = (unsigned)((per + 255) / 256 < 32 ? (per + 255) / 256 : 32);
+    dim3 grid(gx, n_chan, n_sets);
+    if (vec)
+        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+    else
+        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+    hipLaunchKernelGGL(k_loss_finish, dim3(n_sets), dim3(256), 0, s, n_sets, Fc, C, HW, lambda_ch,
+                       (const float*)scratch, h_hat, loss, mean_grad);
+    if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
+    return GS_OK;
+}
 
 extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
                                       int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,

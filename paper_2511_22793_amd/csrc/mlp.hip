@@ -410,6 +410,9 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
         __syncthreads();
     }
     __syncthreads();
+    // only workgroups that had rows flush (the grid is sized for the largest
+    // row count; the others would add zeros into the same few addresses)
+    if (blockIdx.x * 64 >= (int)count) return;
     for (int k = threadIdx.x; k < 2 * MLP_F; k += 256) unsafeAtomicAdd(A.db3 + k, s_db3[k]);
     if (threadIdx.x < MLP_HID) {
         unsafeAtomicAdd(A.db2 + threadIdx.x, s_db2[threadIdx.x]);

@@ -16,7 +16,7 @@ from typing import Optional
 
 import torch
 
-from ._lib import GS_OPT_FORWARD_ONLY, GsAttrs, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
+from ._lib import GS_OPT_FORWARD_ONLY, GsAttrs, GsL2Grad, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
 
 DEFAULT_VIEW = (0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0)
 
@@ -242,6 +242,41 @@ def backward(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Te
     return g
 
 
+def backward_l2(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Tensor, spectrum: torch.Tensor,
+                target: torch.Tensor, mean_grad: torch.Tensor, scale: float, tx: Optional[torch.Tensor] = None,
+                is_complex: bool = False, n_sets: Optional[int] = None, d_attr: Optional[torch.Tensor] = None,
+                out: Optional[dict] = None) -> dict:
+    """backward() for dL/dspectrum = scale (spectrum - target) + mean_grad
+    (the loss of loss_stats()), formed inside the kernel."""
+    sc = _scene_c(scene)
+    n = sc.n
+    B = rx.shape[0]
+    per_set = attr.dim() == (4 if is_complex else 3)
+    S = n_sets if n_sets is not None else (attr.shape[0] if per_set else B)
+    a = _attrs_c(attr, n, S, is_complex)
+    _check_f32("spectrum", spectrum)
+    _check_f32("target", target, tuple(spectrum.shape))
+    _check_f32("mean_grad", mean_grad)
+    if mean_grad.numel() != S * a.n_chan * (2 if is_complex else 1):
+        raise ValueError("mean_grad must hold n_sets * F * c values")
+    dev = rx.device
+    g = out if out is not None else {
+        "d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+        "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+    flags = 1 if d_attr is not None else 0
+    g["d_attr"] = d_attr if d_attr is not None else torch.empty_like(attr)
+    q = GsQueries(B, _ptr(rx), _ptr(tx))
+    gr, p = workspace.grid.c(), workspace.params.c()
+    lg = GsL2Grad(_ptr(target), _ptr(mean_grad), float(scale))
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_render_backward_l2(ctypes.byref(sc), ctypes.byref(a), ctypes.byref(q), S, ctypes.byref(gr),
+                                      ctypes.byref(p), _ptr(spectrum), ctypes.byref(lg), _ptr(g["d_mean"]),
+                                      _ptr(g["d_log_scale"]), _ptr(g["d_quat"]), _ptr(g["d_opacity_logit"]),
+                                      _ptr(g["d_attr"]), flags, ctypes.c_void_p(workspace.ptr), workspace.nbytes,
+                                      ctypes.c_void_p(stream)), "gs_render_backward_l2")
+    return g
+
+
 def live(workspace: Workspace, lst: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None):
     """Gaussians reaching some pixel, per prepared query: (list [B, n] int32
     (valid prefix of length count[b]), count [B] int32 on the device)."""
@@ -279,3 +314,25 @@ def loss_spectrum(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool
                                  _ptr(loss), _ptr(hhat), _ptr(d), ctypes.c_void_p(base + off),
                                  scratch.numel() - off, ctypes.c_void_p(stream)), "gs_loss_spectrum")
     return loss, hhat, d
+
+
+def loss_stats(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, lambda_ch: float = 1.0):
+    """The loss of loss_spectrum() without the elementwise gradient:
+    (loss per set [B], h_hat [B,F(,2)], mean_grad [B,F*c], scale) for
+    backward_l2()."""
+    _check_f32("spectrum", spectrum)
+    _check_f32("target", target, tuple(spectrum.shape))
+    B, F, H, W = spectrum.shape[:4]
+    C = 2 if is_complex else 1
+    dev = spectrum.device
+    loss = torch.empty(B, device=dev)
+    hhat = torch.empty((B, F, 2) if is_complex else (B, F), device=dev)
+    mgrad = torch.empty(B, F * C, device=dev)
+    scratch = torch.empty(B * F * C * 3 * 4 + 256, dtype=torch.uint8, device=dev)
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_loss_spectrum_stats(_ptr(spectrum), _ptr(target), B, F, int(is_complex), H, W, float(lambda_ch),
+                                       _ptr(loss), _ptr(hhat), _ptr(mgrad), ctypes.c_void_p(base + off),
+                                       scratch.numel() - off, ctypes.c_void_p(stream)), "gs_loss_spectrum_stats")
+    return loss, hhat, mgrad, 2.0 / (F * H * W * B)

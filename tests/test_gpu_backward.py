@@ -63,7 +63,11 @@ def close_scene(n, seed):
     return synth.scene(n, seed=seed, lo=[-2.5, -2.5, 0.1], hi=[2.5, 2.5, 2.0], log_scale_mean=-1.2)
 
 
-@pytest.mark.parametrize("cplx,F,seed", [(False, 1, 0), (True, 2, 1), (False, 3, 2)])
+# channel groups: F=1 real -> 1, F=2 complex -> 4, F=3 real -> 1 (butterfly path);
+# F=16 complex -> 32, F=48 real -> 16 (three groups), F=8 complex -> 16
+# (matrix-core path)
+@pytest.mark.parametrize("cplx,F,seed", [(False, 1, 0), (True, 2, 1), (False, 3, 2), (True, 16, 3), (False, 48, 4),
+                                         (True, 8, 5)])
 def test_gradients_match_autograd_reference(cplx, F, seed):
     n = 48
     sc = close_scene(n, seed)
@@ -151,6 +155,39 @@ def test_autograd_function_matches_direct_backward():
     for k in NAMES:
         compare(params[k].grad.cpu().numpy(), ref[k], k)
     compare(a.grad.cpu().numpy(), ref["attr"], "attr")
+
+
+@pytest.mark.parametrize("cplx,F", [(True, 16), (False, 3)])
+def test_fused_l2_backward_matches_two_pass(cplx, F):
+    # shared geometry, 4 attribute sets; the fused backward forms dL/dout
+    # from (spectrum, target) and must reproduce loss_spectrum + backward
+    n, S = 400, 4
+    sc = close_scene(n, 41)
+    dev = to_dev(sc)
+    attrs = np.stack([synth.channel_attrs(n, F, cplx, seed=42 + s) for s in range(S)])
+    a = torch.from_numpy(attrs).cuda()
+    rx = torch.tensor([[0.1, 0.2, 0.3]]).cuda()
+    grid = gs.Grid(90, 360)
+    ws = gs.prepare(dev, rx, grid=grid)
+    spec = gs.blend(ws, a, is_complex=cplx)
+    target = torch.from_numpy(np.random.default_rng(43).normal(size=tuple(spec.shape)).astype(np.float32)).cuda()
+    loss2, hh2, dspec = gs.loss_spectrum(spec, target, cplx, 0.7)
+    g2 = gs.backward(ws, dev, a, rx, spec, dspec, is_complex=cplx, n_sets=S)
+    g2 = {k: v.clone() for k, v in g2.items()}
+    loss1, hh1, mgrad, scale = gs.loss_stats(spec, target, cplx, 0.7)
+    g1 = gs.backward_l2(ws, dev, a, rx, spec, target, mgrad, scale, is_complex=cplx, n_sets=S)
+    torch.cuda.synchronize()
+    # float-atomic reductions: equal up to summation order
+    assert torch.allclose(loss1, loss2, rtol=1e-5) and torch.allclose(hh1, hh2, rtol=1e-5, atol=1e-7)
+    # mean_grad is the channel-mean term of the stored gradient
+    Fc = F * (2 if cplx else 1)
+    elem = scale * (spec - target)
+    d_minus = (dspec - elem).reshape(S, F, -1, 2 if cplx else 1)
+    mg = mgrad.reshape(S, F, 1, -1)
+    tol = 4e-7 * float(elem.abs().max()) + 1e-6 * float(mgrad.abs().max())  # FP32 rounding of the stored sum
+    assert float((d_minus - mg).abs().max()) <= tol
+    for k in ("d_mean", "d_log_scale", "d_quat", "d_opacity_logit", "d_attr"):
+        compare(g1[k].cpu().numpy(), g2[k].cpu().numpy(), k, abs_frac=1e-5, rel=1e-4)
 
 
 @pytest.mark.parametrize("cplx,lam,H,W", [(True, 1.0, 90, 360), (False, 0.5, 90, 360), (True, 1.0, 7, 9),
