@@ -21,6 +21,7 @@ serving, one query per step for training).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -34,9 +35,19 @@ sys.path.insert(0, ROOT)
 # FP32 vector peak without packed-FP32 instructions (they are disabled in
 # this build): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_VALU_F32_TFLOPS = 78.6
+PEAK_MFMA_F32_TFLOPS = 157.3  # dense FP32 matrix cores
 PEAK_HBM_GBS = 8000.0
+# Algorithmic work of the compositing kernels, per set (attribute set):
+#  forward  : n_eval (pixel, entry) evaluations x FLOPS_PER_EVAL
+#             + n_contrib accepted pairs x (2 Fc + FLOPS_PER_CONTRIB)
+#  backward : the re-walk, n_eval x FLOPS_PER_EVAL,
+#             + n_contrib x (4 Fc + FLOPS_BWD_CONTRIB): gv = v . g (2 Fc) and
+#             dL/dv += w g (2 Fc) -- the two products done on the matrix cores --
+#             plus dalpha, the transmittance/prefix updates and the 8
+#             geometric terms
 FLOPS_PER_EVAL = 12.0       # offsets, quadratic form, exp, clamp and tests of one (pixel, entry)
 FLOPS_PER_CONTRIB = 4.0     # weight and transmittance update of one accepted pair
+FLOPS_BWD_CONTRIB = 22.0
 
 
 def parse():
@@ -54,7 +65,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mix", action="store_true")
+    ap.add_argument("--loss-mode", default="partial", choices=("partial", "two_pass"),
+                    help="one-pass loss with the gradient assembled in the backward, or loss + stored gradient")
     ap.add_argument("--mix-only", action="store_true", help="run only the uneven serving mix (for profiling)")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for hardware-counter passes: 2 training steps, then a 256 MiB copy that "
+                         "calibrates the byte counters")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON) for the serving mix")
     return ap.parse_args()
 
@@ -94,9 +110,11 @@ def main():
         targets[b] = out[0]
     tx = torch.from_numpy(tx_all[:B]).to(dev)
 
+    if args.pmc_run:
+        args.warmup, args.steps = 1, 2
     # ---------------------------------------------------------------- training
     model = train.LearnedScene(scene, emb, train.init_weights(0), [0, 0, 0], B, box_lo, box_hi, grid=grid,
-                               total_steps=args.warmup + args.steps)
+                               total_steps=args.warmup + args.steps, loss_mode=args.loss_mode)
     for _ in range(args.warmup):
         model.train_step(tx, targets)
     torch.cuda.synchronize()
@@ -105,16 +123,33 @@ def main():
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    L = gs._lib.lib()
+    L.gs_timing_enable(1)
     t0.record()
     for k in range(args.steps):
         e = evs[k]
         model.train_step(tx, targets, marks=lambda name, e=e: e[name].record())
     t1.record()
     torch.cuda.synchronize()
+    L.gs_timing_enable(0)
+    kernel_ms = {}
+    for name, tid in (("blend", 0), ("blend_bwd", 1)):
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        assert L.gs_timing_read(tid, ctypes.byref(tot), ctypes.byref(cnt)) == 0 and cnt.value == args.steps
+        kernel_ms[name] = tot.value / cnt.value
     ms_step = t0.elapsed_time(t1) / args.steps
     stages = {}
     for a, b in zip(names[:-1], names[1:]):
         stages[b] = float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))
+    if args.pmc_run:
+        # calibration: a plain device copy of exactly 256 MiB (read 256, write 256)
+        src = torch.ones(64 << 20, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_run": "done", "copy_bytes": src.numel() * 4}), flush=True)
+        return
     live_count = int(model.live_count.item())
     HW = H * W
     n_contrib = model.ws.view("n_contrib", 0, HW, torch.int32).double().sum().item()
@@ -163,19 +198,25 @@ def main():
                   "mean_contrib_per_pixel": round(n_contrib / HW, 2), "entries_evaluated_per_pixel":
                   round(n_eval / HW, 2)},
     }
-    # roofline: the forward blend launch (one kernel between the marks)
+    # roofline of the dominant kernel, from the library's HIP-event timing of
+    # every launch of the two compositing kernels during the timed steps
     Fc = 2 * F
     blend_flops = B * (n_eval * FLOPS_PER_EVAL + n_contrib * (2.0 * Fc + FLOPS_PER_CONTRIB))
-    bwd_flops = B * (n_eval * 2 * FLOPS_PER_EVAL + n_contrib * (3.0 * Fc + 30.0))
-    rf = {"blend": (stages["blend"], blend_flops, "k_blend<32>"),
-          "render_bwd": (stages["render_bwd"], bwd_flops, "k_blend_bwd<32> (+ k_project_bwd, fills)")}
-    dom = max(rf, key=lambda k: rf[k][0])
-    ms, fl, kname = rf[dom]
+    bwd_flops = B * (n_eval * FLOPS_PER_EVAL + n_contrib * (4.0 * Fc + FLOPS_BWD_CONTRIB))
+    kt = {"k_blend<32>": (kernel_ms["blend"], blend_flops, "alu", PEAK_VALU_F32_TFLOPS),
+          "k_blend_bwd<32>": (kernel_ms["blend_bwd"], bwd_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
+    kname = max(kt, key=lambda k: kt[k][0])
+    ms, fl, bound, peak = kt[kname]
     ach = fl / (ms / 1e3) / 1e12
-    res["roofline"] = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_VALU_F32_TFLOPS,
-                       "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_F32_TFLOPS, 4), "traffic": None,
-                       "launch_ms": round(ms, 4),
-                       "work": {"pairs_evaluated_per_set": n_eval, "contributions_per_set": n_contrib, "sets": B}}
+    res["roofline"] = {"kernel": kname, "bound": bound, "achieved": round(ach, 3), "peak": peak,
+                       "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": measured_traffic(kname),
+                       "launch_ms": round(ms, 4), "flops_per_launch": fl,
+                       "work": {"pairs_evaluated_per_set": n_eval, "contributions_per_set": n_contrib, "sets": B,
+                                "channel_floats": Fc},
+                       "other": {k: {"launch_ms": round(v[0], 4),
+                                     "achieved_tflops": round(v[1] / (v[0] / 1e3) / 1e12, 3),
+                                     "frac_valu_fp32": round(v[1] / (v[0] / 1e3) / 1e12 / PEAK_VALU_F32_TFLOPS, 4)}
+                                 for k, v in kt.items()}}
     if not args.no_mix:
         res["serving_mix"] = serving_mix(args, gs, dev)
     if not args.no_plain:
@@ -185,6 +226,39 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(gt, rho, tx_all, H, W, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "compositing_traffic_100k_90x360_f64c_b16.md")
+
+
+def kernel_source_hash(path):
+    """sha256 of a kernel's source file and the shared header it includes."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (path, os.path.join(ROOT, "paper_2511_22793_amd", "csrc", "common.h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
+    when there is none or the kernel's source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    start = text.find("```json")
+    if start < 0:
+        return None
+    data = json.loads(text[start + 7:text.index("```", start + 7)])
+    k = data.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    src = os.path.join(ROOT, "paper_2511_22793_amd", "csrc", k["source"])
+    if kernel_source_hash(src) != k["source_sha256"]:
+        return None
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
 def serving_mix(args, gs, dev):

@@ -203,15 +203,19 @@ gs_status gs_render_backward(const gs_scene* scene, const gs_attrs* attrs, const
                              size_t ws_bytes, void* stream);
 
 /*
- * gs_render_backward() for the loss of gs_loss_spectrum() without reading a
- * stored gradient: dL/dzhat = scale (zhat - z) + mean_grad[s][f*c + comp] is
- * formed inside the kernel from the forward output and the target (for the
- * loss of gs_loss_spectrum(), scale = 2 / (F H W n_sets) and mean_grad comes
- * from gs_loss_spectrum_stats()), which saves a full pass over the spectra.
- * lg is a host struct of device pointers; other arguments as above.
+ * gs_render_backward() for the loss of gs_loss_spectrum() with the gradient
+ * assembled inside the kernel, dL/dzhat = E + mean_grad[s][f*c + comp],
+ * where the elementwise part E is either read from `partial` (d_partial of
+ * gs_loss_spectrum_stats(); one pass over the spectra less than
+ * gs_loss_spectrum() + gs_render_backward()) or, when partial is NULL,
+ * formed as scale (zhat - z) from the forward output and `target` (no
+ * gradient buffer at all; for the loss of gs_loss_spectrum(),
+ * scale = 2 / (F H W n_sets)).  lg is a host struct of device pointers;
+ * other arguments as for gs_render_backward().
  */
 typedef struct {
-    const float* target;    /* z, layout of the spectrum */
+    const float* partial;   /* E, layout of the spectrum, or NULL */
+    const float* target;    /* z (used when partial is NULL) */
     const float* mean_grad; /* [n_sets][F*c] */
     float scale;
 } gs_l2_grad;
@@ -249,14 +253,17 @@ gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n
                            float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes, void* stream);
 
 /*
- * The loss of gs_loss_spectrum() without the elementwise gradient, for
- * gs_render_backward_l2(): writes loss [n_sets], h_hat [n_sets][F][c] and
- * mean_grad [n_sets][F*c] = lambda_ch 2 (h^ - h) / (H W) / n_sets, the
- * channel-mean part of dL/dzhat (same arguments and scratch otherwise).
+ * The loss of gs_loss_spectrum() in one pass over the spectra, for
+ * gs_render_backward_l2(): writes loss [n_sets], h_hat [n_sets][F][c],
+ * mean_grad [n_sets][F*c] = lambda_ch 2 (h^ - h) / (H W) / n_sets (the
+ * channel-mean part of dL/dzhat) and, when d_partial is not NULL,
+ * d_partial = 2 (zhat - z) / (F H W n_sets) (the elementwise part, layout
+ * of the spectrum) in the same pass.  Same arguments and scratch otherwise.
  */
 gs_status gs_loss_spectrum_stats(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
                                  int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
-                                 float* h_hat, float* mean_grad, void* scratch, size_t scratch_bytes, void* stream);
+                                 float* h_hat, float* mean_grad, float* d_partial, void* scratch,
+                                 size_t scratch_bytes, void* stream);
 
 /* ---- attribute network (shared form of the emission predictor, Eq. (1)) ----
  * Per (set s, Gaussian g):  h1 = relu(W1 [e_g, gamma(tx_s), 0] + b1),
@@ -405,6 +412,20 @@ gs_status gs_batch_plan(const gs_batch_job* jobs, int32_t n_jobs, void* plan, si
                         gs_batch_info* info, void* stream);
 gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, size_t plan_bytes,
                        int32_t workgroups, uint64_t* timestamps, void* stream);
+/*
+ * Kernel timing for benchmarks.  While enabled, the library records a HIP
+ * event pair on the launching stream around every launch of the timed
+ * kernels: GS_TIMER_BLEND (the compositing kernel of gs_render_forward /
+ * gs_render_blend) and GS_TIMER_BLEND_BWD (the compositing backward of
+ * gs_render_backward*).  gs_timing_read synchronises on the recorded
+ * events, returns the summed milliseconds and launch count since the last
+ * read, and resets them.  Off by default; not for use under graph capture.
+ */
+#define GS_TIMER_BLEND 0
+#define GS_TIMER_BLEND_BWD 1
+gs_status gs_timing_enable(int32_t on);
+gs_status gs_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
+
 /* Device wall-clock rate (kHz) of the current device, for the timestamps. */
 gs_status gs_wall_clock_khz(int32_t* khz);
 

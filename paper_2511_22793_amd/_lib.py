@@ -74,7 +74,7 @@ class GsAdamSegment(ctypes.Structure):
 
 
 class GsL2Grad(ctypes.Structure):
-    _fields_ = [("target", c_p), ("mean_grad", c_p), ("scale", c_f32)]
+    _fields_ = [("partial", c_p), ("target", c_p), ("mean_grad", c_p), ("scale", c_f32)]
 
 
 class GsBatchJob(ctypes.Structure):
@@ -117,8 +117,8 @@ SIGNATURES = {
     "gs_render_backward_l2": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
                                       c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p,
                                       ctypes.POINTER(GsL2Grad), c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz, c_p]),
-    "gs_loss_spectrum_stats": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
-                                       c_p]),
+    "gs_loss_spectrum_stats": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_p,
+                                       c_sz, c_p]),
     "gs_render_live": (c_i32, [c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_sz, c_p,
                                c_i64, c_p, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
@@ -134,6 +134,8 @@ SIGNATURES = {
     "gs_batch_plan": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, ctypes.POINTER(GsBatchInfo), c_p]),
     "gs_batch_run": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, c_i32, c_p, c_p]),
     "gs_wall_clock_khz": (c_i32, [ctypes.POINTER(c_i32)]),
+    "gs_timing_enable": (c_i32, [c_i32]),
+    "gs_timing_read": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64)]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
                               ctypes.POINTER(GsFlags), c_p]),
 }

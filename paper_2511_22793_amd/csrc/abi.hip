@@ -38,7 +38,9 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->rank_bits = bits_for((uint64_t)(n - 1));
     L->tile_bits = bits_for((uint64_t)(L->T - 1));
     if (L->rank_bits + L->tile_bits > 32) return GS_ERR_CAPACITY;
-    L->pair_passes = (L->tile_bits + RADIX_BITS - 1) / RADIX_BITS;
+    L->pair_passes = L->tile_bits <= TILE_PASS_MAX_BITS ? 1 : (L->tile_bits + RADIX_BITS - 1) / RADIX_BITS;
+    const int digits = L->tile_bits <= RADIX_BITS ? RADIX
+                       : (L->tile_bits <= TILE_PASS_MAX_BITS ? (1 << TILE_PASS_MAX_BITS) : RADIX);
     L->sort_blocks = (n + SORT_TILE - 1) / SORT_TILE;
     L->pair_blocks = (int)((cap + SORT_TILE - 1) / SORT_TILE);
     const int maxb = L->sort_blocks > L->pair_blocks ? L->sort_blocks : L->pair_blocks;
@@ -55,8 +57,8 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_pkeys = align256((size_t)cap * 4);
     L->s_plist = align256((size_t)cap * 4);
     L->s_ranges = align256((size_t)L->T * 8);
-    L->s_counts = align256((size_t)maxb * RADIX * 4);
-    L->s_totals = align256(RADIX * 4);
+    L->s_counts = align256((size_t)maxb * digits * 4);
+    L->s_totals = align256((size_t)(1 << TILE_PASS_MAX_BITS) * 4);
     L->s_pix = align256(HW * 4);
     const bool fwd_only = (p->options & GS_OPT_FORWARD_ONLY) != 0;
     L->s_g2d = fwd_only ? 0 : align256((size_t)n * 8 * 4);
@@ -80,7 +82,8 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->vals_b = take(L->s_keys);
     L->partial = take(L->s_partial);
     L->pkeys_a = take(L->s_pkeys);
-    L->pkeys_b = take(L->s_pkeys);
+    // the single tile pass writes the list directly: no second key buffer
+    L->pkeys_b = take(L->tile_bits <= TILE_PASS_MAX_BITS ? 0 : L->s_pkeys);
     L->plist = take(L->s_plist);
     L->ranges = take(L->s_ranges);
     L->counts = take(L->s_counts);
@@ -328,8 +331,9 @@ gs_status gs_render_backward_l2(const gs_scene* scene, const gs_attrs* attrs, co
                                 float* d_opacity_logit, float* d_attr, int32_t flags, void* workspace,
                                 size_t ws_bytes, void* stream)
 {
-    if (!lg || !lg->target || !lg->mean_grad || !(lg->scale == lg->scale)) return GS_ERR_INVALID_ARG;
-    const BwdUpstream up{nullptr, lg->target, lg->mean_grad, lg->scale};
+    if (!lg || !lg->mean_grad || (!lg->partial && !lg->target) || !(lg->scale == lg->scale))
+        return GS_ERR_INVALID_ARG;
+    const BwdUpstream up{lg->partial, lg->partial ? nullptr : lg->target, lg->mean_grad, lg->scale};
     return render_backward(scene, attrs, queries, n_sets, grid, prm, spectrum, up, d_mean, d_log_scale, d_quat,
                            d_opacity_logit, d_attr, flags, workspace, ws_bytes, stream);
 }

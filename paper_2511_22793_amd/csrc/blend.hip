@@ -32,7 +32,19 @@ struct BlendLds {
     double px[256], py[256], ca[256], cb[256], cc[256];
     float sig[256], att[256];
     uint32_t g[256];
+    // per wave: pixel weights of a run of 16 entries (matrix-core path), then
+    // the output transpose (64 pixels x 17)
+    float w[4][16][68];
 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // One (tile, channel group, set) of a blend job; every thread of the
 // workgroup must call it (it synchronises).  Threads beyond the tile's pixel
@@ -68,11 +80,30 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
     const float amin = J.amin, amax = J.amax, tmin = J.tmin;
 
     float T = 1.0f;
-    float acc[CG];
-#pragma unroll
-    for (int k = 0; k < CG; ++k) acc[k] = 0.0f;
     uint32_t last = 0, cnt = 0;
     bool done = !inside;
+    const size_t HW = (size_t)J.H * J.W, pix = inside ? (size_t)row * J.W + col : 0;
+    const int cs = J.C - 1;  // C is 1 or 2
+    const size_t obase = (size_t)set * Fc * HW;
+    // CG = 16, 32: the channel sums out[p][f] = sum_e w[p][e] v[e][f] of a
+    // run of 16 entries go to the FP32 matrix cores (v_mfma_f32_16x16x4_f32,
+    // A = the wave's pixel weights from LDS, B = the entries' attribute
+    // rows); the walk only produces the weights.  Smaller groups (and 64)
+    // accumulate on the VALU with the row in SGPRs.
+    constexpr bool MF = CG == 16 || CG == 32;
+    constexpr int NB = MF ? CG / 16 : 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float acc[MF ? 1 : CG];
+    f32x4 macc[MF ? 4 : 1][NB];
+    if constexpr (MF) {
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) macc[pb][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    } else {
+#pragma unroll
+        for (int k = 0; k < CG; ++k) acc[k] = 0.0f;
+    }
 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += nthr) {
         if (__syncthreads_count(done) == (int)blockDim.x) break;
@@ -91,43 +122,115 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
         }
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, rg.y - b0);
-        for (int j = 0; j < m && !done; ++j) {
-            // the attribute row is wave-uniform: issue its scalar loads first
-            // so that the alpha evaluation below hides their latency
-            const uint32_t g = __builtin_amdgcn_readfirstlane(S.g[j]);
-            const CFloat* vp = (const CFloat*)(A + (size_t)g * Fc);
-            float v[CG];
+        if constexpr (MF) {
+            for (int j0 = 0; j0 < m; j0 += 16) {
+                if (__ballot(!done) == 0ull) break;  // wave-uniform: all its pixels stopped
+                const int jn = min(16, m - j0);
+                // B operands of the run, loaded ahead of the walk: lane holds
+                // v[entry 4 ks + lane/16][channel 16 nb + lane%16]
+                float bv[4][NB];
 #pragma unroll
-            for (int k = 0; k < CG; ++k) v[k] = vp[k];
-            double dx = pcx - S.px[j];
-            dx += dx >= halfW ? -Wd : (dx < -halfW ? Wd : 0.0);
-            const double dy = pcy - S.py[j];
-            const double qv = S.ca[j] * dx * dx + 2.0 * S.cb[j] * dx * dy + S.cc[j] * dy * dy;
-            const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
-            const float alpha = fminf(amax, S.sig[j] * G);
-            const float Tn = T * (1.0f - alpha);
-            const bool stop = alpha >= amin && Tn < tmin;
-            const bool take = alpha >= amin && !stop;
-            done = stop;
-            // branch-free update (one basic block, so the row loads issue
-            // first): a skipped pair adds zero and keeps T
-            const float wgt = take ? T * alpha * S.att[j] : 0.0f;
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int e = 4 * ks + (lane >> 4);
+                    const bool ev = e < jn;
+                    const float* vr = A + (size_t)(ev ? S.g[j0 + e] : 0u) * Fc + (lane & 15);
 #pragma unroll
-            for (int k = 0; k < CG; ++k) acc[k] = fmaf(wgt, v[k], acc[k]);
-            T = take ? Tn : T;
-            last = take ? b0 + j + 1 - rg.x : last;
-            cnt += take ? 1u : 0u;
+                    for (int nb = 0; nb < NB; ++nb) bv[ks][nb] = ev ? ((const CFloat*)vr)[16 * nb] : 0.0f;
+                }
+#pragma unroll 4
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int j = j0 + jj;
+                    float wgt = 0.0f;
+                    if (jj < jn && !done) {
+                        double dx = pcx - S.px[j];
+                        dx += dx >= halfW ? -Wd : (dx < -halfW ? Wd : 0.0);
+                        const double dy = pcy - S.py[j];
+                        const double qv = S.ca[j] * dx * dx + 2.0 * S.cb[j] * dx * dy + S.cc[j] * dy * dy;
+                        const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
+                        const float alpha = fminf(amax, S.sig[j] * G);
+                        const float Tn = T * (1.0f - alpha);
+                        const bool stop = alpha >= amin && Tn < tmin;
+                        const bool take = alpha >= amin && !stop;
+                        done = stop;
+                        wgt = take ? T * alpha * S.att[j] : 0.0f;
+                        T = take ? Tn : T;
+                        last = take ? b0 + j + 1 - rg.x : last;
+                        cnt += take ? 1u : 0u;
+                    }
+                    S.w[wave][jj][lane] = wgt;
+                }
+                wave_sync_lds();
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+                    for (int pb = 0; pb < 4; ++pb) {
+                        const float a = S.w[wave][4 * ks + (lane >> 4)][16 * pb + (lane & 15)];
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            macc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[ks][nb], macc[pb][nb], 0, 0, 0);
+                    }
+                }
+                wave_sync_lds();
+            }
+        } else {
+            for (int j = 0; j < m && !done; ++j) {
+                // the attribute row is wave-uniform: issue its scalar loads
+                // first so that the alpha evaluation below hides their latency
+                const uint32_t g = __builtin_amdgcn_readfirstlane(S.g[j]);
+                const CFloat* vp = (const CFloat*)(A + (size_t)g * Fc);
+                float v[CG];
+#pragma unroll
+                for (int k = 0; k < CG; ++k) v[k] = vp[k];
+                double dx = pcx - S.px[j];
+                dx += dx >= halfW ? -Wd : (dx < -halfW ? Wd : 0.0);
+                const double dy = pcy - S.py[j];
+                const double qv = S.ca[j] * dx * dx + 2.0 * S.cb[j] * dx * dy + S.cc[j] * dy * dy;
+                const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
+                const float alpha = fminf(amax, S.sig[j] * G);
+                const float Tn = T * (1.0f - alpha);
+                const bool stop = alpha >= amin && Tn < tmin;
+                const bool take = alpha >= amin && !stop;
+                done = stop;
+                // branch-free update (one basic block, so the row loads issue
+                // first): a skipped pair adds zero and keeps T
+                const float wgt = take ? T * alpha * S.att[j] : 0.0f;
+#pragma unroll
+                for (int k = 0; k < CG; ++k) acc[k] = fmaf(wgt, v[k], acc[k]);
+                T = take ? Tn : T;
+                last = take ? b0 + j + 1 - rg.x : last;
+                cnt += take ? 1u : 0u;
+            }
         }
     }
     __syncthreads();  // the LDS batch may be reused by the caller's next item
-    if (!inside) return;
-    const size_t HW = (size_t)J.H * J.W, pix = (size_t)row * J.W + col;
-    const int F = Fc / J.C;
+    if constexpr (MF) {
+        // lane holds out[pixel 16 pb + 4 (lane/16) + r][channel 16 nb + lane%16]:
+        // transpose through LDS so that each lane writes its own pixel
 #pragma unroll
-    for (int k = 0; k < CG; ++k) {
-        const int ch = cg * CG + k;
-        const int f = ch / J.C, comp = ch - f * J.C;
-        ((GLOBAL_AS float*)out)[(((size_t)set * F + f) * HW + pix) * J.C + comp] = acc[k];
+        for (int nb = 0; nb < NB; ++nb) {
+            float* tr = &S.w[wave][0][0];  // [64 pixels][17]
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tr[(16 * pb + 4 * (lane >> 4) + r) * 17 + (lane & 15)] = macc[pb][nb][r];
+            wave_sync_lds();
+            if (inside) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int ch = cg * CG + 16 * nb + k;
+                    ((GLOBAL_AS float*)out)[obase + spec_offset(ch, pix, cs, HW)] = tr[lane * 17 + k];
+                }
+            }
+            wave_sync_lds();
+        }
+    }
+    if (!inside) return;
+    if constexpr (!MF) {
+#pragma unroll
+        for (int k = 0; k < CG; ++k) {
+            const int ch = cg * CG + k;
+            ((GLOBAL_AS float*)out)[obase + spec_offset(ch, pix, cs, HW)] = acc[k];
+        }
     }
     if (cg == 0 && set == q && T_final) {
         ((GLOBAL_AS float*)T_final)[q * J.s_pix + pix] = T;
@@ -362,6 +465,8 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
     J.ncg = Fc / cg;
     dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
 #define ARGS J.rec, J.plist, J.ranges, J.attr, J.out, J.T_final, J.n_last, J.n_contrib
+    void* tok;
+    timing_begin(TK_BLEND, s, &tok);
     switch (cg) {
         case 1: hipLaunchKernelGGL(k_blend<1>, grid, block, 0, s, J, ARGS); break;
         case 2: hipLaunchKernelGGL(k_blend<2>, grid, block, 0, s, J, ARGS); break;
@@ -371,6 +476,7 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
         case 32: hipLaunchKernelGGL(k_blend<32>, grid, block, 0, s, J, ARGS); break;
         default: hipLaunchKernelGGL(k_blend<64>, grid, block, 0, s, J, ARGS); break;
     }
+    timing_end(tok, s);
 #undef ARGS
     return GS_OK;
 }

@@ -67,15 +67,17 @@ __device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
 // completes a stage), the xor-8 stage and the final sum over 8 lanes use
 // DPP row rotations and quad permutations.  Lane l ends with the wave
 // total of value l >> 3 in x[0].
+// (every lane has a source lane in these patterns; old = 0 with bound_ctrl
+// lets the compiler fold the move into the add as a DPP operand)
 __device__ __forceinline__ float dpp_f(float v, int ctrl_sel)
 {
     const int iv = __float_as_int(v);
     int r;
     switch (ctrl_sel) {
-        case 0: r = __builtin_amdgcn_update_dpp(iv, iv, 0x128, 0xF, 0xF, false); break;  // row_ror:8
-        case 1: r = __builtin_amdgcn_update_dpp(iv, iv, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
-        case 2: r = __builtin_amdgcn_update_dpp(iv, iv, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
-        default: r = __builtin_amdgcn_update_dpp(iv, iv, 0x141, 0xF, 0xF, false); break; // row_half_mirror
+        case 0: r = __builtin_amdgcn_update_dpp(0, iv, 0x128, 0xF, 0xF, true); break;  // row_ror:8
+        case 1: r = __builtin_amdgcn_update_dpp(0, iv, 0xB1, 0xF, 0xF, true); break;   // quad_perm [1,0,3,2]
+        case 2: r = __builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xF, 0xF, true); break;   // quad_perm [2,3,0,1]
+        default: r = __builtin_amdgcn_update_dpp(0, iv, 0x141, 0xF, 0xF, true); break; // row_half_mirror
     }
     return __int_as_float(r);
 }
@@ -117,11 +119,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const float* __restrict__ mgrad, float gscale, const uint32_t* __restrict__ n_last, size_t s_pix,
     float* __restrict__ gacc, size_t s_gacc, float* __restrict__ d_attr, int64_t da_stride, int shared_geo)
 {
-    // dL/dout of the element at idx (channel component ch): read, or, for the
-    // spectrum L2 + channel-mean loss, formed from the output and the target
-    auto upstream = [&](size_t idx, int ch) -> float {
-        return tgt ? gscale * (out[idx] - tgt[idx]) + mgrad[(size_t)blockIdx.z * Fc + ch] : dout[idx];
-    };
+    // dL/dout of the element at idx = the elementwise part (read, or formed
+    // from the output and the target) + the set's channel-mean term, which
+    // the callers load once per channel (mg)
+    auto upstream = [&](size_t idx) -> float { return tgt ? gscale * (out[idx] - tgt[idx]) : dout[idx]; };
+    // plus the channel-mean term m_f of the set (0 without mgrad).  It is
+    // not added to the per-pixel operands (that costs a quarter of the kernel
+    // time in register pressure) but folded in exactly by linearity:
+    //   D     += sum_f m_f out_f                    (per pixel, m uniform)
+    //   gv_e  += sum_f m_f v_{e,f}                  (per entry, at staging)
+    //   dL/dv_{e,f} += m_f sum_p w_{p,e}            (per entry, at the flush)
+    auto mean_term = [&](int ch) -> float { return mgrad ? mgrad[(size_t)blockIdx.z * Fc + ch] : 0.0f; };
     // CG >= 16: the attribute gradient of a run of BWD_SUB entries,
     // dA[e][f] = sum_p w[p][e] g[p][f], is a 16 x CG x 64 product per wave
     // on the FP32 matrix cores (v_mfma_f32_16x16x4_f32); w goes through LDS.
@@ -144,6 +152,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const float* A = attr + set * a_stride + cg * CG;
     float* dA = d_attr + set * da_stride + cg * CG;
     const size_t HW = (size_t)H * W, pix = inside ? (size_t)row * W + col : 0;
+    // (the channel split below divides by the run-time C on purpose: the
+    // shift form lets the scheduler interleave these loads with the walk and
+    // the kernel then spills at its 128-register cap)
     const int F = Fc / C;
 
     // per-pixel upstream gradient of the group's channels and D = g . out
@@ -154,8 +165,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int ch = cg * CG + k;
         const int f = ch / C, comp = ch - f * C;
         const size_t idx = (((size_t)set * F + f) * HW + pix) * C + comp;
-        gch[k] = inside ? upstream(idx, ch) : 0.0f;
-        D += inside ? gch[k] * out[idx] : 0.0f;
+        const float mk = mean_term(ch);  // uniform
+        gch[k] = inside ? upstream(idx) + (MFMA ? 0.0f : mk) : 0.0f;
+        D += inside ? (MFMA ? gch[k] + mk : gch[k]) * out[idx] : 0.0f;
     }
     const uint32_t stop = inside ? n_last[q * s_pix + pix] : 0u;
 
@@ -168,6 +180,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     float gB[MFMA ? 16 : 1][NB];
     float gT[MFMA ? 4 : 1][MFMA ? CG / 4 : 1];
     if constexpr (MFMA) {
+        // (t % tw and t / tw are computed directly: stepping them in loops
+        // puts a branch between the loads and serialises their latency)
 #pragma unroll
         for (int pb = 0; pb < 4; ++pb) {
             const int t = wave * 64 + 16 * pb + (lane & 15);
@@ -178,7 +192,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int k = 0; k < CG / 4; ++k) {
                 const int ch = cg * CG + 4 * k + (lane >> 4);
                 const int f = ch / C, comp = ch - f * C;
-                gT[pb][k] = in ? upstream((((size_t)set * F + f) * HW + pp) * C + comp, ch) : 0.0f;
+                gT[pb][k] = in ? upstream((((size_t)set * F + f) * HW + pp) * C + comp) : 0.0f;
             }
         }
 #pragma unroll
@@ -191,7 +205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int nb = 0; nb < NB; ++nb) {
                 const int ch = cg * CG + nb * 16 + (lane & 15);
                 const int f = ch / C, comp = ch - f * C;
-                gB[st][nb] = in ? upstream((((size_t)set * F + f) * HW + pp) * C + comp, ch) : 0.0f;
+                gB[st][nb] = in ? upstream((((size_t)set * F + f) * HW + pp) * C + comp) : 0.0f;
             }
         }
     }
@@ -203,6 +217,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // per-entry sums over the workgroup's pixels, flushed once per batch
     __shared__ float s_ad[BWD_BATCH][CG];
     __shared__ float s_geo[BWD_BATCH][8];
+    __shared__ float s_m[CG];              // m_f of the group's channels
+    __shared__ float s_mvb[BWD_BATCH];     // sum_f m_f v_{e,f} per staged entry
     // per wave, for the current run of entries: gv = v . g from the matrix
     // cores, replaced entry by entry by the pixel weight w (rows padded)
     __shared__ float s_w[MFMA ? 4 : 1][MFMA ? BWD_SUB : 1][65];
@@ -211,6 +227,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // the walk of this workgroup ends at the largest stop position of its pixels
     __shared__ uint32_t s_maxstop;
     if (threadIdx.x == 0) s_maxstop = 0;
+    if ((int)threadIdx.x < CG) s_m[threadIdx.x] = mean_term(cg * CG + threadIdx.x);
     __syncthreads();
     if (stop) atomicMax(&s_maxstop, stop);
     __syncthreads();
@@ -244,6 +261,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int e = threadIdx.x; e < BWD_BATCH * 8; e += nthr) s_geo[e / 8][e % 8] = 0.0f;
         __syncthreads();
         const int m = (int)min((uint32_t)BWD_BATCH, end - b0);
+        if constexpr (MFMA) {
+            // sum_f m_f v_{e,f} of the staged entries: four threads per entry
+            const int e = threadIdx.x >> 2, qd = threadIdx.x & 3;
+            float mv = 0.0f;
+            if (e < m) {
+                const float* vr = A + (size_t)s_g[e] * Fc + qd * (CG / 4);
+#pragma unroll
+                for (int k = 0; k < CG / 4; ++k) mv = fmaf(s_m[qd * (CG / 4) + k], vr[k], mv);
+            }
+            mv += __shfl_xor(mv, 1, 64);
+            mv += __shfl_xor(mv, 2, 64);
+            if (qd == 0 && e < m) s_mvb[e] = mv;
+            __syncthreads();
+        }
         for (int j0 = 0; j0 < m; j0 += (MFMA ? BWD_SUB : m)) {
             if (b0 + j0 >= wend) break;  // wave-uniform: nothing left for this wave
             const int jn = MFMA ? min(BWD_SUB, m - j0) : m;
@@ -256,6 +287,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 float va[CG / 4];
 #pragma unroll
                 for (int k = 0; k < CG / 4; ++k) va[k] = ev ? vr[4 * k] : 0.0f;
+
                 f32x4 gv4[4];
 #pragma unroll
                 for (int pb = 0; pb < 4; ++pb) {
@@ -290,7 +322,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     if (__ballot(take) != 0ull) {  // else the whole wave skips the entry
                         float gv = 0.0f;
                         if constexpr (MFMA) {
-                            gv = s_w[wave][jj][lane];
+                            gv = s_w[wave][jj][lane] + s_mvb[j];
                         } else {
                             const uint32_t g = __builtin_amdgcn_readfirstlane(s_g[j]);
                             const float* vp = A + (size_t)g * Fc;
@@ -317,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             geo[4] = dq * (dyf * dyf);                           // d/dC
                             geo[5] = dsg * G;                                   // d/dsigma
                             geo[6] = Ta * gv;                                   // d/da
-                            geo[7] = 0.0f;
+                            geo[7] = w;                                         // sum_p w (mean term)
                             T = T * (1.0f - alpha);
                             P = Pn;
                         } else {
@@ -371,12 +403,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         // workgroup), geometric terms into the per-pair accumulator
         for (int e = threadIdx.x; e < m * CG; e += nthr) {
             const int j = e / CG, k = e % CG;
-            const float val = s_ad[j][k];
+            const float val = MFMA ? s_ad[j][k] + s_m[k] * s_geo[j][7] : s_ad[j][k];
             if (val != 0.0f) unsafeAtomicAdd(dA + (size_t)s_g[j] * Fc + k, val);
         }
         for (int e = threadIdx.x; e < m * 8; e += nthr) {
             const int j = e / 8, k = e % 8;
-            const float val = s_geo[j][k];
+            const float val = k < 7 ? s_geo[j][k] : 0.0f;  // slot 7 holds sum_p w
             if (val != 0.0f) unsafeAtomicAdd(gacc + (size_t)(b0 + j) * 8 + k, val);
         }
     }
@@ -424,6 +456,8 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
     const int shared = (L.nq == 1 && n_sets > 1) ? 1 : 0;
     dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
     const int64_t das = a.query_stride;  // d_attr mirrors the attribute layout
+    void* tok;
+    timing_begin(TK_BLEND_BWD, s, &tok);
     switch (cg) {
         case 1: bwd_cg<1>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
         case 2: bwd_cg<2>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
@@ -432,6 +466,7 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
         case 16: bwd_cg<16>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
         default: bwd_cg<32>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
     }
+    timing_end(tok, s);
     const int64_t fb = (L.cap * 8 + 255) / 256;
     hipLaunchKernelGGL(k_geo_fold, dim3((unsigned)(fb < 2048 ? fb : 2048), L.nq), dim3(256), 0, s,
                        (float*)(ws + L.gacc), L.s_gacc / 4, (const uint32_t*)(ws + L.plist), L.s_plist / 4,

@@ -50,11 +50,20 @@ struct BlendJob {
     int query0;           // index of the job's first query in the batch
 };
 
+// Offset of channel component ch (0 <= ch < F*C) of pixel pix inside one
+// set's spectrum [F][H][W][C], for C = 1 << cs (cs = 0: real, 1: complex).
+__device__ __forceinline__ size_t spec_offset(int ch, size_t pix, int cs, size_t HW)
+{
+    return (size_t)(ch & ~cs) * HW + (size_t)(ch & cs) + (pix << cs);
+}
+
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 8;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per sort workgroup
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
+// tile ids up to this many bits are sorted in one counting pass
+constexpr int TILE_PASS_MAX_BITS = 10;
 
 // Byte layout of the caller's workspace (all sub-buffers 256-byte aligned,
 // each an array over queries with the given stride).
@@ -99,14 +108,20 @@ void launch_blend_persist(const BlendJob* jobs, int njobs, uint32_t total, uint3
                           unsigned long long* done_ts, int workgroups, int block, hipStream_t s);
 void launch_stamp(unsigned long long* ts, hipStream_t s);
 hipError_t persist_occupancy(int block, int* per_cu);
-// Upstream gradient of the backward: dout, or (target, mean_grad, scale)
-// for the fused spectrum L2 + channel-mean loss.
+// Upstream gradient of the backward: dout alone; or, with mean_grad,
+// dout + mean_grad (dout = the elementwise part of the L2 loss gradient),
+// or scale (out - target) + mean_grad when target is set.
 struct BwdUpstream {
     const float* dout;
     const float* target;
     const float* mean_grad;
     float scale;
 };
+// kernel timing (timing.hip): event pairs around launches when enabled
+enum { TK_BLEND = GS_TIMER_BLEND, TK_BLEND_BWD = GS_TIMER_BLEND_BWD, TK_COUNT = 2 };
+bool timing_on();
+void timing_begin(int kernel, hipStream_t s, void** token);
+void timing_end(void* token, hipStream_t s);
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                            const float* out, const BwdUpstream& up, float* d_attr, hipStream_t s);
 void launch_project_bwd(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,

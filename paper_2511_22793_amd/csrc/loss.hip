@@ -19,9 +19,12 @@ namespace gs {
 // float4, so that component c of element x, y, z, w is 0, 1, 0, 1 (C = 2) or
 // always 0 (C = 1).
 // acc layout per set: [Fc][3] = (sum zhat, sum z, sum (zhat - z)^2)
+// With dpart set, the same pass also writes dpart = scale (zhat - z), the
+// elementwise part of the gradient.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_loss_reduce(const float* __restrict__ zhat, const float* __restrict__ z,
-                                                     int Fc, int C, size_t HW, float* __restrict__ acc)
+                                                     int Fc, int C, size_t HW, float* __restrict__ acc,
+                                                     float* __restrict__ dpart, float scale)
 {
     const int b = blockIdx.z, f = blockIdx.y;  // f indexes complex channels (F)
     const size_t F = Fc / C;
@@ -34,6 +37,9 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const float* __restrict__ z
         const float4* y4 = (const float4*)(z + base);
         for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
             const float4 a = a4[i], y = y4[i];
+            if (dpart)
+                ((float4*)(dpart + base))[i] =
+                    make_float4(scale * (a.x - y.x), scale * (a.y - y.y), scale * (a.z - y.z), scale * (a.w - y.w));
             s[0] += a.x + a.z;
             s[1] += a.y + a.w;
             t[0] += y.x + y.z;
@@ -49,6 +55,7 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const float* __restrict__ z
     }
     for (size_t k = nv * 4 + (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) {
         const float a = zhat[base + k], y = z[base + k];
+        if (dpart) dpart[base + k] = scale * (a - y);
         const int c = (int)(k % C);
         s[c] += a;
         t[c] += y;
@@ -149,7 +156,7 @@ using namespace gs;
 extern "C" gs_status gs_loss_spectrum_stats(const float* spectrum, const float* target, int32_t n_sets,
                                             int32_t n_chan, int32_t is_complex, int32_t H, int32_t W,
                                             float lambda_ch, float* loss, float* h_hat, float* mean_grad,
-                                            void* scratch, size_t scratch_bytes, void* stream)
+                                            float* d_partial, void* scratch, size_t scratch_bytes, void* stream)
 {
     if (!spectrum || !target || !loss || !h_hat || !mean_grad || n_sets < 1 || n_chan < 1 || H < 1 || W < 1 ||
         (is_complex != 0 && is_complex != 1) || !(lambda_ch >= 0.0f))
@@ -163,14 +170,18 @@ extern "C" gs_status gs_loss_spectrum_stats(const float* spectrum, const float* 
     (void)hipGetLastError();
     const size_t HW = (size_t)H * W;
     launch_fill_u32((uint32_t*)scratch, (size_t)n_sets * Fc * 3, 0, 1, 0u, s);
-    const bool vec = (HW * C) % 4 == 0 && (((uintptr_t)spectrum | (uintptr_t)target) & 15) == 0;
+    const bool vec = (HW * C) % 4 == 0 &&
+                     (((uintptr_t)spectrum | (uintptr_t)target | (uintptr_t)d_partial) & 15) == 0;
     const size_t per = vec ? HW * C / 4 : HW * C;
     const unsigned gx = (unsigned)((per + 255) / 256 < 32 ? (per + 255) / 256 : 32);
     dim3 grid(gx, n_chan, n_sets);
+    const float scale = 2.0f / ((float)n_chan * (float)HW * (float)n_sets);
     if (vec)
-        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch,
+                           d_partial, scale);
     else
-        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch,
+                           d_partial, scale);
     hipLaunchKernelGGL(k_loss_finish, dim3(n_sets), dim3(256), 0, s, n_sets, Fc, C, HW, lambda_ch,
                        (const float*)scratch, h_hat, loss, mean_grad);
     if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
@@ -200,11 +211,13 @@ extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target
     const unsigned gx = (unsigned)((per + 255) / 256 < 32 ? (per + 255) / 256 : 32);
     dim3 grid(gx, n_chan, n_sets);
     if (vec) {
-        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch,
+                           nullptr, 0.0f);
         hipLaunchKernelGGL(k_loss_grad<true>, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW, lambda_ch,
                            (const float*)scratch, d_spectrum, h_hat, loss);
     } else {
-        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch);
+        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch,
+                           nullptr, 0.0f);
         hipLaunchKernelGGL(k_loss_grad<false>, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW,
                            lambda_ch, (const float*)scratch, d_spectrum, h_hat, loss);
     }

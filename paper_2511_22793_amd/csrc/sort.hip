@@ -49,17 +49,20 @@ __device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_st
     return n_dev ? n_dev[q * n_stride] : n_fixed;
 }
 
-// Per-workgroup digit histogram; counts laid out [digit][block] per query.
+// Per-workgroup digit histogram (RB-bit digits); counts laid out
+// [digit][block] per query.
+template <int RB>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
     const uint32_t* __restrict__ keys, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, uint32_t* __restrict__ counts, size_t s_counts, int max_blocks)
 {
+    constexpr int R = 1 << RB;
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
     const uint32_t base = blockIdx.x * SORT_TILE;
     if (base >= n) return;
-    __shared__ uint32_t hist[RADIX];
-    hist[threadIdx.x] = 0;
+    __shared__ uint32_t hist[R];
+    for (int d = threadIdx.x; d < R; d += SORT_THREADS) hist[d] = 0;
     __syncthreads();
     keys += q * s_keys;
     uint32_t kv[SORT_ITEMS];
@@ -71,10 +74,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
 #pragma unroll
     for (int i = 0; i < SORT_ITEMS; ++i) {
         const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
-        if (e < n) atomicAdd(&hist[(kv[i] >> shift) & (RADIX - 1)], 1u);
+        if (e < n) atomicAdd(&hist[(kv[i] >> shift) & (R - 1)], 1u);
     }
     __syncthreads();
-    counts[q * s_counts + (size_t)threadIdx.x * max_blocks + blockIdx.x] = hist[threadIdx.x];
+    for (int d = threadIdx.x; d < R; d += SORT_THREADS)
+        counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x] = hist[d];
 }
 
 // Exclusive scan over blocks for one digit (one workgroup per digit and
@@ -115,35 +119,47 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ counts
     if (threadIdx.x == 0) totals[q * s_totals + d] = carry;
 }
 
-// Stable scatter.  Wave w of the workgroup owns keys [w*1024, (w+1)*1024) of
-// the block, consumed as 16 rounds of 64 consecutive keys.  A key's rank is
-// (digit base) + (same digit in earlier blocks) + (in earlier waves) +
-// (in earlier rounds of this wave) + (lanes below it with the same digit in
-// this round, from an 8-ballot match mask).
+// Stable scatter of RB-bit digits.  Wave w of the workgroup owns keys
+// [w*1024, (w+1)*1024) of the block, consumed as 16 rounds of 64 consecutive
+// keys.  A key's rank is (digit base) + (same digit in earlier blocks) +
+// (in earlier waves) + (in earlier rounds of this wave) + (lanes below it
+// with the same digit in this round, from an RB-ballot match mask).
+// With `order` set (the single tile pass over pair keys) the output is the
+// pair's Gaussian, order[key & rank_mask], instead of the key.
+template <int RB>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, const uint32_t* __restrict__ counts, size_t s_counts,
-    const uint32_t* __restrict__ totals, size_t s_totals, int max_blocks)
+    const uint32_t* __restrict__ totals, size_t s_totals, int max_blocks, const uint32_t* __restrict__ order,
+    size_t s_order, uint32_t* __restrict__ plist, size_t s_plist, uint32_t rank_mask)
 {
+    constexpr int R = 1 << RB;
+    constexpr int DPT = R / SORT_THREADS;  // digits per thread in the digit scans
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
     const uint32_t base = blockIdx.x * SORT_TILE;
     if (base >= n) return;
-    __shared__ uint32_t s_goff[RADIX];
-    __shared__ uint32_t s_wcnt[4][RADIX];
+    __shared__ uint32_t s_goff[R];
+    __shared__ uint32_t s_wcnt[4][R];
     __shared__ uint32_t s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     kin += q * s_keys;
-    kout += q * s_keys;
+    if (!order) kout += q * s_keys;
     if (vin) {
         vin += q * s_keys;
         vout += q * s_keys;
     }
-    // digit bases: exclusive scan of the totals over digits
+    // digit bases: exclusive scan of the totals over digits (thread tid owns
+    // digits [tid*DPT, tid*DPT + DPT))
     {
-        const uint32_t t = totals[q * s_totals + tid];
-        uint32_t x = t;
+        uint32_t t[DPT], tsum = 0;
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            t[k] = totals[q * s_totals + tid * DPT + k];
+            tsum += t[k];
+        }
+        uint32_t x = tsum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
@@ -151,11 +167,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
         }
         if (lane == 63) s_wsum[w] = x;
         __syncthreads();
-        uint32_t wb = 0;
-        for (int k = 0; k < w; ++k) wb += s_wsum[k];
-        s_goff[tid] = wb + x - t + counts[q * s_counts + (size_t)tid * max_blocks + blockIdx.x];
+        uint32_t run = x - tsum;
+        for (int k = 0; k < w; ++k) run += s_wsum[k];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s_wcnt[k][tid] = 0;
+        for (int k = 0; k < DPT; ++k) {
+            const int d = tid * DPT + k;
+            s_goff[d] = run + counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x];
+            run += t[k];
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) s_wcnt[ww][d] = 0;
+        }
     }
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -171,10 +192,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     for (int j = 0; j < SORT_ITEMS; ++j) {
         const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
         const bool valid = e < n;
-        const uint32_t dig = (key[j] >> shift) & (RADIX - 1);
+        const uint32_t dig = (key[j] >> shift) & (R - 1);
         unsigned long long m = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
+        for (int b = 0; b < RB; ++b) {
             const unsigned long long bb = __ballot((dig >> b) & 1u);
             m &= ((dig >> b) & 1u) ? bb : ~bb;
         }
@@ -188,12 +209,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
+    for (int d = tid; d < R; d += SORT_THREADS) {
         uint32_t run = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint32_t c = s_wcnt[k][tid];
-            s_wcnt[k][tid] = run;
+            const uint32_t c = s_wcnt[k][d];
+            s_wcnt[k][d] = run;
             run += c;
         }
     }
@@ -202,11 +223,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     for (int j = 0; j < SORT_ITEMS; ++j) {
         const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
         if (e < n) {
-            const uint32_t dig = (key[j] >> shift) & (RADIX - 1);
+            const uint32_t dig = (key[j] >> shift) & (R - 1);
             const uint32_t dst = s_goff[dig] + s_wcnt[w][dig] + pos[j];
             if (dst < n) {  // always true when the counts are consistent
-                kout[dst] = key[j];
-                if (vout) vout[dst] = val[j];
+                if (order) {
+                    plist[q * s_plist + dst] = order[q * s_order + (key[j] & rank_mask)];
+                } else {
+                    kout[dst] = key[j];
+                    if (vout) vout[dst] = val[j];
+                }
             }
         }
     }
@@ -225,12 +250,13 @@ static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, si
     uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
         const int shift = first_bit + p * RADIX_BITS;
-        hipLaunchKernelGGL(k_sort_count, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, s_keys, n_dev,
-                           n_stride, n_fixed, shift, counts, sc, maxb);
+        hipLaunchKernelGGL(k_sort_count<RADIX_BITS>, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, s_keys,
+                           n_dev, n_stride, n_fixed, shift, counts, sc, maxb);
         hipLaunchKernelGGL(k_sort_scan, dim3(RADIX, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev,
                            n_stride, n_fixed, maxb);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, vin, kout, vout,
-                           s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, maxb);
+        hipLaunchKernelGGL(k_sort_scatter<RADIX_BITS>, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, vin,
+                           kout, vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, maxb,
+                           nullptr, (size_t)0, nullptr, (size_t)0, 0u);
         uint32_t* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
@@ -401,6 +427,30 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pke
     }
 }
 
+// Tile ranges of the single tile pass: [start, end) = exclusive scan of the
+// per-tile pair totals (tiles beyond T have zero totals).
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ totals, size_t s_totals,
+                                                     uint2* __restrict__ ranges, size_t s_ranges, int T)
+{
+    const int q = blockIdx.x;
+    totals += q * s_totals;
+    ranges += q * s_ranges;
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int t0 = 0; t0 < T; t0 += 256) {
+        const int t = t0 + threadIdx.x;
+        const uint32_t v = t < T ? totals[t] : 0u;
+        const uint32_t ex = block_exclusive_scan_256(v, wsum);
+        const uint32_t c = carry;
+        if (t < T) ranges[t] = make_uint2(c + ex, c + ex + v);
+        __syncthreads();
+        if (threadIdx.x == 255) carry = c + ex + v;
+        __syncthreads();
+    }
+}
+
 void launch_binning(const Layout& L, char* ws, hipStream_t s)
 {
     const uint32_t* order = (const uint32_t*)(ws + L.vals_a);
@@ -419,10 +469,43 @@ void launch_binning(const Layout& L, char* ws, hipStream_t s)
                        pa, spk, L.cap, L.TX, L.rank_bits);
     // pairs are emitted in depth-rank order, so a stable sort on the tile
     // digits alone yields (tile, depth) order
+    uint2* ranges = (uint2*)(ws + L.ranges);
+    if (L.tile_bits <= TILE_PASS_MAX_BITS) {
+        // one counting pass over all tile digits: the scatter writes each
+        // pair's Gaussian straight into the list, and the tile ranges are
+        // the scan of the per-tile totals
+        uint32_t* counts = (uint32_t*)(ws + L.counts);
+        uint32_t* totals = (uint32_t*)(ws + L.totals);
+        const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
+        const int maxb = L.pair_blocks > L.sort_blocks ? L.pair_blocks : L.sort_blocks;
+        const uint32_t* nd = flags + FL_PUSED;
+        const uint32_t rmask = (1u << L.rank_bits) - 1u;
+        uint32_t* plist = (uint32_t*)(ws + L.plist);
+        const size_t spl = L.s_plist / 4;
+        if (L.tile_bits <= RADIX_BITS) {
+            hipLaunchKernelGGL(k_sort_count<RADIX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0, s, pa,
+                               spk, nd, sf, 0u, L.rank_bits, counts, sc, maxb);
+            hipLaunchKernelGGL(k_sort_scan, dim3(1 << RADIX_BITS, L.nq), dim3(256), 0, s, counts, sc, totals, st,
+                               nd, sf, 0u, maxb);
+            hipLaunchKernelGGL(k_sort_scatter<RADIX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0, s, pa,
+                               nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits, counts, sc, totals, st,
+                               maxb, order, so, plist, spl, rmask);
+        } else {
+            hipLaunchKernelGGL(k_sort_count<TILE_PASS_MAX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0,
+                               s, pa, spk, nd, sf, 0u, L.rank_bits, counts, sc, maxb);
+            hipLaunchKernelGGL(k_sort_scan, dim3(1 << TILE_PASS_MAX_BITS, L.nq), dim3(256), 0, s, counts, sc,
+                               totals, st, nd, sf, 0u, maxb);
+            hipLaunchKernelGGL(k_sort_scatter<TILE_PASS_MAX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0,
+                               s, pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits, counts, sc, totals,
+                               st, maxb, order, so, plist, spl, rmask);
+        }
+        hipLaunchKernelGGL(k_tile_ranges, dim3(L.nq), dim3(256), 0, s, totals, st, ranges,
+                           L.s_ranges / sizeof(uint2), L.T);
+        return;
+    }
     const int which = radix_sort(pa, pb, nullptr, nullptr, spk, flags + FL_PUSED, sf, 0, L.rank_bits,
                                  L.pair_passes, L.pair_blocks, L, ws, s);
     uint32_t* sorted = which ? pb : pa;
-    uint2* ranges = (uint2*)(ws + L.ranges);
     launch_fill_u32((uint32_t*)ranges, (size_t)L.T * 2, L.s_ranges / 4, L.nq, 0u, s);
     const int64_t rblocks = (L.cap + 255) / 256;
     dim3 grid((unsigned)(rblocks < 1024 ? rblocks : 1024), L.nq);

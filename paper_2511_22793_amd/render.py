@@ -243,11 +243,13 @@ def backward(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Te
 
 
 def backward_l2(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Tensor, spectrum: torch.Tensor,
-                target: torch.Tensor, mean_grad: torch.Tensor, scale: float, tx: Optional[torch.Tensor] = None,
+                target: Optional[torch.Tensor], mean_grad: torch.Tensor, scale: float,
+                partial: Optional[torch.Tensor] = None, tx: Optional[torch.Tensor] = None,
                 is_complex: bool = False, n_sets: Optional[int] = None, d_attr: Optional[torch.Tensor] = None,
                 out: Optional[dict] = None) -> dict:
-    """backward() for dL/dspectrum = scale (spectrum - target) + mean_grad
-    (the loss of loss_stats()), formed inside the kernel."""
+    """backward() for dL/dspectrum = E + mean_grad (the loss of
+    loss_stats()), assembled inside the kernel: E = partial when given,
+    else scale (spectrum - target)."""
     sc = _scene_c(scene)
     n = sc.n
     B = rx.shape[0]
@@ -255,7 +257,10 @@ def backward_l2(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch
     S = n_sets if n_sets is not None else (attr.shape[0] if per_set else B)
     a = _attrs_c(attr, n, S, is_complex)
     _check_f32("spectrum", spectrum)
-    _check_f32("target", target, tuple(spectrum.shape))
+    if partial is not None:
+        _check_f32("partial", partial, tuple(spectrum.shape))
+    else:
+        _check_f32("target", target, tuple(spectrum.shape))
     _check_f32("mean_grad", mean_grad)
     if mean_grad.numel() != S * a.n_chan * (2 if is_complex else 1):
         raise ValueError("mean_grad must hold n_sets * F * c values")
@@ -267,7 +272,7 @@ def backward_l2(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch
     g["d_attr"] = d_attr if d_attr is not None else torch.empty_like(attr)
     q = GsQueries(B, _ptr(rx), _ptr(tx))
     gr, p = workspace.grid.c(), workspace.params.c()
-    lg = GsL2Grad(_ptr(target), _ptr(mean_grad), float(scale))
+    lg = GsL2Grad(_ptr(partial), _ptr(target), _ptr(mean_grad), float(scale))
     stream = torch.cuda.current_stream(dev).cuda_stream
     check(lib().gs_render_backward_l2(ctypes.byref(sc), ctypes.byref(a), ctypes.byref(q), S, ctypes.byref(gr),
                                       ctypes.byref(p), _ptr(spectrum), ctypes.byref(lg), _ptr(g["d_mean"]),
@@ -316,10 +321,12 @@ def loss_spectrum(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool
     return loss, hhat, d
 
 
-def loss_stats(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, lambda_ch: float = 1.0):
-    """The loss of loss_spectrum() without the elementwise gradient:
-    (loss per set [B], h_hat [B,F(,2)], mean_grad [B,F*c], scale) for
-    backward_l2()."""
+def loss_stats(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, lambda_ch: float = 1.0,
+               partial: Optional[torch.Tensor] = None):
+    """The loss of loss_spectrum() in one pass: (loss per set [B], h_hat
+    [B,F(,2)], mean_grad [B,F*c], scale) for backward_l2(); when `partial`
+    (layout of the spectrum) is given, the same pass writes the elementwise
+    gradient part scale (spectrum - target) into it."""
     _check_f32("spectrum", spectrum)
     _check_f32("target", target, tuple(spectrum.shape))
     B, F, H, W = spectrum.shape[:4]
@@ -332,7 +339,9 @@ def loss_stats(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, l
     base = scratch.data_ptr()
     off = (-base) % 256
     stream = torch.cuda.current_stream(dev).cuda_stream
+    if partial is not None:
+        _check_f32("partial", partial, tuple(spectrum.shape))
     check(lib().gs_loss_spectrum_stats(_ptr(spectrum), _ptr(target), B, F, int(is_complex), H, W, float(lambda_ch),
-                                       _ptr(loss), _ptr(hhat), _ptr(mgrad), ctypes.c_void_p(base + off),
+                                       _ptr(loss), _ptr(hhat), _ptr(mgrad), _ptr(partial), ctypes.c_void_p(base + off),
                                        scratch.numel() - off, ctypes.c_void_p(stream)), "gs_loss_spectrum_stats")
     return loss, hhat, mgrad, 2.0 / (F * H * W * B)

@@ -21,7 +21,7 @@ import numpy as np
 import torch
 
 from . import mlp as gm
-from .render import Grid, Params, Workspace, backward, blend, live, loss_spectrum, prepare
+from .render import Grid, Params, Workspace, backward, backward_l2, blend, live, loss_spectrum, loss_stats, prepare
 
 F = gm.F
 
@@ -55,10 +55,13 @@ class LearnedScene:
 
     def __init__(self, scene: dict, embeddings: np.ndarray, weights: dict, rx, batch: int, box_lo, box_hi,
                  grid: Grid = Grid(), params: Params = Params(), rates: Rates = Rates(), total_steps: int = 1000,
-                 train_geometry: bool = True, lambda_ch: float = 1.0, device="cuda"):
+                 train_geometry: bool = True, lambda_ch: float = 1.0, loss_mode: str = "partial", device="cuda"):
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
+        if loss_mode not in ("partial", "two_pass"):
+            raise ValueError("loss_mode is 'partial' or 'two_pass'")
+        self.loss_mode = loss_mode
         self.n = n = scene["opacity_logit"].shape[0]
         self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
         self.E = torch.tensor(np.asarray(embeddings, np.float32), device=dev)
@@ -70,6 +73,7 @@ class LearnedScene:
         self.attr = torch.zeros(batch, n, F, 2, device=dev)
         self.d_attr = torch.zeros(batch, n, F, 2, device=dev)
         self.spec = torch.empty(batch, F, grid.H, grid.W, 2, device=dev)
+        self.dpart = torch.empty_like(self.spec)
         self.live_list = torch.empty(1, n, dtype=torch.int32, device=dev)
         self.live_count = torch.empty(1, dtype=torch.int32, device=dev)
         self.state = gm.State(batch, n, training=True, device=dev)
@@ -119,10 +123,18 @@ class LearnedScene:
         mark("mlp_fwd")
         spec = blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
         mark("blend")
-        loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
-        mark("loss")
-        backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
-                 d_attr=self.d_attr, out=self.ggrads)
+        if self.loss_mode == "partial":
+            # one pass over (spectrum, target): loss, channel means and the
+            # elementwise gradient; the backward adds the channel-mean term
+            loss, _, mgrad, scale = loss_stats(spec, target, True, self.lambda_ch, partial=self.dpart)
+            mark("loss")
+            backward_l2(self.ws, sc, self.attr, self.rx, spec, None, mgrad, scale, partial=self.dpart,
+                        is_complex=True, n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
+        else:
+            loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
+            mark("loss")
+            backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
+                     d_attr=self.d_attr, out=self.ggrads)
         mark("render_bwd")
         self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
                                   self.mgrads, clear_d_attr=True)

@@ -174,9 +174,14 @@ def test_fused_l2_backward_matches_two_pass(cplx, F):
     loss2, hh2, dspec = gs.loss_spectrum(spec, target, cplx, 0.7)
     g2 = gs.backward(ws, dev, a, rx, spec, dspec, is_complex=cplx, n_sets=S)
     g2 = {k: v.clone() for k, v in g2.items()}
-    loss1, hh1, mgrad, scale = gs.loss_stats(spec, target, cplx, 0.7)
+    part = torch.empty_like(spec)
+    loss1, hh1, mgrad, scale = gs.loss_stats(spec, target, cplx, 0.7, partial=part)
     g1 = gs.backward_l2(ws, dev, a, rx, spec, target, mgrad, scale, is_complex=cplx, n_sets=S)
+    g1 = {k: v.clone() for k, v in g1.items()}
+    g3 = gs.backward_l2(ws, dev, a, rx, spec, None, mgrad, scale, partial=part, is_complex=cplx, n_sets=S)
     torch.cuda.synchronize()
+    # the elementwise part written by the loss pass
+    assert torch.allclose(part, scale * (spec - target), rtol=1e-6, atol=1e-12)
     # float-atomic reductions: equal up to summation order
     assert torch.allclose(loss1, loss2, rtol=1e-5) and torch.allclose(hh1, hh2, rtol=1e-5, atol=1e-7)
     # mean_grad is the channel-mean term of the stored gradient
@@ -188,6 +193,7 @@ def test_fused_l2_backward_matches_two_pass(cplx, F):
     assert float((d_minus - mg).abs().max()) <= tol
     for k in ("d_mean", "d_log_scale", "d_quat", "d_opacity_logit", "d_attr"):
         compare(g1[k].cpu().numpy(), g2[k].cpu().numpy(), k, abs_frac=1e-5, rel=1e-4)
+        compare(g3[k].cpu().numpy(), g2[k].cpu().numpy(), k, abs_frac=1e-5, rel=1e-4)
 
 
 @pytest.mark.parametrize("cplx,lam,H,W", [(True, 1.0, 90, 360), (False, 0.5, 90, 360), (True, 1.0, 7, 9),

@@ -50,12 +50,17 @@ def test_projection_records_match_oracle():
         assert np.array_equal(g["rect"][vis], p["rect"][vis])
 
 
+# tile counts 138 (one 8-bit pass), 540 and 276 (one 10-bit pass) and 2070
+# (12 bits: two 8-bit passes, then the range/list pass)
 @pytest.mark.parametrize("n,H,W,tile", [(2048, 90, 360, (16, 16)), (5000, 90, 360, (8, 8)),
-                                        (4097, 180, 720, (16, 16)), (3000, 90, 360, (8, 16))])
+                                        (4097, 180, 720, (16, 16)), (3000, 90, 360, (8, 16)),
+                                        (3000, 180, 720, (8, 8))])
 def test_depth_order_and_tile_lists_bit_exact(n, H, W, tile):
     sc = synth.scene(n, seed=1)
     rx = np.array([[0.0, 0.0, 0.0], [-2.0, 1.5, 0.3]], np.float32)
-    _, ws = gpu_forward(sc, synth.rss_attrs(n), rx, H=H, W=W, tile=tile)
+    # small tiles on the fine grid need more than the default 64 pairs per Gaussian
+    prm = gs.Params(pair_capacity=n * 512 + 4096)
+    _, ws = gpu_forward(sc, synth.rss_attrs(n), rx, H=H, W=W, tile=tile, prm=prm)
     flags = ws.flags()
     th, tw = tile
     TX, TY = oracle.tile_grid(H, W, tw, th)
