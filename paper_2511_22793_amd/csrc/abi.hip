@@ -43,7 +43,8 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
                        : (L->tile_bits <= TILE_PASS_MAX_BITS ? (1 << TILE_PASS_MAX_BITS) : RADIX);
     L->sort_blocks = (n + SORT_TILE - 1) / SORT_TILE;
     L->pair_blocks = (int)((cap + SORT_TILE - 1) / SORT_TILE);
-    const int maxb = L->sort_blocks > L->pair_blocks ? L->sort_blocks : L->pair_blocks;
+    const int64_t ttile = (int64_t)SORT_THREADS * TILE_PASS_ITEMS;
+    L->tile_blocks = (int)((cap + ttile - 1) / ttile);
     const size_t HW = (size_t)g->H * g->W;
 
     L->s_flags = align256(FL_WORDS * 4);
@@ -57,7 +58,14 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_pkeys = align256((size_t)cap * 4);
     L->s_plist = align256((size_t)cap * 4);
     L->s_ranges = align256((size_t)L->T * 8);
-    L->s_counts = align256((size_t)maxb * digits * 4);
+    {
+        // depth passes: sort_blocks x 256; 8-bit or multi-pass tile sorts:
+        // pair_blocks x 256; the single 10-bit tile pass: tile_blocks x 1024
+        size_t rows = (size_t)L->sort_blocks * RADIX;
+        if (L->pair_passes > 1 || L->tile_bits <= RADIX_BITS) rows = std::max(rows, (size_t)L->pair_blocks * RADIX);
+        else rows = std::max(rows, (size_t)L->tile_blocks * digits);
+        L->s_counts = align256(rows * 4);
+    }
     L->s_totals = align256((size_t)(1 << TILE_PASS_MAX_BITS) * 4);
     L->s_pix = align256(HW * 4);
     const bool fwd_only = (p->options & GS_OPT_FORWARD_ONLY) != 0;

@@ -64,6 +64,9 @@ constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 // tile ids up to this many bits are sorted in one counting pass
 constexpr int TILE_PASS_MAX_BITS = 10;
+// keys per thread of that pass: large blocks keep its digit-by-block count
+// matrix (up to 1024 rows) small
+constexpr int TILE_PASS_ITEMS = 32;
 
 // Byte layout of the caller's workspace (all sub-buffers 256-byte aligned,
 // each an array over queries with the given stride).
@@ -73,6 +76,7 @@ struct Layout {
     int rank_bits;        // bits of the depth rank inside a pair key
     int tile_bits;        // bits of the tile id inside a pair key
     int pair_passes;      // radix passes over pair keys
+    int tile_blocks;      // workgroups of the single tile pass
     int sort_blocks;      // max sort workgroups for n keys
     int pair_blocks;      // max sort workgroups for cap keys
     size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;

@@ -51,28 +51,29 @@ __device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_st
 
 // Per-workgroup digit histogram (RB-bit digits); counts laid out
 // [digit][block] per query.
-template <int RB>
+template <int RB, int IT = SORT_ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
     const uint32_t* __restrict__ keys, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, uint32_t* __restrict__ counts, size_t s_counts, int max_blocks)
 {
     constexpr int R = 1 << RB;
+    constexpr uint32_t TILE = SORT_THREADS * IT;
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
-    const uint32_t base = blockIdx.x * SORT_TILE;
+    const uint32_t base = blockIdx.x * TILE;
     if (base >= n) return;
     __shared__ uint32_t hist[R];
     for (int d = threadIdx.x; d < R; d += SORT_THREADS) hist[d] = 0;
     __syncthreads();
     keys += q * s_keys;
-    uint32_t kv[SORT_ITEMS];
+    uint32_t kv[IT];
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
         kv[i] = e < n ? keys[e] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
         if (e < n) atomicAdd(&hist[(kv[i] >> shift) & (R - 1)], 1u);
     }
@@ -86,11 +87,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ counts, size_t s_counts,
                                                    uint32_t* __restrict__ totals, size_t s_totals,
                                                    const uint32_t* __restrict__ n_dev, size_t n_stride,
-                                                   uint32_t n_fixed, int max_blocks)
+                                                   uint32_t n_fixed, int max_blocks, uint32_t tile)
 {
     const int d = blockIdx.x, q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
-    const int nb = (int)((n + SORT_TILE - 1) / SORT_TILE);
+    const int nb = (int)((n + tile - 1) / tile);
     uint32_t* row = counts + q * s_counts + (size_t)d * max_blocks;
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t carry;
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ counts
 // with the same digit in this round, from an RB-ballot match mask).
 // With `order` set (the single tile pass over pair keys) the output is the
 // pair's Gaussian, order[key & rank_mask], instead of the key.
-template <int RB>
+template <int RB, int IT = SORT_ITEMS, bool KV = true>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
@@ -136,9 +137,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
 {
     constexpr int R = 1 << RB;
     constexpr int DPT = R / SORT_THREADS;  // digits per thread in the digit scans
+    constexpr uint32_t TILE = SORT_THREADS * IT;
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
-    const uint32_t base = blockIdx.x * SORT_TILE;
+    const uint32_t base = blockIdx.x * TILE;
     if (base >= n) return;
     __shared__ uint32_t s_goff[R];
     __shared__ uint32_t s_wcnt[4][R];
@@ -180,17 +182,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     }
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
-    uint32_t key[SORT_ITEMS], val[SORT_ITEMS], pos[SORT_ITEMS];
+    uint32_t key[IT], val[KV ? IT : 1], pos[IT];
     // issue every load before the rank chain so that they overlap
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j) {
-        const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
+    for (int j = 0; j < IT; ++j) {
+        const uint32_t e = base + w * (TILE / 4) + j * 64 + lane;
         key[j] = e < n ? kin[e] : 0u;
-        val[j] = (e < n && vin) ? vin[e] : 0u;
+        if constexpr (KV) val[j] = (e < n && vin) ? vin[e] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j) {
-        const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
+    for (int j = 0; j < IT; ++j) {
+        const uint32_t e = base + w * (TILE / 4) + j * 64 + lane;
         const bool valid = e < n;
         const uint32_t dig = (key[j] >> shift) & (R - 1);
         unsigned long long m = __ballot(valid);
@@ -220,8 +222,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j) {
-        const uint32_t e = base + w * (SORT_TILE / 4) + j * 64 + lane;
+    for (int j = 0; j < IT; ++j) {
+        const uint32_t e = base + w * (TILE / 4) + j * 64 + lane;
         if (e < n) {
             const uint32_t dig = (key[j] >> shift) & (R - 1);
             const uint32_t dst = s_goff[dig] + s_wcnt[w][dig] + pos[j];
@@ -230,7 +232,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
                     plist[q * s_plist + dst] = order[q * s_order + (key[j] & rank_mask)];
                 } else {
                     kout[dst] = key[j];
-                    if (vout) vout[dst] = val[j];
+                    if constexpr (KV) {
+                        if (vout) vout[dst] = val[j];
+                    }
                 }
             }
         }
@@ -246,14 +250,14 @@ static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, si
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* totals = (uint32_t*)(ws + L.totals);
     const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
-    const int maxb = L.pair_blocks > L.sort_blocks ? L.pair_blocks : L.sort_blocks;
+    const int maxb = blocks;  // count-row stride of this sort (the layout sizes rows for it)
     uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
         const int shift = first_bit + p * RADIX_BITS;
         hipLaunchKernelGGL(k_sort_count<RADIX_BITS>, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, s_keys,
                            n_dev, n_stride, n_fixed, shift, counts, sc, maxb);
         hipLaunchKernelGGL(k_sort_scan, dim3(RADIX, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev,
-                           n_stride, n_fixed, maxb);
+                           n_stride, n_fixed, maxb, (uint32_t)SORT_TILE);
         hipLaunchKernelGGL(k_sort_scatter<RADIX_BITS>, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, vin,
                            kout, vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, maxb,
                            nullptr, (size_t)0, nullptr, (size_t)0, 0u);
@@ -477,27 +481,32 @@ void launch_binning(const Layout& L, char* ws, hipStream_t s)
         uint32_t* counts = (uint32_t*)(ws + L.counts);
         uint32_t* totals = (uint32_t*)(ws + L.totals);
         const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
-        const int maxb = L.pair_blocks > L.sort_blocks ? L.pair_blocks : L.sort_blocks;
         const uint32_t* nd = flags + FL_PUSED;
         const uint32_t rmask = (1u << L.rank_bits) - 1u;
         uint32_t* plist = (uint32_t*)(ws + L.plist);
         const size_t spl = L.s_plist / 4;
         if (L.tile_bits <= RADIX_BITS) {
-            hipLaunchKernelGGL(k_sort_count<RADIX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0, s, pa,
-                               spk, nd, sf, 0u, L.rank_bits, counts, sc, maxb);
+            // 256 digits: the usual blocks of SORT_ITEMS keys per thread
+            const int pb = L.pair_blocks;
+            hipLaunchKernelGGL((k_sort_count<RADIX_BITS>), dim3(pb, L.nq), dim3(SORT_THREADS), 0, s, pa, spk, nd, sf,
+                               0u, L.rank_bits, counts, sc, pb);
             hipLaunchKernelGGL(k_sort_scan, dim3(1 << RADIX_BITS, L.nq), dim3(256), 0, s, counts, sc, totals, st,
-                               nd, sf, 0u, maxb);
-            hipLaunchKernelGGL(k_sort_scatter<RADIX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0, s, pa,
-                               nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits, counts, sc, totals, st,
-                               maxb, order, so, plist, spl, rmask);
+                               nd, sf, 0u, pb, (uint32_t)SORT_TILE);
+            hipLaunchKernelGGL((k_sort_scatter<RADIX_BITS, SORT_ITEMS, false>), dim3(pb, L.nq), dim3(SORT_THREADS),
+                               0, s, pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits, counts, sc, totals,
+                               st, pb, order, so, plist, spl, rmask);
         } else {
-            hipLaunchKernelGGL(k_sort_count<TILE_PASS_MAX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0,
-                               s, pa, spk, nd, sf, 0u, L.rank_bits, counts, sc, maxb);
+            // 1024 digits: blocks of TILE_PASS_ITEMS keys per thread keep the
+            // digit-by-block count matrix small
+            const int tb = L.tile_blocks;
+            const uint32_t ttile = (uint32_t)(SORT_THREADS * TILE_PASS_ITEMS);
+            hipLaunchKernelGGL((k_sort_count<TILE_PASS_MAX_BITS, TILE_PASS_ITEMS>), dim3(tb, L.nq),
+                               dim3(SORT_THREADS), 0, s, pa, spk, nd, sf, 0u, L.rank_bits, counts, sc, tb);
             hipLaunchKernelGGL(k_sort_scan, dim3(1 << TILE_PASS_MAX_BITS, L.nq), dim3(256), 0, s, counts, sc,
-                               totals, st, nd, sf, 0u, maxb);
-            hipLaunchKernelGGL(k_sort_scatter<TILE_PASS_MAX_BITS>, dim3(L.pair_blocks, L.nq), dim3(SORT_THREADS), 0,
-                               s, pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits, counts, sc, totals,
-                               st, maxb, order, so, plist, spl, rmask);
+                               totals, st, nd, sf, 0u, tb, ttile);
+            hipLaunchKernelGGL((k_sort_scatter<TILE_PASS_MAX_BITS, TILE_PASS_ITEMS, false>), dim3(tb, L.nq),
+                               dim3(SORT_THREADS), 0, s, pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits,
+                               counts, sc, totals, st, tb, order, so, plist, spl, rmask);
         }
         hipLaunchKernelGGL(k_tile_ranges, dim3(L.nq), dim3(256), 0, s, totals, st, ranges,
                            L.s_ranges / sizeof(uint2), L.T);
