@@ -288,7 +288,8 @@ typedef struct {
 /* Rows to evaluate: for set s, the Gaussians list[s*list_stride + i],
  * i < count[count_stride ? s : 0] (device count, so the list can come from a
  * device-side pass).  row_cap: rows per set the saved-activation buffers
- * hold (>= every count).  grid_x: workgroups per set (0 = 256). */
+ * hold (>= every count).  grid_x: workgroups per set, each taking 64 rows
+ * per round (0 = 32). */
 typedef struct {
     int32_t n_sets;
     const float* tx;        /* [S][3] */

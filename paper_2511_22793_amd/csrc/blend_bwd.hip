@@ -329,33 +329,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
                             for (int k = 0; k < CG; ++k) gv = fmaf(gch[k], vp[k], gv);
                         }
+                        // branch-free: a lane that does not take the entry
+                        // gets Ta = 0, so every term below is zero and T, P
+                        // stay as they are
                         const float cA = att * gv;
-                        const float Ta = T * alpha;
+                        const float Ta = take ? T * alpha : 0.0f;
                         const float Pn = P + Ta * cA;
                         // alpha <= alpha_max < 1; a one-ulp reciprocal is ample here
                         const float dalpha = T * cA - (D - Pn) * __builtin_amdgcn_rcpf(1.0f - alpha);
-                        const float dsg = sg < amax ? dalpha : 0.0f;  // clamp passes nothing
+                        const float dsg = (take && sg < amax) ? dalpha : 0.0f;  // clamp passes nothing
                         const float dq = -0.5f * dsg * sig * G;
-                        w = take ? Ta * att : 0.0f;
+                        w = Ta * att;
+                        // gradient factors in FP32 from the exact offsets
+                        const float dxf = (float)dx, dyf = (float)dy;
+                        const float dq2 = -2.0f * dq;
                         float geo[8];
-                        if (take) {
-                            // gradient factors in FP32 from the exact offsets
-                            const float dxf = (float)dx, dyf = (float)dy;
-                            const float dq2 = -2.0f * dq;
-                            geo[0] = dq2 * fmaf(s_caf[j], dxf, s_cbf[j] * dyf);  // d/dpx
-                            geo[1] = dq2 * fmaf(s_cbf[j], dxf, s_ccf[j] * dyf);  // d/dpy
-                            geo[2] = dq * (dxf * dxf);                           // d/dA
-                            geo[3] = dq * (2.0f * dxf * dyf);                    // d/dB
-                            geo[4] = dq * (dyf * dyf);                           // d/dC
-                            geo[5] = dsg * G;                                   // d/dsigma
-                            geo[6] = Ta * gv;                                   // d/da
-                            geo[7] = w;                                         // sum_p w (mean term)
-                            T = T * (1.0f - alpha);
-                            P = Pn;
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) geo[k] = 0.0f;
-                        }
+                        geo[0] = dq2 * fmaf(s_caf[j], dxf, s_cbf[j] * dyf);  // d/dpx
+                        geo[1] = dq2 * fmaf(s_cbf[j], dxf, s_ccf[j] * dyf);  // d/dpy
+                        geo[2] = dq * (dxf * dxf);                           // d/dA
+                        geo[3] = dq * (2.0f * dxf * dyf);                    // d/dB
+                        geo[4] = dq * (dyf * dyf);                           // d/dC
+                        geo[5] = dsg * G;                                   // d/dsigma
+                        geo[6] = Ta * gv;                                   // d/da
+                        geo[7] = w;                                         // sum_p w (mean term)
+                        T = take ? T * (1.0f - alpha) : T;
+                        P = Pn;
                         wave_reduce_scatter8(geo, lane);
                         if ((lane & 7) == 0) atomicAdd(&s_geo[j][lane >> 3], geo[0]);
                         if constexpr (!MFMA) {

@@ -577,7 +577,7 @@ gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, 
     A.list = rows->list; A.list_stride = rows->list_stride; A.count = rows->count; A.count_stride = rows->count_stride;
     A.row_cap = rows->row_cap; A.attr = attr; A.attr_stride = attr_stride;
     A.save_h1 = st->save_h1; A.save_h2 = st->save_h2;
-    const int gx = rows->grid_x > 0 ? rows->grid_x : 256;
+    const int gx = rows->grid_x > 0 ? rows->grid_x : 32;
     hipLaunchKernelGGL(k_mlp_fwd, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
@@ -613,7 +613,7 @@ gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mea
     A.clear = clear_d_attr ? d_attr : nullptr;
     A.save_h1 = st->save_h1; A.save_h2 = st->save_h2; A.save_do = st->save_do; A.save_dz2 = st->save_dz2;
     A.save_dz1 = st->save_dz1; A.db3 = gr->db3; A.db2 = gr->db2; A.dc = st->dc; A.dE = gr->dE;
-    const int gx = rows->grid_x > 0 ? rows->grid_x : 256;
+    const int gx = rows->grid_x > 0 ? rows->grid_x : 32;
     hipLaunchKernelGGL(k_mlp_bwd_data, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
     const int P = st->n_partial;
     const size_t cap = (size_t)rows->row_cap;

@@ -71,7 +71,7 @@ class Rows:
 class State:
     """Scratch of the network calls for S sets and row_cap rows per set."""
 
-    def __init__(self, S: int, row_cap: int, training: bool = True, n_partial: int = 64, device="cuda"):
+    def __init__(self, S: int, row_cap: int, training: bool = True, n_partial: int = 16, device="cuda"):
         dev = torch.device(device)
         u16 = torch.int16
         self.cb = torch.empty(S, HID, device=dev)

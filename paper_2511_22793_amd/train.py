@@ -59,8 +59,8 @@ class LearnedScene:
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
-        if loss_mode not in ("partial", "two_pass"):
-            raise ValueError("loss_mode is 'partial' or 'two_pass'")
+        if loss_mode not in ("partial", "target", "two_pass"):
+            raise ValueError("loss_mode is 'partial', 'target' or 'two_pass'")
         self.loss_mode = loss_mode
         self.n = n = scene["opacity_logit"].shape[0]
         self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
@@ -130,6 +130,12 @@ class LearnedScene:
             mark("loss")
             backward_l2(self.ws, sc, self.attr, self.rx, spec, None, mgrad, scale, partial=self.dpart,
                         is_complex=True, n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
+        elif self.loss_mode == "target":
+            # the backward forms the elementwise part from (spec, target)
+            loss, _, mgrad, scale = loss_stats(spec, target, True, self.lambda_ch)
+            mark("loss")
+            backward_l2(self.ws, sc, self.attr, self.rx, spec, target, mgrad, scale, is_complex=True,
+                        n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
         else:
             loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
             mark("loss")
