@@ -104,7 +104,9 @@ typedef struct {
     int32_t atten_ref; /* d measured to: 0 the receiver, 1 the transmitter (0) */
     float margin;      /* support-rectangle margin, px (1e-3) */
     int64_t pair_capacity; /* (Gaussian, tile) pairs per query; 0 = n * min(tiles, 64) + 4096 */
-    int32_t chan_group;    /* channel floats per blend workgroup, 0 = automatic */
+    int32_t chan_group;    /* channel floats per blend workgroup (a power of two dividing F*c, at most
+                              64; the backward and batched blends use at most 32), 0 = automatic:
+                              the largest such power of two */
     int32_t options;       /* GS_OPT_* bits (0) */
 } gs_params;
 

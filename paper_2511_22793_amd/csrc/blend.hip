@@ -90,7 +90,7 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
     // A = the wave's pixel weights from LDS, B = the entries' attribute
     // rows); the walk only produces the weights.  Smaller groups (and 64)
     // accumulate on the VALU with the row in SGPRs.
-    constexpr bool MF = CG == 16 || CG == 32;
+    constexpr bool MF = CG == 16 || CG == 32 || CG == 64;
     constexpr int NB = MF ? CG / 16 : 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float acc[MF ? 1 : CG];
@@ -443,13 +443,14 @@ BlendJob make_blend_job(const gs_attrs& a, const gs_params& p, const Layout& L, 
 }
 
 // Channel floats per workgroup: the largest power of two that divides F*c,
-// at most 32, or the caller's choice (a power of two up to 64 dividing F*c).
+// at most 64, or the caller's choice (a power of two up to 64 dividing F*c).
+// (The backward and the persistent batch kernel cap it at 32.)
 int choose_chan_group(int Fc, int requested)
 {
     if (requested > 0 && requested <= 64 && (requested & (requested - 1)) == 0 && Fc % requested == 0)
         return requested;
     int cg = 1;
-    while (cg < 32 && Fc % (cg * 2) == 0) cg *= 2;
+    while (cg < 64 && Fc % (cg * 2) == 0) cg *= 2;
     return cg;
 }
 
