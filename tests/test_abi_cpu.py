@@ -134,3 +134,22 @@ def test_python_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libgsparc.so")
     with pytest.raises(RuntimeError, match="not built"):
         _lib.lib()
+
+
+def test_kernel_timing_api_on_host():
+    # enabling, disabling and reading with no launch recorded needs no device
+    L = _lib.lib()
+    tot, cnt = ctypes.c_double(), ctypes.c_int64()
+    assert L.gs_timing_enable(0) == _lib.GS_OK
+    assert L.gs_timing_read(0, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_OK and cnt.value == 0
+    assert L.gs_timing_read(1, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_OK and tot.value == 0.0
+    assert L.gs_timing_read(2, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_ERR_INVALID_ARG
+    assert L.gs_timing_read(0, None, ctypes.byref(cnt)) == _lib.GS_ERR_INVALID_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
