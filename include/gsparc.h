@@ -315,7 +315,7 @@ typedef struct {
     uint16_t* save_dz1;  /* [S][row_cap][64] bf16 */
     float* dc;           /* [S][64] */
     uint16_t* wT;        /* 32*64 + 64*64 + 64*128 bf16 transposed weights */
-    float* partial;      /* n_partial * 8192 floats */
+    float* partial;      /* n_partial * (128*64 + 64*64 + 64*32) floats (the three weight gradients) */
     int32_t n_partial;   /* split-K workgroups of the weight gradients */
 } gs_mlp_state;
 

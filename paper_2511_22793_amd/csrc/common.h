@@ -91,6 +91,13 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
 
 // kernel launchers (stream-ordered, no synchronisation)
 void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_t v, hipStream_t s);
+constexpr int FILL_SEGS = 8;
+struct FillSegs {
+    uint32_t* p[FILL_SEGS];
+    size_t count[FILL_SEGS];
+    int n;
+};
+void launch_fill_segs(const FillSegs& f, hipStream_t s);  // zero-fills f.n buffers (words)
 // fills [0, per_query * n_dev[q]) of each query, n_dev read on the device
 void launch_fill_dev(uint32_t* p, size_t max_count, size_t q_stride, int nq, const uint32_t* n_dev, size_t n_stride,
                      uint32_t per_query, hipStream_t s);

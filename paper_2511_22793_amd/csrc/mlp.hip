@@ -424,19 +424,28 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
 // operands, FP32 accumulation).  a rows: [S][cap][M]; b rows: [S][cap][N], or
 // when b_gather is set, b = E[list[i]] ([n][N]).  Each workgroup handles K
 // blocks of 32 rows round-robin and writes its partial [M][N].
-template <int M, int N>
-__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b,
-                                               const uint16_t* __restrict__ bgather, const uint32_t* __restrict__ list,
-                                               size_t list_stride, const uint32_t* __restrict__ count,
-                                               int count_stride, int S, size_t cap, float* __restrict__ partial)
+// LDS of one weight-gradient workgroup: A and B row blocks, [m][32 rows] padded
+struct WgradLds {
+    __attribute__((aligned(16))) uint16_t tA[2 * MLP_F][40];
+    __attribute__((aligned(16))) uint16_t tB[MLP_HID][40];
+};
+
+// (M and N are run-time values so that one kernel carries all three
+// matrices; the accumulator array is sized for the largest, 8 tiles a wave)
+__device__ __forceinline__ void wgrad_body(WgradLds& L, const int M, const int N, const uint16_t* __restrict__ a,
+                                           const uint16_t* __restrict__ b, const uint16_t* __restrict__ bgather,
+                                           const uint32_t* __restrict__ list, size_t list_stride,
+                                           const uint32_t* __restrict__ count, int count_stride, int S, size_t cap,
+                                           float* __restrict__ partial)
 {
-    constexpr int MT = M / 16, NT = N / 16, TILES = MT * NT, PER_WAVE = TILES / 4;
+    constexpr int MAXPW = (2 * MLP_F / 16) * (MLP_HID / 16) / 4;
+    const int NT = N / 16, PER_WAVE = (M / 16) * NT / 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __shared__ __attribute__((aligned(16))) uint16_t tA[M][40];  // [m][32 rows], padded
-    __shared__ __attribute__((aligned(16))) uint16_t tB[N][40];
-    f32x4 acc[PER_WAVE];
+    auto& tA = L.tA;
+    auto& tB = L.tB;
+    f32x4 acc[MAXPW];
 #pragma unroll
-    for (int t = 0; t < PER_WAVE; ++t) acc[t] = f32x4{0, 0, 0, 0};
+    for (int t = 0; t < MAXPW; ++t) acc[t] = f32x4{0, 0, 0, 0};
     // K blocks enumerate (set, 32-row block)
     int kb = blockIdx.x;
     for (int s = 0; s < S; ++s) {
@@ -459,12 +468,14 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ a, c
             }
             __syncthreads();
 #pragma unroll
-            for (int t = 0; t < PER_WAVE; ++t) {
-                const int tile = w * PER_WAVE + t;
-                const int mt = tile / NT, nt = tile % NT;
-                const bf16x8 av = load8(&tA[mt * 16 + (lane & 15)][8 * (lane >> 4)]);
-                const bf16x8 bv = load8(&tB[nt * 16 + (lane & 15)][8 * (lane >> 4)]);
-                acc[t] = mfma(av, bv, acc[t]);
+            for (int t = 0; t < MAXPW; ++t) {
+                if (t < PER_WAVE) {
+                    const int tile = w * PER_WAVE + t;
+                    const int mt = tile / NT, nt = tile % NT;
+                    const bf16x8 av = load8(&tA[mt * 16 + (lane & 15)][8 * (lane >> 4)]);
+                    const bf16x8 bv = load8(&tB[nt * 16 + (lane & 15)][8 * (lane >> 4)]);
+                    acc[t] = mfma(av, bv, acc[t]);
+                }
             }
             __syncthreads();
             kb += gridDim.x;
@@ -473,23 +484,71 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ a, c
     }
     float* P = partial + (size_t)blockIdx.x * M * N;
 #pragma unroll
-    for (int t = 0; t < PER_WAVE; ++t) {
-        const int tile = w * PER_WAVE + t;
-        const int mt = tile / NT, nt = tile % NT;
+    for (int t = 0; t < MAXPW; ++t) {
+        if (t < PER_WAVE) {
+            const int tile = w * PER_WAVE + t;
+            const int mt = tile / NT, nt = tile % NT;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) P[(mt * 16 + 4 * (lane >> 4) + i) * N + nt * 16 + (lane & 15)] = acc[t][i];
+            for (int i = 0; i < 4; ++i) P[(mt * 16 + 4 * (lane >> 4) + i) * N + nt * 16 + (lane & 15)] = acc[t][i];
+        }
     }
 }
 
-__global__ void k_reduce_partials(const float* __restrict__ partial, int nparts, int len, float* __restrict__ out,
-                                  int out_ld, int out_col0, int ncols)
+// The three weight gradients in one launch (blockIdx.y picks the matrix);
+// their split-K partials sit one after the other in `partial`.
+struct WgradArgs {
+    const uint16_t *do_, *h2, *dz2, *h1, *dz1, *E;
+    const uint32_t* list;
+    size_t list_stride;
+    const uint32_t* count;
+    int count_stride, S;
+    size_t cap;
+    float* partial;
+};
+
+constexpr int WG3_LEN0 = 2 * MLP_F * MLP_HID, WG3_LEN1 = MLP_HID * MLP_HID, WG3_LEN2 = MLP_HID * MLP_EMB;
+
+__global__ __launch_bounds__(256) void k_wgrad3(WgradArgs A)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= len) return;
-    float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * len + e];
-    const int r = e / ncols, c = e % ncols;
-    out[(size_t)r * out_ld + out_col0 + c] = s;
+    __shared__ WgradLds L;
+    const int P = gridDim.x;
+    // y = 0: dW3 = d_o^T h2; 1: dW2 = dZ2^T h1; 2: dW1e = dZ1^T E[g]
+    const int y = blockIdx.y;
+    const int M = y == 0 ? 2 * MLP_F : MLP_HID, N = y == 2 ? MLP_EMB : MLP_HID;
+    const uint16_t* a = y == 0 ? A.do_ : (y == 1 ? A.dz2 : A.dz1);
+    const uint16_t* b = y == 0 ? A.h2 : (y == 1 ? A.h1 : nullptr);
+    float* part = A.partial + (y == 0 ? 0 : (y == 1 ? (size_t)P * WG3_LEN0 : (size_t)P * (WG3_LEN0 + WG3_LEN1)));
+    wgrad_body(L, M, N, a, b, y == 2 ? A.E : nullptr, A.list, A.list_stride, A.count, A.count_stride, A.S, A.cap,
+               part);
+}
+
+// Sums the partials of the three weight gradients into dW3, dW2 and the
+// embedding columns of dW1.
+__global__ void k_reduce3(const float* __restrict__ partial, int nparts, float* __restrict__ dW3,
+                          float* __restrict__ dW2, float* __restrict__ dW1)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const float* base = partial;
+    int len = WG3_LEN0, ncols = MLP_HID, ld = MLP_HID;
+    float* out = dW3;
+    if (e >= WG3_LEN0) {
+        e -= WG3_LEN0;
+        base += (size_t)nparts * WG3_LEN0;
+        len = WG3_LEN1;
+        out = dW2;
+        if (e >= WG3_LEN1) {
+            e -= WG3_LEN1;
+            base += (size_t)nparts * WG3_LEN1;
+            len = WG3_LEN2;
+            ncols = MLP_EMB;
+            ld = MLP_IN;
+            out = dW1;
+            if (e >= WG3_LEN2) return;
+        }
+    }
+    float acc = 0.0f;
+    for (int p = 0; p < nparts; ++p) acc += base[(size_t)p * len + e];
+    out[(size_t)(e / ncols) * ld + e % ncols] = acc;
 }
 
 // dW1t = sum_s dc_s gamma_s^T (bf16 gamma), db1 = sum_s dc_s
@@ -599,11 +658,16 @@ gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mea
     uint16_t* W3T = W2T + MLP_HID * MLP_HID;
     hipLaunchKernelGGL(k_mlp_transpose, dim3((MLP_HID * 2 * MLP_F + 255) / 256), dim3(256), 0, s, net->W1, net->W2,
                        net->W3, W1eT, W2T, W3T);
-    launch_fill_u32((uint32_t*)gr->db3, 2 * MLP_F, 0, 1, 0u, s);
-    launch_fill_u32((uint32_t*)gr->db2, MLP_HID, 0, 1, 0u, s);
-    launch_fill_u32((uint32_t*)gr->dW1, (size_t)MLP_HID * MLP_IN, 0, 1, 0u, s);
-    launch_fill_u32((uint32_t*)st->dc, (size_t)rows->n_sets * MLP_HID, 0, 1, 0u, s);
-    launch_fill_u32((uint32_t*)gr->dE, (size_t)n * MLP_EMB, 0, 1, 0u, s);
+    {
+        FillSegs f{};
+        f.p[0] = (uint32_t*)gr->db3; f.count[0] = 2 * MLP_F;
+        f.p[1] = (uint32_t*)gr->db2; f.count[1] = MLP_HID;
+        f.p[2] = (uint32_t*)gr->dW1; f.count[2] = (size_t)MLP_HID * MLP_IN;
+        f.p[3] = (uint32_t*)st->dc; f.count[3] = (size_t)rows->n_sets * MLP_HID;
+        f.p[4] = (uint32_t*)gr->dE; f.count[4] = (size_t)n * MLP_EMB;
+        f.n = 5;
+        launch_fill_segs(f, s);
+    }
     MlpArgs A{};
     A.W2 = net->W2; A.b2 = net->b2; A.W3 = net->W3; A.b3 = net->b3;
     A.W2T = W2T; A.W3T = W3T; A.W1eT = W1eT;
@@ -616,20 +680,12 @@ gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mea
     const int gx = rows->grid_x > 0 ? rows->grid_x : 32;
     hipLaunchKernelGGL(k_mlp_bwd_data, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
     const int P = st->n_partial;
-    const size_t cap = (size_t)rows->row_cap;
-    // dW3 = d_o^T h2, dW2 = dZ2^T h1, dW1e = dZ1^T E
-    hipLaunchKernelGGL((k_wgrad<2 * MLP_F, MLP_HID>), dim3(P), dim3(256), 0, s, st->save_do, st->save_h2, nullptr,
-                       rows->list, rows->list_stride, rows->count, rows->count_stride, rows->n_sets, cap, st->partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3((2 * MLP_F * MLP_HID + 255) / 256), dim3(256), 0, s, st->partial, P,
-                       2 * MLP_F * MLP_HID, gr->dW3, MLP_HID, 0, MLP_HID);
-    hipLaunchKernelGGL((k_wgrad<MLP_HID, MLP_HID>), dim3(P), dim3(256), 0, s, st->save_dz2, st->save_h1, nullptr,
-                       rows->list, rows->list_stride, rows->count, rows->count_stride, rows->n_sets, cap, st->partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3((MLP_HID * MLP_HID + 255) / 256), dim3(256), 0, s, st->partial, P,
-                       MLP_HID * MLP_HID, gr->dW2, MLP_HID, 0, MLP_HID);
-    hipLaunchKernelGGL((k_wgrad<MLP_HID, MLP_EMB>), dim3(P), dim3(256), 0, s, st->save_dz1, nullptr, E, rows->list,
-                       rows->list_stride, rows->count, rows->count_stride, rows->n_sets, cap, st->partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3((MLP_HID * MLP_EMB + 255) / 256), dim3(256), 0, s, st->partial, P,
-                       MLP_HID * MLP_EMB, gr->dW1, MLP_IN, 0, MLP_EMB);
+    // dW3 = d_o^T h2, dW2 = dZ2^T h1, dW1e = dZ1^T E: one split-K launch, one reduction
+    WgradArgs W{st->save_do, st->save_h2, st->save_dz2, st->save_h1, st->save_dz1, E, rows->list, (size_t)rows->list_stride,
+                rows->count, rows->count_stride, rows->n_sets, (size_t)rows->row_cap, st->partial};
+    hipLaunchKernelGGL(k_wgrad3, dim3(P, 3), dim3(256), 0, s, W);
+    hipLaunchKernelGGL(k_reduce3, dim3((WG3_LEN0 + WG3_LEN1 + WG3_LEN2 + 255) / 256), dim3(256), 0, s, st->partial, P,
+                       gr->dW3, gr->dW2, gr->dW1);
     hipLaunchKernelGGL(k_mlp_bias_grad, dim3(MLP_ENC + 1), dim3(MLP_HID), 0, s, st->dc, st->genc, rows->n_sets,
                        gr->dW1, gr->db1);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;

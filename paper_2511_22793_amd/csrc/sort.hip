@@ -22,6 +22,25 @@ __global__ void k_fill_u32(uint32_t* p, size_t count, size_t q_stride, uint32_t 
     if (i < count) p[blockIdx.y * q_stride + i] = v;
 }
 
+// Zero-fills up to FILL_SEGS buffers in one launch (blockIdx.y = segment).
+__global__ void k_fill_segs(FillSegs f)
+{
+    const int k = blockIdx.y;
+    if (k >= f.n) return;
+    uint32_t* p = f.p[k];
+    const size_t c = f.count[k];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < c; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+void launch_fill_segs(const FillSegs& f, hipStream_t s)
+{
+    size_t mx = 1;
+    for (int k = 0; k < f.n; ++k) mx = f.count[k] > mx ? f.count[k] : mx;
+    const size_t blocks = (mx + 255) / 256;
+    hipLaunchKernelGGL(k_fill_segs, dim3((unsigned)(blocks < 1024 ? blocks : 1024), f.n), dim3(256), 0, s, f);
+}
+
 void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_t v, hipStream_t s)
 {
     if (count == 0) return;

@@ -85,7 +85,7 @@ class State:
             self.dz1 = torch.empty(S, row_cap, HID, dtype=u16, device=dev)
             self.dc = torch.empty(S, HID, device=dev)
             self.wT = torch.empty(EMB * HID + HID * HID + HID * 2 * F, dtype=u16, device=dev)
-            self.partial = torch.empty(n_partial, 2 * F * HID, device=dev)
+            self.partial = torch.empty(n_partial, 2 * F * HID + HID * HID + HID * EMB, device=dev)
         self.n_partial = n_partial
 
     def c(self) -> GsMlpState:
