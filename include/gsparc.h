@@ -105,7 +105,8 @@ typedef struct {
     float margin;      /* support-rectangle margin, px (1e-3) */
     int64_t pair_capacity; /* (Gaussian, tile) pairs per query; 0 = n * min(tiles, 64) + 4096 */
     int32_t chan_group;    /* channel floats per blend workgroup (a power of two dividing F*c, at most
-                              64; the backward and batched blends use at most 32), 0 = automatic:
+                              64; the per-group backward and batched blends use at most 32; the
+                              shared-geometry backward takes all columns at once), 0 = automatic:
                               the largest such power of two */
     int32_t options;       /* GS_OPT_* bits (0) */
 } gs_params;
@@ -115,6 +116,11 @@ typedef struct {
  * gs_render_live() then reject it.  For serving, where the pair
  * accumulators would otherwise be the largest part of the workspace. */
 #define GS_OPT_FORWARD_ONLY 1
+/* options: the backward takes the per-set, per-channel-group decomposition
+ * even where the sets share one geometry (the default there evaluates the
+ * geometry once for all sets and channels; both give the same gradients up
+ * to summation order).  For comparisons and tests. */
+#define GS_OPT_BWD_PER_GROUP 2
 
 /* Per-query device-side results, read with gs_read_flags(). */
 typedef struct {
@@ -194,6 +200,13 @@ gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, i
  * position, recomputing alpha and the transmittance.  Discrete decisions
  * (alpha >= alpha_min, the stop, the alpha_max clamp) are those of the
  * forward; a clamped alpha passes no gradient to opacity or footprint.
+ * Where every set shares one prepared query and F*c is a multiple of 16,
+ * the walk runs once per pixel for all sets and channels (the per-set terms
+ * enter the geometric gradient only through sum_{s,f} g v, formed on the
+ * matrix cores, and the attribute gradient only through the set-independent
+ * weight T alpha a); otherwise once per set and channel group.  The option
+ * GS_OPT_BWD_PER_GROUP forces the second form, and so does a set spectrum
+ * of 2^30 or more floats.
  * Float atomics make the summation order, and so the last bits, vary
  * between runs.
  */

@@ -43,6 +43,7 @@ class GsParams(ctypes.Structure):
                 ("pair_capacity", c_i64), ("chan_group", c_i32), ("options", c_i32)]
 
 GS_OPT_FORWARD_ONLY = 1
+GS_OPT_BWD_PER_GROUP = 2
 
 
 class GsFlags(ctypes.Structure):

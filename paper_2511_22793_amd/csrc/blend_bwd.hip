@@ -21,6 +21,8 @@
 // that a second pass folds into the per-Gaussian sums.  The nearest
 // Gaussians cover every tile, so per-wave atomics would serialise on a few
 // addresses.
+#include <type_traits>
+
 #include "common.h"
 
 namespace gs {
@@ -412,6 +414,425 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// ---------------------------------------------------------------------------
+// Backward over attribute sets that share one geometry (one prepared query,
+// S attribute sets: the transmitter batch of the training step).
+//
+// T_k, alpha_k, G_k and a_k do not depend on the set, so the per-set terms
+// above combine linearly:
+//   sum over sets and channels of dL/dalpha_k
+//     = T_k a_k GV_k - (D - P_k) / (1 - alpha_k),
+//   GV_k = sum_{s,f} g_{s,f} v_{s,k,f},  D = sum_{s,f} g_{s,f} out_{s,f},
+//   P_k = sum_{m<=k} T_m alpha_m a_m GV_m,
+// and dL/dv_{s,k,f} = w_k g_{s,f} with the set-independent weight
+// w_k = T_k alpha_k a_k.  One workgroup takes 64 pixels of a tile and every
+// column (set, channel) at once: per batch of entries the matrix cores form
+// GV (entries x pixels, contracted over all S*F*c columns), one wave walks
+// the pixels' lists once for the geometric terms and the weights, and the
+// matrix cores form dL/dv = W^T g (entries x columns, contracted over the
+// pixels).  Eight waves split the columns; the geometry is evaluated once
+// per (pixel, entry) instead of once per set and channel group.
+// ---------------------------------------------------------------------------
+constexpr int SG_WAVES = 8;   // column split
+constexpr int SG_E = 64;      // entries per batch
+constexpr int SG_PIX = 64;    // pixels per workgroup
+
+struct SgUp {  // upstream gradient g = upstream + mean term
+    const float* out;
+    const float* dout;
+    const float* tgt;
+    const float* mgrad;
+    float scale;
+};
+
+// Raw upstream words of one element: dout, or (out, target) with TGT.
+template <bool TGT>
+struct SgRaw {
+    float a, b;
+};
+template <bool TGT>
+__device__ __forceinline__ SgRaw<TGT> sg_fetch(const SgUp& u, size_t idx)
+{
+    if constexpr (TGT) return SgRaw<TGT>{u.out[idx], u.tgt[idx]};
+    else return SgRaw<TGT>{u.dout[idx], 0.0f};
+}
+template <bool TGT>
+__device__ __forceinline__ float sg_value(const SgUp& u, SgRaw<TGT> r)
+{
+    if constexpr (TGT) return u.scale * (r.a - r.b);
+    else return r.a;
+}
+// (re, im) or two consecutive real channels at element index idx (even)
+template <bool TGT>
+__device__ __forceinline__ float2 sg_load2(const SgUp& u, size_t idx)
+{
+    if constexpr (TGT) {
+        const float2 o = *(const float2*)(u.out + idx), t = *(const float2*)(u.tgt + idx);
+        return float2{u.scale * (o.x - t.x), u.scale * (o.y - t.y)};
+    } else {
+        return *(const float2*)(u.dout + idx);
+    }
+}
+
+// stands in for an absent mean-term vector (read with stride 0)
+__device__ const float sg_zero[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+
+template <int CS, bool TGT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_bwd_sg(
+    const GRec* __restrict__ rec, const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
+    const float* __restrict__ attr, int64_t a_stride, int S, int Fc, int H, int W, int tw_log, int th, int TX,
+    float amin, float amax, SgUp up, const uint32_t* __restrict__ n_last, float* __restrict__ gacc,
+    float* __restrict__ d_attr, int64_t da_stride)
+{
+    const int tw = 1 << tw_log;
+    const int tile = blockIdx.x, pg = blockIdx.y;
+    // (wave-uniform values go through readfirstlane so that they live in
+    // scalar registers)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j4 = lane >> 4, l16 = lane & 15;
+    const int txi = tile % TX, tyi = tile / TX;
+    const uint2 rg = ranges[tile];
+    const size_t HW = (size_t)H * W;
+    const int F = Fc >> CS;
+    const int ncb = S * Fc / 16;  // 16-column blocks (Fc % 16 == 0)
+    const int cb_lo = wave * ncb / SG_WAVES, cb_hi = (wave + 1) * ncb / SG_WAVES;
+    // mean term m[s * Fc + c], or zeros
+    const float* mg = up.mgrad ? up.mgrad : sg_zero;
+    const size_t mstr = up.mgrad ? 1 : 0;
+
+    // pixel of tile-local index t: image offset, or -1 outside the image
+    auto pixel_of = [&](int t) -> int {
+        const int col = txi * tw + (t & (tw - 1)), row = tyi * th + (t >> tw_log);
+        return (t < (tw * th) && col < W && row < H) ? row * W + col : -1;
+    };
+
+    __shared__ float s_gv[SG_E][SG_PIX + 1];  // GV of the batch
+    __shared__ float s_w[SG_E][SG_PIX + 1];   // weights w of the batch
+    __shared__ int s_pix[SG_PIX];             // image offset of each pixel of the group (-1 outside)
+    __shared__ double s_px[SG_E], s_py[SG_E], s_ca[SG_E], s_cb[SG_E], s_cc[SG_E];
+    __shared__ float s_caf[SG_E], s_cbf[SG_E], s_ccf[SG_E], s_sig[SG_E], s_att[SG_E];
+    __shared__ uint32_t s_g[SG_E];
+    __shared__ float s_D[SG_PIX];
+    __shared__ uint32_t s_maxstop;
+
+    // the walking wave's pixel (lane) and its stop position
+    const int wpix = pixel_of(pg * SG_PIX + lane);
+    const uint32_t stop = (wave == 0 && wpix >= 0) ? n_last[wpix] : 0u;
+    if (threadIdx.x == 0) s_maxstop = 0;
+    if (threadIdx.x < SG_PIX) {
+        s_D[threadIdx.x] = 0.0f;
+        s_pix[threadIdx.x] = pixel_of(pg * SG_PIX + threadIdx.x);
+    }
+    for (int e = threadIdx.x; e < SG_E * (SG_PIX + 1); e += blockDim.x) (&s_gv[0][0])[e] = 0.0f;
+    __syncthreads();
+    if (stop) atomicMax(&s_maxstop, stop);
+    __syncthreads();
+    const uint32_t end = __builtin_amdgcn_readfirstlane(rg.x + s_maxstop);
+    // one batch holds the whole walk of the group (the common case): D is
+    // then the walk's own final prefix sum_k w_k GV_k (out = sum_k w_k v_k),
+    // else it is formed from the forward output first
+    const bool one_batch = end - rg.x <= (uint32_t)SG_E;
+
+    if (end > rg.x && !one_batch) {
+        int pixB[4];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) pixB[pb] = s_pix[16 * pb + l16];
+        float dp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int cb = cb_lo; cb < cb_hi; ++cb) {
+            const int s = cb * 16 / Fc;
+            const int ch = cb * 16 - s * Fc + 4 * j4;
+            float mk[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) mk[kk] = mg[((size_t)s * Fc + ch + kk) * mstr];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int px = pixB[pb];
+                if (px < 0) continue;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const size_t i = (((size_t)(s * F + ((ch + kk) >> CS)) * HW + px) << CS) + ((ch + kk) & CS);
+                    dp[pb] += (sg_value<TGT>(up, sg_fetch<TGT>(up, i)) + mk[kk]) * up.out[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            float v = dp[pb];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (j4 == 0 && cb_hi > cb_lo) atomicAdd(&s_D[16 * pb + l16], v);
+        }
+    }
+
+    float T = 1.0f, P = 0.0f, D = 0.0f;
+
+    for (uint32_t b0 = rg.x; b0 < end; b0 += SG_E) {
+        const int m = (int)min((uint32_t)SG_E, end - b0);
+        const int neb = (m + 15) >> 4;
+        const bool first = b0 == rg.x;
+        if ((int)threadIdx.x < m) {
+            const uint32_t g = plist[b0 + threadIdx.x];
+            const GRec r = rec[g];
+            s_px[threadIdx.x] = r.px;
+            s_py[threadIdx.x] = r.py;
+            s_ca[threadIdx.x] = r.ca;
+            s_cb[threadIdx.x] = r.cb;
+            s_cc[threadIdx.x] = r.cc;
+            s_caf[threadIdx.x] = (float)r.ca;
+            s_cbf[threadIdx.x] = (float)r.cb;
+            s_ccf[threadIdx.x] = (float)r.cc;
+            s_sig[threadIdx.x] = r.sigma;
+            s_att[threadIdx.x] = r.att;
+            s_g[threadIdx.x] = g;
+        }
+        __syncthreads();
+
+        // ---- GV[e][p] = sum over this wave's columns of v[e][c] g[p][c]
+        // K-step kk of a 16-column block pairs lane group j4 with channel
+        // ch0 + 4 j4 + kk, so each lane reads 4 consecutive channels.
+        // NEB = entry blocks of 16 in the batch (a compile-time count keeps
+        // the matrix-core sequence free of branches).
+        // Wave w takes pixel blocks 2 (w & 1) and 2 (w & 1) + 1 and one of
+        // SG_WAVES / 2 column ranges (32 accumulator registers).
+        auto gv_phase = [&](auto nebc) {
+            constexpr int NEB = decltype(nebc)::value;
+            const int ph = wave & 1, cq = wave >> 1;
+            const int q_lo = cq * ncb / (SG_WAVES / 2), q_hi = (cq + 1) * ncb / (SG_WAVES / 2);
+            int pixB[2];
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) pixB[pb] = s_pix[16 * (2 * ph + pb) + l16];
+            f32x4 acc[NEB][2];
+#pragma unroll
+            for (int eb = 0; eb < NEB; ++eb)
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) acc[eb][pb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            uint32_t ge[NEB];
+#pragma unroll
+            for (int eb = 0; eb < NEB; ++eb) {
+                const int e = 16 * eb + l16;
+                ge[eb] = e < m ? s_g[e] : 0xFFFFFFFFu;
+            }
+            for (int cb = q_lo; cb < q_hi; ++cb) {
+                const int s = cb * 16 / Fc;
+                const int ch = cb * 16 - s * Fc + 4 * j4;
+                const float* As = attr + s * a_stride + ch;
+                // two channels (K-steps 2h, 2h + 1) at a time keeps the
+                // operands of one step pair in registers next to the
+                // accumulators
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    float2 a[NEB];
+#pragma unroll
+                    for (int eb = 0; eb < NEB; ++eb)
+                        a[eb] = ge[eb] != 0xFFFFFFFFu ? *(const float2*)(As + (size_t)ge[eb] * Fc + 2 * h)
+                                                      : float2{0.0f, 0.0f};
+                    const size_t mi = ((size_t)s * Fc + ch + 2 * h) * mstr;
+                    const float mm0 = mg[mi], mm1 = mg[mi + mstr];
+                    float2 bv[2];
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb) {
+                        const int px = pixB[pb];
+                        float2 u = float2{0.0f, 0.0f};
+                        if (px >= 0) {
+                            if constexpr (CS == 1) {
+                                u = sg_load2<TGT>(up, ((size_t)(s * F + (ch >> 1) + h) * HW + px) * 2);
+                            } else {
+                                const size_t i0 = (size_t)(s * F + ch + 2 * h) * HW + px;
+                                u = float2{sg_value<TGT>(up, sg_fetch<TGT>(up, i0)),
+                                           sg_value<TGT>(up, sg_fetch<TGT>(up, i0 + HW))};
+                            }
+                            u.x += mm0;
+                            u.y += mm1;
+                        }
+                        bv[pb] = u;
+                    }
+#pragma unroll
+                    for (int k2 = 0; k2 < 2; ++k2)
+#pragma unroll
+                        for (int eb = 0; eb < NEB; ++eb)
+#pragma unroll
+                            for (int pb = 0; pb < 2; ++pb)
+                                acc[eb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    k2 == 0 ? a[eb].x : a[eb].y, k2 == 0 ? bv[pb].x : bv[pb].y, acc[eb][pb], 0, 0, 0);
+                }
+            }
+            // lane holds GV of entry 16 eb + 4 j4 + r, pixel 16 (2 ph + pb) + l16
+            if (q_hi > q_lo) {
+#pragma unroll
+                for (int eb = 0; eb < NEB; ++eb)
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            atomicAdd(&s_gv[16 * eb + 4 * j4 + r][16 * (2 * ph + pb) + l16], acc[eb][pb][r]);
+            }
+        };
+        switch (neb) {
+            case 1: gv_phase(std::integral_constant<int, 1>{}); break;
+            case 2: gv_phase(std::integral_constant<int, 2>{}); break;
+            case 3: gv_phase(std::integral_constant<int, 3>{}); break;
+            default: gv_phase(std::integral_constant<int, 4>{}); break;
+        }
+        __syncthreads();
+
+        // ---- the walk: one lane per pixel, front to back
+        if (wave == 0) {
+            const double pcx = (wpix >= 0 ? wpix % W : 0) + 0.5, pcy = (wpix >= 0 ? wpix / W : 0) + 0.5;
+            const double halfW = 0.5 * W;
+            // offsets, G and alpha of entry e at this lane's pixel
+            auto geom = [&](int e, double& dx, double& dy, float& G) -> float {
+                dx = pcx - s_px[e];
+                dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
+                dy = pcy - s_py[e];
+                const double qv = s_ca[e] * dx * dx + 2.0 * s_cb[e] * dx * dy + s_cc[e] * dy * dy;
+                G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E_B * qv));
+                return s_sig[e] * G;
+            };
+            if (first) {
+                if (one_batch) {
+                    // D = the final prefix of the walk below, same operations
+                    float Tq = 1.0f, Pq = 0.0f;
+                    for (int e = 0; e < m; ++e) {
+                        double dx, dy;
+                        float G;
+                        const float sg = geom(e, dx, dy, G);
+                        const float alpha = fminf(amax, sg);
+                        const bool take = (b0 + e - rg.x) < stop && alpha >= amin;
+                        const float cA = s_att[e] * s_gv[e][lane];
+                        const float Ta = take ? Tq * alpha : 0.0f;
+                        Pq = Pq + Ta * cA;
+                        Tq = take ? Tq * (1.0f - alpha) : Tq;
+                    }
+                    D = Pq;
+                } else {
+                    D = s_D[lane];
+                }
+            }
+            for (int e = 0; e < m; ++e) {
+                float w = 0.0f;
+                double dx, dy;
+                float G;
+                const float sg = geom(e, dx, dy, G);
+                const float sig = s_sig[e], att = s_att[e];
+                const float alpha = fminf(amax, sg);
+                const bool take = (b0 + e - rg.x) < stop && alpha >= amin;
+                if (__ballot(take) != 0ull) {
+                    const float gv = s_gv[e][lane];
+                    const float cA = att * gv;
+                    const float Ta = take ? T * alpha : 0.0f;
+                    const float Pn = P + Ta * cA;
+                    const float dalpha = T * cA - (D - Pn) * __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float dsg = (take && sg < amax) ? dalpha : 0.0f;
+                    const float dq = -0.5f * dsg * sig * G;
+                    w = Ta * att;
+                    const float dxf = (float)dx, dyf = (float)dy;
+                    const float dq2 = -2.0f * dq;
+                    float geo[8];
+                    geo[0] = dq2 * fmaf(s_caf[e], dxf, s_cbf[e] * dyf);
+                    geo[1] = dq2 * fmaf(s_cbf[e], dxf, s_ccf[e] * dyf);
+                    geo[2] = dq * (dxf * dxf);
+                    geo[3] = dq * (2.0f * dxf * dyf);
+                    geo[4] = dq * (dyf * dyf);
+                    geo[5] = dsg * G;
+                    geo[6] = Ta * gv;
+                    geo[7] = 0.0f;
+                    T = take ? T * (1.0f - alpha) : T;
+                    P = Pn;
+                    wave_reduce_scatter8(geo, lane);
+                    if ((lane & 7) == 0 && lane < 56 && geo[0] != 0.0f)
+                        unsafeAtomicAdd(gacc + (size_t)(b0 + e) * 8 + (lane >> 3), geo[0]);
+                }
+                s_w[e][lane] = w;
+                s_gv[e][lane] = 0.0f;  // cleared for the next batch
+            }
+        }
+        __syncthreads();
+
+        // ---- dL/dv[e][c] = sum_p w[e][p] g[p][c]: K-step kk pairs lane
+        // group j4 with pixel 4 kk + j4.  The next block's upstream words
+        // are fetched before this block's products (software pipelining).
+        auto da_phase = [&](auto nebc) {
+            constexpr int NEB = decltype(nebc)::value;
+            uint32_t pvalid = 0;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) pvalid |= (s_pix[4 * kk + j4] >= 0 ? 1u : 0u) << kk;
+            SgRaw<TGT> rb[2][16];
+            // a uniform base per set and 32-bit lane offsets (one register
+            // per address)
+            auto fetch = [&](int cb, SgRaw<TGT>* r) {
+                const int s = cb * 16 / Fc;
+                const int c = cb * 16 - s * Fc + l16;
+                const size_t sbase = ((size_t)s * F * HW) << CS;
+                const uint32_t coff = ((uint32_t)((c >> CS) * HW) << CS) + (uint32_t)(c & CS);
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int px = s_pix[4 * kk + j4];
+                    r[kk] = sg_fetch<TGT>(up, sbase + (coff + (px >= 0 ? ((uint32_t)px << CS) : 0u)));
+                }
+            };
+            for (int cb = cb_lo; cb < cb_hi; cb += 2) {
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int cc = cb + half;
+                    if (cc < cb_hi) {
+                        fetch(cc, rb[half]);
+                        const int s = cc * 16 / Fc;
+                        const int c = cc * 16 - s * Fc + l16;
+                        const float mk = mg[((size_t)s * Fc + c) * mstr];
+                        f32x4 acc[NEB];
+#pragma unroll
+                        for (int eb = 0; eb < NEB; ++eb) acc[eb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                        // the weights in four groups of four K-steps, the
+                        // next group read from LDS while this one multiplies
+                        float wv[2][4][NEB];
+                        auto ldw = [&](int grp, float (*w)[NEB]) {
+#pragma unroll
+                            for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                                for (int eb = 0; eb < NEB; ++eb) w[k4][eb] = s_w[16 * eb + l16][4 * (4 * grp + k4) + j4];
+                        };
+                        ldw(0, wv[0]);
+#pragma unroll
+                        for (int grp = 0; grp < 4; ++grp) {
+                            if (grp < 3) ldw(grp + 1, wv[(grp + 1) & 1]);
+                            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                            for (int k4 = 0; k4 < 4; ++k4) {
+                                const int kk = 4 * grp + k4;
+                                const float bvl =
+                                    ((pvalid >> kk) & 1u) ? sg_value<TGT>(up, rb[half][kk]) + mk : 0.0f;
+#pragma unroll
+                                for (int eb = 0; eb < NEB; ++eb)
+                                    acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[grp & 1][k4][eb], bvl, acc[eb],
+                                                                                   0, 0, 0);
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                        // lane holds entry 16 eb + 4 j4 + r, column c
+                        float* dA = d_attr + s * da_stride + c;
+#pragma unroll
+                        for (int eb = 0; eb < NEB; ++eb)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int e = 16 * eb + 4 * j4 + r;
+                                if (e < m && acc[eb][r] != 0.0f) unsafeAtomicAdd(dA + (size_t)s_g[e] * Fc, acc[eb][r]);
+                            }
+                    }
+                }
+            }
+        };
+        if (cb_hi > cb_lo) {
+            switch (neb) {
+                case 1: da_phase(std::integral_constant<int, 1>{}); break;
+                case 2: da_phase(std::integral_constant<int, 2>{}); break;
+                case 3: da_phase(std::integral_constant<int, 3>{}); break;
+                default: da_phase(std::integral_constant<int, 4>{}); break;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Folds the per-pair geometric sums into the per-Gaussian accumulators and
 // clears the pair accumulator for the next call.
 __global__ __launch_bounds__(256) void k_geo_fold(float* __restrict__ gacc, size_t s_gacc,
@@ -448,6 +869,24 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
 {
     const int C = a.is_complex ? 2 : 1;
     const int Fc = a.n_chan * C;
+    // (32-bit element offsets inside one set's spectrum)
+    const bool offs32 = (uint64_t)Fc * L.H * L.W < (1ull << 30);
+    if (L.nq == 1 && Fc % 16 == 0 && offs32 && !(p.options & GS_OPT_BWD_PER_GROUP)) {
+        // one geometry for every set: the factorised backward
+        int tw_log = 0;
+        while ((1 << tw_log) < L.tw) ++tw_log;
+        const SgUp sup{out, up.dout, up.target, up.mean_grad, up.scale};
+        const dim3 grid(L.T, (L.tw * L.th) / SG_PIX), block(SG_WAVES * 64);
+        void* tok;
+        timing_begin(TK_BLEND_BWD, s, &tok);
+        auto kern = C == 2 ? (up.target ? k_blend_bwd_sg<1, true> : k_blend_bwd_sg<1, false>)
+                           : (up.target ? k_blend_bwd_sg<0, true> : k_blend_bwd_sg<0, false>);
+        hipLaunchKernelGGL(kern, grid, block, 0, s, (const GRec*)(ws + L.rec), (const uint32_t*)(ws + L.plist),
+                           (const uint2*)(ws + L.ranges), a.data, a.query_stride, n_sets, Fc, L.H, L.W, tw_log,
+                           L.th, L.TX, p.alpha_min, p.alpha_max, sup, (const uint32_t*)(ws + L.n_last),
+                           (float*)(ws + L.gacc), d_attr, a.query_stride);
+        timing_end(tok, s);
+    } else {
     int cg = choose_chan_group(Fc, p.chan_group);
     if (cg > 32) cg = 32;
     if (Fc / cg > 65535) return GS_ERR_CAPACITY;
@@ -465,6 +904,7 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
         default: bwd_cg<32>(grid, block, s, a, p, L, ws, out, up, d_attr, das, C, shared); break;
     }
     timing_end(tok, s);
+    }
     const int64_t fb = (L.cap * 8 + 255) / 256;
     hipLaunchKernelGGL(k_geo_fold, dim3((unsigned)(fb < 2048 ? fb : 2048), L.nq), dim3(256), 0, s,
                        (float*)(ws + L.gacc), L.s_gacc / 4, (const uint32_t*)(ws + L.plist), L.s_plist / 4,

@@ -47,8 +47,12 @@ def test_forward_only_workspace_is_smaller_and_rejects_backward():
     # the per-pair gradient accumulators (32 B per pair) are gone
     assert full.total - fwd.total >= 4 * full.pair_capacity * 32
     assert fwd.pair_list == full.pair_list and fwd.T_final == full.T_final
-    assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(grid()), ctypes.byref(params(options=2)),
+    # unknown option bits are rejected; the backward-decomposition bit is known
+    assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(grid()), ctypes.byref(params(options=4)),
                                           ctypes.byref(GsLayout())) == _lib.GS_ERR_INVALID_ARG
+    assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(grid()),
+                                          ctypes.byref(params(options=_lib.GS_OPT_BWD_PER_GROUP)),
+                                          ctypes.byref(GsLayout())) == _lib.GS_OK
     sc, at, q = _valid_args()
     p = params(options=_lib.GS_OPT_FORWARD_ONLY)
     st = _lib.lib().gs_render_backward(ctypes.byref(sc), ctypes.byref(at), ctypes.byref(q), 1,
