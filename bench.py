@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--channels", type=int, default=64)
     ap.add_argument("--H", type=int, default=90)
     ap.add_argument("--W", type=int, default=360)
+    ap.add_argument("--tile", type=int, nargs=2, default=(16, 16), metavar=("TH", "TW"),
+                    help="tile rows and columns of the training and serving renders")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-plain", action="store_true")
@@ -95,7 +97,7 @@ def main():
         return
     n, B, SB, F, H, W = args.n, args.batch, args.serve_batch, args.channels, args.H, args.W
     assert F == train.F, "the attribute network has 64 complex outputs"
-    grid = gs.Grid(H, W)
+    grid = gs.Grid(H, W, args.tile[0], args.tile[1])
     scene = synth.scene(n, seed=synth.SEED_SCENE)
     emb = synth.embeddings(n)
     box_lo, box_hi = list(synth.BOX_LO), list(synth.BOX_HI)
@@ -189,7 +191,7 @@ def main():
         "config": {"workload": "fwd+bwd training step: %d Gaussians, %dx%d grid, %d complex subcarriers from the "
                                "BF16 attribute network, %d transmitter queries per step, fixed receiver"
                                % (n, H, W, F, B, ),
-                   "n_gaussians": n, "grid": [H, W], "tile": [16, 16], "channels": F, "complex": True,
+                   "n_gaussians": n, "grid": [H, W], "tile": list(args.tile), "channels": F, "complex": True,
                    "queries_per_step": B, "network": "32-d embedding + 51-d transmitter encoding -> 64 -> 64 -> 128, "
                                                      "bf16 weights, fp32 accumulation"},
         "fwd_bwd_steps_per_s": round(1e3 / ms_step, 3),

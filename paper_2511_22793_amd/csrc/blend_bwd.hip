@@ -475,7 +475,7 @@ __device__ __forceinline__ float2 sg_load2(const SgUp& u, size_t idx)
 }
 
 // stands in for an absent mean-term vector (read with stride 0)
-__device__ const float sg_zero[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+__device__ const float4 sg_zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
 
 template <int CS, bool TGT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_bwd_sg(
@@ -497,13 +497,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int ncb = S * Fc / 16;  // 16-column blocks (Fc % 16 == 0)
     const int cb_lo = wave * ncb / SG_WAVES, cb_hi = (wave + 1) * ncb / SG_WAVES;
     // mean term m[s * Fc + c], or zeros
-    const float* mg = up.mgrad ? up.mgrad : sg_zero;
+    const float* mg = up.mgrad ? up.mgrad : (const float*)&sg_zero4;
     const size_t mstr = up.mgrad ? 1 : 0;
 
-    // pixel of tile-local index t: image offset, or -1 outside the image
-    auto pixel_of = [&](int t) -> int {
-        const int col = txi * tw + (t & (tw - 1)), row = tyi * th + (t >> tw_log);
-        return (t < (tw * th) && col < W && row < H) ? row * W + col : -1;
+    // The tile's pixels inside the image (vw x vh, row-major) are packed
+    // into groups of 64: edge tiles need fewer groups, and the spare
+    // workgroups leave at once.
+    const int vw = min(tw, W - txi * tw), vh = min(th, H - tyi * th);
+    if (pg * SG_PIX >= vw * vh) return;
+    auto pixel_of = [&](int k) -> int {
+        return k < vw * vh ? (tyi * th + k / vw) * W + txi * tw + k % vw : -1;
     };
 
     __shared__ float s_gv[SG_E][SG_PIX + 1];  // GV of the batch
@@ -612,48 +615,80 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const int e = 16 * eb + l16;
                 ge[eb] = e < m ? s_g[e] : 0xFFFFFFFFu;
             }
-            for (int cb = q_lo; cb < q_hi; ++cb) {
+            // Operands of one 16-column block: v of 4 consecutive channels per
+            // entry block, the raw upstream words of those channels per pixel
+            // block, and the mean terms; the next block's are fetched while
+            // this block multiplies (software pipelining).
+            constexpr int NR = TGT ? 2 : 1;
+            struct Ops {
+                float4 a[NEB];
+                float b[2][4][NR];
+                float4 mm;
+            };
+            auto load = [&](int cb, Ops& o) {
                 const int s = cb * 16 / Fc;
                 const int ch = cb * 16 - s * Fc + 4 * j4;
                 const float* As = attr + s * a_stride + ch;
-                // two channels (K-steps 2h, 2h + 1) at a time keeps the
-                // operands of one step pair in registers next to the
-                // accumulators
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    float2 a[NEB];
+                for (int eb = 0; eb < NEB; ++eb)
+                    o.a[eb] = ge[eb] != 0xFFFFFFFFu ? *(const float4*)(As + (size_t)ge[eb] * Fc)
+                                                    : float4{0.0f, 0.0f, 0.0f, 0.0f};
+                o.mm = *(const float4*)(mg + ((size_t)s * Fc + ch) * mstr);
 #pragma unroll
-                    for (int eb = 0; eb < NEB; ++eb)
-                        a[eb] = ge[eb] != 0xFFFFFFFFu ? *(const float2*)(As + (size_t)ge[eb] * Fc + 2 * h)
-                                                      : float2{0.0f, 0.0f};
-                    const size_t mi = ((size_t)s * Fc + ch + 2 * h) * mstr;
-                    const float mm0 = mg[mi], mm1 = mg[mi + mstr];
-                    float2 bv[2];
+                for (int pb = 0; pb < 2; ++pb) {
+                    const size_t px = pixB[pb] >= 0 ? (size_t)pixB[pb] : 0;
+                    if constexpr (CS == 1) {
 #pragma unroll
-                    for (int pb = 0; pb < 2; ++pb) {
-                        const int px = pixB[pb];
-                        float2 u = float2{0.0f, 0.0f};
-                        if (px >= 0) {
-                            if constexpr (CS == 1) {
-                                u = sg_load2<TGT>(up, ((size_t)(s * F + (ch >> 1) + h) * HW + px) * 2);
-                            } else {
-                                const size_t i0 = (size_t)(s * F + ch + 2 * h) * HW + px;
-                                u = float2{sg_value<TGT>(up, sg_fetch<TGT>(up, i0)),
-                                           sg_value<TGT>(up, sg_fetch<TGT>(up, i0 + HW))};
+                        for (int h = 0; h < 2; ++h) {
+                            const size_t i = ((size_t)(s * F + (ch >> 1) + h) * HW + px) * 2;
+                            const float2 u = *(const float2*)(TGT ? up.out + i : up.dout + i);
+                            o.b[pb][2 * h][0] = u.x;
+                            o.b[pb][2 * h + 1][0] = u.y;
+                            if constexpr (TGT) {
+                                const float2 t = *(const float2*)(up.tgt + i);
+                                o.b[pb][2 * h][NR - 1] = t.x;
+                                o.b[pb][2 * h + 1][NR - 1] = t.y;
                             }
-                            u.x += mm0;
-                            u.y += mm1;
                         }
-                        bv[pb] = u;
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const size_t i = (size_t)(s * F + ch + kk) * HW + px;
+                            o.b[pb][kk][0] = TGT ? up.out[i] : up.dout[i];
+                            if constexpr (TGT) o.b[pb][kk][NR - 1] = up.tgt[i];
+                        }
                     }
+                }
+            };
+            Ops ops[2];
+            if (q_hi > q_lo) load(q_lo, ops[0]);
+            for (int cb = q_lo; cb < q_hi; cb += 2) {
 #pragma unroll
-                    for (int k2 = 0; k2 < 2; ++k2)
+                for (int half = 0; half < 2; ++half) {
+                    const int cc = cb + half;
+                    if (cc < q_hi) {
+                        if (cc + 1 < q_hi) load(cc + 1, ops[half ^ 1]);
+                        __builtin_amdgcn_sched_barrier(0);
+                        const Ops& o = ops[half];
+                        const float mk[4] = {o.mm.x, o.mm.y, o.mm.z, o.mm.w};
 #pragma unroll
-                        for (int eb = 0; eb < NEB; ++eb)
+                        for (int kk = 0; kk < 4; ++kk) {
+                            float bv[2];
 #pragma unroll
-                            for (int pb = 0; pb < 2; ++pb)
-                                acc[eb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                    k2 == 0 ? a[eb].x : a[eb].y, k2 == 0 ? bv[pb].x : bv[pb].y, acc[eb][pb], 0, 0, 0);
+                            for (int pb = 0; pb < 2; ++pb) {
+                                const float u = TGT ? up.scale * (o.b[pb][kk][0] - o.b[pb][kk][NR - 1]) : o.b[pb][kk][0];
+                                bv[pb] = pixB[pb] >= 0 ? u + mk[kk] : 0.0f;
+                            }
+#pragma unroll
+                            for (int eb = 0; eb < NEB; ++eb) {
+                                const float av = kk == 0 ? o.a[eb].x : (kk == 1 ? o.a[eb].y : (kk == 2 ? o.a[eb].z : o.a[eb].w));
+#pragma unroll
+                                for (int pb = 0; pb < 2; ++pb)
+                                    acc[eb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[pb], acc[eb][pb], 0, 0, 0);
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
             }
             // lane holds GV of entry 16 eb + 4 j4 + r, pixel 16 (2 ph + pb) + l16
