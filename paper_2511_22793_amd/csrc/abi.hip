@@ -102,14 +102,6 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->g2d = take(L->s_g2d);
     L->live = take(L->s_live);
     L->gacc = take(L->s_gacc);
-    // weights of the shared-geometry backward: up to 4 groups of 64 pixels
-    // per tile, 64 entries x 64 pixels each, and the group's entry count
-    L->s_wbuf = fwd_only ? 0 : align256((size_t)L->T * 4 * 64 * 64 * 4);
-    L->s_wcnt = fwd_only ? 0 : align256((size_t)L->T * 4 * 4);
-    L->wbuf = off;
-    off += L->s_wbuf;
-    L->wcnt = off;
-    off += L->s_wcnt;
     L->total = off;
     return GS_OK;
 }

@@ -482,7 +482,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const GRec* __restrict__ rec, const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
     const float* __restrict__ attr, int64_t a_stride, int S, int Fc, int H, int W, int tw_log, int th, int TX,
     float amin, float amax, SgUp up, const uint32_t* __restrict__ n_last, float* __restrict__ gacc,
-    float* __restrict__ d_attr, int64_t da_stride, float* __restrict__ wbuf, uint32_t* __restrict__ wcnt)
+    float* __restrict__ d_attr, int64_t da_stride)
 {
     const int tw = 1 << tw_log;
     const int tile = blockIdx.x, pg = blockIdx.y;
@@ -504,14 +504,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     // into groups of 64: edge tiles need fewer groups, and the spare
     // workgroups leave at once.
     const int vw = min(tw, W - txi * tw), vh = min(th, H - tyi * th);
-    // a group whose walk fits one batch hands its weights to the tile-level
-    // attribute-gradient kernel (k_blend_bwd_sg_attr) through wbuf / wcnt;
-    // wcnt = 0 marks a group that has none or did that product itself
-    uint32_t* const gcnt = wcnt + tile * 4 + pg;
-    if (pg * SG_PIX >= vw * vh) {
-        if (threadIdx.x == 0) *gcnt = 0u;
-        return;
-    }
+    if (pg * SG_PIX >= vw * vh) return;
     auto pixel_of = [&](int k) -> int {
         return k < vw * vh ? (tyi * th + k / vw) * W + txi * tw + k % vw : -1;
     };
@@ -542,7 +535,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     // then the walk's own final prefix sum_k w_k GV_k (out = sum_k w_k v_k),
     // else it is formed from the forward output first
     const bool one_batch = end - rg.x <= (uint32_t)SG_E;
-    if (threadIdx.x == 0) *gcnt = one_batch ? end - rg.x : 0u;
 
     if (end > rg.x && !one_batch) {
         int pixB[4];
@@ -864,15 +856,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                 }
             }
         };
-        if (one_batch) {
-            // weights of all 64 entry slots (zero past the walk) to the
-            // group's slot
-            float* wg = wbuf + (size_t)(tile * 4 + pg) * (SG_E * SG_PIX);
-            for (int i = threadIdx.x; i < SG_E * SG_PIX; i += blockDim.x) {
-                const int e = i / SG_PIX, px = i % SG_PIX;
-                wg[i] = e < m ? s_w[e][px] : 0.0f;
-            }
-        } else if (cb_hi > cb_lo) {
+        if (cb_hi > cb_lo) {
             switch (neb) {
                 case 1: da_phase(std::integral_constant<int, 1>{}); break;
                 case 2: da_phase(std::integral_constant<int, 2>{}); break;
@@ -881,144 +865,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
         }
         __syncthreads();
-    }
-}
-
-// dL/dv[s][k][f] = sum over the tile's pixels of w_k(p) g_{s,f}(p) for the
-// groups whose weights k_blend_bwd_sg left in wbuf: one workgroup per (tile,
-// slice of 128 columns), four waves of 32 columns, the contraction over up
-// to 256 pixels on the matrix cores, one atomic per (entry, column) and
-// tile (a quarter of the per-group count).
-constexpr int SGA_COLS = 128;
-
-template <int CS, bool TGT>
-__global__ __launch_bounds__(256) void k_blend_bwd_sg_attr(
-    const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges, int S, int Fc, int H, int W, int tw, int th,
-    int TX, SgUp up, float* __restrict__ d_attr, int64_t da_stride, const float* __restrict__ wbuf,
-    const uint32_t* __restrict__ wcnt)
-{
-    const int tile = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j4 = lane >> 4, l16 = lane & 15;
-    const int txi = tile % TX, tyi = tile / TX;
-    const int vw = min(tw, W - txi * tw), vh = min(th, H - tyi * th);
-    const int ngroups = (vw * vh + SG_PIX - 1) / SG_PIX;
-    const int F = Fc >> CS;
-    const size_t HW = (size_t)H * W;
-    // this wave's two 16-column blocks
-    const int ncb = S * Fc / 16;
-    const int cb0 = blockIdx.y * (SGA_COLS / 16) + 2 * wave;
-    const int ncbw = max(0, min(2, ncb - cb0));
-
-    uint32_t cnt[4], M = 0;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        cnt[g] = g < ngroups ? wcnt[tile * 4 + g] : 0u;
-        M = max(M, cnt[g]);
-    }
-    if (M == 0) return;
-    const float* mg = up.mgrad ? up.mgrad : (const float*)&sg_zero4;
-    const size_t mstr = up.mgrad ? 1 : 0;
-
-    __shared__ float s_w[SG_E][SG_PIX + 1];
-    __shared__ uint32_t s_g[SG_E];
-    const uint2 rg = ranges[tile];
-    if ((int)threadIdx.x < (int)M) s_g[threadIdx.x] = plist[rg.x + threadIdx.x];
-
-    auto run = [&](auto nebc) {
-        constexpr int NEB = decltype(nebc)::value;
-        f32x4 acc[2][NEB];
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int eb = 0; eb < NEB; ++eb) acc[q][eb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        float mk[2];
-        size_t cbase[2];
-        // (a wave past the last column block keeps a valid block for its
-        // addresses and loads nothing)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int cb = min(cb0 + (q < ncbw ? q : 0), ncb - 1);
-            const int s = cb * 16 / Fc;
-            const int c = cb * 16 - s * Fc + l16;
-            mk[q] = mg[((size_t)s * Fc + c) * mstr];
-            cbase[q] = (((size_t)(s * F + (c >> CS)) * HW) << CS) + (size_t)(c & CS);
-        }
-        for (int g = 0; g < ngroups; ++g) {
-            if (cnt[g] == 0) continue;  // uniform
-            // the group's weights (NEB x 16 rows of 64, as float4) and the
-            // upstream words of the wave's columns at pixel 4 kk + j4, all
-            // issued before the first wait
-            const float4* wg = (const float4*)(wbuf + (size_t)(tile * 4 + g) * (SG_E * SG_PIX));
-            float4 wst[NEB];
-#pragma unroll
-            for (int j = 0; j < NEB; ++j) wst[j] = wg[threadIdx.x + 256 * j];
-            float bq[2][16][TGT ? 2 : 1];
-            uint32_t pvalid = 0;
-            if (ncbw > 0) {
-#pragma unroll
-                for (int kk = 0; kk < 16; ++kk) {
-                    const int k = g * SG_PIX + 4 * kk + j4;
-                    const bool in = k < vw * vh;
-                    pvalid |= (in ? 1u : 0u) << kk;
-                    const size_t po = in ? ((size_t)((tyi * th + k / vw) * W + txi * tw + k % vw) << CS) : 0;
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const size_t i = cbase[q] + po;
-                        bq[q][kk][0] = TGT ? up.out[i] : up.dout[i];
-                        if constexpr (TGT) bq[q][kk][1] = up.tgt[i];
-                    }
-                }
-            }
-            __syncthreads();  // the previous group's weights are consumed
-#pragma unroll
-            for (int j = 0; j < NEB; ++j) {
-                const int i = 4 * (threadIdx.x + 256 * j);
-                const int e = i / SG_PIX, px = i % SG_PIX;
-                s_w[e][px] = wst[j].x;
-                s_w[e][px + 1] = wst[j].y;
-                s_w[e][px + 2] = wst[j].z;
-                s_w[e][px + 3] = wst[j].w;
-            }
-            __syncthreads();
-            if (ncbw == 0) continue;
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                float wv[NEB];
-#pragma unroll
-                for (int eb = 0; eb < NEB; ++eb) wv[eb] = s_w[16 * eb + l16][4 * kk + j4];
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const float u = TGT ? up.scale * (bq[q][kk][0] - bq[q][kk][TGT ? 1 : 0]) : bq[q][kk][0];
-                    const float b = ((pvalid >> kk) & 1u) ? u + mk[q] : 0.0f;
-#pragma unroll
-                    for (int eb = 0; eb < NEB; ++eb)
-                        acc[q][eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[eb], b, acc[q][eb], 0, 0, 0);
-                }
-            }
-        }
-        // lane holds entry 16 eb + 4 j4 + r, column 16 cb + l16
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (q >= ncbw) break;
-            const int cb = cb0 + q;
-            const int s = cb * 16 / Fc;
-            const int c = cb * 16 - s * Fc + l16;
-            float* dA = d_attr + s * da_stride + c;
-#pragma unroll
-            for (int eb = 0; eb < NEB; ++eb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int e = 16 * eb + 4 * j4 + r;
-                    if (e < (int)M && acc[q][eb][r] != 0.0f) unsafeAtomicAdd(dA + (size_t)s_g[e] * Fc, acc[q][eb][r]);
-                }
-        }
-    };
-    switch ((M + 15) >> 4) {
-        case 1: run(std::integral_constant<int, 1>{}); break;
-        case 2: run(std::integral_constant<int, 2>{}); break;
-        case 3: run(std::integral_constant<int, 3>{}); break;
-        default: run(std::integral_constant<int, 4>{}); break;
     }
 }
 
@@ -1073,14 +919,7 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
         hipLaunchKernelGGL(kern, grid, block, 0, s, (const GRec*)(ws + L.rec), (const uint32_t*)(ws + L.plist),
                            (const uint2*)(ws + L.ranges), a.data, a.query_stride, n_sets, Fc, L.H, L.W, tw_log,
                            L.th, L.TX, p.alpha_min, p.alpha_max, sup, (const uint32_t*)(ws + L.n_last),
-                           (float*)(ws + L.gacc), d_attr, a.query_stride, (float*)(ws + L.wbuf),
-                           (uint32_t*)(ws + L.wcnt));
-        auto kern2 = C == 2 ? (up.target ? k_blend_bwd_sg_attr<1, true> : k_blend_bwd_sg_attr<1, false>)
-                            : (up.target ? k_blend_bwd_sg_attr<0, true> : k_blend_bwd_sg_attr<0, false>);
-        hipLaunchKernelGGL(kern2, dim3(L.T, (n_sets * Fc + SGA_COLS - 1) / SGA_COLS), dim3(256), 0, s,
-                           (const uint32_t*)(ws + L.plist), (const uint2*)(ws + L.ranges), n_sets, Fc, L.H, L.W,
-                           L.tw, L.th, L.TX, sup, d_attr, a.query_stride, (const float*)(ws + L.wbuf),
-                           (const uint32_t*)(ws + L.wcnt));
+                           (float*)(ws + L.gacc), d_attr, a.query_stride);
         timing_end(tok, s);
     } else {
     int cg = choose_chan_group(Fc, p.chan_group);

@@ -81,8 +81,6 @@ struct Layout {
     int pair_blocks;      // max sort workgroups for cap keys
     size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;
     size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live, gacc;
-    size_t wbuf, wcnt;      // shared-geometry backward: per 64-pixel group weights and entry counts
-    size_t s_wbuf, s_wcnt;  // (one copy, not per query)
     size_t s_flags, s_rec, s_rect, s_status, s_tinfo, s_keys, s_partial, s_pkeys, s_plist, s_ranges,
         s_counts, s_totals, s_pix, s_g2d, s_live, s_gacc;
     size_t total;
