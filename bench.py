@@ -37,14 +37,15 @@ sys.path.insert(0, ROOT)
 PEAK_VALU_F32_TFLOPS = 78.6
 PEAK_MFMA_F32_TFLOPS = 157.3  # dense FP32 matrix cores
 PEAK_HBM_GBS = 8000.0
-# Algorithmic work of the compositing kernels, per set (attribute set):
-#  forward  : n_eval (pixel, entry) evaluations x FLOPS_PER_EVAL
+# Algorithmic work of the compositing kernels for B attribute sets over one
+# shared geometry (the training step):
+#  forward  : per set, n_eval (pixel, entry) evaluations x FLOPS_PER_EVAL
 #             + n_contrib accepted pairs x (2 Fc + FLOPS_PER_CONTRIB)
-#  backward : the re-walk, n_eval x FLOPS_PER_EVAL,
-#             + n_contrib x (4 Fc + FLOPS_BWD_CONTRIB): gv = v . g (2 Fc) and
-#             dL/dv += w g (2 Fc) -- the two products done on the matrix cores --
-#             plus dalpha, the transmittance/prefix updates and the 8
-#             geometric terms
+#  backward : per set, n_contrib x 4 Fc: gv = v . g (2 Fc) and dL/dv += w g
+#             (2 Fc), the two products on the matrix cores; once for all sets
+#             (the geometry is shared), the re-walk n_eval x FLOPS_PER_EVAL
+#             and n_contrib x FLOPS_BWD_CONTRIB for dalpha, the
+#             transmittance/prefix updates and the geometric terms
 FLOPS_PER_EVAL = 12.0       # offsets, quadratic form, exp, clamp and tests of one (pixel, entry)
 FLOPS_PER_CONTRIB = 4.0     # weight and transmittance update of one accepted pair
 FLOPS_BWD_CONTRIB = 22.0
@@ -206,9 +207,11 @@ def main():
     # every launch of the two compositing kernels during the timed steps
     Fc = 2 * F
     blend_flops = B * (n_eval * FLOPS_PER_EVAL + n_contrib * (2.0 * Fc + FLOPS_PER_CONTRIB))
-    bwd_flops = B * (n_eval * FLOPS_PER_EVAL + n_contrib * (4.0 * Fc + FLOPS_BWD_CONTRIB))
-    kt = {"k_blend<32>": (kernel_ms["blend"], blend_flops, "alu", PEAK_VALU_F32_TFLOPS),
-          "k_blend_bwd<32>": (kernel_ms["blend_bwd"], bwd_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
+    bwd_flops = B * n_contrib * 4.0 * Fc + n_eval * FLOPS_PER_EVAL + n_contrib * FLOPS_BWD_CONTRIB
+    fwd_name = "k_blend<%d>" % min(64, Fc)
+    bwd_name = "k_blend_bwd_sg<1, %s>" % ("true" if args.loss_mode == "target" else "false")
+    kt = {fwd_name: (kernel_ms["blend"], blend_flops, "alu", PEAK_VALU_F32_TFLOPS),
+          bwd_name: (kernel_ms["blend_bwd"], bwd_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
     kname = max(kt, key=lambda k: kt[k][0])
     ms, fl, bound, peak = kt[kname]
     ach = fl / (ms / 1e3) / 1e12
