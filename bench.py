@@ -68,10 +68,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mix", action="store_true")
-    ap.add_argument("--loss-mode", default="partial", choices=("partial", "target", "two_pass"),
-                    help="one-pass loss writing the elementwise gradient (partial), a loss pass without it "
-                         "and the gradient formed in the backward from the target (target), or loss + stored "
-                         "gradient (two_pass)")
+    ap.add_argument("--loss-mode", default="partial", choices=("partial", "fused", "target", "two_pass"),
+                    help="a one-pass loss writing the elementwise gradient (partial), the same folded into the "
+                         "compositing kernel (fused), a loss pass without the gradient, formed in the backward "
+                         "from the target (target), or loss + stored gradient (two_pass)")
     ap.add_argument("--mix-only", action="store_true", help="run only the uneven serving mix (for profiling)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: 2 training steps, then a 256 MiB copy that "

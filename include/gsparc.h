@@ -280,6 +280,29 @@ gs_status gs_loss_spectrum_stats(const float* spectrum, const float* target, int
                                  float* h_hat, float* mean_grad, float* d_partial, void* scratch,
                                  size_t scratch_bytes, void* stream);
 
+/*
+ * gs_render_blend() with the loss of gs_loss_spectrum_stats() fused into its
+ * output stage (Eq. (3) compositing, then Eq. (2) spatial means and Eq. (4)
+ * channel loss): as each spectrum element is written the kernel reads the
+ * target element, writes the elementwise gradient part to d_partial (when
+ * not NULL) and adds the per-channel sums the loss needs; a small second
+ * kernel forms loss, h_hat and mean_grad.  Same results as gs_render_blend()
+ * followed by gs_loss_spectrum_stats() (the spectrum and d_partial
+ * bit-identical, the loss sums up to float summation order), without a
+ * second pass over the spectrum.  Arguments: those of gs_render_blend(),
+ * then target [n_sets][F][H][W][c] (device), lambda_ch, and the outputs of
+ * gs_loss_spectrum_stats().  scratch (device, 256-byte aligned, caller-
+ * owned) holds the loss sums and one partial sum per wave: at least
+ * align256(n_sets*F*c*3*4) + n_sets*F*c*3 * tiles * (tile_h*tile_w/64) * 4
+ * bytes (tiles = ceil(H/tile_h) * ceil(W/tile_w)).  Errors as for either
+ * call; nothing is enqueued on an argument error.
+ */
+gs_status gs_render_blend_loss(const gs_attrs* attrs, int32_t n, int32_t n_queries, int32_t n_sets,
+                               const gs_grid* grid, const gs_params* prm, float* spectrum, void* workspace,
+                               size_t ws_bytes, const float* target, float lambda_ch, float* loss, float* h_hat,
+                               float* mean_grad, float* d_partial, void* scratch, size_t scratch_bytes,
+                               void* stream);
+
 /* ---- attribute network (shared form of the emission predictor, Eq. (1)) ----
  * Per (set s, Gaussian g):  h1 = relu(W1 [e_g, gamma(tx_s), 0] + b1),
  * h2 = relu(W2 h1 + b2), o = W3 h2 + b3, A_f = sigmoid(o_f - ln d),

@@ -2,6 +2,6 @@
 path): projection onto a receiver-centred equirectangular grid, tile binning
 with a (tile, depth) radix sort, and front-to-back compositing, as hand-written
 HIP kernels for gfx950 behind the C ABI of include/gsparc.h."""
-from .render import (Grid, Params, Workspace, backward, backward_l2, blend, forward, layout, live,  # noqa: F401
-                     loss_spectrum, loss_stats, prepare)
+from .render import (Grid, Params, Workspace, backward, backward_l2, blend, blend_loss, forward, layout,  # noqa: F401
+                     live, loss_spectrum, loss_stats, prepare)
 from .autograd import GSRender, render  # noqa: F401

@@ -112,6 +112,9 @@ SIGNATURES = {
                                   ctypes.POINTER(GsParams), c_p, c_sz, c_p]),
     "gs_render_blend": (c_i32, [ctypes.POINTER(GsAttrs), c_i32, c_i32, c_i32, ctypes.POINTER(GsGrid),
                                 ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p]),
+    "gs_render_blend_loss": (c_i32, [ctypes.POINTER(GsAttrs), c_i32, c_i32, c_i32, ctypes.POINTER(GsGrid),
+                                     ctypes.POINTER(GsParams), c_p, c_p, c_sz, c_p, c_f32, c_p, c_p, c_p, c_p, c_p,
+                                     c_sz, c_p]),
     "gs_render_backward": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries),
                                    c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p, c_p, c_p,
                                    c_p, c_p, c_p, c_i32, c_p, c_sz, c_p]),

@@ -274,6 +274,45 @@ gs_status gs_render_blend(const gs_attrs* attrs, int32_t n, int32_t n_queries, i
     return GS_OK;
 }
 
+gs_status gs_render_blend_loss(const gs_attrs* attrs, int32_t n, int32_t n_queries, int32_t n_sets,
+                               const gs_grid* grid, const gs_params* prm, float* spectrum, void* workspace,
+                               size_t ws_bytes, const float* target, float lambda_ch, float* loss, float* h_hat,
+                               float* mean_grad, float* d_partial, void* scratch, size_t scratch_bytes,
+                               void* stream)
+{
+    if (!attrs || !attrs->data || attrs->n_chan < 1 || attrs->query_stride < 0 || !spectrum || !grid || !prm)
+        return GS_ERR_INVALID_ARG;
+    if (!target || !loss || !h_hat || !mean_grad || !(lambda_ch >= 0.0f)) return GS_ERR_INVALID_ARG;
+    if (attrs->is_complex != 0 && attrs->is_complex != 1) return GS_ERR_INVALID_ARG;
+    if ((int64_t)attrs->n_chan * (attrs->is_complex ? 2 : 1) > 65536) return GS_ERR_CAPACITY;
+    if (n_sets < 1 || n_queries < 1) return GS_ERR_INVALID_ARG;
+    if (n_sets != n_queries && !(n_queries == 1 && prm->atten_ref == 0)) return GS_ERR_INVALID_ARG;
+    if (n_sets > 65535) return GS_ERR_CAPACITY;
+    Layout L;
+    gs_status st = make_layout(n, n_queries, grid, prm, &L);
+    if (st != GS_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255) || ws_bytes < L.total) return GS_ERR_WORKSPACE;
+    const int C = attrs->is_complex ? 2 : 1;
+    const int Fc = attrs->n_chan * C;
+    // scratch: the loss accumulators, then the per-wave partial sums
+    const int np = L.T * ((L.tw * L.th) >> 6);
+    const size_t acc_bytes = align256((size_t)n_sets * Fc * 3 * sizeof(float));
+    const size_t need = acc_bytes + (size_t)n_sets * Fc * 3 * np * sizeof(float);
+    if (!scratch || scratch_bytes < need || ((uintptr_t)scratch & 255)) return GS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    const size_t HW = (size_t)L.H * L.W;
+    float* acc = (float*)scratch;
+    float* part = (float*)((char*)scratch + acc_bytes);
+    const float scale = 2.0f / ((float)attrs->n_chan * (float)HW * (float)n_sets);
+    st = launch_blend(*attrs, *prm, L, n_sets, (char*)workspace, spectrum, s, target, d_partial, part, scale);
+    if (st != GS_OK) return st;
+    launch_loss_parts(n_sets, Fc, C, np, part, acc, s);
+    launch_loss_finish(n_sets, Fc, C, HW, lambda_ch, acc, h_hat, loss, mean_grad, s);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
 gs_status gs_render_live(int32_t n, int32_t n_queries, const gs_grid* grid, const gs_params* prm, void* workspace,
                          size_t ws_bytes, uint32_t* live_list, int64_t list_stride, uint32_t* live_count,
                          void* stream)

@@ -11,6 +11,8 @@
 // The whole workgroup leaves the list once every pixel has stopped.
 // The attribute row of the current Gaussian is wave-uniform and is read
 // through scalar loads.
+#include <type_traits>
+
 #include "common.h"
 
 namespace gs {
@@ -52,7 +54,7 @@ __device__ __forceinline__ void wave_sync_lds()
 // The buffers are passed as restrict parameters so that, once inlined, the
 // attribute rows are known not to alias the stores and load through the
 // scalar cache.
-template <int CG>
+template <int CG, bool FUSE = false>
 __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, int tile, int cg, int set,
                                                 const GRec* __restrict__ rec, const uint32_t* __restrict__ plist,
                                                 const uint2* __restrict__ ranges, const float* __restrict__ attr,
@@ -88,7 +90,7 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
     // CG = 16, 32: the channel sums out[p][f] = sum_e w[p][e] v[e][f] of a
     // run of 16 entries go to the FP32 matrix cores (v_mfma_f32_16x16x4_f32,
     // A = the wave's pixel weights from LDS, B = the entries' attribute
-    // rows); the walk only produces the weights.  Smaller groups (and 64)
+    // rows); the walk only produces the weights.  Smaller groups
     // accumulate on the VALU with the row in SGPRs.
     constexpr bool MF = CG == 16 || CG == 32 || CG == 64;
     constexpr int NB = MF ? CG / 16 : 1;
@@ -203,6 +205,22 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
         }
     }
     __syncthreads();  // the LDS batch may be reused by the caller's next item
+    // the fused loss (FUSE: k_blend with a target): per written element the
+    // target, the elementwise gradient part and the three sums,
+    // reduce-scattered over the wave (lane 4 k + 0 ends with channel k's
+    // totals) and stored per wave
+    constexpr bool fuse = FUSE;
+    // one of the sums (slot 0: out, 1: tgt, 2: squared error) of V channels
+    // from ch0 on
+    auto loss_sum = [&](auto vc, float* x, int ch0, int slot) {
+        constexpr int V = decltype(vc)::value;
+        wave_reduce_scatter<V>(x, lane);
+        constexpr int sh = V >= 64 ? 0 : (V == 32 ? 1 : (V == 16 ? 2 : (V == 8 ? 3 : (V == 4 ? 4 : (V == 2 ? 5 : 6)))));
+        if ((lane & ((1 << sh) - 1)) == 0) {
+            const int ch = ch0 + (lane >> sh);
+            J.lpart[(((size_t)set * Fc + ch) * 3 + slot) * J.lnp + (size_t)tile * (nthr >> 6) + wave] = x[0];
+        }
+    };
     if constexpr (MF) {
         // lane holds out[pixel 16 pb + 4 (lane/16) + r][channel 16 nb + lane%16]:
         // transpose through LDS so that each lane writes its own pixel
@@ -214,7 +232,35 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) tr[(16 * pb + 4 * (lane >> 4) + r) * 17 + (lane & 15)] = macc[pb][nb][r];
             wave_sync_lds();
-            if (inside) {
+            if constexpr (fuse) {
+                // two 16-value arrays at a time next to the accumulators;
+                // the 16 target loads are issued before any store (the
+                // buffers are not known not to alias, so a store would
+                // order the loads after it)
+                const int ch0 = cg * CG + 16 * nb;
+                float x[16], y[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    y[k] = inside ? J.tgt[obase + spec_offset(ch0 + k, pix, cs, HW)] : 0.0f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const size_t idx = obase + spec_offset(ch0 + k, pix, cs, HW);
+                    const float o = tr[lane * 17 + k];
+                    if (inside) {
+                        ((GLOBAL_AS float*)out)[idx] = o;
+                        if (J.dpart) J.dpart[idx] = J.lscale * (o - y[k]);
+                    }
+                    x[k] = inside ? o : 0.0f;
+                }
+                loss_sum(std::integral_constant<int, 16>{}, x, ch0, 0);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const float d = tr[lane * 17 + k] - y[k];
+                    x[k] = inside ? d * d : 0.0f;
+                }
+                loss_sum(std::integral_constant<int, 16>{}, x, ch0, 2);
+                loss_sum(std::integral_constant<int, 16>{}, y, ch0, 1);
+            } else if (inside) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     const int ch = cg * CG + 16 * nb + k;
@@ -223,13 +269,35 @@ __device__ __forceinline__ void blend_tile_impl(const BlendJob& J, BlendLds& S, 
             }
             wave_sync_lds();
         }
+    } else {
+        if constexpr (fuse) {
+            float x[CG], y[CG];
+#pragma unroll
+            for (int k = 0; k < CG; ++k) y[k] = inside ? J.tgt[obase + spec_offset(cg * CG + k, pix, cs, HW)] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < CG; ++k) {
+                const size_t idx = obase + spec_offset(cg * CG + k, pix, cs, HW);
+                if (inside) {
+                    ((GLOBAL_AS float*)out)[idx] = acc[k];
+                    if (J.dpart) J.dpart[idx] = J.lscale * (acc[k] - y[k]);
+                }
+                x[k] = inside ? (acc[k] - y[k]) * (acc[k] - y[k]) : 0.0f;
+            }
+            loss_sum(std::integral_constant<int, CG>{}, x, cg * CG, 2);
+            loss_sum(std::integral_constant<int, CG>{}, y, cg * CG, 1);
+#pragma unroll
+            for (int k = 0; k < CG; ++k) x[k] = inside ? acc[k] : 0.0f;
+            loss_sum(std::integral_constant<int, CG>{}, x, cg * CG, 0);
+        }
     }
     if (!inside) return;
     if constexpr (!MF) {
+        if constexpr (!fuse) {
 #pragma unroll
-        for (int k = 0; k < CG; ++k) {
-            const int ch = cg * CG + k;
-            ((GLOBAL_AS float*)out)[obase + spec_offset(ch, pix, cs, HW)] = acc[k];
+            for (int k = 0; k < CG; ++k) {
+                const int ch = cg * CG + k;
+                ((GLOBAL_AS float*)out)[obase + spec_offset(ch, pix, cs, HW)] = acc[k];
+            }
         }
     }
     if (cg == 0 && set == q && T_final) {
@@ -246,7 +314,7 @@ __device__ __forceinline__ void blend_tile(const BlendJob& J, BlendLds& S, int t
                         J.n_contrib);
 }
 
-template <int CG>
+template <int CG, bool FUSE>
 __global__ __launch_bounds__(256) void k_blend(BlendJob J, const GRec* __restrict__ rec,
                                                const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
                                                const float* __restrict__ attr, float* __restrict__ out,
@@ -254,8 +322,8 @@ __global__ __launch_bounds__(256) void k_blend(BlendJob J, const GRec* __restric
                                                uint32_t* __restrict__ n_contrib)
 {
     __shared__ BlendLds S;
-    blend_tile_impl<CG>(J, S, blockIdx.x, blockIdx.y, blockIdx.z, rec, plist, ranges, attr, out, T_final, n_last,
-                        n_contrib);
+    blend_tile_impl<CG, FUSE>(J, S, blockIdx.x, blockIdx.y, blockIdx.z, rec, plist, ranges, attr, out, T_final,
+                              n_last, n_contrib);
 }
 
 // Persistent blend over a table of jobs (scenes of any size, grid, tile
@@ -439,6 +507,11 @@ BlendJob make_blend_job(const gs_attrs& a, const gs_params& p, const Layout& L, 
     J.n_last = (uint32_t*)(ws + L.n_last);
     J.n_contrib = (uint32_t*)(ws + L.n_contrib);
     J.s_pix = L.s_pix / 4;
+    J.tgt = nullptr;
+    J.dpart = nullptr;
+    J.lpart = nullptr;
+    J.lnp = 0;
+    J.lscale = 0.0f;
     return J;
 }
 
@@ -455,28 +528,39 @@ int choose_chan_group(int Fc, int requested)
 }
 
 gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
-                       hipStream_t s)
+                       hipStream_t s, const float* tgt, float* dpart, float* lpart, float lscale)
 {
     const int C = a.is_complex ? 2 : 1;
     const int Fc = a.n_chan * C;
-    const int cg = choose_chan_group(Fc, p.chan_group);
+    int cg = choose_chan_group(Fc, p.chan_group);
+    if (tgt && cg > 32) cg = 32;  // the fused loss stage needs the registers of a 64-channel group
     if (Fc / cg > 65535) return GS_ERR_CAPACITY;
     BlendJob J = make_blend_job(a, p, L, n_sets, ws, out);
     J.cg = cg;
     J.ncg = Fc / cg;
+    J.tgt = tgt;
+    J.dpart = dpart;
+    J.lpart = lpart;
+    J.lnp = L.T * ((L.tw * L.th) >> 6);
+    J.lscale = lscale;
     dim3 grid(L.T, Fc / cg, n_sets), block(L.tw * L.th);
 #define ARGS J.rec, J.plist, J.ranges, J.attr, J.out, J.T_final, J.n_last, J.n_contrib
     void* tok;
     timing_begin(TK_BLEND, s, &tok);
-    switch (cg) {
-        case 1: hipLaunchKernelGGL(k_blend<1>, grid, block, 0, s, J, ARGS); break;
-        case 2: hipLaunchKernelGGL(k_blend<2>, grid, block, 0, s, J, ARGS); break;
-        case 4: hipLaunchKernelGGL(k_blend<4>, grid, block, 0, s, J, ARGS); break;
-        case 8: hipLaunchKernelGGL(k_blend<8>, grid, block, 0, s, J, ARGS); break;
-        case 16: hipLaunchKernelGGL(k_blend<16>, grid, block, 0, s, J, ARGS); break;
-        case 32: hipLaunchKernelGGL(k_blend<32>, grid, block, 0, s, J, ARGS); break;
-        default: hipLaunchKernelGGL(k_blend<64>, grid, block, 0, s, J, ARGS); break;
-    }
+    auto go = [&](auto fz) {
+        constexpr bool FZ = decltype(fz)::value;
+        switch (cg) {
+            case 1: hipLaunchKernelGGL((k_blend<1, FZ>), grid, block, 0, s, J, ARGS); break;
+            case 2: hipLaunchKernelGGL((k_blend<2, FZ>), grid, block, 0, s, J, ARGS); break;
+            case 4: hipLaunchKernelGGL((k_blend<4, FZ>), grid, block, 0, s, J, ARGS); break;
+            case 8: hipLaunchKernelGGL((k_blend<8, FZ>), grid, block, 0, s, J, ARGS); break;
+            case 16: hipLaunchKernelGGL((k_blend<16, FZ>), grid, block, 0, s, J, ARGS); break;
+            case 32: hipLaunchKernelGGL((k_blend<32, FZ>), grid, block, 0, s, J, ARGS); break;
+            default: hipLaunchKernelGGL((k_blend<64, FZ>), grid, block, 0, s, J, ARGS); break;
+        }
+    };
+    if (tgt) go(std::true_type{});
+    else go(std::false_type{});
     timing_end(tok, s);
 #undef ARGS
     return GS_OK;

@@ -32,37 +32,6 @@ constexpr double LOG2E_B = 1.4426950408889634;
 // read-only attribute rows through the scalar/constant path where uniform
 typedef __attribute__((address_space(4))) const float CFloatB;
 
-// Butterfly reduce-scatter of V values over the 64 lanes of a wave.  On
-// return x[0] of lane l holds the wave total of value (l >> (6 - log2 V)).
-// Each stage exchanges half of the remaining values with the lane at xor
-// distance M; all sizes are compile-time so the arrays stay in registers.
-template <int V, int M>
-__device__ __forceinline__ void reduce_scatter_step(float* x, int lane)
-{
-    if constexpr (M >= 1) {
-        if constexpr (V > 1) {
-            constexpr int half = V / 2;
-            const bool up = (lane & M) != 0;
-#pragma unroll
-            for (int i = 0; i < half; ++i) {
-                const float send = up ? x[i] : x[i + half];
-                const float keep = up ? x[i + half] : x[i];
-                x[i] = keep + __shfl_xor(send, M, 64);
-            }
-            reduce_scatter_step<half, M / 2>(x, lane);
-        } else {
-            x[0] += __shfl_xor(x[0], M, 64);
-            reduce_scatter_step<1, M / 2>(x, lane);
-        }
-    }
-}
-
-template <int V>
-__device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
-{
-    reduce_scatter_step<V, 32>(x, lane);
-}
-
 // The same reduce-scatter for 8 values without the LDS crossbar: lane
 // halves and quarter rows are exchanged with v_permlane32_swap /
 // v_permlane16_swap (each swap also moves the partner's half, so one add

@@ -48,6 +48,17 @@ struct BlendJob {
     size_t s_pix;
     uint32_t item_begin;  // first work item of this job in a persistent launch
     int query0;           // index of the job's first query in the batch
+    // training loss fused into the output stage (k_blend only; null = off):
+    // reads the target at each written element, writes lscale (out - tgt)
+    // to dpart (when set), and each wave stores its sums of out, of tgt and
+    // of (out - tgt)^2 per (set, channel component) to
+    // lpart[((set * F*c + ch) * 3 + slot) * lnp + tile * waves + wave]
+    // (no atomics: a few hundred workgroups add into every channel)
+    const float* tgt;
+    float* dpart;
+    float* lpart;
+    int lnp;
+    float lscale;
 };
 
 // Offset of channel component ch (0 <= ch < F*C) of pixel pix inside one
@@ -55,6 +66,37 @@ struct BlendJob {
 __device__ __forceinline__ size_t spec_offset(int ch, size_t pix, int cs, size_t HW)
 {
     return (size_t)(ch & ~cs) * HW + (size_t)(ch & cs) + (pix << cs);
+}
+
+// Butterfly reduce-scatter of V values over the 64 lanes of a wave.  On
+// return x[0] of lane l holds the wave total of value (l >> (6 - log2 V)).
+// Each stage exchanges half of the remaining values with the lane at xor
+// distance M; all sizes are compile-time so the arrays stay in registers.
+template <int V, int M>
+__device__ __forceinline__ void reduce_scatter_step(float* x, int lane)
+{
+    if constexpr (M >= 1) {
+        if constexpr (V > 1) {
+            constexpr int half = V / 2;
+            const bool up = (lane & M) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const float send = up ? x[i] : x[i + half];
+                const float keep = up ? x[i + half] : x[i];
+                x[i] = keep + __shfl_xor(send, M, 64);
+            }
+            reduce_scatter_step<half, M / 2>(x, lane);
+        } else {
+            x[0] += __shfl_xor(x[0], M, 64);
+            reduce_scatter_step<1, M / 2>(x, lane);
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
+{
+    reduce_scatter_step<V, 32>(x, lane);
 }
 
 constexpr int SORT_THREADS = 256;
@@ -106,7 +148,14 @@ void launch_project(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, 
 void launch_depth_sort(const Layout& L, char* ws, hipStream_t s);
 void launch_binning(const Layout& L, char* ws, hipStream_t s);
 gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
-                       hipStream_t s);
+                       hipStream_t s, const float* tgt = nullptr, float* dpart = nullptr, float* lpart = nullptr,
+                       float lscale = 0.0f);
+// loss accumulators [set][F*c][3] from the per-wave sums of the fused
+// blend (np partials per entry), then loss, spatial means and the
+// channel-mean gradient term from them (loss.hip)
+void launch_loss_parts(int n_sets, int Fc, int C, int np, const float* part, float* acc, hipStream_t s);
+void launch_loss_finish(int n_sets, int Fc, int C, size_t HW, float lambda, const float* acc, float* h_hat,
+                        float* loss, float* mean_grad, hipStream_t s);
 void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, size_t s_list, uint32_t* count,
                  hipStream_t s);
 gs_status check_forward(const gs_scene* sc, const gs_attrs* a, const gs_queries* qs, const gs_grid* g,

@@ -149,6 +149,39 @@ __global__ void k_loss_finish(int B, int Fc, int C, size_t HW, float lambda, con
     }
 }
 
+// acc[set][ch][slot] = sum of the np per-wave partials (slot 2, the squared
+// error, of both components of a complex channel into its first component)
+__global__ __launch_bounds__(256) void k_loss_parts(int n_sets, int Fc, int C, int np, const float* __restrict__ part,
+                                                    float* __restrict__ acc)
+{
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);  // (set, ch, slot), one wave each
+    const int lane = threadIdx.x & 63;
+    if (i >= n_sets * Fc * 3) return;
+    const int slot = i % 3, ch = (i / 3) % Fc;
+    float v = 0.0f;
+    if (slot < 2 || ch % C == 0) {
+        for (int c = 0; c < (slot == 2 ? C : 1); ++c) {
+            const float* p = part + (size_t)(i + 3 * c) * np;
+            for (int k = lane; k < np; k += 64) v += p[k];
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) acc[i] = v;
+}
+
+void launch_loss_parts(int n_sets, int Fc, int C, int np, const float* part, float* acc, hipStream_t s)
+{
+    const int n = n_sets * Fc * 3;
+    hipLaunchKernelGGL(k_loss_parts, dim3((n + 3) / 4), dim3(256), 0, s, n_sets, Fc, C, np, part, acc);
+}
+
+void launch_loss_finish(int n_sets, int Fc, int C, size_t HW, float lambda, const float* acc, float* h_hat,
+                        float* loss, float* mean_grad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss_finish, dim3(n_sets), dim3(256), 0, s, n_sets, Fc, C, HW, lambda, acc, h_hat, loss,
+                       mean_grad);
+}
+
 }  // namespace gs
 
 using namespace gs;

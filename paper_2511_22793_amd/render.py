@@ -213,6 +213,51 @@ def blend(workspace: Workspace, attr: torch.Tensor, n_sets: Optional[int] = None
     return out
 
 
+def blend_loss(workspace: Workspace, attr: torch.Tensor, target: torch.Tensor, lambda_ch: float = 1.0,
+               n_sets: Optional[int] = None, is_complex: bool = False, out: Optional[torch.Tensor] = None,
+               partial: Optional[torch.Tensor] = None):
+    """blend() with loss_stats() fused into the compositing kernel's output
+    stage (gs_render_blend_loss): returns (spectrum, loss per set, h_hat,
+    mean_grad, scale); `partial`, when given, receives scale (spectrum -
+    target) from the same pass."""
+    _check_f32("attr", attr)
+    n, B = workspace.n, workspace.nq
+    per_set = attr.dim() == (4 if is_complex else 3)
+    S = attr.shape[0] if per_set else (n_sets if n_sets is not None else B)
+    if n_sets is not None and n_sets != S:
+        raise ValueError("n_sets %d does not match attr" % n_sets)
+    a = _attrs_c(attr, n, S, is_complex)
+    F, H, W = a.n_chan, workspace.grid.H, workspace.grid.W
+    C = 2 if is_complex else 1
+    shape = (S, F, H, W) + ((2,) if is_complex else ())
+    dev = attr.device
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
+    else:
+        _check_f32("out", out, shape)
+    _check_f32("target", target, shape)
+    if partial is not None:
+        _check_f32("partial", partial, shape)
+    loss = torch.empty(S, device=dev)
+    hhat = torch.empty((S, F, 2) if is_complex else (S, F), device=dev)
+    mgrad = torch.empty(S, F * C, device=dev)
+    gr = workspace.grid
+    tiles = -(-gr.H // gr.tile_h) * -(-gr.W // gr.tile_w)
+    nacc = S * F * C * 3
+    nbytes = -(-nacc * 4 // 256) * 256 + nacc * tiles * (gr.tile_h * gr.tile_w // 64) * 4
+    scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    g, p = workspace.grid.c(), workspace.params.c()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_render_blend_loss(ctypes.byref(a), n, B, S, ctypes.byref(g), ctypes.byref(p), _ptr(out),
+                                     ctypes.c_void_p(workspace.ptr), workspace.nbytes, _ptr(target),
+                                     float(lambda_ch), _ptr(loss), _ptr(hhat), _ptr(mgrad), _ptr(partial),
+                                     ctypes.c_void_p(base + off), scratch.numel() - off, ctypes.c_void_p(stream)),
+          "gs_render_blend_loss")
+    return out, loss, hhat, mgrad, 2.0 / (F * H * W * S)
+
+
 def backward(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Tensor, spectrum: torch.Tensor,
              d_spectrum: torch.Tensor, tx: Optional[torch.Tensor] = None, is_complex: bool = False,
              n_sets: Optional[int] = None, d_attr: Optional[torch.Tensor] = None, out: Optional[dict] = None) -> dict:

@@ -21,7 +21,8 @@ import numpy as np
 import torch
 
 from . import mlp as gm
-from .render import Grid, Params, Workspace, backward, backward_l2, blend, live, loss_spectrum, loss_stats, prepare
+from .render import (Grid, Params, Workspace, backward, backward_l2, blend, blend_loss, live, loss_spectrum,
+                     loss_stats, prepare)
 
 F = gm.F
 
@@ -59,8 +60,8 @@ class LearnedScene:
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
-        if loss_mode not in ("partial", "target", "two_pass"):
-            raise ValueError("loss_mode is 'partial', 'target' or 'two_pass'")
+        if loss_mode not in ("fused", "partial", "target", "two_pass"):
+            raise ValueError("loss_mode is 'fused', 'partial', 'target' or 'two_pass'")
         self.loss_mode = loss_mode
         self.n = n = scene["opacity_logit"].shape[0]
         self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
@@ -121,26 +122,39 @@ class LearnedScene:
         gm.embed(self.net, self.E_bf, self.Z1)
         gm.forward(self.net, self.Z1, sc["mean"], self._rows(tx), self.attr, self.state)
         mark("mlp_fwd")
-        spec = blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
-        mark("blend")
-        if self.loss_mode == "partial":
-            # one pass over (spectrum, target): loss, channel means and the
-            # elementwise gradient; the backward adds the channel-mean term
-            loss, _, mgrad, scale = loss_stats(spec, target, True, self.lambda_ch, partial=self.dpart)
+        if self.loss_mode == "fused":
+            # the loss pass folded into the compositing kernel's output stage:
+            # loss, channel means and the elementwise gradient part written
+            # as the spectrum is written; the backward adds the channel-mean
+            # term
+            spec, loss, _, mgrad, scale = blend_loss(self.ws, self.attr, target, self.lambda_ch, n_sets=self.B,
+                                                     is_complex=True, out=self.spec, partial=self.dpart)
+            mark("blend")
             mark("loss")
             backward_l2(self.ws, sc, self.attr, self.rx, spec, None, mgrad, scale, partial=self.dpart,
                         is_complex=True, n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
-        elif self.loss_mode == "target":
-            # the backward forms the elementwise part from (spec, target)
-            loss, _, mgrad, scale = loss_stats(spec, target, True, self.lambda_ch)
-            mark("loss")
-            backward_l2(self.ws, sc, self.attr, self.rx, spec, target, mgrad, scale, is_complex=True,
-                        n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
         else:
-            loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
-            mark("loss")
-            backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
-                     d_attr=self.d_attr, out=self.ggrads)
+            spec = blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
+            mark("blend")
+            if self.loss_mode == "partial":
+                # one pass over (spectrum, target): loss, channel means and
+                # the elementwise gradient; the backward adds the
+                # channel-mean term
+                loss, _, mgrad, scale = loss_stats(spec, target, True, self.lambda_ch, partial=self.dpart)
+                mark("loss")
+                backward_l2(self.ws, sc, self.attr, self.rx, spec, None, mgrad, scale, partial=self.dpart,
+                            is_complex=True, n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
+            elif self.loss_mode == "target":
+                # the backward forms the elementwise part from (spec, target)
+                loss, _, mgrad, scale = loss_stats(spec, target, True, self.lambda_ch)
+                mark("loss")
+                backward_l2(self.ws, sc, self.attr, self.rx, spec, target, mgrad, scale, is_complex=True,
+                            n_sets=self.B, d_attr=self.d_attr, out=self.ggrads)
+            else:
+                loss, _, dspec = loss_spectrum(spec, target, True, self.lambda_ch)
+                mark("loss")
+                backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
+                         d_attr=self.d_attr, out=self.ggrads)
         mark("render_bwd")
         self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
                                   self.mgrads, clear_d_attr=True)

@@ -76,3 +76,24 @@ def test_network_beats_fixed_attributes_on_held_out_transmitters():
     e_learned, e_fixed = nmse(pl, ref), nmse(pf, ref)
     print("held-out NMSE: network %.4f, fixed attributes %.4f" % (e_learned, e_fixed))
     assert e_learned < 0.7 * e_fixed
+
+
+@pytest.mark.parametrize("mode", ["fused", "two_pass"])
+def test_loss_modes_take_the_same_step(mode):
+    # the one-pass loss (default), the loss folded into the compositing
+    # kernel and the two-pass loss give the same loss and, after one step,
+    # the same parameters up to float summation order
+    grid = gs.Grid(45, 180, 16, 16)
+    n, B = 600, 4
+    sc, tx, target = ground_truth(n, B, grid=grid)
+    txt = torch.from_numpy(tx).cuda()
+    models = [train.LearnedScene(sc, synth.embeddings(n), mlp_ref.init(2), [0, 0, 0], B, LO, HI, grid=grid,
+                                 total_steps=4, loss_mode=m) for m in ("partial", mode)]
+    losses = [m.train_step(txt, target) for m in models]
+    torch.cuda.synchronize()
+    assert torch.allclose(losses[0], losses[1], rtol=2e-5)
+    for k in ("mean", "log_scale", "quat", "opacity_logit"):
+        a, b = models[0].g[k], models[1].g[k]
+        assert torch.allclose(a, b, rtol=1e-4, atol=1e-6), k
+    for k in models[0].net.w:
+        assert torch.allclose(models[0].net.w[k], models[1].net.w[k], rtol=1e-4, atol=1e-6), k
