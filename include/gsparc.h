@@ -121,6 +121,11 @@ typedef struct {
  * geometry once for all sets and channels; both give the same gradients up
  * to summation order).  For comparisons and tests. */
 #define GS_OPT_BWD_PER_GROUP 2
+/* options: gs_render_blend() takes the per-set, per-channel-group kernel
+ * even where the sets share one geometry (the default there walks each
+ * pixel once for all sets and forms the channel sums on the matrix cores;
+ * the spectra agree to FP32 summation order).  For comparisons and tests. */
+#define GS_OPT_BLEND_PER_GROUP 4
 
 /* Per-query device-side results, read with gs_read_flags(). */
 typedef struct {

@@ -44,6 +44,7 @@ class GsParams(ctypes.Structure):
 
 GS_OPT_FORWARD_ONLY = 1
 GS_OPT_BWD_PER_GROUP = 2
+GS_OPT_BLEND_PER_GROUP = 4
 
 
 class GsFlags(ctypes.Structure):

@@ -16,7 +16,7 @@ static int bits_for(uint64_t v)  // bits needed to hold values 0..v
 gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* p, Layout* L)
 {
     if (n < 1 || nq < 1 || !g || !p) return GS_ERR_INVALID_ARG;
-    if (p->options & ~(GS_OPT_FORWARD_ONLY | GS_OPT_BWD_PER_GROUP)) return GS_ERR_INVALID_ARG;
+    if (p->options & ~(GS_OPT_FORWARD_ONLY | GS_OPT_BWD_PER_GROUP | GS_OPT_BLEND_PER_GROUP)) return GS_ERR_INVALID_ARG;
     if (g->H < 1 || g->W < 2 || g->tile_h < 1 || g->tile_w < 1) return GS_ERR_INVALID_ARG;
     const int nthr = g->tile_h * g->tile_w;
     if (nthr != 64 && nthr != 128 && nthr != 256) return GS_ERR_INVALID_ARG;

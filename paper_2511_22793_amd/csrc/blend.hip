@@ -515,6 +515,214 @@ BlendJob make_blend_job(const gs_attrs& a, const gs_params& p, const Layout& L, 
     return J;
 }
 
+// ---------------------------------------------------------------------------
+// Compositing of S attribute sets over one shared geometry (the training
+// batch: one receiver, S transmitters whose effect is in the attributes).
+// The pixel weight w_k(p) = T_k alpha_k a_k and the walk's decisions do not
+// depend on the set, so out[s][f](p) = sum_k w_k(p) v[s][k][f] is one
+// product of the weights W (entries x pixels) with the attribute rows V
+// (entries x S*F*c columns).  One workgroup (8 waves) takes 64 pixels of a
+// tile (the tile's in-image pixels packed into groups of 64): wave 0 walks
+// the list once per pixel (the same decisions, in the same order, as
+// k_blend), the weights of up to SGF_BUF entries collect in LDS, and the
+// eight waves then form out = W^T V on the FP32 matrix cores, each for its
+// share of the columns.  A walk longer than the buffer flushes it and the
+// next products add to the stored spectrum (only this workgroup writes
+// these pixels).
+// ---------------------------------------------------------------------------
+constexpr int SGF_WAVES = 8;
+constexpr int SGF_PIX = 64;
+constexpr int SGF_BATCH = 64;   // entries staged per walk step
+constexpr int SGF_BUF = 128;    // entries whose weights the LDS holds
+
+template <int CS>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_sg(
+    const GRec* __restrict__ rec, const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
+    const float* __restrict__ attr, int64_t a_stride, int S, int Fc, int H, int W, int tw, int th, int TX,
+    float amin, float amax, float tmin, float* __restrict__ out, float* __restrict__ T_final,
+    uint32_t* __restrict__ n_last, uint32_t* __restrict__ n_contrib)
+{
+    const int tile = blockIdx.x, pg = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j4 = lane >> 4, l16 = lane & 15;
+    const int txi = tile % TX, tyi = tile / TX;
+    const int vw = min(tw, W - txi * tw), vh = min(th, H - tyi * th);
+    if (pg * SGF_PIX >= vw * vh) return;
+    const uint2 rg = ranges[tile];
+    const size_t HW = (size_t)H * W;
+    const int F = Fc >> CS;
+    const int ncb = S * Fc / 16;  // 16-column blocks (Fc % 16 == 0)
+    const int cb_lo = wave * ncb / SGF_WAVES, cb_hi = (wave + 1) * ncb / SGF_WAVES;
+
+    __shared__ float s_w[SGF_BUF][SGF_PIX + 1];         // weights of the buffered entries
+    __shared__ uint32_t s_gb[SGF_BUF];                   // their Gaussians
+    __shared__ float s_t[SGF_WAVES][16][SGF_PIX + 1];   // per-wave output transpose
+    __shared__ double s_px[SGF_BATCH], s_py[SGF_BATCH], s_ca[SGF_BATCH], s_cb[SGF_BATCH], s_cc[SGF_BATCH];
+    __shared__ float s_sig[SGF_BATCH], s_att[SGF_BATCH];
+    __shared__ uint32_t s_g[SGF_BATCH];
+    __shared__ int s_pix[SGF_PIX];
+    __shared__ int s_walked, s_alldone;
+
+    if (threadIdx.x < SGF_PIX) {
+        const int k = pg * SGF_PIX + threadIdx.x;
+        s_pix[threadIdx.x] = k < vw * vh ? (tyi * th + k / vw) * W + txi * tw + k % vw : -1;
+    }
+    __syncthreads();
+    // the walking wave's pixel and state
+    const int wpix = s_pix[lane];
+    const double pcx = (wpix >= 0 ? wpix % W : 0) + 0.5, pcy = (wpix >= 0 ? wpix / W : 0) + 0.5;
+    const double halfW = 0.5 * W, Wd = (double)W;
+    float T = 1.0f;
+    uint32_t last = 0, cnt = 0;
+    bool done = wpix < 0;
+
+    // out = W^T V over the nbuf buffered entries for this wave's columns;
+    // add: add to what an earlier flush stored
+    auto contract = [&](int nbuf, bool add) {
+        const int nks = (nbuf + 3) >> 2;  // K-steps of 4 entries (rows past nbuf hold zero weights)
+        for (int cb = cb_lo; cb < cb_hi; ++cb) {
+            const int s = cb * 16 / Fc;
+            const int c0 = cb * 16 - s * Fc;
+            const CFloat* vb = (const CFloat*)(attr + s * a_stride + c0 + l16);
+            // the B operands of every K-step first (independent loads)
+            float bq[SGF_BUF / 4];
+#pragma unroll
+            for (int ks = 0; ks < SGF_BUF / 4; ++ks)
+                if (ks < nks) bq[ks] = vb[(size_t)s_gb[4 * ks + j4] * Fc];
+            f32x4 acc[4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) acc[pb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < SGF_BUF / 4; ++ks) {
+                if (ks < nks) {
+#pragma unroll
+                    for (int pb = 0; pb < 4; ++pb)
+                        acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_w[4 * ks + j4][16 * pb + l16], bq[ks],
+                                                                       acc[pb], 0, 0, 0);
+                }
+            }
+            // lane holds out[pixel 16 pb + 4 j4 + r][column c0 + l16]: through
+            // LDS so that each lane stores its own pixel
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s_t[wave][l16][16 * pb + 4 * j4 + r] = acc[pb][r];
+            wave_sync_lds();
+            const int px = s_pix[lane];
+            if (px >= 0) {
+                float* ob = out + ((size_t)s * F * HW << CS);
+                if constexpr (CS == 1) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        float2* o2 = (float2*)(ob + (((size_t)((c0 >> 1) + q) * HW + px) << 1));
+                        float2 v = float2{s_t[wave][2 * q][lane], s_t[wave][2 * q + 1][lane]};
+                        if (add) {
+                            const float2 o = *o2;
+                            v.x += o.x;
+                            v.y += o.y;
+                        }
+                        *o2 = v;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        float* o1 = ob + (size_t)(c0 + q) * HW + px;
+                        const float v = s_t[wave][q][lane];
+                        *o1 = add ? *o1 + v : v;
+                    }
+                }
+            }
+            wave_sync_lds();
+        }
+    };
+
+    int nbuf = 0;
+    bool stored = false, alldone = false;
+    for (uint32_t b0 = rg.x; b0 < rg.y && !alldone; b0 += SGF_BATCH) {
+        const int m = (int)min((uint32_t)SGF_BATCH, rg.y - b0);
+        if ((int)threadIdx.x < m) {
+            const uint32_t g = plist[b0 + threadIdx.x];
+            const GRec r = rec[g];
+            s_px[threadIdx.x] = r.px;
+            s_py[threadIdx.x] = r.py;
+            s_ca[threadIdx.x] = r.ca;
+            s_cb[threadIdx.x] = r.cb;
+            s_cc[threadIdx.x] = r.cc;
+            s_sig[threadIdx.x] = r.sigma;
+            s_att[threadIdx.x] = r.att;
+            s_g[threadIdx.x] = g;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // the walk, as in k_blend: stop before an entry that would take
+            // T below T_min; entries past the group's last live pixel are
+            // not buffered
+            int j = 0;
+            for (; j < m; ++j) {
+                if (__ballot(!done) == 0ull) break;
+                float wgt = 0.0f;
+                if (!done) {
+                    double dx = pcx - s_px[j];
+                    dx += dx >= halfW ? -Wd : (dx < -halfW ? Wd : 0.0);
+                    const double dy = pcy - s_py[j];
+                    const double qv = s_ca[j] * dx * dx + 2.0 * s_cb[j] * dx * dy + s_cc[j] * dy * dy;
+                    const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
+                    const float alpha = fminf(amax, s_sig[j] * G);
+                    const float Tn = T * (1.0f - alpha);
+                    const bool stop = alpha >= amin && Tn < tmin;
+                    const bool take = alpha >= amin && !stop;
+                    done = stop;
+                    wgt = take ? T * alpha * s_att[j] : 0.0f;
+                    T = take ? Tn : T;
+                    last = take ? b0 + j + 1 - rg.x : last;
+                    cnt += take ? 1u : 0u;
+                }
+                s_w[nbuf + j][lane] = wgt;
+                if (lane == 0) s_gb[nbuf + j] = s_g[j];
+            }
+            // zero weight rows up to the next multiple of 4 (valid Gaussians)
+            for (int k = j; k < ((j + 3) & ~3); ++k) {
+                s_w[nbuf + k][lane] = 0.0f;
+                if (lane == 0) s_gb[nbuf + k] = s_g[0];
+            }
+            const bool ad = __ballot(!done) == 0ull;
+            if (lane == 0) {
+                s_walked = j;
+                s_alldone = ad ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        nbuf += s_walked;
+        alldone = s_alldone != 0;
+        const bool last_batch = alldone || b0 + SGF_BATCH >= rg.y;
+        if (last_batch || nbuf + SGF_BATCH > SGF_BUF) {
+            if (nbuf > 0) {
+                contract(nbuf, stored);
+                stored = true;
+            }
+            nbuf = 0;
+        }
+        __syncthreads();
+    }
+    if (!stored) {
+        // no entry reached the group: its spectrum is zero
+        const int px = s_pix[lane];
+        if (px >= 0) {
+            for (int cb = cb_lo; cb < cb_hi; ++cb) {
+                const int s = cb * 16 / Fc;
+                const int c0 = cb * 16 - s * Fc;
+                float* ob = out + ((size_t)s * F * HW << CS);
+                for (int q = 0; q < 16; ++q) ob[((size_t)((c0 + q) >> CS) * HW + px) * (1 << CS) + ((c0 + q) & CS)] = 0.0f;
+            }
+        }
+    }
+    if (wave == 0 && wpix >= 0) {
+        T_final[wpix] = T;
+        n_last[wpix] = last;
+        n_contrib[wpix] = cnt;
+    }
+}
+
 // Channel floats per workgroup: the largest power of two that divides F*c,
 // at most 64, or the caller's choice (a power of two up to 64 dividing F*c).
 // (The backward and the persistent batch kernel cap it at 32.)
@@ -532,6 +740,19 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
 {
     const int C = a.is_complex ? 2 : 1;
     const int Fc = a.n_chan * C;
+    if (!tgt && L.nq == 1 && Fc % 16 == 0 && !(p.options & GS_OPT_BLEND_PER_GROUP)) {
+        // every set over the one prepared geometry: the walk once per pixel
+        void* tok;
+        timing_begin(TK_BLEND, s, &tok);
+        auto kern = C == 2 ? k_blend_sg<1> : k_blend_sg<0>;
+        hipLaunchKernelGGL(kern, dim3(L.T, (L.tw * L.th) / SGF_PIX), dim3(64 * SGF_WAVES), 0, s,
+                           (const GRec*)(ws + L.rec), (const uint32_t*)(ws + L.plist), (const uint2*)(ws + L.ranges),
+                           a.data, a.query_stride, n_sets, Fc, L.H, L.W, L.tw, L.th, L.TX, p.alpha_min, p.alpha_max,
+                           p.T_min, out, (float*)(ws + L.T_final), (uint32_t*)(ws + L.n_last),
+                           (uint32_t*)(ws + L.n_contrib));
+        timing_end(tok, s);
+        return GS_OK;
+    }
     int cg = choose_chan_group(Fc, p.chan_group);
     if (tgt && cg > 32) cg = 32;  // the fused loss stage needs the registers of a 64-channel group
     if (Fc / cg > 65535) return GS_ERR_CAPACITY;

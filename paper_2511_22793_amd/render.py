@@ -16,7 +16,7 @@ from typing import Optional
 
 import torch
 
-from ._lib import GS_OPT_BWD_PER_GROUP, GS_OPT_FORWARD_ONLY, GsAttrs, GsL2Grad, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
+from ._lib import GS_OPT_BLEND_PER_GROUP, GS_OPT_BWD_PER_GROUP, GS_OPT_FORWARD_ONLY, GsAttrs, GsL2Grad, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
 
 DEFAULT_VIEW = (0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0)
 
@@ -35,12 +35,14 @@ class Params:
     chan_group: int = 0
     forward_only: bool = False
     bwd_per_group: bool = False  # backward per set and channel group even over shared geometry
+    blend_per_group: bool = False  # compositing per set and channel group even over shared geometry
 
     def c(self) -> GsParams:
         return GsParams(self.alpha_min, self.alpha_max, self.T_min, self.dilation, self.r_near, self.atten_power,
                         int(self.atten_ref), self.margin, int(self.pair_capacity), int(self.chan_group),
                         (GS_OPT_FORWARD_ONLY if self.forward_only else 0)
-                        | (GS_OPT_BWD_PER_GROUP if self.bwd_per_group else 0))
+                        | (GS_OPT_BWD_PER_GROUP if self.bwd_per_group else 0)
+                        | (GS_OPT_BLEND_PER_GROUP if self.blend_per_group else 0))
 
 
 @dataclass

@@ -1,9 +1,10 @@
 """The compositing kernel with the training loss fused into its output stage
 (gs_render_blend_loss) against gs_render_blend + gs_loss_spectrum_stats: the
-spectrum and the elementwise gradient part bit-identical (same arithmetic on
-the same values), the loss, spatial means and channel-mean term equal up to
-FP32 summation order (the fused sums add per-wave partials, the loss pass
-per-workgroup strided partials)."""
+spectrum and the elementwise gradient part bit-identical to the per-group
+compositing kernel's (GS_OPT_BLEND_PER_GROUP: the fused stage lives in that
+kernel, so the arithmetic is the same), the loss, spatial means and
+channel-mean term equal up to FP32 summation order (the fused sums add
+per-wave partials, the loss pass per-workgroup strided partials)."""
 import numpy as np
 import pytest
 import torch
@@ -35,7 +36,7 @@ def test_fused_loss_matches_blend_then_loss_pass(S, F, cplx, tile, n, seed):
                                        for s in range(S)])).cuda()
     rx = torch.tensor([[0.1, -0.2, 0.3]]).cuda()
     grid = gs.Grid(90, 360, tile[0], tile[1])
-    ws = gs.prepare(dev, rx, grid=grid)
+    ws = gs.prepare(dev, rx, grid=grid, params=gs.Params(blend_per_group=True))
     ref = gs.blend(ws, attrs, n_sets=S, is_complex=cplx)
     target = torch.from_numpy(np.random.default_rng(seed + 99).normal(size=tuple(ref.shape)).astype(np.float32)).cuda()
     lam = 0.7
@@ -59,7 +60,7 @@ def test_fused_loss_without_partial_and_repeated_calls():
     dev = to_dev(sc)
     attrs = torch.from_numpy(np.stack([synth.channel_attrs(n, F, True, seed=70 + s) for s in range(S)])).cuda()
     rx = torch.zeros(1, 3).cuda()
-    ws = gs.prepare(dev, rx)
+    ws = gs.prepare(dev, rx, params=gs.Params(blend_per_group=True))
     ref = gs.blend(ws, attrs, n_sets=S, is_complex=True)
     target = torch.from_numpy(np.random.default_rng(8).normal(size=tuple(ref.shape)).astype(np.float32)).cuda()
     loss_ref, hh_ref, mg_ref, _ = gs.loss_stats(ref, target, True, 1.0)

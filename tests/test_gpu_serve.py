@@ -2,6 +2,7 @@
 uneven size, grid, tile shape and channel count reproduces the per-query
 renderer bit for bit (and so the oracle), replays of its graph capture
 reproduce the eager run, and the autotuner's choices keep that identity."""
+import dataclasses
 import json
 
 import numpy as np
@@ -33,7 +34,11 @@ def small_jobs(seed=9, n_scenes=4, n_queries=10, variants=True):
 
 
 def single(job):
-    out, ws = gs.forward(job.scene, job.attr, job.rx, grid=job.grid, params=job.params, is_complex=job.is_complex)
+    # the per-group compositing kernel: the batched kernel's arithmetic (a
+    # one-query forward over F*c % 16 == 0 channels would otherwise take the
+    # shared-geometry kernel, which sums in another order)
+    prm = dataclasses.replace(job.params, blend_per_group=True)
+    out, ws = gs.forward(job.scene, job.attr, job.rx, grid=job.grid, params=prm, is_complex=job.is_complex)
     return out, ws
 
 

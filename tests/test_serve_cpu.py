@@ -48,7 +48,7 @@ def test_forward_only_workspace_is_smaller_and_rejects_backward():
     assert full.total - fwd.total >= 4 * full.pair_capacity * 32
     assert fwd.pair_list == full.pair_list and fwd.T_final == full.T_final
     # unknown option bits are rejected; the backward-decomposition bit is known
-    assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(grid()), ctypes.byref(params(options=4)),
+    assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(grid()), ctypes.byref(params(options=8)),
                                           ctypes.byref(GsLayout())) == _lib.GS_ERR_INVALID_ARG
     assert _lib.lib().gs_workspace_layout(100, 1, ctypes.byref(grid()),
                                           ctypes.byref(params(options=_lib.GS_OPT_BWD_PER_GROUP)),
