@@ -39,8 +39,9 @@ PEAK_MFMA_F32_TFLOPS = 157.3  # dense FP32 matrix cores
 PEAK_HBM_GBS = 8000.0
 # Algorithmic work of the compositing kernels for B attribute sets over one
 # shared geometry (the training step):
-#  forward  : per set, n_eval (pixel, entry) evaluations x FLOPS_PER_EVAL
-#             + n_contrib accepted pairs x (2 Fc + FLOPS_PER_CONTRIB)
+#  forward  : per set, n_contrib accepted pairs x 2 Fc (out += w v, on the
+#             matrix cores); once for all sets, n_eval (pixel, entry)
+#             evaluations x FLOPS_PER_EVAL + n_contrib x FLOPS_PER_CONTRIB
 #  backward : per set, n_contrib x 4 Fc: gv = v . g (2 Fc) and dL/dv += w g
 #             (2 Fc), the two products on the matrix cores; once for all sets
 #             (the geometry is shared), the re-walk n_eval x FLOPS_PER_EVAL
@@ -206,11 +207,11 @@ def main():
     # roofline of the dominant kernel, from the library's HIP-event timing of
     # every launch of the two compositing kernels during the timed steps
     Fc = 2 * F
-    blend_flops = B * (n_eval * FLOPS_PER_EVAL + n_contrib * (2.0 * Fc + FLOPS_PER_CONTRIB))
+    blend_flops = B * n_contrib * 2.0 * Fc + n_eval * FLOPS_PER_EVAL + n_contrib * FLOPS_PER_CONTRIB
     bwd_flops = B * n_contrib * 4.0 * Fc + n_eval * FLOPS_PER_EVAL + n_contrib * FLOPS_BWD_CONTRIB
-    fwd_name = "k_blend<%d>" % min(64, Fc)
+    fwd_name = "k_blend<32, true>" if args.loss_mode == "fused" else "k_blend_sg<1>"
     bwd_name = "k_blend_bwd_sg<1, %s>" % ("true" if args.loss_mode == "target" else "false")
-    kt = {fwd_name: (kernel_ms["blend"], blend_flops, "alu", PEAK_VALU_F32_TFLOPS),
+    kt = {fwd_name: (kernel_ms["blend"], blend_flops, "mfma", PEAK_MFMA_F32_TFLOPS),
           bwd_name: (kernel_ms["blend_bwd"], bwd_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
     kname = max(kt, key=lambda k: kt[k][0])
     ms, fl, bound, peak = kt[kname]
@@ -222,7 +223,7 @@ def main():
                                 "channel_floats": Fc},
                        "other": {k: {"launch_ms": round(v[0], 4),
                                      "achieved_tflops": round(v[1] / (v[0] / 1e3) / 1e12, 3),
-                                     "frac_valu_fp32": round(v[1] / (v[0] / 1e3) / 1e12 / PEAK_VALU_F32_TFLOPS, 4)}
+                                     "bound": v[2], "frac": round(v[1] / (v[0] / 1e3) / 1e12 / v[3], 4)}
                                  for k, v in kt.items()}}
     if not args.no_mix:
         res["serving_mix"] = serving_mix(args, gs, dev)
