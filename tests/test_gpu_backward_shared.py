@@ -44,6 +44,7 @@ CASES = [
     (2, 24, True, (8, 32), 90, 3),    # 48 columns per set, wide tiles
     (4, 16, True, (32, 8), 80, 4),    # narrow tiles
     (2, 32, False, (16, 8), 70, 5),   # two pixel groups per tile
+    (4, 32, True, (16, 16), 100, 6),  # 16 column blocks: two per wave; the bottom tiles' 32-pixel groups
 ]
 
 
