@@ -32,8 +32,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 vector peak without packed-FP32 instructions (they are disabled in
-# this build): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# FP32 vector peak without packed-FP32 instructions (the HIP sources are
+# compiled with them disabled): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_VALU_F32_TFLOPS = 78.6
 PEAK_MFMA_F32_TFLOPS = 157.3  # dense FP32 matrix cores
 PEAK_HBM_GBS = 8000.0
@@ -84,8 +84,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (sharding is described in DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path, run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
