@@ -11,6 +11,8 @@ Contents
     tiled variant; loaded here through ctypes.
   * ``torch_ref`` -- an independent dense FP64 PyTorch-CPU implementation of
     the same forward, differentiated by autograd (gradient reference).
+  * ``confidence_ref`` -- FP64 confidence head and the confidence-weighted
+    loss (Eq. (6)) with its gradients.
   * ``mlp_ref`` -- FP64 attribute network with BF16 rounding emulation,
     losses and Adam.
 
