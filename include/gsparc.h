@@ -401,6 +401,22 @@ typedef struct {
 gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, int32_t step, float beta1,
                        float beta2, float eps, void* stream);
 
+/* ---- confidence head and confidence-weighted loss (Sec. 4.2, Eq. (6)) ----
+ * Per sample b (receiver position x_rx[b][3], task loss task_loss[b]):
+ *   h = relu(W1 x + b1) (32 units; hidden activation: a reading, the paper
+ *   names none), g = w2 . h + b2, C = 1 + exp(g) > 1,
+ *   loss[b] = C task_loss[b] - alpha log C;  conf[b] = C, which is also
+ *   d loss[b] / d task_loss[b] (the factor on the task loss gradient).
+ * Gradients of sum_b loss[b]: dW1 [32][3], db1 [32], dw2 [32], db2 [1],
+ * overwritten.  Layout: W1 row-major [32][3], all FP32 device pointers,
+ * caller-owned; the paper's alpha is 0.3.  One workgroup; the weight
+ * gradients are summed in a fixed order (deterministic).
+ * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1 or alpha negative or
+ * not finite; GS_ERR_CAPACITY for n > 65536. */
+gs_status gs_confidence_loss(const float* x_rx, const float* task_loss, int32_t n, const float* W1,
+                             const float* b1, const float* w2, const float* b2, float alpha, float* conf,
+                             float* loss, float* dW1, float* db1, float* dw2, float* db2, void* stream);
+
 /*
  * Batched serving: many queries over several scenes of uneven size, grid,
  * tile shape and channel count in one persistent blend launch.

@@ -5,3 +5,4 @@ HIP kernels for gfx950 behind the C ABI of include/gsparc.h."""
 from .render import (Grid, Params, Workspace, backward, backward_l2, blend, blend_loss, forward, layout,  # noqa: F401
                      live, loss_spectrum, loss_stats, prepare)
 from .autograd import GSRender, render  # noqa: F401
+from .confidence import confidence_loss  # noqa: F401
