@@ -224,6 +224,7 @@ def main():
                                      "achieved_tflops": round(v[1] / (v[0] / 1e3) / 1e12, 3),
                                      "bound": v[2], "frac": round(v[1] / (v[0] / 1e3) / 1e12 / v[3], 4)}
                                  for k, v in kt.items()}}
+    res["confidence"] = confidence_head(gs, dev)
     if not args.no_mix:
         res["serving_mix"] = serving_mix(args, gs, dev)
     if not args.no_plain:
@@ -266,6 +267,45 @@ def measured_traffic(kernel):
     if kernel_source_hash(src) != k["source_sha256"]:
         return None
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
+# confidence head + Eq. (6) per sample: layer 1 (3x32 FMA), layer 2 (32 FMA),
+# the backward through both (32 + 3x32 + 32 + 32 FMA/adds): ~600 flops
+CONF_FLOPS_PER_SAMPLE = 2 * (3 * 32 + 32) + 32 + 2 * 3 * 32 + 32 + 2 * 32
+
+
+def confidence_head(gs, dev):
+    """Kernel time of gs_confidence_loss (one workgroup) for one sample per
+    step (the training workload's single receiver) and for 65536 samples,
+    inputs resident on the device, HIP events on the launch stream."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(5)
+    w = {"W1": torch.randn(32, 3, generator=g) * 0.5, "b1": torch.randn(32, generator=g) * 0.5,
+         "w2": torch.randn(32, generator=g) * 0.3, "b2": torch.randn(1, generator=g) * 0.3}
+    w = {k: v.to(dev) for k, v in w.items()}
+    out = {}
+    for n in (1, 65536):
+        x = (torch.randn(n, 3, generator=g) * 2).to(dev)
+        L = (torch.rand(n, generator=g) * 0.5 + 0.01).to(dev)
+        for _ in range(3):
+            gs.confidence_loss(x, L, w)
+        reps = 50
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            gs.confidence_loss(x, L, w)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out["n%d_call_us" % n] = round(us, 2)  # per call, host marshalling included
+        if n > 1:
+            ach = CONF_FLOPS_PER_SAMPLE * n / (us * 1e-6) / 1e12
+            out["samples_per_s"] = round(n / (us * 1e-6), 1)
+            out["roofline"] = {"bound": "latency", "achieved": round(ach, 5), "peak": PEAK_VALU_F32_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_F32_TFLOPS, 6),
+                               "note": "one workgroup by design: a step has one sample per receiver"}
+    return out
 
 
 def serving_mix(args, gs, dev):

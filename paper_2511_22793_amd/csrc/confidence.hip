@@ -5,17 +5,18 @@
 // batch sum of L_conf: dL/dL_task = C, dL/dC = L_task - alpha / C,
 // dC/dg = C - 1, then through the two layers.
 //
-// One workgroup of four waves.  Lane j of every wave owns hidden unit j
-// (lanes 32..63 idle in the products); each wave takes every fourth sample,
-// forms g with a wave reduction, and keeps its lane's partial weight
-// gradients in registers; the four waves' partials are added in LDS in a
-// fixed order, so the result does not depend on timing.
+// One workgroup of sixteen waves.  Each half of a wave (32 lanes) takes one
+// sample at a time, lane j of the half owning hidden unit j; the half forms
+// g with a 32-lane reduction and keeps its lane's partial weight gradients in
+// registers; the 32 halves' partials are added in LDS in a fixed order, so
+// the result does not depend on timing.
 #include "common.h"
 
 namespace gs {
 
 constexpr int CONF_HIDDEN = 32;
-constexpr int CONF_WAVES = 4;
+constexpr int CONF_WAVES = 16;
+constexpr int CONF_HALVES = 2 * CONF_WAVES;
 
 __global__ __launch_bounds__(CONF_WAVES * 64) void k_confidence(const float* __restrict__ x,
                                                                 const float* __restrict__ task, int n,
@@ -27,29 +28,27 @@ __global__ __launch_bounds__(CONF_WAVES * 64) void k_confidence(const float* __r
                                                                 float* __restrict__ dW1, float* __restrict__ db1,
                                                                 float* __restrict__ dw2, float* __restrict__ db2)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool unit = lane < CONF_HIDDEN;
-    const float w10 = unit ? W1[3 * lane] : 0.0f, w11 = unit ? W1[3 * lane + 1] : 0.0f;
-    const float w12 = unit ? W1[3 * lane + 2] : 0.0f;
-    const float bj = unit ? b1[lane] : 0.0f, vj = unit ? w2[lane] : 0.0f;
+    const int j = threadIdx.x & 31, half = threadIdx.x >> 5;  // hidden unit, half-wave
+    const float w10 = W1[3 * j], w11 = W1[3 * j + 1], w12 = W1[3 * j + 2];
+    const float bj = b1[j], vj = w2[j];
     const float bias2 = b2[0];
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gb = 0.0f, gv = 0.0f, go = 0.0f;
-    for (int b = wave; b < n; b += CONF_WAVES) {
+    for (int b = half; b < n; b += CONF_HALVES) {
         const float x0 = x[3 * b], x1 = x[3 * b + 1], x2 = x[3 * b + 2];
         const float z = fmaf(w10, x0, fmaf(w11, x1, fmaf(w12, x2, bj)));
-        const float h = unit ? fmaxf(z, 0.0f) : 0.0f;
+        const float h = fmaxf(z, 0.0f);
         float s = vj * h;
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);  // within the half
         const float g = s + bias2;
         const float e = expf(g);
         const float C = 1.0f + e;
         const float L = task[b];
-        if (lane == 0) {
+        if (j == 0) {
             conf[b] = C;
             loss[b] = C * L - alpha * logf(C);
         }
         const float dg = (L - alpha / C) * e;  // dL/dC * dC/dg
-        const float dh = (z > 0.0f && unit) ? dg * vj : 0.0f;
+        const float dh = z > 0.0f ? dg * vj : 0.0f;
         g0 = fmaf(dh, x0, g0);
         g1 = fmaf(dh, x1, g1);
         g2 = fmaf(dh, x2, g2);
@@ -57,22 +56,21 @@ __global__ __launch_bounds__(CONF_WAVES * 64) void k_confidence(const float* __r
         gv = fmaf(dg, h, gv);
         go += dg;
     }
-    __shared__ float part[CONF_WAVES][6][CONF_HIDDEN];
-    if (unit) {
-        part[wave][0][lane] = g0;
-        part[wave][1][lane] = g1;
-        part[wave][2][lane] = g2;
-        part[wave][3][lane] = gb;
-        part[wave][4][lane] = gv;
-        part[wave][5][lane] = go;
-    }
+    // (the two halves of a wave may run different trip counts; the
+    // reduction above never crosses a half)
+    __shared__ float part[CONF_HALVES][6][CONF_HIDDEN];
+    part[half][0][j] = g0;
+    part[half][1][j] = g1;
+    part[half][2][j] = g2;
+    part[half][3][j] = gb;
+    part[half][4][j] = gv;
+    part[half][5][j] = go;
     __syncthreads();
     if (threadIdx.x < CONF_HIDDEN) {
-        const int j = threadIdx.x;
         float r[6];
         for (int k = 0; k < 6; ++k) {
             float v = 0.0f;
-            for (int w = 0; w < CONF_WAVES; ++w) v += part[w][k][j];
+            for (int w = 0; w < CONF_HALVES; ++w) v += part[w][k][j];
             r[k] = v;
         }
         dW1[3 * j] = r[0];
@@ -80,7 +78,7 @@ __global__ __launch_bounds__(CONF_WAVES * 64) void k_confidence(const float* __r
         dW1[3 * j + 2] = r[2];
         db1[j] = r[3];
         dw2[j] = r[4];
-        if (j == 0) db2[0] = r[5];  // every lane of a wave holds the same dg sum
+        if (j == 0) db2[0] = r[5];  // every lane of a half holds the same dg sum
     }
 }
 
