@@ -13,6 +13,8 @@ Contents
     the same forward, differentiated by autograd (gradient reference).
   * ``confidence_ref`` -- FP64 confidence head and the confidence-weighted
     loss (Eq. (6)) with its gradients.
+  * ``emission_ref`` -- FP64 per-Gaussian 3 -> 16 -> 2 emission networks
+    (the paper's own form of Eq. (1)) with their gradients.
   * ``mlp_ref`` -- FP64 attribute network with BF16 rounding emulation,
     losses and Adam.
 
