@@ -413,6 +413,30 @@ gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, i
  * gradients are summed in a fixed order (deterministic).
  * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1 or alpha negative or
  * not finite; GS_ERR_CAPACITY for n > 65536. */
+/* ---- the paper's own emission form: one network per Gaussian (Sec. 4.1, Eq. (1)) ----
+ * Gaussian i owns a 3 -> 16 -> 2 network (98 FP32 parameters, stored as
+ * params[k * param_stride + i], k = W1 [16][3] row-major, b1 [16], W2 [2][16]
+ * row-major, b2 [2]; param_stride >= n).  For query q (receiver rx[q][3],
+ * transmitter tx[q][3], device pointers):
+ *   h = relu(W1 rx + b1) (hidden activation: a reading, the paper names
+ *   none), f = W2 h + b2, d = max(|tx - mean_i|, r_near),
+ *   attr[q * attr_query_stride + 2 i + {0, 1}] = sigmoid(f - log d) (Re, Im),
+ * i.e. one complex channel per Gaussian in the attribute layout of the
+ * renderer.  mean [n][3].  All pointers are caller-owned device memory.
+ * The backward takes d_attr in the same layout and writes (overwrites) the
+ * gradients of sum(d_attr * attr) with respect to the parameters (d_params,
+ * same layout as params) and the means (d_mean [n][3]), summed over queries.
+ * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1, n_queries < 1,
+ * param_stride < n, attr_query_stride < 2 n or odd, r_near not positive and
+ * finite; GS_ERR_CAPACITY for n_queries > 1024. */
+gs_status gs_emission_forward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+                              const float* rx, const float* tx, int32_t n_queries, float r_near, float* attr,
+                              int64_t attr_query_stride, void* stream);
+gs_status gs_emission_backward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+                               const float* rx, const float* tx, int32_t n_queries, float r_near,
+                               const float* d_attr, int64_t attr_query_stride, float* d_params, float* d_mean,
+                               void* stream);
+
 gs_status gs_confidence_loss(const float* x_rx, const float* task_loss, int32_t n, const float* W1,
                              const float* b1, const float* w2, const float* b2, float alpha, float* conf,
                              float* loss, float* dW1, float* db1, float* dw2, float* db2, void* stream);

@@ -6,3 +6,4 @@ from .render import (Grid, Params, Workspace, backward, backward_l2, blend, blen
                      live, loss_spectrum, loss_stats, prepare)
 from .autograd import GSRender, render  # noqa: F401
 from .confidence import confidence_loss  # noqa: F401
+from .emission import emission_backward, emission_forward  # noqa: F401

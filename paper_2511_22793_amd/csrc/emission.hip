@@ -1,0 +1,151 @@
+// The paper's own emission form: one 3 -> 16 -> 2 network per Gaussian
+// (Sec. 4.1, Eq. (1)).  For query q (receiver rx_q, transmitter tx_q):
+//   h = relu(W1_i rx_q + b1_i), f = W2_i h + b2_i,
+//   d = max(|tx_q - mu_i|, r_near),  s = sigmoid(f - log d)  (Re, Im).
+// Parameters are stored per parameter index, then per Gaussian
+// (params[k * stride + i], k < 98: W1 [16][3], b1 [16], W2 [2][16], b2 [2]),
+// so that one load instruction of a wave reads 64 consecutive Gaussians.
+// One thread per Gaussian holds its 98 parameters in registers and takes
+// every query, so the parameters leave HBM once per launch (a batched
+// matrix-vector product: HBM-bound, not a matrix-core shape).
+#include "common.h"
+
+namespace gs {
+
+constexpr int EM_H = 16;
+constexpr int EM_NP = 3 * EM_H + EM_H + 2 * EM_H + 2;  // 98
+
+__device__ __forceinline__ float em_sigmoid(float u) { return 1.0f / (1.0f + expf(-u)); }
+
+__global__ __launch_bounds__(256) void k_emission_fwd(const float* __restrict__ P, int64_t ps,
+                                                      const float* __restrict__ mean, int n,
+                                                      const float* __restrict__ rx, const float* __restrict__ tx,
+                                                      int nq, float r_near, float* __restrict__ attr, int64_t as)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float p[EM_NP];
+#pragma unroll
+    for (int k = 0; k < EM_NP; ++k) p[k] = P[(size_t)k * ps + i];
+    const float m0 = mean[3 * i], m1 = mean[3 * i + 1], m2 = mean[3 * i + 2];
+    for (int q = 0; q < nq; ++q) {
+        const float x0 = rx[3 * q], x1 = rx[3 * q + 1], x2 = rx[3 * q + 2];
+        float f0 = p[96], f1 = p[97];
+#pragma unroll
+        for (int j = 0; j < EM_H; ++j) {
+            const float z = fmaf(p[3 * j], x0, fmaf(p[3 * j + 1], x1, fmaf(p[3 * j + 2], x2, p[48 + j])));
+            const float h = fmaxf(z, 0.0f);
+            f0 = fmaf(p[64 + j], h, f0);
+            f1 = fmaf(p[80 + j], h, f1);
+        }
+        const float v0 = tx[3 * q] - m0, v1 = tx[3 * q + 1] - m1, v2 = tx[3 * q + 2] - m2;
+        const float d = fmaxf(sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2))), r_near);
+        const float ld = logf(d);
+        float2* o = (float2*)(attr + q * as) + i;
+        *o = float2{em_sigmoid(f0 - ld), em_sigmoid(f1 - ld)};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ P, int64_t ps,
+                                                      const float* __restrict__ mean, int n,
+                                                      const float* __restrict__ rx, const float* __restrict__ tx,
+                                                      int nq, float r_near, const float* __restrict__ dattr,
+                                                      int64_t as, float* __restrict__ dP,
+                                                      float* __restrict__ dmean)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float p[EM_NP], g[EM_NP];
+#pragma unroll
+    for (int k = 0; k < EM_NP; ++k) {
+        p[k] = P[(size_t)k * ps + i];
+        g[k] = 0.0f;
+    }
+    const float m0 = mean[3 * i], m1 = mean[3 * i + 1], m2 = mean[3 * i + 2];
+    float gm0 = 0.0f, gm1 = 0.0f, gm2 = 0.0f;
+    for (int q = 0; q < nq; ++q) {
+        const float x0 = rx[3 * q], x1 = rx[3 * q + 1], x2 = rx[3 * q + 2];
+        float z[EM_H];
+        float f0 = p[96], f1 = p[97];
+#pragma unroll
+        for (int j = 0; j < EM_H; ++j) {
+            z[j] = fmaf(p[3 * j], x0, fmaf(p[3 * j + 1], x1, fmaf(p[3 * j + 2], x2, p[48 + j])));
+            const float h = fmaxf(z[j], 0.0f);
+            f0 = fmaf(p[64 + j], h, f0);
+            f1 = fmaf(p[80 + j], h, f1);
+        }
+        const float v0 = tx[3 * q] - m0, v1 = tx[3 * q + 1] - m1, v2 = tx[3 * q + 2] - m2;
+        const float dist = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
+        const float d = fmaxf(dist, r_near);
+        const float ld = logf(d);
+        const float s0 = em_sigmoid(f0 - ld), s1 = em_sigmoid(f1 - ld);
+        const float2 up = ((const float2*)(dattr + q * as))[i];
+        const float u0 = up.x * s0 * (1.0f - s0), u1 = up.y * s1 * (1.0f - s1);
+        g[96] += u0;
+        g[97] += u1;
+#pragma unroll
+        for (int j = 0; j < EM_H; ++j) {
+            const float h = fmaxf(z[j], 0.0f);
+            g[64 + j] = fmaf(u0, h, g[64 + j]);
+            g[80 + j] = fmaf(u1, h, g[80 + j]);
+            const float dz = z[j] > 0.0f ? fmaf(u0, p[64 + j], u1 * p[80 + j]) : 0.0f;
+            g[48 + j] += dz;
+            g[3 * j] = fmaf(dz, x0, g[3 * j]);
+            g[3 * j + 1] = fmaf(dz, x1, g[3 * j + 1]);
+            g[3 * j + 2] = fmaf(dz, x2, g[3 * j + 2]);
+        }
+        // d(-log d)/d mu = (tx - mu) / d^2 where d is not floored
+        if (dist > r_near) {
+            const float c = -(u0 + u1) / (dist * dist);  // dL/dlog d times d(log d)/d mu = -v / d^2
+            gm0 = fmaf(-c, v0, gm0);
+            gm1 = fmaf(-c, v1, gm1);
+            gm2 = fmaf(-c, v2, gm2);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < EM_NP; ++k) dP[(size_t)k * ps + i] = g[k];
+    dmean[3 * i] = gm0;
+    dmean[3 * i + 1] = gm1;
+    dmean[3 * i + 2] = gm2;
+}
+
+static gs_status em_check(const float* P, int64_t ps, const float* mean, int n, const float* rx, const float* tx,
+                          int nq, float r_near, int64_t as)
+{
+    if (!P || !mean || !rx || !tx || n < 1 || nq < 1 || ps < n || as < 2 * (int64_t)n || (as & 1) || !(r_near > 0.0f) ||
+        !(r_near < INFINITY))
+        return GS_ERR_INVALID_ARG;
+    if (nq > 1024) return GS_ERR_CAPACITY;
+    return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" gs_status gs_emission_forward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+                                         const float* rx, const float* tx, int32_t n_queries, float r_near,
+                                         float* attr, int64_t attr_query_stride, void* stream)
+{
+    gs_status st = em_check(params, param_stride, mean, n, rx, tx, n_queries, r_near, attr_query_stride);
+    if (st != GS_OK) return st;
+    if (!attr) return GS_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_emission_fwd, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
+                       param_stride, mean, n, rx, tx, n_queries, r_near, attr, attr_query_stride);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+extern "C" gs_status gs_emission_backward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+                                          const float* rx, const float* tx, int32_t n_queries, float r_near,
+                                          const float* d_attr, int64_t attr_query_stride, float* d_params,
+                                          float* d_mean, void* stream)
+{
+    gs_status st = em_check(params, param_stride, mean, n, rx, tx, n_queries, r_near, attr_query_stride);
+    if (st != GS_OK) return st;
+    if (!d_attr || !d_params || !d_mean) return GS_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_emission_bwd, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
+                       param_stride, mean, n, rx, tx, n_queries, r_near, d_attr, attr_query_stride, d_params, d_mean);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}

@@ -1,0 +1,69 @@
+"""The paper's per-Gaussian emission networks (Sec. 4.1, Eq. (1)) on the GPU
+against the FP64 oracle (oracle/emission_ref.py) through the C ABI.
+
+Inputs are FP32-rounded before both sides see them; hidden biases whose
+pre-activation comes within 1e-3 of the ReLU kink for some query are redrawn,
+so both sides take the same ReLU decisions.  At 100k Gaussians the oracle
+checks a seeded sample of 2000 of them (each Gaussian's output depends on its
+own parameters only, so the sample is exact).  Tolerance: emissions (in
+(0, 1)) to 2e-6 absolute; gradients, FP32 sums over the queries, to 1e-5 of
+their largest magnitude plus 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2511_22793_amd as gs
+from paper_2511_22793_amd._lib import GS_ERR_CAPACITY, GS_ERR_INVALID_ARG, GsError
+from oracle import emission_ref as er
+
+pytestmark = pytest.mark.gpu
+
+
+def case(n, Q, seed):
+    r = np.random.default_rng(seed)
+    P = r.normal(0, 0.6, (n, er.NPARAM)).astype(np.float32)
+    mean = r.uniform(-5, 5, (n, 3)).astype(np.float32)
+    rx = r.uniform(-2, 2, (Q, 3)).astype(np.float32)
+    tx = r.uniform(-5, 5, (Q, 3)).astype(np.float32)
+    tx[0] = mean[0]                          # one floored distance
+    for _ in range(100):
+        W1 = P[:, :48].reshape(n, 16, 3).astype(np.float64)
+        z = np.einsum("nij,qj->qni", W1, rx.astype(np.float64)) + P[:, 48:64]
+        bad = (np.abs(z) < 1e-3).any(0)      # (n, 16)
+        if not bad.any():
+            break
+        P[:, 48:64][bad] = r.normal(0, 0.6, int(bad.sum())).astype(np.float32)
+    return P, mean, rx, tx
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n,Q,seed", [(1, 1, 1), (1000, 1, 2), (1000, 16, 3), (257, 7, 4), (100_000, 16, 5)])
+def test_emission_matches_oracle(n, Q, seed):
+    P, mean, rx, tx = case(n, Q, seed)
+    Pt = dev(np.ascontiguousarray(P.T))      # [98, n]
+    attr = gs.emission_forward(Pt, dev(mean), dev(rx), dev(tx))
+    ds = np.random.default_rng(seed + 100).normal(size=(Q, n, 2)).astype(np.float32)
+    dP, dm = gs.emission_backward(Pt, dev(mean), dev(rx), dev(tx), dev(ds))
+    torch.cuda.synchronize()
+    attr, dP, dm = attr.cpu().numpy(), dP.cpu().numpy().T, dm.cpu().numpy()
+    idx = np.arange(n) if n <= 5000 else np.sort(np.random.default_rng(seed).choice(n, 2000, replace=False))
+    want = er.forward(P[idx], mean[idx], rx, tx)
+    assert np.abs(attr[:, idx] - want).max() <= 2e-6
+    wP, wm = er.backward(P[idx], mean[idx], rx, tx, ds[:, idx])
+    assert np.abs(dP[idx] - wP).max() <= 1e-5 * np.abs(wP).max() + 1e-8
+    assert np.abs(dm[idx] - wm).max() <= 1e-5 * np.abs(wm).max() + 1e-8
+
+
+def test_input_checks():
+    P, mean, rx, tx = case(10, 1, 6)
+    Pt = dev(np.ascontiguousarray(P.T))
+    with pytest.raises(GsError) as e:
+        gs.emission_forward(Pt, dev(mean), dev(np.zeros((1025, 3), np.float32)), dev(np.zeros((1025, 3), np.float32)))
+    assert e.value.status == GS_ERR_CAPACITY
+    with pytest.raises(GsError) as e:
+        gs.emission_forward(Pt, dev(mean), dev(rx), dev(tx), r_near=0.0)
+    assert e.value.status == GS_ERR_INVALID_ARG
