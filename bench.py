@@ -318,7 +318,7 @@ def emission_nets(gs, dev, n, Q):
     import torch
     g = torch.Generator(device="cpu").manual_seed(9)
     P = (torch.randn(98, n, generator=g) * 0.6).to(dev)
-    mean = (torch.rand(n, 3, generator=g) * 10 - 5).to(dev)
+    mean = (torch.rand(3, n, generator=g) * 10 - 5).to(dev)   # the scene's [3][n]
     rx = (torch.rand(Q, 3, generator=g) * 4 - 2).to(dev)
     tx = (torch.rand(Q, 3, generator=g) * 10 - 5).to(dev)
     ds = torch.randn(Q, n, 2, generator=g).to(dev)

@@ -422,10 +422,11 @@ gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, i
  *   none), f = W2 h + b2, d = max(|tx - mean_i|, r_near),
  *   attr[q * attr_query_stride + 2 i + {0, 1}] = sigmoid(f - log d) (Re, Im),
  * i.e. one complex channel per Gaussian in the attribute layout of the
- * renderer.  mean [n][3].  All pointers are caller-owned device memory.
+ * renderer.  mean [3][n] (the scene's layout).  All pointers are
+ * caller-owned device memory.
  * The backward takes d_attr in the same layout and writes (overwrites) the
  * gradients of sum(d_attr * attr) with respect to the parameters (d_params,
- * same layout as params) and the means (d_mean [n][3]), summed over queries.
+ * same layout as params) and the means (d_mean [3][n]), summed over queries.
  * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1, n_queries < 1,
  * param_stride < n, attr_query_stride < 2 n or odd, r_near not positive and
  * finite; GS_ERR_CAPACITY for n_queries > 1024. */

@@ -1,7 +1,8 @@
 // The paper's own emission form: one 3 -> 16 -> 2 network per Gaussian
 // (Sec. 4.1, Eq. (1)).  For query q (receiver rx_q, transmitter tx_q):
 //   h = relu(W1_i rx_q + b1_i), f = W2_i h + b2_i,
-//   d = max(|tx_q - mu_i|, r_near),  s = sigmoid(f - log d)  (Re, Im).
+//   d = max(|tx_q - mu_i|, r_near),  s = sigmoid(f - log d)  (Re, Im);
+// the means in the scene's layout [3][n].
 // Parameters are stored per parameter index, then per Gaussian
 // (params[k * stride + i], k < 98: W1 [16][3], b1 [16], W2 [2][16], b2 [2]),
 // so that one load instruction of a wave reads 64 consecutive Gaussians.
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(256) void k_emission_fwd(const float* __restrict__ 
     float p[EM_NP];
 #pragma unroll
     for (int k = 0; k < EM_NP; ++k) p[k] = P[(size_t)k * ps + i];
-    const float m0 = mean[3 * i], m1 = mean[3 * i + 1], m2 = mean[3 * i + 2];
+    const float m0 = mean[i], m1 = mean[n + i], m2 = mean[2 * n + i];  // [3][n], as the scene
     for (int q = 0; q < nq; ++q) {
         const float x0 = rx[3 * q], x1 = rx[3 * q + 1], x2 = rx[3 * q + 2];
         float f0 = p[96], f1 = p[97];
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ 
         p[k] = P[(size_t)k * ps + i];
         g[k] = 0.0f;
     }
-    const float m0 = mean[3 * i], m1 = mean[3 * i + 1], m2 = mean[3 * i + 2];
+    const float m0 = mean[i], m1 = mean[n + i], m2 = mean[2 * n + i];  // [3][n], as the scene
     float gm0 = 0.0f, gm1 = 0.0f, gm2 = 0.0f;
     for (int q = 0; q < nq; ++q) {
         const float x0 = rx[3 * q], x1 = rx[3 * q + 1], x2 = rx[3 * q + 2];
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ 
     }
 #pragma unroll
     for (int k = 0; k < EM_NP; ++k) dP[(size_t)k * ps + i] = g[k];
-    dmean[3 * i] = gm0;
-    dmean[3 * i + 1] = gm1;
-    dmean[3 * i + 2] = gm2;
+    dmean[i] = gm0;
+    dmean[n + i] = gm1;
+    dmean[2 * n + i] = gm2;
 }
 
 static gs_status em_check(const float* P, int64_t ps, const float* mean, int n, const float* rx, const float* tx,

@@ -30,13 +30,14 @@ def _stream(dev):
 
 def emission_forward(params: torch.Tensor, mean: torch.Tensor, rx: torch.Tensor, tx: torch.Tensor,
                      r_near: float = R_NEAR) -> torch.Tensor:
-    """params [98, stride] (parameter-major, stride >= n), mean [n, 3],
-    rx/tx [Q, 3] -> attr [Q, n, 2] (Re, Im of one complex channel)."""
-    n = mean.shape[0]
+    """params [98, stride] (parameter-major, stride >= n), mean [3, n] (the
+    scene's layout), rx/tx [Q, 3] -> attr [Q, n, 2] (Re, Im of one complex
+    channel)."""
+    n = mean.shape[1]
     _dev(params, "params")
     if params.shape[0] != NPARAM or params.shape[1] < n:
         raise ValueError("params: [98, stride >= n] expected")
-    _dev(mean, "mean", (n, 3))
+    _dev(mean, "mean", (3, n))
     Q = rx.shape[0]
     _dev(rx, "rx", (Q, 3))
     _dev(tx, "tx", (Q, 3))
@@ -49,12 +50,12 @@ def emission_forward(params: torch.Tensor, mean: torch.Tensor, rx: torch.Tensor,
 def emission_backward(params: torch.Tensor, mean: torch.Tensor, rx: torch.Tensor, tx: torch.Tensor,
                       d_attr: torch.Tensor, r_near: float = R_NEAR):
     """Gradients of sum(d_attr * attr) with respect to params ([98, stride])
-    and mean ([n, 3]), summed over the queries."""
-    n = mean.shape[0]
+    and mean ([3, n]), summed over the queries."""
+    n = mean.shape[1]
     Q = rx.shape[0]
     _dev(d_attr, "d_attr", (Q, n, 2))
     _dev(params, "params")
-    _dev(mean, "mean", (n, 3))
+    _dev(mean, "mean", (3, n))
     _dev(rx, "rx", (Q, 3))
     _dev(tx, "tx", (Q, 3))
     d_params = torch.empty_like(params)

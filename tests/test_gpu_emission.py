@@ -45,11 +45,12 @@ def dev(a):
 def test_emission_matches_oracle(n, Q, seed):
     P, mean, rx, tx = case(n, Q, seed)
     Pt = dev(np.ascontiguousarray(P.T))      # [98, n]
-    attr = gs.emission_forward(Pt, dev(mean), dev(rx), dev(tx))
+    mt = dev(np.ascontiguousarray(mean.T))   # [3, n], the scene's layout
+    attr = gs.emission_forward(Pt, mt, dev(rx), dev(tx))
     ds = np.random.default_rng(seed + 100).normal(size=(Q, n, 2)).astype(np.float32)
-    dP, dm = gs.emission_backward(Pt, dev(mean), dev(rx), dev(tx), dev(ds))
+    dP, dm = gs.emission_backward(Pt, mt, dev(rx), dev(tx), dev(ds))
     torch.cuda.synchronize()
-    attr, dP, dm = attr.cpu().numpy(), dP.cpu().numpy().T, dm.cpu().numpy()
+    attr, dP, dm = attr.cpu().numpy(), dP.cpu().numpy().T, dm.cpu().numpy().T
     idx = np.arange(n) if n <= 5000 else np.sort(np.random.default_rng(seed).choice(n, 2000, replace=False))
     want = er.forward(P[idx], mean[idx], rx, tx)
     assert np.abs(attr[:, idx] - want).max() <= 2e-6
@@ -61,9 +62,38 @@ def test_emission_matches_oracle(n, Q, seed):
 def test_input_checks():
     P, mean, rx, tx = case(10, 1, 6)
     Pt = dev(np.ascontiguousarray(P.T))
+    mt = dev(np.ascontiguousarray(mean.T))
     with pytest.raises(GsError) as e:
-        gs.emission_forward(Pt, dev(mean), dev(np.zeros((1025, 3), np.float32)), dev(np.zeros((1025, 3), np.float32)))
+        gs.emission_forward(Pt, mt, dev(np.zeros((1025, 3), np.float32)), dev(np.zeros((1025, 3), np.float32)))
     assert e.value.status == GS_ERR_CAPACITY
     with pytest.raises(GsError) as e:
-        gs.emission_forward(Pt, dev(mean), dev(rx), dev(tx), r_near=0.0)
+        gs.emission_forward(Pt, mt, dev(rx), dev(tx), r_near=0.0)
     assert e.value.status == GS_ERR_INVALID_ARG
+
+
+def test_emission_feeds_the_renderer():
+    # the emission of one query, as one complex channel per Gaussian, rendered
+    # by the compositing path and compared with the oracle's render of the
+    # oracle's emission
+    import oracle
+    import synth
+    from gpu_util import check_parity, gpu_forward
+    n = 1500
+    sc = synth.scene(n, seed=41)
+    P, _, _, _ = case(n, 1, 42)
+    rx = np.array([[0.1, -0.2, 0.05]], np.float32)
+    tx = np.array([[1.0, 2.0, 0.5]], np.float32)
+    r = np.random.default_rng(43)
+    for _ in range(100):  # keep the hidden pre-activations away from the ReLU kink
+        z = np.einsum("nij,j->ni", P[:, :48].reshape(n, 16, 3).astype(np.float64), rx[0].astype(np.float64)) \
+            + P[:, 48:64]
+        bad = np.abs(z) < 1e-3
+        if not bad.any():
+            break
+        P[:, 48:64][bad] = r.normal(0, 0.6, int(bad.sum())).astype(np.float32)
+    attr = gs.emission_forward(dev(np.ascontiguousarray(P.T)), dev(sc["mean"]), dev(rx), dev(tx))
+    torch.cuda.synchronize()
+    got, _ = gpu_forward(sc, attr[0].cpu().numpy().reshape(n, 1, 2), rx, is_complex=True)
+    ref_attr = er.forward(P, sc["mean"].T, rx, tx)[0].reshape(n, 1, 2)
+    ref = oracle.render(sc, ref_attr, rx[0], 90, 360)
+    check_parity(got[0], ref, "emission -> render")
