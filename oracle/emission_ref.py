@@ -12,7 +12,7 @@ bias log d_i, d_i = |x_tx - mu_i|, and the emission is
 applied to the real and to the imaginary output separately.
 
 Readings: the hidden activation is ReLU (not named in the paper); d_i is
-floored at r_near (0.2 m), as everywhere else in this code, so that log d_i
+floored at r_near (0.2 m), as for the attenuation of the renderer, so that log d_i
 stays finite.  Parameter order per Gaussian: W1 [16][3] row-major, b1 [16],
 W2 [2][16] row-major, b2 [2].
 """
