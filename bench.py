@@ -310,38 +310,42 @@ def confidence_head(gs, dev):
 
 
 def emission_nets(gs, dev, n, Q):
-    """The paper's per-Gaussian 3 -> 16 -> 2 emission networks at the
-    training workload's size (n Gaussians, Q queries): forward and backward
-    kernel times from HIP events, priced against HBM (parameter-major
-    storage; algorithmic bytes: parameters and means read once, attributes
-    written or read once, gradients written once)."""
+    """The paper's per-Gaussian 3 -> H -> 2 emission networks at the training
+    workload's size (n Gaussians, Q queries) for the widths of the paper's
+    ablation (8, 16, 64): forward and backward kernel times from HIP events,
+    priced against HBM (parameter-major storage; algorithmic bytes:
+    parameters and means read once, attributes written or read once,
+    gradients written once)."""
     import torch
     g = torch.Generator(device="cpu").manual_seed(9)
-    P = (torch.randn(98, n, generator=g) * 0.6).to(dev)
     mean = (torch.rand(3, n, generator=g) * 10 - 5).to(dev)   # the scene's [3][n]
     rx = (torch.rand(Q, 3, generator=g) * 4 - 2).to(dev)
     tx = (torch.rand(Q, 3, generator=g) * 10 - 5).to(dev)
     ds = torch.randn(Q, n, 2, generator=g).to(dev)
-    out = {"gaussians": n, "queries": Q}
-    nbytes = {"forward": n * (98 + 3) * 4 + Q * n * 2 * 4,
-              "backward": n * (98 + 3) * 4 + Q * n * 2 * 4 + n * (98 + 3) * 4}
-    for name, fn in (("forward", lambda: gs.emission_forward(P, mean, rx, tx)),
-                     ("backward", lambda: gs.emission_backward(P, mean, rx, tx, ds))):
-        for _ in range(3):
-            fn()
-        reps = 20
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / reps
-        gbs = nbytes[name] / (us * 1e-6) / 1e9
-        out[name] = {"us": round(us, 2), "bytes": nbytes[name],
-                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                  "frac": round(gbs / PEAK_HBM_GBS, 4)}}
+    out = {"gaussians": n, "queries": Q, "widths": {}}
+    for H in (8, 16, 64):
+        P = (torch.randn(6 * H + 2, n, generator=g) * 0.6 * (16 / H) ** 0.5).to(dev)
+        per = (6 * H + 2 + 3) * 4
+        nbytes = {"forward": n * per + Q * n * 2 * 4, "backward": 2 * n * per + Q * n * 2 * 4}
+        row = {}
+        for name, fn in (("forward", lambda: gs.emission_forward(P, mean, rx, tx)),
+                         ("backward", lambda: gs.emission_backward(P, mean, rx, tx, ds))):
+            for _ in range(3):
+                fn()
+            reps = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            gbs = nbytes[name] / (us * 1e-6) / 1e9
+            row[name] = {"us": round(us, 2), "bytes": nbytes[name],
+                         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                      "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}}
+        out["widths"][str(H)] = row
     return out
 
 

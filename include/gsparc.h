@@ -414,9 +414,10 @@ gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, i
  * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1 or alpha negative or
  * not finite; GS_ERR_CAPACITY for n > 65536. */
 /* ---- the paper's own emission form: one network per Gaussian (Sec. 4.1, Eq. (1)) ----
- * Gaussian i owns a 3 -> 16 -> 2 network (98 FP32 parameters, stored as
- * params[k * param_stride + i], k = W1 [16][3] row-major, b1 [16], W2 [2][16]
- * row-major, b2 [2]; param_stride >= n).  For query q (receiver rx[q][3],
+ * Gaussian i owns a 3 -> H -> 2 network, H = hidden in {8, 16, 64} (16 in
+ * the paper, 8 and 64 in its width ablation): 6H + 2 FP32 parameters, stored
+ * as params[k * param_stride + i], k = W1 [H][3] row-major, b1 [H],
+ * W2 [2][H] row-major, b2 [2]; param_stride >= n.  For query q (receiver rx[q][3],
  * transmitter tx[q][3], device pointers):
  *   h = relu(W1 rx + b1) (hidden activation: a reading, the paper names
  *   none), f = W2 h + b2, d = max(|tx - mean_i|, r_near),
@@ -427,13 +428,13 @@ gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, i
  * The backward takes d_attr in the same layout and writes (overwrites) the
  * gradients of sum(d_attr * attr) with respect to the parameters (d_params,
  * same layout as params) and the means (d_mean [3][n]), summed over queries.
- * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1, n_queries < 1,
- * param_stride < n, attr_query_stride < 2 n or odd, r_near not positive and
- * finite; GS_ERR_CAPACITY for n_queries > 1024. */
-gs_status gs_emission_forward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+ * Errors: GS_ERR_INVALID_ARG for a null pointer, hidden not 8, 16 or 64,
+ * n < 1, n_queries < 1, param_stride < n, attr_query_stride < 2 n or odd,
+ * r_near not positive and finite; GS_ERR_CAPACITY for n_queries > 1024. */
+gs_status gs_emission_forward(const float* params, int64_t param_stride, int32_t hidden, const float* mean, int32_t n,
                               const float* rx, const float* tx, int32_t n_queries, float r_near, float* attr,
                               int64_t attr_query_stride, void* stream);
-gs_status gs_emission_backward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+gs_status gs_emission_backward(const float* params, int64_t param_stride, int32_t hidden, const float* mean, int32_t n,
                                const float* rx, const float* tx, int32_t n_queries, float r_near,
                                const float* d_attr, int64_t attr_query_stride, float* d_params, float* d_mean,
                                void* stream);

@@ -135,8 +135,9 @@ SIGNATURES = {
                                 c_i32, ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
     "gs_mfma_probe": (c_i32, [c_p, c_p, c_p, c_p]),
     "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p]),
-    "gs_emission_forward": (c_i32, [c_p, c_i64, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p]),
-    "gs_emission_backward": (c_i32, [c_p, c_i64, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p, c_p, c_p]),
+    "gs_emission_forward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p]),
+    "gs_emission_backward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p, c_p,
+                                     c_p]),
     "gs_confidence_loss": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_f32, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "gs_batch_plan_bytes": (c_sz, [c_i32]),
     "gs_batch_plan": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, ctypes.POINTER(GsBatchInfo), c_p]),

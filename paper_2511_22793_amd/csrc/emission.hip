@@ -1,23 +1,25 @@
-// The paper's own emission form: one 3 -> 16 -> 2 network per Gaussian
-// (Sec. 4.1, Eq. (1)).  For query q (receiver rx_q, transmitter tx_q):
+// The paper's own emission form: one 3 -> H -> 2 network per Gaussian
+// (Sec. 4.1, Eq. (1); H = 16, and 8 or 64 for the width ablation).  For
+// query q (receiver rx_q, transmitter tx_q):
 //   h = relu(W1_i rx_q + b1_i), f = W2_i h + b2_i,
 //   d = max(|tx_q - mu_i|, r_near),  s = sigmoid(f - log d)  (Re, Im);
 // the means in the scene's layout [3][n].
 // Parameters are stored per parameter index, then per Gaussian
-// (params[k * stride + i], k < 98: W1 [16][3], b1 [16], W2 [2][16], b2 [2]),
+// (params[k * stride + i], k < 6H + 2: W1 [H][3], b1 [H], W2 [2][H], b2 [2]),
 // so that one load instruction of a wave reads 64 consecutive Gaussians.
-// One thread per Gaussian holds its 98 parameters in registers and takes
+// One thread per Gaussian holds its 6H + 2 parameters in registers and takes
 // every query, so the parameters leave HBM once per launch (a batched
 // matrix-vector product: HBM-bound, not a matrix-core shape).
 #include "common.h"
 
 namespace gs {
 
-constexpr int EM_H = 16;
-constexpr int EM_NP = 3 * EM_H + EM_H + 2 * EM_H + 2;  // 98
+// parameters of a width-H network: W1 at 0 (3H), b1 at 3H, W2 at 4H (2H), b2 at 6H (2)
+__host__ __device__ constexpr int em_np(int H) { return 6 * H + 2; }
 
 __device__ __forceinline__ float em_sigmoid(float u) { return 1.0f / (1.0f + expf(-u)); }
 
+template <int H>
 __global__ __launch_bounds__(256) void k_emission_fwd(const float* __restrict__ P, int64_t ps,
                                                       const float* __restrict__ mean, int n,
                                                       const float* __restrict__ rx, const float* __restrict__ tx,
@@ -25,19 +27,20 @@ __global__ __launch_bounds__(256) void k_emission_fwd(const float* __restrict__ 
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float p[EM_NP];
+    constexpr int NP = em_np(H);
+    float p[NP];
 #pragma unroll
-    for (int k = 0; k < EM_NP; ++k) p[k] = P[(size_t)k * ps + i];
+    for (int k = 0; k < NP; ++k) p[k] = P[(size_t)k * ps + i];
     const float m0 = mean[i], m1 = mean[n + i], m2 = mean[2 * n + i];  // [3][n], as the scene
     for (int q = 0; q < nq; ++q) {
         const float x0 = rx[3 * q], x1 = rx[3 * q + 1], x2 = rx[3 * q + 2];
-        float f0 = p[96], f1 = p[97];
+        float f0 = p[6 * H], f1 = p[6 * H + 1];
 #pragma unroll
-        for (int j = 0; j < EM_H; ++j) {
-            const float z = fmaf(p[3 * j], x0, fmaf(p[3 * j + 1], x1, fmaf(p[3 * j + 2], x2, p[48 + j])));
+        for (int j = 0; j < H; ++j) {
+            const float z = fmaf(p[3 * j], x0, fmaf(p[3 * j + 1], x1, fmaf(p[3 * j + 2], x2, p[3 * H + j])));
             const float h = fmaxf(z, 0.0f);
-            f0 = fmaf(p[64 + j], h, f0);
-            f1 = fmaf(p[80 + j], h, f1);
+            f0 = fmaf(p[4 * H + j], h, f0);
+            f1 = fmaf(p[5 * H + j], h, f1);
         }
         const float v0 = tx[3 * q] - m0, v1 = tx[3 * q + 1] - m1, v2 = tx[3 * q + 2] - m2;
         const float d = fmaxf(sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2))), r_near);
@@ -47,6 +50,7 @@ __global__ __launch_bounds__(256) void k_emission_fwd(const float* __restrict__ 
     }
 }
 
+template <int H>
 __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ P, int64_t ps,
                                                       const float* __restrict__ mean, int n,
                                                       const float* __restrict__ rx, const float* __restrict__ tx,
@@ -56,9 +60,10 @@ __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ 
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float p[EM_NP], g[EM_NP];
+    constexpr int NP = em_np(H);
+    float p[NP], g[NP];
 #pragma unroll
-    for (int k = 0; k < EM_NP; ++k) {
+    for (int k = 0; k < NP; ++k) {
         p[k] = P[(size_t)k * ps + i];
         g[k] = 0.0f;
     }
@@ -66,14 +71,14 @@ __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ 
     float gm0 = 0.0f, gm1 = 0.0f, gm2 = 0.0f;
     for (int q = 0; q < nq; ++q) {
         const float x0 = rx[3 * q], x1 = rx[3 * q + 1], x2 = rx[3 * q + 2];
-        float z[EM_H];
-        float f0 = p[96], f1 = p[97];
+        float z[H];
+        float f0 = p[6 * H], f1 = p[6 * H + 1];
 #pragma unroll
-        for (int j = 0; j < EM_H; ++j) {
-            z[j] = fmaf(p[3 * j], x0, fmaf(p[3 * j + 1], x1, fmaf(p[3 * j + 2], x2, p[48 + j])));
+        for (int j = 0; j < H; ++j) {
+            z[j] = fmaf(p[3 * j], x0, fmaf(p[3 * j + 1], x1, fmaf(p[3 * j + 2], x2, p[3 * H + j])));
             const float h = fmaxf(z[j], 0.0f);
-            f0 = fmaf(p[64 + j], h, f0);
-            f1 = fmaf(p[80 + j], h, f1);
+            f0 = fmaf(p[4 * H + j], h, f0);
+            f1 = fmaf(p[5 * H + j], h, f1);
         }
         const float v0 = tx[3 * q] - m0, v1 = tx[3 * q + 1] - m1, v2 = tx[3 * q + 2] - m2;
         const float dist = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
@@ -82,15 +87,15 @@ __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ 
         const float s0 = em_sigmoid(f0 - ld), s1 = em_sigmoid(f1 - ld);
         const float2 up = ((const float2*)(dattr + q * as))[i];
         const float u0 = up.x * s0 * (1.0f - s0), u1 = up.y * s1 * (1.0f - s1);
-        g[96] += u0;
-        g[97] += u1;
+        g[6 * H] += u0;
+        g[6 * H + 1] += u1;
 #pragma unroll
-        for (int j = 0; j < EM_H; ++j) {
+        for (int j = 0; j < H; ++j) {
             const float h = fmaxf(z[j], 0.0f);
-            g[64 + j] = fmaf(u0, h, g[64 + j]);
-            g[80 + j] = fmaf(u1, h, g[80 + j]);
-            const float dz = z[j] > 0.0f ? fmaf(u0, p[64 + j], u1 * p[80 + j]) : 0.0f;
-            g[48 + j] += dz;
+            g[4 * H + j] = fmaf(u0, h, g[4 * H + j]);
+            g[5 * H + j] = fmaf(u1, h, g[5 * H + j]);
+            const float dz = z[j] > 0.0f ? fmaf(u0, p[4 * H + j], u1 * p[5 * H + j]) : 0.0f;
+            g[3 * H + j] += dz;
             g[3 * j] = fmaf(dz, x0, g[3 * j]);
             g[3 * j + 1] = fmaf(dz, x1, g[3 * j + 1]);
             g[3 * j + 2] = fmaf(dz, x2, g[3 * j + 2]);
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(256) void k_emission_bwd(const float* __restrict__ 
         }
     }
 #pragma unroll
-    for (int k = 0; k < EM_NP; ++k) dP[(size_t)k * ps + i] = g[k];
+    for (int k = 0; k < NP; ++k) dP[(size_t)k * ps + i] = g[k];
     dmean[i] = gm0;
     dmean[n + i] = gm1;
     dmean[2 * n + i] = gm2;
@@ -124,29 +129,31 @@ static gs_status em_check(const float* P, int64_t ps, const float* mean, int n, 
 
 using namespace gs;
 
-extern "C" gs_status gs_emission_forward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+extern "C" gs_status gs_emission_forward(const float* params, int64_t param_stride, int32_t hidden, const float* mean, int32_t n,
                                          const float* rx, const float* tx, int32_t n_queries, float r_near,
                                          float* attr, int64_t attr_query_stride, void* stream)
 {
     gs_status st = em_check(params, param_stride, mean, n, rx, tx, n_queries, r_near, attr_query_stride);
     if (st != GS_OK) return st;
-    if (!attr) return GS_ERR_INVALID_ARG;
+    if (!attr || (hidden != 8 && hidden != 16 && hidden != 64)) return GS_ERR_INVALID_ARG;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_emission_fwd, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
-                       param_stride, mean, n, rx, tx, n_queries, r_near, attr, attr_query_stride);
+    auto kern = hidden == 8 ? k_emission_fwd<8> : (hidden == 16 ? k_emission_fwd<16> : k_emission_fwd<64>);
+    hipLaunchKernelGGL(kern, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, param_stride, mean,
+                       n, rx, tx, n_queries, r_near, attr, attr_query_stride);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
-extern "C" gs_status gs_emission_backward(const float* params, int64_t param_stride, const float* mean, int32_t n,
+extern "C" gs_status gs_emission_backward(const float* params, int64_t param_stride, int32_t hidden, const float* mean, int32_t n,
                                           const float* rx, const float* tx, int32_t n_queries, float r_near,
                                           const float* d_attr, int64_t attr_query_stride, float* d_params,
                                           float* d_mean, void* stream)
 {
     gs_status st = em_check(params, param_stride, mean, n, rx, tx, n_queries, r_near, attr_query_stride);
     if (st != GS_OK) return st;
-    if (!d_attr || !d_params || !d_mean) return GS_ERR_INVALID_ARG;
+    if (!d_attr || !d_params || !d_mean || (hidden != 8 && hidden != 16 && hidden != 64)) return GS_ERR_INVALID_ARG;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_emission_bwd, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
-                       param_stride, mean, n, rx, tx, n_queries, r_near, d_attr, attr_query_stride, d_params, d_mean);
+    auto kern = hidden == 8 ? k_emission_bwd<8> : (hidden == 16 ? k_emission_bwd<16> : k_emission_bwd<64>);
+    hipLaunchKernelGGL(kern, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, param_stride, mean,
+                       n, rx, tx, n_queries, r_near, d_attr, attr_query_stride, d_params, d_mean);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }

@@ -22,7 +22,25 @@ def scene(n, seed):
 
 
 def test_parameter_count():
-    assert er.NPARAM == 98
+    assert er.NPARAM == 98 == er.nparam(16)
+    assert er.nparam(8) == 50 and er.nparam(64) == 386
+
+
+def test_other_widths_zero_network_and_finite_differences():
+    for H in (8, 64):
+        P, mean, rx, tx = scene(3, 20 + H)
+        P = np.random.default_rng(H).normal(0, 0.4, (3, er.nparam(H)))
+        s = er.forward(np.zeros_like(P), mean, rx, tx)
+        d = np.maximum(np.linalg.norm(tx[0] - mean, axis=1), er.R_NEAR)
+        assert np.allclose(s[0, :, 0], 1.0 / (1.0 + d), rtol=0, atol=1e-15)
+        ds = np.random.default_rng(H + 1).normal(size=(3, 3, 2))
+        dP, _ = er.backward(P, mean, rx, tx, ds)
+        f = lambda P_: float((ds * er.forward(P_, mean, rx, tx)).sum())  # noqa: E731
+        for k in range(0, er.nparam(H), 7):
+            a = P.copy(); a[1, k] += 1e-6
+            b = P.copy(); b[1, k] -= 1e-6
+            num = (f(a) - f(b)) / 2e-6
+            assert abs(dP[1, k] - num) <= 1e-6 * max(1.0, abs(num)), (H, k)
 
 
 def test_zero_network_is_inverse_one_plus_distance():

@@ -1,4 +1,5 @@
-"""The paper's per-Gaussian emission networks (Sec. 4.1, Eq. (1)) on the GPU
+"""The paper's per-Gaussian emission networks (Sec. 4.1, Eq. (1); hidden
+width 16, and 8 and 64 from the width ablation) on the GPU
 against the FP64 oracle (oracle/emission_ref.py) through the C ABI.
 
 Inputs are FP32-rounded before both sides see them; hidden biases whose
@@ -20,20 +21,20 @@ from oracle import emission_ref as er
 pytestmark = pytest.mark.gpu
 
 
-def case(n, Q, seed):
+def case(n, Q, seed, H=16):
     r = np.random.default_rng(seed)
-    P = r.normal(0, 0.6, (n, er.NPARAM)).astype(np.float32)
+    P = r.normal(0, 0.6 * (16 / H) ** 0.5, (n, er.nparam(H))).astype(np.float32)
     mean = r.uniform(-5, 5, (n, 3)).astype(np.float32)
     rx = r.uniform(-2, 2, (Q, 3)).astype(np.float32)
     tx = r.uniform(-5, 5, (Q, 3)).astype(np.float32)
     tx[0] = mean[0]                          # one floored distance
     for _ in range(100):
-        W1 = P[:, :48].reshape(n, 16, 3).astype(np.float64)
-        z = np.einsum("nij,qj->qni", W1, rx.astype(np.float64)) + P[:, 48:64]
-        bad = (np.abs(z) < 1e-3).any(0)      # (n, 16)
+        W1 = P[:, :3 * H].reshape(n, H, 3).astype(np.float64)
+        z = np.einsum("nij,qj->qni", W1, rx.astype(np.float64)) + P[:, 3 * H:4 * H]
+        bad = (np.abs(z) < 1e-3).any(0)      # (n, H)
         if not bad.any():
             break
-        P[:, 48:64][bad] = r.normal(0, 0.6, int(bad.sum())).astype(np.float32)
+        P[:, 3 * H:4 * H][bad] = r.normal(0, 0.6, int(bad.sum())).astype(np.float32)
     return P, mean, rx, tx
 
 
@@ -41,9 +42,10 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("n,Q,seed", [(1, 1, 1), (1000, 1, 2), (1000, 16, 3), (257, 7, 4), (100_000, 16, 5)])
-def test_emission_matches_oracle(n, Q, seed):
-    P, mean, rx, tx = case(n, Q, seed)
+@pytest.mark.parametrize("n,Q,seed,H", [(1, 1, 1, 16), (1000, 1, 2, 16), (1000, 16, 3, 16), (257, 7, 4, 16),
+                                       (100_000, 16, 5, 16), (1000, 16, 7, 8), (1000, 16, 8, 64)])
+def test_emission_matches_oracle(n, Q, seed, H):
+    P, mean, rx, tx = case(n, Q, seed, H)
     Pt = dev(np.ascontiguousarray(P.T))      # [98, n]
     mt = dev(np.ascontiguousarray(mean.T))   # [3, n], the scene's layout
     attr = gs.emission_forward(Pt, mt, dev(rx), dev(tx))
@@ -69,6 +71,8 @@ def test_input_checks():
     with pytest.raises(GsError) as e:
         gs.emission_forward(Pt, mt, dev(rx), dev(tx), r_near=0.0)
     assert e.value.status == GS_ERR_INVALID_ARG
+    with pytest.raises(ValueError):  # 6 H + 2 rows with H = 12: not a built width
+        gs.emission_forward(dev(np.zeros((74, 10), np.float32)), mt, dev(rx), dev(tx))
 
 
 def test_emission_feeds_the_renderer():
