@@ -94,3 +94,34 @@ def test_alpha_zero_is_the_weighted_task_loss():
     L = np.array([0.1, 0.2, 0.3, 0.4])
     g = cr.backward(x, L, W1, b1, w2, b2, 0.0)
     assert np.allclose(g["loss"], g["C"] * L, rtol=0, atol=1e-15)
+
+
+def test_hand_computed_head():
+    # x = (0.5, -1, 2); unit j < 8 reads input j mod 3 with weight 1:
+    #   z = (0.75, -0.5, -1, 1.5, -1, 1, -0.5, 1), h = (0.75, 0, 0, 1.5, 0, 1, 0, 1)
+    # units 8..31 read (1, 1, 1) with bias -10 (dead) and output weight 7,
+    # which only a missing ReLU would let through.
+    # g = 0.75*1 + 1.5*0.5 + 1*(-1) + 1*(-0.25) + b2 = 0.25 + 0.5 = 0.75
+    W1 = np.zeros((32, 3))
+    b1 = np.full(32, -10.0)
+    for j in range(8):
+        W1[j, j % 3] = 1.0
+    W1[8:] = 1.0
+    b1[:8] = [0.25, 0.5, -3.0, 1.0, 0.0, -1.0, -1.0, 2.0]
+    w2 = np.full(32, 7.0)
+    w2[:8] = [1.0, -2.0, 3.0, 0.5, 2.0, -1.0, 4.0, -0.25]
+    h, g, C = cr.forward(np.array([[0.5, -1.0, 2.0]]), W1, b1, w2, 0.5)
+    assert np.allclose(h[0, :8], [0.75, 0, 0, 1.5, 0, 1, 0, 1], rtol=0, atol=1e-15)
+    assert abs(g[0] - 0.75) <= 1e-15
+    assert abs(C[0] - (1.0 + np.exp(0.75))) <= 1e-15
+    # Eq. (6) at L_task = 0.2, alpha = 0.3: C L - alpha log C
+    Lc = cr.loss([0.2], C, 0.3)[0]
+    assert abs(Lc - ((1.0 + np.exp(0.75)) * 0.2 - 0.3 * np.log(1.0 + np.exp(0.75)))) <= 1e-15
+    # the output-bias gradient by hand: (L - alpha / C) (C - 1)
+    d = cr.backward(np.array([[0.5, -1.0, 2.0]]), [0.2], W1, b1, w2, 0.5, 0.3)
+    c = 1.0 + np.exp(0.75)
+    assert abs(d["db2"] - (0.2 - 0.3 / c) * (c - 1.0)) <= 1e-15
+    # hidden-unit gradients reach the live units only: dw2 = dg h
+    assert np.allclose(d["dw2"][:8], (0.2 - 0.3 / c) * (c - 1.0) * np.array([0.75, 0, 0, 1.5, 0, 1, 0, 1]),
+                       rtol=0, atol=1e-15)
+    assert np.all(d["dW1"][8:] == 0) and np.all(d["db1"][[1, 2, 4, 6]] == 0)

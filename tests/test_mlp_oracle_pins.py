@@ -99,3 +99,89 @@ def test_adam_matches_torch_optim():
         opt.step()
         q, m, v = mlp_ref.adam(q, g, m, v, t, 3e-3)
     assert np.allclose(q, p.detach().numpy(), rtol=0, atol=1e-14)
+
+
+LO, HI = [-5.0, -5.0, 0.0], [5.0, 5.0, 3.0]
+
+
+def _zeros():
+    return dict(W1=np.zeros((64, 96)), b1=np.zeros(64), W2=np.zeros((64, 64)), b2=np.zeros(64),
+                W3=np.zeros((128, 64)), b3=np.zeros(128))
+
+
+@pytest.mark.parametrize("rounding", [True, False])
+def test_zero_network_closed_form(rounding):
+    # every weight zero: o = b3, amplitude sigmoid(b3_f - ln d) = 1 / (1 + d exp(-b3_f)),
+    # phase b3_{64+f}; with b3 = 0, amplitude 1 / (1 + d) and phase 0
+    w = _zeros()
+    w["b3"][:64] = np.linspace(-2.0, 2.0, 64)
+    w["b3"][64:] = np.linspace(-3.0, 3.0, 64)
+    rng = np.random.default_rng(7)
+    n = 6
+    E = rng.normal(0, 0.1, size=(n, 32))
+    tx = np.array([[1.0, -2.0, 0.5], [0.0, 0.0, 3.0]])
+    mean = rng.uniform(LO, HI, size=(n, 3))
+    mean[2] = tx[0] + [0.0, 0.05, 0.0]          # within r_near of transmitter 0: d floored at 0.2
+    fw = mlp_ref.forward(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], E, tx, mean.T, 0.2, LO, HI,
+                         round_bf16=rounding)
+    for s in range(2):
+        d = np.maximum(np.linalg.norm(mean - tx[s], axis=1), 0.2)
+        amp = 1.0 / (1.0 + d[:, None] * np.exp(-w["b3"][None, :64]))
+        ph = w["b3"][None, 64:]
+        assert np.allclose(fw["attr"][s, ..., 0], amp * np.cos(ph), rtol=0, atol=1e-15)
+        assert np.allclose(fw["attr"][s, ..., 1], amp * np.sin(ph), rtol=0, atol=1e-15)
+    assert abs(np.hypot(*fw["attr"][0, 2, 32]) - 1.0 / (1.0 + 0.2 * np.exp(-w["b3"][32]))) < 1e-15
+
+
+@pytest.mark.parametrize("rounding", [True, False])
+def test_one_hot_network_by_hand(rounding):
+    """Three Gaussians with one-hot embeddings 0.5 e_i, a transmitter at
+    (2.5, 0, 1.5) (encoded u = (0.5, 0, 0)); every value is exact in BF16, so
+    the rounding points change nothing.
+      layer 1: unit j < 3 reads embedding dim j (weight 1), unit 3 reads u_x
+               (weight 2); b1[1] = -0.75, b1[3] = 0.25
+               z1 for Gaussian 0 = (0.5, -0.75, 0, 1.25)  h1 = (0.5, 0, 0, 1.25)
+                          1      (0, -0.25, 0, 1.25)             (0, 0, 0, 1.25)
+                          2      (0, -0.75, 0.5, 1.25)           (0, 0, 0.5, 1.25)
+      layer 2: identity on units 0..3: h2 = h1
+      layer 3: o_0 = 2 h2_0 + h2_3, o_1 = -4 h2_2, o_2 = b3[2] = 0.5,
+               o_64 = h2_3, o_65 = -2 h2_0, o_66 = b3[66] = 0.25
+               Gaussian 0: o_0 = 2.25, o_1 = 0,  phases (1.25, -1, 0.25)
+                        1: o_0 = 1.25, o_1 = 0,  phases (1.25, 0, 0.25)
+                        2: o_0 = 1.25, o_1 = -2, phases (1.25, 0, 0.25)
+    Distances to the transmitter: 1, 2 and 0.1 (floored at r_near = 0.2);
+    amplitude 1 / (1 + d exp(-o)), all other subcarriers amplitude 1/(1+d),
+    phase 0."""
+    w = _zeros()
+    for j in range(3):
+        w["W1"][j, j] = 1.0
+    w["W1"][3, 32] = 2.0
+    w["b1"][1], w["b1"][3] = -0.75, 0.25
+    for j in range(4):
+        w["W2"][j, j] = 1.0
+    w["W3"][0, 0], w["W3"][0, 3] = 2.0, 1.0
+    w["W3"][1, 2] = -4.0
+    w["W3"][64, 3] = 1.0
+    w["W3"][65, 0] = -2.0
+    w["b3"][2], w["b3"][66] = 0.5, 0.25
+    E = np.zeros((3, 32))
+    for i in range(3):
+        E[i, i] = 0.5
+    tx = np.array([[2.5, 0.0, 1.5]])
+    mean = np.array([[3.5, 0.0, 1.5], [2.5, 2.0, 1.5], [2.5, 0.0, 1.4]], np.float32)
+    fw = mlp_ref.forward(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], E, tx, mean.T, 0.2, LO, HI,
+                         round_bf16=rounding)
+    assert np.allclose(fw["g"][0, :3], [0.5, 0.0, 0.0], rtol=0, atol=1e-15)
+    d = [1.0, 2.0, 0.2]
+    o = [(2.25, 0.0), (1.25, 0.0), (1.25, -2.0)]
+    ph = [(1.25, -1.0), (1.25, 0.0), (1.25, 0.0)]
+    for i in range(3):
+        amp = np.full(64, 1.0 / (1.0 + d[i]))
+        amp[0] = 1.0 / (1.0 + d[i] * np.exp(-o[i][0]))
+        amp[1] = 1.0 / (1.0 + d[i] * np.exp(-o[i][1]))
+        amp[2] = 1.0 / (1.0 + d[i] * np.exp(-0.5))
+        phase = np.zeros(64)
+        phase[0], phase[1], phase[2] = ph[i][0], ph[i][1], 0.25
+        a = fw["attr"][0, i]
+        assert np.allclose(a[:, 0], amp * np.cos(phase), rtol=0, atol=1e-12), i
+        assert np.allclose(a[:, 1], amp * np.sin(phase), rtol=0, atol=1e-12), i
