@@ -14,7 +14,7 @@ import oracle
 import paper_2511_22793_amd as gs
 import synth
 from gpu_util import oracle_params, to_dev
-from oracle import torch_ref
+from oracle import loss_ref, torch_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -206,17 +206,15 @@ def test_loss_kernel_matches_definition(cplx, lam, H, W):
     zh = rng.normal(size=shape).astype(np.float32)
     z = rng.normal(size=shape).astype(np.float32)
     loss, hh, d = gs.loss_spectrum(torch.from_numpy(zh).cuda(), torch.from_numpy(z).cuda(), cplx, lam)
+    L_ref, h_ref, g_ref = loss_ref.l2_channel_loss(zh, z, cplx, lam)
+    assert np.allclose(loss.cpu().numpy(), L_ref, rtol=1e-4)
+    assert np.allclose(hh.cpu().numpy(), h_ref, atol=1e-6)
+    # the pixel and channel terms of the gradient can cancel in FP32:
+    # absolute tolerance scaled by the larger term
     zh64, z64 = zh.astype(np.float64), z.astype(np.float64)
-    hmean = zh64.mean(axis=(2, 3))
-    tmean = z64.mean(axis=(2, 3))
-    per = ((zh64 - z64) ** 2).reshape(B, -1).sum(1) / (F * H * W) + lam * ((hmean - tmean) ** 2).reshape(B, -1).sum(1)
-    assert np.allclose(loss.cpu().numpy(), per, rtol=1e-4)
-    assert np.allclose(hh.cpu().numpy(), hmean, atol=1e-6)
-    # gradient of mean_b L_b by its definition
-    gdef = (2 * (zh64 - z64) / (F * H * W) + lam * 2 * (hmean - tmean)[:, :, None, None] / (H * W)) / B
-    # the two FP32 terms can cancel: absolute tolerance scaled by the terms
-    terms = np.abs(2 * (zh64 - z64) / (F * H * W) / B).max() + np.abs(lam * 2 * (hmean - tmean) / (H * W) / B).max()
-    assert np.allclose(d.cpu().numpy(), gdef, rtol=1e-4, atol=1e-6 * terms)
+    dm = np.abs(h_ref - loss_ref.spatial_mean(z64, cplx)).max()
+    terms = np.abs(2 * (zh64 - z64) / (F * H * W) / B).max() + lam * 2 * dm / (H * W) / B
+    assert np.allclose(d.cpu().numpy(), g_ref, rtol=1e-4, atol=1e-6 * terms)
 
 
 @pytest.mark.slow
