@@ -74,7 +74,7 @@ def lib():
         L.orc_order.restype = i32
         L.orc_order.argtypes = [i32, P, P, P]
         L.orc_render.restype = i32
-        L.orc_render.argtypes = [i32, P, P, i32, P, i32, i32, i32, i32, P, P, i32, P, P, P, P, P, i32]
+        L.orc_render.argtypes = [i32, P, P, i32, P, i32, i32, i32, i32, P, P, i32, P, P, P, P, P, P, P, i32]
         L.orc_bin.restype = ctypes.c_long
         L.orc_bin.argtypes = [i32, P, P, i32, i32, i32, i32, P, P, ctypes.c_long]
         L.orc_render_tiled.restype = i32
@@ -143,7 +143,11 @@ def composite(proj: dict, order: np.ndarray, attr, H: int, W: int, prm=None, pix
               nthreads: int = 0) -> dict:
     """Per-pixel compositing over `order` (no tiles). attr: [n, F] real or
     [n, F, 2] complex. Returns out [F,H,W] (complex128 when complex), absacc,
-    T_final, n_contrib, ambig."""
+    T_final, n_contrib, ambig, ambig_kind (bits: 1 alpha_min, 2 alpha_max,
+    4 the stop, 8 the seam), flip_bound [F,H,W] (the change a flip of the
+    ambiguous decisions can cause; 0 on unambiguous pixels) and live [n]
+    (bit 0: taken at an unambiguous pixel; bit 1: taken at, or a decision in
+    doubt at, an ambiguous pixel)."""
     prm = params() if prm is None else prm
     attr = _f32(attr)
     n = proj["n"]
@@ -156,6 +160,8 @@ def composite(proj: dict, order: np.ndarray, attr, H: int, W: int, prm=None, pix
     Tf = np.ones((H, W), np.float64)
     nc = np.zeros((H, W), np.int32)
     amb = np.zeros((H, W), np.uint8)
+    flipb = np.zeros((F, H, W), np.float64)
+    live = np.zeros(max(n, 1), np.uint8)
     order = np.ascontiguousarray(order, dtype=np.int32)
     if pixels is None:
         pix, npix = None, 0
@@ -164,10 +170,11 @@ def composite(proj: dict, order: np.ndarray, attr, H: int, W: int, prm=None, pix
         npix = pix.shape[0]
     rc = lib().orc_render(n, _p(proj["rec"]), _p(order), order.shape[0], _p(attr), F, int(cplx), H, W,
                           _p(prm), None if pix is None else _p(pix), npix, _p(out), _p(Tf), _p(nc),
-                          _p(absacc), _p(amb), _nthreads(nthreads))
+                          _p(absacc), _p(amb), _p(flipb), _p(live), _nthreads(nthreads))
     assert rc == 0
     val = out[..., 0] + 1j * out[..., 1] if cplx else out[..., 0]
-    return dict(out=val, absacc=absacc, T_final=Tf, n_contrib=nc, ambig=amb.astype(bool))
+    return dict(out=val, absacc=absacc, T_final=Tf, n_contrib=nc, ambig=amb.astype(bool), ambig_kind=amb,
+                flip_bound=flipb, live=live[:n])
 
 
 def render(scene: dict, attr, rx, H: int, W: int, prm=None, tx=None, view=None, pixels=None,

@@ -223,25 +223,75 @@ typedef struct {
     int* n_contrib;
     double* absacc;
     unsigned char* ambig;
+    double* flipb;
+    unsigned char* live;
+    int* scratch; /* per thread: 2 * nvis + 8 ints when live is set */
     int thread, nthreads;
     const int* tile_off; /* non-NULL: tiled variant */
     const int* tile_list;
     int tw, th;
 } job_t;
 
-/* margin of a decision relative to its threshold */
-static int near_rel(double v, double thr) { return fabs(v - thr) <= 1e-5 * fabs(thr); }
+/* A decision counts as ambiguous when its value lies within 1e-5 of its
+ * threshold, relative: an FP32 evaluation of the same decision carries a few
+ * roundings in alpha = sigma G (~6e-7 relative) and, in the transmittance, a
+ * product of ~30 rounded factors (1 - alpha), each carrying alpha's error
+ * scaled by alpha / (1 - alpha): up to ~1e-5. */
+#define AMB_ALPHA 1e-5
+#define AMB_T 1e-5
+static int near_rel(double v, double thr, double m) { return fabs(v - thr) <= m * fabs(thr); }
 
+/* |u_{g,f}| of every channel f of Gaussian g: attenuation times the modulus */
+static void mag_u(const job_t* J, int g, double att, double* m)
+{
+    const int C = J->cplx ? 2 : 1;
+    const float* v = J->attr + (size_t)g * J->F * C;
+    for (int f = 0; f < J->F; ++f) {
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += (double)v[f * C + c] * (double)v[f * C + c];
+        m[f] = fabs(att) * sqrt(s);
+    }
+}
+
+/* clamped alpha of a pair, 0 when below alpha_min */
+static double alpha_of(double sg, double amin, double amax)
+{
+    const double a = sg < amax ? sg : amax;
+    return a < amin ? 0.0 : a;
+}
+
+/* One pixel over `list` (Eq. (3)).  Besides the output, the final
+ * transmittance and the contributor count, it records:
+ *  absacc[f] = sum_i T_i alpha_i |u_i,f| (the absolute-sum magnitude A);
+ *  ambig     = some decision (alpha >= alpha_min, the T_min stop, the
+ *              alpha_max clamp, the seam wrap of a reaching Gaussian) lies
+ *              within 1e-5 relative of its threshold;
+ *  flipb[f]  = an upper bound of how far an evaluation that takes any of
+ *              those decisions the other way can move out_f: a flipped
+ *              alpha test or wrap changes alpha_i by d (<= alpha_min(1+1e-5)
+ *              for the test, |alpha(wrap 1) - alpha(wrap 2)| for the wrap),
+ *              which moves the term T_i alpha_i u_i by d T_i |u_i| and scales
+ *              every later term by (1 - alpha_i)/(1 - alpha_i +- d): at most
+ *              d A more; a flipped stop adds or drops T_i alpha_i u_i (the
+ *              next entry then stops either way, as alpha >= alpha_min >>
+ *              1e-5); after a flipped alpha the stop may also move by one
+ *              entry either way (the last accepted term, or the term that
+ *              stopped the walk at T / (1 - sum d)).  Plus 1e-5 A for the
+ *              ordinary rounding of the compared evaluation.  The clamp at
+ *              alpha_max is continuous in the value: it adds nothing. */
 static void shade_pixel(const job_t* J, int row, int col, const int* list, int len)
 {
     const double amin = J->prm[PRM_AMIN], amax = J->prm[PRM_AMAX], tmin = J->prm[PRM_TMIN];
     const int F = J->F, C = J->cplx ? 2 : 1, W = J->W, H = J->H;
     const size_t HW = (size_t)H * W, pix = (size_t)row * W + col;
-    double acc[2 * 512], aab[2 * 512];
-    for (int k = 0; k < F * C; ++k) acc[k] = aab[k] = 0.0;
-    double T = 1.0;
-    int cnt = 0;
+    double acc[2 * 512], aab[512], direct[512], um[512], last[512];
+    for (int k = 0; k < F * C; ++k) acc[k] = 0.0;
+    for (int f = 0; f < F; ++f) aab[f] = direct[f] = last[f] = 0.0;
+    double T = 1.0, dsum = 0.0;
+    int cnt = 0, ncand = 0;
     unsigned char amb = 0;
+    int* taken = J->live ? J->scratch : NULL;   /* taken entries, then candidates from the top */
+    int* cand = J->live ? J->scratch + len + 4 : NULL;
     for (int k = 0; k < len; ++k) {
         const int g = list[k];
         const double* R_ = J->rec + (size_t)g * NREC;
@@ -250,19 +300,39 @@ static void shade_pixel(const job_t* J, int row, int col, const int* list, int l
         else if (dx < -0.5 * W) dx += W;
         const double dy = (row + 0.5) - R_[R_PY];
         const double q = R_[R_CA] * dx * dx + 2.0 * R_[R_CB] * dx * dy + R_[R_CC] * dy * dy;
+        const double sg = R_[R_SIG] * exp(-0.5 * q);
+        double dflip = 0.0;
         if (fabs(fabs(dx) - 0.5 * W) < 1e-4) {
             /* offset on the seam: ambiguous only if either wrap reaches the support */
             const double dx2 = dx < 0 ? dx + W : dx - W;
             const double q2 = R_[R_CA] * dx2 * dx2 + 2.0 * R_[R_CB] * dx2 * dy + R_[R_CC] * dy * dy;
             const double qm = q < q2 ? q : q2;
-            if (R_[R_SIG] * exp(-0.5 * qm) >= 0.5 * amin) amb = 1;
+            if (R_[R_SIG] * exp(-0.5 * qm) >= 0.5 * amin) {
+                amb |= 8;
+                dflip = fabs(alpha_of(sg, amin, amax) - alpha_of(R_[R_SIG] * exp(-0.5 * q2), amin, amax));
+            }
         }
-        const double sg = R_[R_SIG] * exp(-0.5 * q);
-        if (near_rel(sg, amin) || near_rel(sg, amax)) amb = 1;
+        if (near_rel(sg, amin, AMB_ALPHA)) { amb |= 1; dflip += amin * (1.0 + AMB_ALPHA); }
+        if (near_rel(sg, amax, AMB_ALPHA)) amb |= 2;
+        if (dflip > 0.0) {
+            if (cand) cand[ncand++] = g;
+            mag_u(J, g, R_[R_ATT], um);
+            for (int f = 0; f < F; ++f) direct[f] += dflip * T * um[f];
+            dsum += dflip;
+        }
         const double alpha = sg < amax ? sg : amax;
         if (alpha < amin) continue;
         const double Tn = T * (1.0 - alpha);
-        if (near_rel(Tn, tmin)) amb = 1;
+        const int stop_amb = near_rel(Tn, tmin, AMB_T);
+        if (stop_amb || (Tn < tmin && dsum > 0.0)) {
+            mag_u(J, g, R_[R_ATT], um);
+            /* the flipped stop adds or drops this term; after a flipped
+             * alpha the walk's transmittance here is at most T / (1 - dsum) */
+            const double Tb = (Tn < tmin && dsum > 0.0) ? T / (1.0 - (dsum < 0.5 ? dsum : 0.5)) : T;
+            for (int f = 0; f < F; ++f) direct[f] += Tb * alpha * um[f];
+            if (stop_amb) amb |= 4;
+            if (cand) cand[ncand++] = g;
+        }
         if (Tn < tmin) break;
         const double w = T * alpha * R_[R_ATT];
         const float* v = J->attr + (size_t)g * F * C;
@@ -272,10 +342,17 @@ static void shade_pixel(const job_t* J, int row, int col, const int* list, int l
                 acc[f * C + c] += w * (double)v[f * C + c];
                 mag += (double)v[f * C + c] * (double)v[f * C + c];
             }
-            aab[f] += fabs(w) * sqrt(mag);
+            last[f] = fabs(w) * sqrt(mag);
+            aab[f] += last[f];
         }
+        if (taken) taken[cnt] = g;
         T = Tn;
         ++cnt;
+    }
+    if (J->live) {
+        for (int k = 0; k < cnt; ++k) __atomic_fetch_or(&J->live[taken[k]], amb ? 2 : 1, __ATOMIC_RELAXED);
+        if (amb)
+            for (int k = 0; k < ncand; ++k) __atomic_fetch_or(&J->live[cand[k]], 2, __ATOMIC_RELAXED);
     }
     for (int f = 0; f < F; ++f)
         for (int c = 0; c < C; ++c) {
@@ -283,14 +360,33 @@ static void shade_pixel(const job_t* J, int row, int col, const int* list, int l
             /* absolute-sum magnitude sum_i T_i alpha_i |u_i,f| (complex modulus) */
             if (J->absacc && c == 0) J->absacc[(size_t)f * HW + pix] = aab[f];
         }
+    if (J->flipb)
+        for (int f = 0; f < F; ++f)
+            J->flipb[(size_t)f * HW + pix] =
+                amb ? 1e-5 * aab[f] + direct[f] + dsum * aab[f] + (dsum > 0.0 ? last[f] : 0.0) : 0.0;
     J->T_final[pix] = T;
     J->n_contrib[pix] = cnt;
     if (J->ambig) J->ambig[pix] = amb;
 }
 
+static void render_rows(const job_t* J);
+
 static void* render_worker(void* arg)
 {
-    const job_t* J = (const job_t*)arg;
+    job_t* J = (job_t*)arg;
+    if (J->live) {
+        int m = J->nvis > 0 ? J->nvis : 1;
+        if (J->tile_off) m = J->n;
+        J->scratch = (int*)malloc(sizeof(int) * (2 * (size_t)m + 8));
+    }
+    render_rows(J);
+    free(J->scratch);
+    J->scratch = NULL;
+    return NULL;
+}
+
+static void render_rows(const job_t* J)
+{
     if (J->tile_off) {
         const int TX = (J->W + J->tw - 1) / J->tw, TY = (J->H + J->th - 1) / J->th;
         for (int t = J->thread; t < TX * TY; t += J->nthreads) {
@@ -308,7 +404,6 @@ static void* render_worker(void* arg)
         for (int row = J->thread; row < J->H; row += J->nthreads)
             for (int col = 0; col < J->W; ++col) shade_pixel(J, row, col, J->order, J->nvis);
     }
-    return NULL;
 }
 
 static int run_jobs(job_t* base, int nthreads)
@@ -332,10 +427,15 @@ static int run_jobs(job_t* base, int nthreads)
  * non-NULL) walks the full depth order.  out is [F][H][W][C] (C = 2 when
  * complex), absacc [F][H][W] (may be NULL), T_final and n_contrib [H][W],
  * ambig [H][W] (may be NULL) flags pixels with a decision within 1e-5 of its
- * threshold.  Unlisted pixels are left untouched.  */
+ * threshold, flipb [F][H][W] (may be NULL) bounds what flipping those
+ * decisions can change (see shade_pixel).  live [n] (may be NULL, zeroed by
+ * the caller) gets bit 0 for a Gaussian taken at some unambiguous pixel and
+ * bit 1 for one taken, or whose decision is ambiguous, at an ambiguous
+ * pixel.  Unlisted pixels are left untouched.  */
 int orc_render(int n, const double* rec, const int* order, int nvis, const float* attr, int F,
                int cplx, int H, int W, const double* prm, const int* pix, int npix, double* out,
-               double* T_final, int* n_contrib, double* absacc, unsigned char* ambig, int nthreads)
+               double* T_final, int* n_contrib, double* absacc, unsigned char* ambig, double* flipb,
+               unsigned char* live, int nthreads)
 {
     if (F < 1 || F > 512) return -1;
     job_t J;
@@ -343,6 +443,8 @@ int orc_render(int n, const double* rec, const int* order, int nvis, const float
     J.n = n; J.nvis = nvis; J.F = F; J.cplx = cplx; J.H = H; J.W = W;
     J.rec = rec; J.order = order; J.attr = attr; J.prm = prm; J.pix = pix; J.npix = npix;
     J.out = out; J.T_final = T_final; J.n_contrib = n_contrib; J.absacc = absacc; J.ambig = ambig;
+    J.flipb = flipb;
+    J.live = live;
     return run_jobs(&J, nthreads);
 }
 

@@ -448,3 +448,54 @@ def test_autograd_gradients_match_central_differences():
     assert (_loss_c(sc, A2, G, rx, prm)[0] - base) / np.float64(np.float32(A2[3, 1, 0]) - np.float32(A[3, 1, 0])) == \
         pytest.approx(ga[3, 1, 0], rel=1e-5, abs=1e-9)
     assert checked >= 12
+
+
+@pytest.mark.parametrize("n,seed,rx,T_min", [(2048, 0, (0.0, 0.0, 0.0), 1e-4), (10_001, 7, (2.0, 2.0, 0.2), 1e-4),
+                                             (2048, 41, (0.0, 0.0, 0.0), 1e-2)])
+def test_flip_bound_covers_flipped_decisions(n, seed, rx, T_min):
+    # Moving alpha_min and T_min by 1e-5 relative takes exactly the
+    # decisions within the ambiguity margin the other way (the oracle's
+    # model of an evaluation that decides them differently): every changed
+    # pixel must be marked ambiguous and stay within its flip bound.
+    sc = synth.scene(n, seed=seed)
+    attr = synth.channel_attrs(n, 3, True, seed=seed + 1)
+    base = oracle.render(sc, attr, rx, 90, 360, prm=oracle.params(T_min=T_min))
+    amb = base["ambig"]
+    assert amb.any()
+    changed_any = np.zeros_like(amb)
+    for sa, st in ((1, 1), (-1, -1), (1, -1), (-1, 1)):
+        prm = oracle.params(T_min=T_min)
+        prm[0] *= 1.0 + sa * 1e-5
+        prm[2] *= 1.0 + st * 1e-5
+        r = oracle.render(sc, attr, rx, 90, 360, prm=prm)
+        d = np.abs(r["out"] - base["out"])
+        changed = (d > 1e-12 * np.maximum(base["absacc"], 1e-30)).any(axis=0)
+        assert not (changed & ~amb).any()
+        assert np.all(d[:, amb] <= base["flip_bound"][:, amb])
+        changed_any |= changed
+    assert changed_any.any()
+    assert np.all(base["flip_bound"][:, ~amb] == 0)
+
+
+def test_live_set_is_whose_attributes_reach_the_image():
+    # a Gaussian outside the live set is never added at any pixel (it is
+    # skipped, or lies past the stop; the Gaussian that stops a pixel is not
+    # added either): any attributes for all of them leave the image
+    # bit-identical, while changing a live Gaussian's attributes changes it
+    n = 2000
+    sc = synth.scene(n, seed=91, lo=[-3, -3, 0.1], hi=[3, 3, 2.0], log_scale_mean=-1.0)
+    attr = synth.channel_attrs(n, 2, True, seed=92)
+    rx = [0.1, 0.2, 0.0]
+    base = oracle.render(sc, attr, rx, 90, 360)
+    live = base["live"]
+    L = np.nonzero(live & 1)[0]
+    dead = np.nonzero(live == 0)[0]
+    assert 20 < len(L) < n and len(dead) > n // 2
+    a2 = attr.copy()
+    a2[dead] = synth.channel_attrs(len(dead), 2, True, seed=94) * 1e3
+    r = oracle.render(sc, a2, rx, 90, 360)
+    assert np.array_equal(r["out"], base["out"]) and np.array_equal(r["live"], live)
+    for g in L[synth.subset(len(L), 24, seed=93)]:
+        a3 = attr.copy()
+        a3[g] += 1.0
+        assert not np.array_equal(oracle.render(sc, a3, rx, 90, 360)["out"], base["out"]), g
