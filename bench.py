@@ -110,7 +110,7 @@ def main():
     rx1 = torch.zeros(1, 3, device=dev)
     targets = torch.empty(B, F, H, W, 2, device=dev)
     for b in range(B):
-        a = torch.from_numpy(train.ground_truth_attributes(gt, rho, tx_all[b:b + 1])[0]).to(dev)
+        a = torch.from_numpy(synth.ground_truth_attributes(gt, rho, tx_all[b:b + 1])[0]).to(dev)
         out, _ = gs.forward(gt_dev, a, rx1, grid=grid, is_complex=True)
         targets[b] = out[0]
     tx = torch.from_numpy(tx_all[:B]).to(dev)
@@ -422,7 +422,7 @@ def plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, box_lo, b
     n, B, SB = args.n, args.batch, args.serve_batch
     sc = {k: torch.from_numpy(v).to(dev) for k, v in scene.items()}
     rx1 = torch.zeros(1, 3, device=dev)
-    attrs = [torch.from_numpy(train.ground_truth_attributes(gt, rho, tx_all[b:b + 1])[0]).to(dev) for b in range(4)]
+    attrs = [torch.from_numpy(synth.ground_truth_attributes(gt, rho, tx_all[b:b + 1])[0]).to(dev) for b in range(4)]
     ws = gs.Workspace(n, 1, grid, gs.Params(), device=dev)
     out = torch.empty(1, train.F, grid.H, grid.W, 2, device=dev)
     for a in attrs:
@@ -462,7 +462,7 @@ def cpu_baseline(gt, rho, tx_all, H, W, seconds):
     t = time.perf_counter()
     k = 0
     while True:
-        attr = train.ground_truth_attributes(gt, rho, tx_all[k % len(tx_all):k % len(tx_all) + 1])[0]
+        attr = synth.ground_truth_attributes(gt, rho, tx_all[k % len(tx_all):k % len(tx_all) + 1])[0]
         oracle.render(gt, attr, [0, 0, 0], H, W, nthreads=threads)
         k += 1
         if time.perf_counter() - t >= seconds and k >= 2:

@@ -388,7 +388,14 @@ gs_status gs_mfma_probe(const uint16_t* A, const uint16_t* B, float* C, void* st
 /* ---- fused Adam over parameter segments (Kingma and Ba) ----
  * For each segment: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); when shadow is
- * set, shadow = bf16(p).  Segments are described on the host. */
+ * set, shadow = bf16(p).  Segments are described on the host (at most 16).
+ * skip_if (device, or NULL): when the word it points to is non-zero at run
+ * time, nothing is updated and *skip_count (device, or NULL) is incremented
+ * -- e.g. the overflow word of the render workspace, so that a step whose
+ * pair buffer overflowed (its spectra and gradients undefined) changes no
+ * parameter, without a host synchronisation.  Errors: GS_ERR_INVALID_ARG
+ * for a null segment pointer, a negative count, n_segs outside [1, 16],
+ * step < 1 or beta / eps out of range. */
 typedef struct {
     float* p;
     const float* g;
@@ -399,7 +406,12 @@ typedef struct {
     float lr;
 } gs_adam_segment;
 gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, int32_t step, float beta1,
-                       float beta2, float eps, void* stream);
+                       float beta2, float eps, const uint32_t* skip_if, uint32_t* skip_count, void* stream);
+
+/* Device address of query q's overflow word in a workspace laid out for
+ * (n, n_queries, grid, prm): for gs_adam_step's skip_if.  Host-side only. */
+gs_status gs_overflow_word(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries,
+                           const gs_grid* grid, const gs_params* prm, int32_t q, const uint32_t** word);
 
 /* ---- confidence head and confidence-weighted loss (Sec. 4.2, Eq. (6)) ----
  * Per sample b (receiver position x_rx[b][3], task loss task_loss[b]):

@@ -134,7 +134,9 @@ SIGNATURES = {
     "gs_mlp_backward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
                                 c_i32, ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
     "gs_mfma_probe": (c_i32, [c_p, c_p, c_p, c_p]),
-    "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p]),
+    "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p, c_p, c_p]),
+    "gs_overflow_word": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_i32,
+                                 ctypes.POINTER(c_p)]),
     "gs_emission_forward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p]),
     "gs_emission_backward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p, c_p,
                                      c_p]),

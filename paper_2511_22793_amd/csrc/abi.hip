@@ -385,6 +385,18 @@ gs_status gs_render_backward_l2(const gs_scene* scene, const gs_attrs* attrs, co
                            d_opacity_logit, d_attr, flags, workspace, ws_bytes, stream);
 }
 
+gs_status gs_overflow_word(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries,
+                           const gs_grid* grid, const gs_params* prm, int32_t q, const uint32_t** word)
+{
+    if (!word || q < 0 || q >= n_queries) return GS_ERR_INVALID_ARG;
+    Layout L;
+    gs_status st = make_layout(n, n_queries, grid, prm, &L);
+    if (st != GS_OK) return st;
+    if (!workspace || ws_bytes < L.total) return GS_ERR_WORKSPACE;
+    *word = (const uint32_t*)((const char*)workspace + L.flags + (size_t)q * L.s_flags) + FL_OVERFLOW;
+    return GS_OK;
+}
+
 gs_status gs_read_flags(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries, const gs_grid* grid,
                         const gs_params* prm, gs_flags* out, void* stream)
 {

@@ -25,8 +25,15 @@ __device__ __forceinline__ uint16_t f2bf_rne(float x)
     return (uint16_t)(u >> 16);
 }
 
-__global__ __launch_bounds__(256) void k_adam(AdamSegs S, float b1, float b2, float eps, float c1, float c2)
+__global__ __launch_bounds__(256) void k_adam(AdamSegs S, float b1, float b2, float eps, float c1, float c2,
+                                              const uint32_t* __restrict__ skip_if, uint32_t* __restrict__ skip_count)
 {
+    // a set guard word (e.g. a render's pair-overflow flag) leaves every
+    // parameter and moment untouched; one thread counts the skipped step
+    if (skip_if && *skip_if) {
+        if (skip_count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(skip_count, 1u);
+        return;
+    }
     const int64_t total = S.start[S.nseg];
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
         int k = 0;
@@ -48,7 +55,8 @@ __global__ __launch_bounds__(256) void k_adam(AdamSegs S, float b1, float b2, fl
 using namespace gs;
 
 extern "C" gs_status gs_adam_step(const gs_adam_segment* segs, int32_t n_segs, int32_t step, float beta1,
-                                  float beta2, float eps, void* stream)
+                                  float beta2, float eps, const uint32_t* skip_if, uint32_t* skip_count,
+                                  void* stream)
 {
     if (!segs || n_segs < 1 || n_segs > ADAM_MAX_SEGS || step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) ||
         !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
@@ -69,6 +77,6 @@ extern "C" gs_status gs_adam_step(const gs_adam_segment* segs, int32_t n_segs, i
     (void)hipGetLastError();
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, (hipStream_t)stream,
-                       S, beta1, beta2, eps, (float)c1, (float)c2);
+                       S, beta1, beta2, eps, (float)c1, (float)c2, skip_if, skip_count);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }

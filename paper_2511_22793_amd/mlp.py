@@ -141,13 +141,19 @@ def backward(net: AttributeNet, E_bf: torch.Tensor, mean: torch.Tensor, rows: Ro
     return grads
 
 
-def adam_step(segments, step: int, beta1=0.9, beta2=0.999, eps=1e-15):
-    """segments: list of (param, grad, m, v, bf16_shadow or None, lr)."""
+def adam_step(segments, step: int, beta1=0.9, beta2=0.999, eps=1e-15, skip_if=None,
+              skip_count: Optional[torch.Tensor] = None):
+    """segments: list of (param, grad, m, v, bf16_shadow or None, lr).
+    skip_if: device address (int) of a guard word; when it holds a non-zero
+    value at run time nothing is updated and skip_count (int32 device
+    tensor) is incremented."""
     arr = (GsAdamSegment * len(segments))()
     dev = segments[0][0].device
     for k, (p, g, m, v, sh, lr) in enumerate(segments):
         arr[k] = GsAdamSegment(_p(p), _p(g), _p(m), _p(v), _p(sh), p.numel(), float(lr))
-    check(lib().gs_adam_step(arr, len(segments), int(step), beta1, beta2, eps, _stream(dev)), "gs_adam_step")
+    check(lib().gs_adam_step(arr, len(segments), int(step), beta1, beta2, eps,
+                             None if skip_if is None else ctypes.c_void_p(skip_if), _p(skip_count), _stream(dev)),
+          "gs_adam_step")
 
 
 def mfma_probe(A_bits: torch.Tensor, B_bits: torch.Tensor) -> torch.Tensor:

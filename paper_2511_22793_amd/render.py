@@ -103,6 +103,14 @@ class Workspace:
         b = self.buf[self.offset + off:self.offset + off + count * itemsize]
         return b.view(dtype)
 
+    def overflow_word(self, q: int = 0) -> int:
+        """Device address of query q's pair-overflow word (for Adam's guard)."""
+        g, p = self.grid.c(), self.params.c()
+        w = ctypes.c_void_p()
+        check(lib().gs_overflow_word(ctypes.c_void_p(self.ptr), self.nbytes, self.n, self.nq, ctypes.byref(g),
+                                     ctypes.byref(p), q, ctypes.byref(w)), "gs_overflow_word")
+        return w.value
+
     def flags(self, stream=None):
         out = (GsFlags * self.nq)()
         g, p = self.grid.c(), self.params.c()

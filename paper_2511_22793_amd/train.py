@@ -84,6 +84,9 @@ class LearnedScene:
         self.mgrads = None
         self.moments = {}
         self.step_count = 0
+        # steps whose pair buffer overflowed: their spectra and gradients are
+        # undefined, so Adam skips them (guarded on the device) and counts them
+        self.skipped = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def _rows(self, tx):
         return gm.Rows(tx, self.live_list[0], self.live_count, row_cap=self.n)
@@ -173,9 +176,15 @@ class LearnedScene:
                           ("opacity_logit", r.opacity)):
                 m, v = self._moment(k, sc[k])
                 segs.append((sc[k], self.ggrads["d_" + k], m, v, None, lr))
-        gm.adam_step(segs, self.step_count)
+        gm.adam_step(segs, self.step_count, skip_if=self.ws.overflow_word(0), skip_count=self.skipped)
         mark("adam")
         return loss
+
+    def skipped_steps(self) -> int:
+        """Steps left out because the render's pair buffer overflowed
+        (synchronises).  A caller that sees a non-zero count raises the
+        pair capacity (Params.pair_capacity) and rebuilds the scene."""
+        return int(self.skipped.item())
 
 
 class FixedAttributeScene:
@@ -195,6 +204,7 @@ class FixedAttributeScene:
         self.ws = Workspace(n, 1, grid, params, device=dev)
         self.spec = torch.empty(batch, F, grid.H, grid.W, 2, device=dev)
         self.step_count = 0
+        self.skipped = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def render(self, tx=None) -> torch.Tensor:
         prepare(self.g, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
@@ -207,20 +217,6 @@ class FixedAttributeScene:
         # shared attributes: the backward sums the attribute gradient over sets
         g = backward(self.ws, self.g, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B)
         self.step_count += 1
-        gm.adam_step([(self.attr, g["d_attr"], self.m, self.v, None, self.lr)], self.step_count)
+        gm.adam_step([(self.attr, g["d_attr"], self.m, self.v, None, self.lr)], self.step_count,
+                     skip_if=self.ws.overflow_word(0), skip_count=self.skipped)
         return loss
-
-
-def ground_truth_attributes(scene: dict, rho: np.ndarray, tx: np.ndarray, r_near: float = 0.2,
-                            f_c: float = 2.4e9, df: float = 312.5e3, nf: int = F) -> np.ndarray:
-    """Synthetic transmitter-dependent emissions: Gaussian reflectivity rho_i
-    times the baseband delay phase and free-space loss of the transmitter leg,
-    c_i[k] = rho_i exp(-j 2 pi (f_k - f_c) d_i / c0) / max(d_i, r_near),
-    f_k = f_c + (k - (nf-1)/2) df.  Returns [S, n, nf, 2] float32."""
-    c0 = 299_792_458.0
-    m = np.asarray(scene["mean"], np.float64).T
-    d = np.linalg.norm(m[None] - np.asarray(tx, np.float64)[:, None], axis=-1)      # [S, n]
-    fk = (np.arange(nf) - (nf - 1) / 2.0) * df
-    ph = -2.0 * np.pi * fk[None, None, :] * d[..., None] / c0
-    a = np.asarray(rho, np.float64)[None, :, None] / np.maximum(d, r_near)[..., None]
-    return np.stack([a * np.cos(ph), a * np.sin(ph)], -1).astype(np.float32)

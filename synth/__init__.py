@@ -158,3 +158,20 @@ def serving_arrays(mix: list, n_scale: float = 1.0) -> list:
         out.append((scene(n, seed=m["scene_seed"]), channel_attrs(n, m["F"], m["complex"], seed=m["attr_seed"]),
                     points(m["n_queries"], seed=m["query_seed"]), m["complex"], m["H"], m["W"]))
     return out
+
+
+def ground_truth_attributes(scene: dict, rho: np.ndarray, tx: np.ndarray, r_near: float = 0.2,
+                            f_c: float = 2.4e9, df: float = 312.5e3, nf: int = 64) -> np.ndarray:
+    """Target emissions for the learned-attribute workloads (a stand-in for
+    measured channels): Gaussian reflectivity rho_i times the baseband delay
+    phase and free-space loss of the transmitter leg (the multipath model
+    reduced to one bounce per Gaussian),
+    c_i[k] = rho_i exp(-j 2 pi (f_k - f_c) d_i / c0) / max(d_i, r_near),
+    f_k = f_c + (k - (nf-1)/2) df.  Returns [S, n, nf, 2] float32."""
+    c0 = 299_792_458.0
+    m = np.asarray(scene["mean"], np.float64).T
+    d = np.linalg.norm(m[None] - np.asarray(tx, np.float64)[:, None], axis=-1)      # [S, n]
+    fk = (np.arange(nf) - (nf - 1) / 2.0) * df
+    ph = -2.0 * np.pi * fk[None, None, :] * d[..., None] / c0
+    a = np.asarray(rho, np.float64)[None, :, None] / np.maximum(d, r_near)[..., None]
+    return np.stack([a * np.cos(ph), a * np.sin(ph)], -1).astype(np.float32)

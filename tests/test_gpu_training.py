@@ -24,7 +24,7 @@ def ground_truth(n, n_tx, seed=synth.SEED_GT_SCENE, grid=gs.Grid(45, 180, 16, 16
     sc = synth.scene(n, seed=seed)
     rho = synth.uniform(n, 0.0, 1.0, seed=seed + 10)
     tx = synth.points(n_tx, seed=seed + 20)
-    attr = train.ground_truth_attributes(sc, rho, tx)
+    attr = synth.ground_truth_attributes(sc, rho, tx)
     dev = {k: torch.from_numpy(v).cuda() for k, v in sc.items()}
     rx = torch.zeros(n_tx, 3).cuda()
     # the plain renderer, one query per transmitter
@@ -97,3 +97,31 @@ def test_loss_modes_take_the_same_step(mode):
         assert torch.allclose(a, b, rtol=1e-4, atol=1e-6), k
     for k in models[0].net.w:
         assert torch.allclose(models[0].net.w[k], models[1].net.w[k], rtol=1e-4, atol=1e-6), k
+
+
+def test_step_with_overflowed_pair_buffer_changes_no_parameter():
+    # a pair capacity far below what the scene needs: the render is
+    # undefined, so the guarded Adam step must leave every parameter and
+    # moment as it was and count the step as skipped
+    grid = gs.Grid(45, 180, 16, 16)
+    n, B = 800, 4
+    sc, tx, target = ground_truth(n, B, grid=grid)
+    txt = torch.from_numpy(tx).cuda()
+    small = train.LearnedScene(sc, synth.embeddings(n), mlp_ref.init(0), [0, 0, 0], B, LO, HI, grid=grid,
+                               params=gs.Params(pair_capacity=500))
+    before = [t.clone() for t in list(small.g.values()) + list(small.net.w.values()) + [small.E]]
+    small.train_step(txt, target)
+    torch.cuda.synchronize()
+    assert small.ws.flags()[0]["overflow"] == 1
+    assert small.skipped_steps() == 1
+    after = list(small.g.values()) + list(small.net.w.values()) + [small.E]
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
+    for m, v in small.moments.values():
+        assert float(m.abs().max()) == 0.0 and float(v.abs().max()) == 0.0
+    # the same step with room for every pair updates the parameters
+    full = train.LearnedScene(sc, synth.embeddings(n), mlp_ref.init(0), [0, 0, 0], B, LO, HI, grid=grid)
+    full.train_step(txt, target)
+    torch.cuda.synchronize()
+    assert full.skipped_steps() == 0 and full.ws.flags()[0]["overflow"] == 0
+    assert not torch.equal(full.net.w["W3"], small.net.w["W3"])
