@@ -1,0 +1,138 @@
+"""One whole training step against the oracle chain.
+
+The step (train.LearnedScene.train_step) runs on the GPU: projection, depth
+sort and binning, the live pass, the attribute network forward (BF16 matrix
+cores), compositing of the batch's attribute sets, the loss (Eq. (2) mean,
+Eq. (4) channel term and the pixel term), the compositing and projection
+backward, the network backward and the fused Adam update.  Each stage is
+then checked against the oracle on the GPU's own inputs of that stage
+(re-anchored), so a mistake anywhere in the wiring fails here even when every
+kernel passes on its own:
+
+  live list       the oracle's live set (Gaussians some pixel takes)
+  attributes      the FP64 network on the BF16-rounded weights (flip bound);
+                  rows outside the live list must stay zero
+  spectra         the oracle's render with the GPU's attributes on the live
+                  rows and the oracle network's on all others (a dropped
+                  contributor would show here)
+  loss            the loss oracle on the GPU's spectra
+  gradients       the FP64 autograd renderer with the loss oracle's gradient
+                  (scene gradients), then the FP64 network backward (weight
+                  and embedding gradients, flip bound)
+  update          textbook Adam with the step's own gradients and the
+                  learning rates of the hyper-parameter table, and the BF16
+                  copies of the updated weights
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import check_parity, oracle_params
+from oracle import loss_ref, mlp_ref, torch_ref
+from paper_2511_22793_amd import mlp as gm
+from paper_2511_22793_amd import train
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = [-5.0, -5.0, 0.0], [5.0, 5.0, 3.0]
+NAMES = ("mean", "log_scale", "quat", "opacity_logit")
+
+
+def _close(got, ref, label, abs_frac=2e-4, rel=2e-3):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = float(np.abs(ref).max())
+    assert scale > 0, label
+    err = np.abs(got - ref)
+    assert err.max() <= abs_frac * scale, "%s: max err %.3g vs scale %.3g" % (label, err.max(), scale)
+    big = np.abs(ref) >= 1e-2 * scale
+    r = (err[big] / np.abs(ref[big])).max()
+    assert r <= rel, "%s: max relative err %.3g on significant entries" % (label, r)
+
+
+def test_whole_training_step_matches_oracle_chain():
+    n, B, F, H, W = 160, 8, 64, 90, 360
+    sc = synth.scene(n, seed=111, lo=[-2.5, -2.5, 0.1], hi=[2.5, 2.5, 2.0], log_scale_mean=-1.2)
+    E = synth.embeddings(n, seed=112)
+    w = mlp_ref.init(113)
+    rng = np.random.default_rng(114)
+    w["b1"], w["b2"], w["b3"] = rng.normal(0, 0.1, 64), rng.normal(0, 0.1, 64), rng.normal(0, 0.3, 128)
+    tx = synth.points(B, seed=115)
+    target = synth.normal((B, F, H, W, 2), 0.05, seed=116)
+    total = 10
+    model = train.LearnedScene(sc, E, w, [0, 0, 0], B, LO, HI, total_steps=total)
+    loss = model.train_step(torch.from_numpy(tx).cuda(), torch.from_numpy(target).cuda())
+    torch.cuda.synchronize()
+    assert model.ws.flags()[0]["overflow"] == 0
+
+    # live list
+    proj = oracle.project(sc, [0, 0, 0], H, W)
+    order = oracle.depth_order(proj)
+    live = oracle.composite(proj, order, synth.rss_attrs(n), H, W)["live"]
+    cnt = int(model.live_count[0])
+    listed = np.sort(model.live_list[0, :cnt].cpu().numpy())
+    g = np.zeros(n, bool)
+    g[listed] = True
+    assert not ((live & 1 > 0) & ~g).any() and not (g & (live == 0)).any()
+
+    # attributes: the FP64 network on the BF16-rounded operands (flip bound)
+    full = mlp_ref.forward(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], E, tx, sc["mean"], 0.2, LO, HI)
+    A = model.attr.cpu().numpy().astype(np.float64)
+    e2 = np.abs(A[:, listed] - full["attr"][:, listed]) / np.maximum(full["amp"][:, listed][..., None], 1e-6)
+    assert e2.max() <= 5e-2 and np.mean(e2 > 1e-4) <= 0.05
+    rest = np.ones(n, bool)
+    rest[listed] = False
+    assert np.all(A[:, rest] == 0)
+    used = full["attr"].copy()
+    used[:, listed] = A[:, listed]
+
+    # spectra
+    spec = model.spec.cpu().numpy().astype(np.float64)
+    for s in range(B):
+        ref = oracle.composite(proj, order, used[s].astype(np.float32), H, W)
+        check_parity(spec[s, ..., 0] + 1j * spec[s, ..., 1], ref, "set %d" % s)
+
+    # loss on the GPU's spectra
+    L_ref, _, G = loss_ref.l2_channel_loss(spec, target, True, 1.0)
+    assert np.allclose(loss.cpu().numpy(), L_ref, rtol=1e-4)
+
+    # scene gradients: autograd through the FP64 renderer, sets stacked on
+    # the channel axis (their scene gradients add up)
+    cat = np.ascontiguousarray(used.astype(np.float32).transpose(1, 0, 2, 3).reshape(n, B * F, 2))
+    t, at = torch_ref.to_tensors(sc, cat, requires_grad=True)
+    out = torch_ref.render(t["mean"], t["log_scale"], t["quat"], t["opacity_logit"], at, [0, 0, 0], H, W,
+                           prm=oracle_params(model.params))["out"]
+    Gcat = torch.as_tensor(G.transpose(0, 1, 2, 3, 4).reshape(B * F, H, W, 2))
+    (out * Gcat).sum().backward()
+    for k in NAMES:
+        _close(model.ggrads["d_" + k].cpu().numpy(), t[k].grad.numpy(), k)
+    d_attr = at.grad.numpy().reshape(n, B, F, 2).transpose(1, 0, 2, 3)
+
+    # network gradients: the FP64 network backward (flip bound)
+    dmask = np.zeros_like(d_attr)
+    dmask[:, listed] = d_attr[:, listed]
+    gref = mlp_ref.backward(full, dmask)
+    for k in ("W1", "W2", "W3", "b3", "E"):
+        want = gref[k]
+        got = model.mgrads[k].cpu().numpy()
+        assert np.abs(got - want).max() <= 2e-2 * np.abs(want).max(), k
+
+    # the update: Adam (first step) with the step's own gradients
+    r = train.Rates()
+    tt = 1.0 / (total - 1)
+    lr_pos = math.exp((1 - tt) * math.log(r.position) + tt * math.log(r.position_final))
+    checks = [(model.net.w[k], w[k], model.mgrads[k], r.mlp) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    checks.append((model.E, E, model.mgrads["E"], r.embedding))
+    for k, lr in (("mean", lr_pos), ("log_scale", r.scaling), ("quat", r.rotation), ("opacity_logit", r.opacity)):
+        checks.append((model.g[k], sc[k], model.ggrads["d_" + k], lr))
+    for p_new, p0, gr, lr in checks:
+        g64 = gr.cpu().numpy().astype(np.float64)
+        want, _, _ = mlp_ref.adam(np.asarray(p0, np.float32).astype(np.float64), g64, 0.0, 0.0, 1, lr)
+        assert np.allclose(p_new.cpu().numpy(), want, rtol=1e-6, atol=1e-7 * lr)
+    for k in ("W1", "W2", "W3"):
+        assert np.array_equal(model.net.bf[k].cpu().numpy().view(np.uint16),
+                              gm.bf16_bits(model.net.w[k].cpu().numpy()))
