@@ -94,6 +94,8 @@ def test_forward_layers_reanchored_and_end_to_end(shared):
     d = setup(shared=shared)
     n, S = d["n"], d["S"]
     st = gm.State(S, n // 2)
+    for t in (st.h1, st.h2):  # rows past a set's count are never written: keep them defined
+        t.zero_()
     Z1 = gm.embed(d["net"], d["E_bf"])
     attr = torch.zeros(S, n, 64, 2, device="cuda")
     gm.forward(d["net"], Z1, d["mean"], d["rows"], attr, st)
@@ -133,6 +135,8 @@ def test_backward_reanchored():
     d = setup(n=256, S=3, seed=5)
     n, S = d["n"], d["S"]
     st = gm.State(S, n // 2, n_partial=8)
+    for t in (st.h1, st.h2, st.do, st.dz2, st.dz1):
+        t.zero_()
     Z1 = gm.embed(d["net"], d["E_bf"])
     attr = torch.zeros(S, n, 64, 2, device="cuda")
     gm.forward(d["net"], Z1, d["mean"], d["rows"], attr, st)
