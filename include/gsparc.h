@@ -273,6 +273,24 @@ gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n
                            float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes, void* stream);
 
 /*
+ * gs_loss_spectrum() for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no scratch argument.  The per-channel accumulators live in a
+ * device array inside the library, GS_LOSS_NOALLOC_MAX_FLOATS floats on each
+ * device the library runs on, held until the process ends.  The caller
+ * still passes inputs and outputs (as for gs_loss_spectrum()).
+ * Errors: those of gs_loss_spectrum(), and GS_ERR_CAPACITY (nothing
+ * enqueued) when n_sets * n_chan * c * 3 > GS_LOSS_NOALLOC_MAX_FLOATS;
+ * GS_ERR_HIP if the array's device address cannot be found.  Calls share
+ * the device's array and leave their sums in it: calls that overlap on one
+ * device (different streams) race.  Each call clears what it accumulates.
+ */
+#define GS_LOSS_NOALLOC_MAX_FLOATS 65536
+gs_status gs_loss_spectrum_noalloc(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                                   int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
+                                   float* h_hat, float* d_spectrum, void* stream);
+
+/*
  * The loss of gs_loss_spectrum() in one pass over the spectra, for
  * gs_render_backward_l2(): writes loss [n_sets], h_hat [n_sets][F][c],
  * mean_grad [n_sets][F*c] = lambda_ch 2 (h^ - h) / (H W) / n_sets (the

@@ -128,6 +128,7 @@ SIGNATURES = {
                                c_i64, c_p, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
                                  c_p]),
+    "gs_loss_spectrum_noalloc": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p]),
     "gs_mlp_embed": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_i32, c_p, c_p]),
     "gs_mlp_forward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
                                ctypes.POINTER(GsMlpState), c_p]),

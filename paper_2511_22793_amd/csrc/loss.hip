@@ -9,6 +9,8 @@
 // Two passes: a reduction per (set, channel component) into FP32
 // accumulators (workgroup partial sums, then atomics), then the elementwise
 // gradient.  Both passes stream the spectra once.
+#include <mutex>
+
 #include "common.h"
 
 namespace gs {
@@ -221,20 +223,14 @@ extern "C" gs_status gs_loss_spectrum_stats(const float* spectrum, const float* 
     return GS_OK;
 }
 
-extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
-                                      int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
-                                      float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes,
-                                      void* stream)
+// The two passes of gs_loss_spectrum() with a checked scratch of at least
+// n_sets * F*c * 3 floats.
+static gs_status loss_spectrum_run(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                                   int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
+                                   float* h_hat, float* d_spectrum, float* scratch, hipStream_t s)
 {
-    if (!spectrum || !target || !loss || !h_hat || !d_spectrum || n_sets < 1 || n_chan < 1 || H < 1 || W < 1 ||
-        (is_complex != 0 && is_complex != 1) || !(lambda_ch >= 0.0f))
-        return GS_ERR_INVALID_ARG;
-    if (n_chan > 65535 || n_sets > 65535) return GS_ERR_CAPACITY;
     const int C = is_complex ? 2 : 1;
     const int Fc = n_chan * C;
-    const size_t need = (size_t)n_sets * Fc * 3 * sizeof(float);
-    if (!scratch || scratch_bytes < need || ((uintptr_t)scratch & 255)) return GS_ERR_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();
     const size_t HW = (size_t)H * W;
     launch_fill_u32((uint32_t*)scratch, (size_t)n_sets * Fc * 3, 0, 1, 0u, s);
@@ -244,16 +240,84 @@ extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target
     const unsigned gx = (unsigned)((per + 255) / 256 < 32 ? (per + 255) / 256 : 32);
     dim3 grid(gx, n_chan, n_sets);
     if (vec) {
-        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch,
+        hipLaunchKernelGGL(k_loss_reduce<true>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, scratch,
                            nullptr, 0.0f);
         hipLaunchKernelGGL(k_loss_grad<true>, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW, lambda_ch,
                            (const float*)scratch, d_spectrum, h_hat, loss);
     } else {
-        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, (float*)scratch,
+        hipLaunchKernelGGL(k_loss_reduce<false>, grid, dim3(256), 0, s, spectrum, target, Fc, C, HW, scratch,
                            nullptr, 0.0f);
         hipLaunchKernelGGL(k_loss_grad<false>, grid, dim3(256), 0, s, spectrum, target, n_sets, Fc, C, HW,
                            lambda_ch, (const float*)scratch, d_spectrum, h_hat, loss);
     }
     if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
     return GS_OK;
+}
+
+static bool loss_args_ok(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                         int32_t is_complex, int32_t H, int32_t W, float lambda_ch, const float* loss,
+                         const float* h_hat, const float* d_spectrum)
+{
+    return spectrum && target && loss && h_hat && d_spectrum && n_sets >= 1 && n_chan >= 1 && H >= 1 && W >= 1 &&
+           (is_complex == 0 || is_complex == 1) && lambda_ch >= 0.0f;
+}
+
+extern "C" gs_status gs_loss_spectrum(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan,
+                                      int32_t is_complex, int32_t H, int32_t W, float lambda_ch, float* loss,
+                                      float* h_hat, float* d_spectrum, void* scratch, size_t scratch_bytes,
+                                      void* stream)
+{
+    if (!loss_args_ok(spectrum, target, n_sets, n_chan, is_complex, H, W, lambda_ch, loss, h_hat, d_spectrum))
+        return GS_ERR_INVALID_ARG;
+    if (n_chan > 65535 || n_sets > 65535) return GS_ERR_CAPACITY;
+    const size_t need = (size_t)n_sets * n_chan * (is_complex ? 2 : 1) * 3 * sizeof(float);
+    if (!scratch || scratch_bytes < need || ((uintptr_t)scratch & 255)) return GS_ERR_WORKSPACE;
+    return loss_spectrum_run(spectrum, target, n_sets, n_chan, is_complex, H, W, lambda_ch, loss, h_hat, d_spectrum,
+                             (float*)scratch, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// gs_loss_spectrum_noalloc: the same loss with its per-channel accumulators
+// in a file-scope device array instead of caller scratch.  Each device the
+// library runs on holds its own copy of the array (until the process ends);
+// its device address is looked up once per device, with that device
+// current, on the entry point's first call there.  In host code the array's
+// name is only a host-side stand-in: every kernel argument and fill uses the
+// looked-up address.  Calls on one device share the array, so calls that
+// overlap on one device (different streams) race; each call clears the
+// accumulators it uses before accumulating.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[GS_LOSS_NOALLOC_MAX_FLOATS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+float* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+extern "C" gs_status gs_loss_spectrum_noalloc(const float* spectrum, const float* target, int32_t n_sets,
+                                              int32_t n_chan, int32_t is_complex, int32_t H, int32_t W,
+                                              float lambda_ch, float* loss, float* h_hat, float* d_spectrum,
+                                              void* stream)
+{
+    if (!loss_args_ok(spectrum, target, n_sets, n_chan, is_complex, H, W, lambda_ch, loss, h_hat, d_spectrum))
+        return GS_ERR_INVALID_ARG;
+    if (n_chan > 65535 || n_sets > 65535) return GS_ERR_CAPACITY;
+    const size_t need = (size_t)n_sets * n_chan * (is_complex ? 2 : 1) * 3;
+    if (need > (size_t)GS_LOSS_NOALLOC_MAX_FLOATS) return GS_ERR_CAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return GS_ERR_CAPACITY;
+    float* acc = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GS_ERR_HIP;
+            g_noalloc_ptr[dev] = (float*)ptr;
+        }
+        acc = g_noalloc_ptr[dev];
+    }
+    return loss_spectrum_run(spectrum, target, n_sets, n_chan, is_complex, H, W, lambda_ch, loss, h_hat, d_spectrum,
+                             acc, (hipStream_t)stream);
 }
