@@ -32,6 +32,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import synth  # noqa: E402  (seeded synthetic inputs)
+
 # FP32 vector peak without packed-FP32 instructions (the HIP sources are
 # compiled with them disabled): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_VALU_F32_TFLOPS = 78.6
@@ -69,8 +71,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mix", action="store_true")
-    ap.add_argument("--loss-mode", default="partial", choices=("partial", "fused", "target", "two_pass"),
-                    help="a one-pass loss writing the elementwise gradient (partial), the same folded into the "
+    ap.add_argument("--loss-mode", default="train_pass",
+                    choices=("train_pass", "partial", "fused", "target", "two_pass"),
+                    help="compositing, loss and backward in one fused pass (train_pass), or as separate passes: "
+                         "a one-pass loss writing the elementwise gradient (partial), the same folded into the "
                          "compositing kernel (fused), a loss pass without the gradient, formed in the backward "
                          "from the target (target), or loss + stored gradient (two_pass)")
     ap.add_argument("--mix-only", action="store_true", help="run only the uneven serving mix (for profiling)")
@@ -78,6 +82,8 @@ def parse():
                     help="short run for hardware-counter passes: 2 training steps, then a 256 MiB copy that "
                          "calibrates the byte counters")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON) for the serving mix")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (plain 2k render, 50k fwd+bwd, 300k training step, N sweep)")
     return ap.parse_args()
 
 
@@ -89,7 +95,6 @@ def main():
     import torch
 
     import paper_2511_22793_amd as gs
-    import synth
     from paper_2511_22793_amd import train
 
     dev = torch.device("cuda:0")
@@ -114,16 +119,22 @@ def main():
         out, _ = gs.forward(gt_dev, a, rx1, grid=grid, is_complex=True)
         targets[b] = out[0]
     tx = torch.from_numpy(tx_all[:B]).to(dev)
+    # each training sample's channel (Eq. (2) of its target spectrum), formed
+    # once with the samples
+    target_means = gs.spatial_mean(targets, True)
 
     if args.pmc_run:
         args.warmup, args.steps = 1, 2
     # ---------------------------------------------------------------- training
     model = train.LearnedScene(scene, emb, train.init_weights(0), [0, 0, 0], B, box_lo, box_hi, grid=grid,
-                               total_steps=args.warmup + args.steps, loss_mode=args.loss_mode)
+                               total_steps=1000, loss_mode=args.loss_mode)
     for _ in range(args.warmup):
-        model.train_step(tx, targets)
+        model.train_step(tx, targets, target_mean=target_means)
     torch.cuda.synchronize()
-    names = ["start", "prepare", "live", "mlp_fwd", "blend", "loss", "render_bwd", "mlp_bwd", "adam"]
+    if args.loss_mode == "train_pass":
+        names = ["start", "prepare", "live", "mlp_fwd", "train_pass", "mlp_bwd", "adam"]
+    else:
+        names = ["start", "prepare", "live", "mlp_fwd", "blend", "loss", "render_bwd", "mlp_bwd", "adam"]
     evs = [{k: torch.cuda.Event(enable_timing=True) for k in names} for _ in range(args.steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -133,16 +144,17 @@ def main():
     t0.record()
     for k in range(args.steps):
         e = evs[k]
-        model.train_step(tx, targets, marks=lambda name, e=e: e[name].record())
+        model.train_step(tx, targets, marks=lambda name, e=e: e[name].record(), target_mean=target_means)
     t1.record()
     torch.cuda.synchronize()
     L.gs_timing_enable(0)
     kernel_ms = {}
-    for name, tid in (("blend", 0), ("blend_bwd", 1)):
+    timers = (("train", 2),) if args.loss_mode == "train_pass" else (("blend", 0), ("blend_bwd", 1))
+    for name, tid in timers:
         tot, cnt = ctypes.c_double(), ctypes.c_int64()
         assert L.gs_timing_read(tid, ctypes.byref(tot), ctypes.byref(cnt)) == 0 and cnt.value == args.steps
         kernel_ms[name] = tot.value / cnt.value
-    ms_step = t0.elapsed_time(t1) / args.steps
+    ms_step_eager = t0.elapsed_time(t1) / args.steps
     stages = {}
     for a, b in zip(names[:-1], names[1:]):
         stages[b] = float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))
@@ -160,6 +172,21 @@ def main():
     n_contrib = model.ws.view("n_contrib", 0, HW, torch.int32).double().sum().item()
     n_eval = model.ws.view("n_last", 0, HW, torch.int32).double().sum().item()
     flags = model.ws.flags()[0]
+    # the step captured once as a HIP graph: K replays timed as a block (the
+    # headline), then REPLAYS replays timed one by one (median, p99); every
+    # replay is a whole training step (parameters move each time)
+    step_graph = capture(lambda: model.train_step(tx, targets, target_mean=target_means))
+    for _ in range(args.warmup):
+        step_graph.replay()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        step_graph.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    step_each = replay_times(step_graph, REPLAYS)
+    assert model.skipped_steps() == 0, "a step overflowed its pair buffer"
 
     # ---------------------------------------------------------------- serving
     serve = train.LearnedScene(scene, emb, train.init_weights(0), [0, 0, 0], SB, box_lo, box_hi, grid=grid)
@@ -174,7 +201,10 @@ def main():
         serve.render(stx)
     s1.record()
     torch.cuda.synchronize()
-    ms_serve = s0.elapsed_time(s1) / args.steps
+    ms_serve_eager = s0.elapsed_time(s1) / args.steps
+    serve_graph = capture(lambda: serve.render(stx))
+    serve_each = replay_times(serve_graph, REPLAYS)
+    ms_serve = float(np.median(serve_each))
 
     res = {
         "metric": "hemispherical spectra/s + fwd+bwd steps/s, 100k Gaussians 360x90, vs plain",
@@ -196,9 +226,19 @@ def main():
                    "queries_per_step": B, "network": "32-d embedding + 51-d transmitter encoding -> 64 -> 64 -> 128, "
                                                      "bf16 weights, fp32 accumulation"},
         "fwd_bwd_steps_per_s": round(1e3 / ms_step, 3),
+        "timing": {"headline": "the step captured as a HIP graph, %d replays timed as one block" % args.steps,
+                   "graph_replays": REPLAYS, "step_median_ms": round(float(np.median(step_each)), 4),
+                   "step_p99_ms": round(float(np.percentile(step_each, 99)), 4),
+                   "steps_per_s_at_median": round(1e3 / float(np.median(step_each)), 3),
+                   "eager_ms_per_step": round(ms_step_eager, 4),
+                   "target_channels": "Eq. (2) of each target, formed once with the training samples"},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "stages_note": "eager steps with events between stages (the graph has no stage marks)",
         "serving": {"spectra_per_s": round(SB / (ms_serve / 1e3), 2), "queries_per_launch_sequence": SB,
-                    "ms_per_batch": round(ms_serve, 4), "includes": "network + prepare + live pass + blend"},
+                    "ms_per_batch_median": round(ms_serve, 4),
+                    "ms_per_batch_p99": round(float(np.percentile(serve_each, 99)), 4), "graph_replays": REPLAYS,
+                    "eager_ms_per_batch": round(ms_serve_eager, 4),
+                    "includes": "network + prepare + live pass + blend, captured as a HIP graph"},
         "stats": {"n_visible": flags["n_visible"], "n_pairs": flags["n_pairs"], "live_gaussians": live_count,
                   "mean_contrib_per_pixel": round(n_contrib / HW, 2), "entries_evaluated_per_pixel":
                   round(n_eval / HW, 2)},
@@ -208,10 +248,18 @@ def main():
     Fc = 2 * F
     blend_flops = B * n_contrib * 2.0 * Fc + n_eval * FLOPS_PER_EVAL + n_contrib * FLOPS_PER_CONTRIB
     bwd_flops = B * n_contrib * 4.0 * Fc + n_eval * FLOPS_PER_EVAL + n_contrib * FLOPS_BWD_CONTRIB
-    fwd_name = "k_blend<32, true>" if args.loss_mode == "fused" else "k_blend_sg<1>"
-    bwd_name = "k_blend_bwd_sg<1, %s>" % ("true" if args.loss_mode == "target" else "false")
-    kt = {fwd_name: (kernel_ms["blend"], blend_flops, "mfma", PEAK_MFMA_F32_TFLOPS),
-          bwd_name: (kernel_ms["blend_bwd"], bwd_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
+    if args.loss_mode == "train_pass":
+        # the fused pass: the forward product, GV and dL/dv (three products
+        # of 2 Fc flops per set and accepted pair), the walk twice (alpha and
+        # weights, then the backward recurrence and geometric terms)
+        train_flops = B * n_contrib * 6.0 * Fc + n_eval * FLOPS_PER_EVAL + n_contrib * (FLOPS_PER_CONTRIB +
+                                                                                         FLOPS_BWD_CONTRIB)
+        kt = {"k_train_fb + k_train_walk": (kernel_ms["train"], train_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
+    else:
+        fwd_name = "k_blend<32, true>" if args.loss_mode == "fused" else "k_blend_sg<1>"
+        bwd_name = "k_blend_bwd_sg<1, %s>" % ("true" if args.loss_mode == "target" else "false")
+        kt = {fwd_name: (kernel_ms["blend"], blend_flops, "mfma", PEAK_MFMA_F32_TFLOPS),
+              bwd_name: (kernel_ms["blend_bwd"], bwd_flops, "mfma", PEAK_MFMA_F32_TFLOPS)}
     kname = max(kt, key=lambda k: kt[k][0])
     ms, fl, bound, peak = kt[kname]
     ach = fl / (ms / 1e3) / 1e12
@@ -229,12 +277,50 @@ def main():
     if not args.no_mix:
         res["serving_mix"] = serving_mix(args, gs, dev)
     if not args.no_plain:
-        res["plain"] = plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, box_lo, box_hi, dev)
+        res["plain"] = plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, target_means, box_lo,
+                             box_hi, dev)
         res["plain"]["speedup_training"] = round(res["value"] / res["plain"]["training_spectra_per_s"], 3)
         res["plain"]["speedup_serving"] = round(res["serving"]["spectra_per_s"] / res["plain"]["serving_spectra_per_s"], 3)
+    if not args.no_configs:
+        res["configs"] = other_configs(args, gs, train, dev)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(gt, rho, tx_all, H, W, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+REPLAYS = 100
+
+
+def capture(fn, warm=2):
+    """fn captured into a HIP graph (torch.cuda.CUDAGraph) after `warm`
+    eager calls on the capture stream."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(warm):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def replay_times(g, reps):
+    """Per-replay times (ms) of `reps` back-to-back replays, HIP events
+    around each replay on the replay stream."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        g.replay()
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "compositing_traffic_100k_90x360_f64c_b16.md")
@@ -273,6 +359,110 @@ def measured_traffic(kernel):
 # confidence head + Eq. (6) per sample: layer 1 (3x32 FMA), layer 2 (32 FMA),
 # the backward through both (32 + 3x32 + 32 + 32 FMA/adds): ~600 flops
 CONF_FLOPS_PER_SAMPLE = 2 * (3 * 32 + 32) + 32 + 2 * 3 * 32 + 32 + 2 * 32
+
+
+def _timed(g, reps):
+    t = replay_times(g, reps)
+    return {"ms_median": round(float(np.median(t)), 4), "ms_p99": round(float(np.percentile(t, 99)), 4),
+            "replays": reps}
+
+
+def other_configs(args, gs, train, dev):
+    """The other workloads of the metric, each captured as a HIP graph and
+    replayed (median and p99 per replay):
+      plain_2k   2,048 Gaussians, one receiver at the origin, 1 real RSS
+                 channel (1/d^2 to the receiver), 90x360: spectra/s;
+      fwd_bwd_50k  50,000 Gaussians, 16 receivers uniform in the room, 1
+                 real channel: forward, L2 loss to the render of a perturbed
+                 scene, backward (scene and attribute gradients): steps/s;
+      train_300k the whole training step at 300,000 Gaussians, 180x720, 32
+                 complex subcarriers from the attribute network, 64
+                 transmitters: steps/s and spectra/s;
+      n_sweep    the plain single-query forward (1 real channel, 90x360) at
+                 N in {2k, 10k, 30k, 62k, 100k, 200k, 300k}: ms per spectrum."""
+    import torch
+    out = {}
+    reps = REPLAYS
+    grid = gs.Grid(90, 360)
+    rx0 = torch.zeros(1, 3, device=dev)
+
+    def forward_graph(n, seed):
+        sc = {k: torch.from_numpy(v).to(dev) for k, v in synth.scene(n, seed=seed).items()}
+        a = torch.from_numpy(synth.rss_attrs(n)).to(dev)
+        ws = gs.Workspace(n, 1, grid, gs.Params(forward_only=True), device=dev)
+        o = torch.empty(1, 1, 90, 360, device=dev)
+        g = capture(lambda: gs.forward(sc, a, rx0, grid=grid, workspace=ws, out=o))
+        return g, ws
+
+    g, ws = forward_graph(2048, synth.SEED_SCENE)
+    t = _timed(g, reps)
+    out["plain_2k"] = dict(workload="plain forward render, 2048 Gaussians, 1 real channel, 90x360, one receiver",
+                           spectra_per_s=round(1e3 / t["ms_median"], 1), **t)
+    # 50k forward + L2 loss + backward over 16 receivers
+    n, B = 50_000, 16
+    base = synth.scene(n, seed=synth.SEED_SCENE)
+    attr = synth.rss_attrs(n)
+    pert = synth.perturbation(n)
+    tgt_scene = {k: (base[k] + pert[k]).astype(np.float32) if k in pert else base[k] for k in base}
+    tgt_attr = (attr + pert["rng"].normal(0.0, pert["attr_sd"], size=attr.shape)).astype(np.float32)
+    rx = torch.from_numpy(synth.points(B, seed=synth.SEED_QUERIES)).to(dev)
+    scd = {k: torch.from_numpy(v).to(dev) for k, v in base.items()}
+    tsd = {k: torch.from_numpy(v).to(dev) for k, v in tgt_scene.items()}
+    a = torch.from_numpy(attr).to(dev)
+    target, _ = gs.forward(tsd, torch.from_numpy(tgt_attr).to(dev), rx, grid=grid)
+    ws = gs.Workspace(n, B, grid, gs.Params(), device=dev)
+    spec = torch.empty(B, 1, 90, 360, device=dev)
+    gout = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+            "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+    d_attr = torch.empty_like(a)
+    lbuf = {}
+
+    def step50k():
+        gs.forward(scd, a, rx, grid=grid, workspace=ws, out=spec)
+        lbuf["l"] = gs.loss_spectrum(spec, target, False, 0.0)
+        gs.backward(ws, scd, a, rx, spec, lbuf["l"][2], out=gout)
+    g = capture(step50k)
+    t = _timed(g, reps)
+    out["fwd_bwd_50k"] = dict(workload="forward + L2 loss + backward, 50000 Gaussians, 16 receivers, 1 real "
+                                       "channel, 90x360", steps_per_s=round(1e3 / t["ms_median"], 2),
+                              spectra_per_s=round(B * 1e3 / t["ms_median"], 1), **t)
+    del ws, spec, target, gout, d_attr, lbuf
+    # the 300k training step at 180x720, 32 subcarriers, 64 transmitters
+    n, B, F = 300_000, 64, 32
+    grid4 = gs.Grid(180, 720)
+    sc4 = synth.scene(n, seed=synth.SEED_SCENE)
+    gt = synth.scene(n, seed=synth.SEED_GT_SCENE)
+    rho = synth.uniform(n, 0.0, 1.0, seed=synth.SEED_GT_SCENE + 10)
+    tx = synth.points(B, seed=synth.SEED_QUERIES)
+    gtd = {k: torch.from_numpy(v).to(dev) for k, v in gt.items()}
+    targets = torch.empty(B, F, 180, 720, 2, device=dev)
+    wsg = gs.Workspace(n, 1, grid4, gs.Params(forward_only=True), device=dev)
+    for b in range(B):
+        ab = torch.from_numpy(synth.ground_truth_attributes(gt, rho, tx[b:b + 1], nf=F)[0]).to(dev)
+        gs.forward(gtd, ab, rx0, grid=grid4, is_complex=True, workspace=wsg, out=targets[b:b + 1])
+    del wsg, gtd
+    tmeans = gs.spatial_mean(targets, True)
+    model = train.LearnedScene(sc4, synth.embeddings(n), train.init_weights(0, n_chan=F), [0, 0, 0], B,
+                               list(synth.BOX_LO), list(synth.BOX_HI), grid=grid4, total_steps=1000)
+    txd = torch.from_numpy(tx).to(dev)
+    g = capture(lambda: model.train_step(txd, targets, target_mean=tmeans))
+    t = _timed(g, max(20, reps // 4))
+    assert model.skipped_steps() == 0
+    live4 = int(model.live_count.item())
+    out["train_300k"] = dict(workload="whole training step, 300000 Gaussians, 180x720, 32 complex subcarriers "
+                                      "from the attribute network, 64 transmitters, fixed receiver",
+                             steps_per_s=round(1e3 / t["ms_median"], 3),
+                             spectra_per_s=round(B * 1e3 / t["ms_median"], 1), live_gaussians=live4, **t)
+    del model, targets, tmeans
+    torch.cuda.empty_cache()
+    sweep = {}
+    for n in (2_000, 10_000, 30_000, 62_000, 100_000, 200_000, 300_000):
+        g, _ = forward_graph(n, synth.SEED_SCENE)
+        tt = _timed(g, 50)
+        sweep[str(n)] = {"ms_median": tt["ms_median"], "ms_p99": tt["ms_p99"]}
+    out["n_sweep"] = {"workload": "plain single-query forward (projection, sort, binning, blend), 1 real channel, "
+                                  "90x360, receiver at the floor centre", "ms_per_spectrum": sweep}
+    return out
 
 
 def confidence_head(gs, dev):
@@ -415,7 +605,7 @@ def serving_mix(args, gs, dev):
             "speedup_vs_plain": round(ms_plain / ms_batch, 3)}
 
 
-def plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, box_lo, box_hi, dev):
+def plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, target_means, box_lo, box_hi, dev):
     """One query at a time: fixed-attribute forward per query (serving) and a
     one-query training step (training), same shapes."""
     import torch
@@ -436,14 +626,17 @@ def plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, box_lo, b
     e1.record()
     torch.cuda.synchronize()
     serve_ms = e0.elapsed_time(e1) / SB
-    one = train.LearnedScene(scene, emb, train.init_weights(0), [0, 0, 0], 1, box_lo, box_hi, grid=grid)
+    one = train.LearnedScene(scene, emb, train.init_weights(0), [0, 0, 0], 1, box_lo, box_hi, grid=grid,
+                             loss_mode=args.loss_mode)
     tx = torch.from_numpy(tx_all[:B]).to(dev)
+    tgt1 = [targets[b:b + 1].contiguous() for b in range(B)]
+    tm1 = [target_means[b:b + 1].contiguous() for b in range(B)]
     for b in range(2):
-        one.train_step(tx[b:b + 1].contiguous(), targets[b:b + 1].contiguous())
+        one.train_step(tx[b:b + 1].contiguous(), tgt1[b], target_mean=tm1[b])
     torch.cuda.synchronize()
     e0.record()
     for b in range(B):
-        one.train_step(tx[b:b + 1].contiguous(), targets[b:b + 1].contiguous())
+        one.train_step(tx[b:b + 1].contiguous(), tgt1[b], target_mean=tm1[b])
     e1.record()
     torch.cuda.synchronize()
     train_ms = e0.elapsed_time(e1) / B

@@ -57,7 +57,7 @@ typedef enum {
     GS_ERR_WORKSPACE = 2,   /* workspace NULL, misaligned (256 B) or smaller than required */
     GS_ERR_CAPACITY = 3,    /* a size exceeds what the library supports */
     GS_ERR_HIP = 4,         /* a HIP runtime call failed (launch, copy, sync) */
-    GS_ERR_NONFINITE = 5    /* reserved for callers checking gs_flags */
+    GS_ERR_NONFINITE = 5    /* gs_check(): a Gaussian with non-finite or degenerate parameters was dropped */
 } gs_status;
 
 /* N Gaussians, structure of arrays (see file header). */
@@ -304,6 +304,88 @@ gs_status gs_loss_spectrum_stats(const float* spectrum, const float* target, int
                                  size_t scratch_bytes, void* stream);
 
 /*
+ * Magnitude-spectrum loss, Eq. (5), for real spectra zhat, z
+ * [n_sets][F][H][W] (e.g. magnitude spectra):
+ *   L_b = (1 - lambda_1) L1_b + lambda_1 (1 - SSIM_b)
+ * with L1_b the mean |zhat - z| over channels and pixels and SSIM_b the mean
+ * structural similarity (Wang et al.): an 11 x 11 Gaussian window, sigma
+ * 1.5, normalised, applied as a same-size filter with zero padding (no wrap
+ * at the azimuth seam), C1 = 0.01^2, C2 = 0.03^2 (a dynamic range of 1), the
+ * map averaged over channels and pixels.  The paper takes lambda_1 = 0.2.
+ * Writes loss [n_sets], and when not NULL ssim [n_sets], l1 [n_sets] and
+ * d_spectrum = dL/dzhat for L = (1/n_sets) sum_b L_b (layout of zhat; the
+ * L1 term contributes 0 where zhat = z).  scratch: >=
+ * gs_loss_l1_ssim_scratch_bytes() bytes, 256-byte aligned, caller-owned
+ * (one pair of partial sums per 32 x 16 tile and channel, summed in a fixed
+ * order: deterministic).  Errors: GS_ERR_INVALID_ARG (null input, a
+ * non-positive size, lambda_1 outside [0, 1]), GS_ERR_CAPACITY (n_sets * F >
+ * 65535), GS_ERR_WORKSPACE.
+ */
+size_t gs_loss_l1_ssim_scratch_bytes(int32_t n_sets, int32_t n_chan, int32_t H, int32_t W);
+gs_status gs_loss_l1_ssim(const float* spectrum, const float* target, int32_t n_sets, int32_t n_chan, int32_t H,
+                          int32_t W, float lambda_1, float* loss, float* ssim, float* l1, float* d_spectrum,
+                          void* scratch, size_t scratch_bytes, void* stream);
+
+/*
+ * Spectrum-to-channel map, Eq. (2): h[s][f][c] = (1/(H W)) sum_p z[s][f][p][c]
+ * for spectra z [n_sets][F][H][W][c] (c = 2 when complex: real and
+ * imaginary parts separately).  h: [n_sets][F][c] (device, overwritten).
+ * Deterministic (fixed summation order).  Errors: GS_ERR_INVALID_ARG for a
+ * null pointer, a non-positive size or a complex spectrum not 8-byte
+ * aligned; GS_ERR_CAPACITY for n_chan or n_sets above 65535.
+ */
+gs_status gs_spatial_mean(const float* spectrum, int32_t n_sets, int32_t n_chan, int32_t is_complex, int32_t H,
+                          int32_t W, float* h, void* stream);
+
+/*
+ * One fused training pass over S complex attribute sets that share one
+ * prepared receiver (the transmitter batch of the training step): Eq. (3)
+ * compositing, the loss of gs_loss_spectrum() against targets z (pixel term
+ * plus the Eq. (4) channel term on the Eq. (2) means) and its backward,
+ * without materialising the spectra or their gradient.
+ *
+ * Preconditions: the workspace was prepared for queries->count == 1 with
+ * atten_ref == 0 (gs_render_prepare) and then walked by gs_render_live()
+ * (its stop positions, live list and per-Gaussian weight sums are used);
+ * attrs complex with 2 F a multiple of 16; attrs->query_stride 0 (one
+ * shared set) or >= n * 2F.
+ * tt (host struct of device pointers):
+ *   target       z [S][F][H][W][2];
+ *   target_mean  h [S][F][2] = Eq. (2) of the target (gs_spatial_mean), a
+ *                property of each training sample;
+ *   lambda_ch    weight of the channel term;
+ *   loss [S], h_hat [S][F][2]: outputs (per-set loss, Eq. (2) of the
+ *                rendered spectra, formed from the live pass's per-Gaussian
+ *                weight sums: h_hat = (1/HW) sum_g (sum_p w_g(p)) v_g).
+ * spectrum: [S][F][H][W][2], written in full with GS_TRAIN_WRITE_SPECTRUM
+ *   (bit-identical to gs_render_blend()), else used only for the groups of
+ *   64 pixels whose walk exceeds 64 list entries (those take the unfused
+ *   compositing and backward kernels inside this call).
+ * Gradient outputs as for gs_render_backward() for L = (1/S) sum_b L_b
+ * (d_attr cleared first unless GS_BWD_ATTR_GRAD_ZEROED).
+ * scratch: >= gs_train_scratch_bytes(n_sets, F, grid) bytes, 256-byte
+ *   aligned, caller-owned (GV partials, loss partials, the mean term).
+ * Errors: GS_ERR_INVALID_ARG (null pointer, an unsupported shape above,
+ * unknown flag bits), GS_ERR_WORKSPACE, GS_ERR_CAPACITY; nothing is enqueued
+ * on an argument error.  Float atomics make the last bits of the gradients
+ * vary between runs.
+ */
+typedef struct {
+    const float* target;
+    const float* target_mean;
+    float lambda_ch;
+    float* loss;
+    float* h_hat;
+} gs_train_target;
+#define GS_TRAIN_WRITE_SPECTRUM 2 /* flags: also store the spectra */
+size_t gs_train_scratch_bytes(int32_t n_sets, int32_t n_chan, const gs_grid* grid);
+gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries, int32_t n_sets,
+                          const gs_grid* grid, const gs_params* prm, const uint32_t* live_list,
+                          const uint32_t* live_count, const gs_train_target* tt, float* spectrum, float* d_mean,
+                          float* d_log_scale, float* d_quat, float* d_opacity_logit, float* d_attr, int32_t flags,
+                          void* workspace, size_t ws_bytes, void* scratch, size_t scratch_bytes, void* stream);
+
+/*
  * gs_render_blend() with the loss of gs_loss_spectrum_stats() fused into its
  * output stage (Eq. (3) compositing, then Eq. (2) spatial means and Eq. (4)
  * channel loss): as each spectrum element is written the kernel reads the
@@ -331,19 +413,21 @@ gs_status gs_render_blend_loss(const gs_attrs* attrs, int32_t n, int32_t n_queri
  * h2 = relu(W2 h1 + b2), o = W3 h2 + b3, A_f = sigmoid(o_f - ln d),
  * phi_f = o_{64+f}, attr = A e^{j phi}, d = max(|tx_s - mu_g|, r_near);
  * gamma = Fourier features (u, sin 2^k pi u, cos 2^k pi u), k = 0..7, u the
- * transmitter scaled to [-1, 1] by the box.  Shapes fixed: embedding 32,
- * input padded to 96, hidden 64, 64 complex subcarriers.  Weights are BF16
- * ([out][in] row-major), biases FP32; products run on BF16 matrix cores with
- * FP32 accumulation. */
+ * transmitter scaled to [-1, 1] by the box.  Shapes: embedding 32, input
+ * padded to 96, hidden 64, F = n_chan complex subcarriers (32 or 64), so
+ * 2F outputs.  Weights are BF16 ([out][in] row-major), biases FP32;
+ * products run on BF16 matrix cores with FP32 accumulation.  Errors:
+ * GS_ERR_INVALID_ARG also for n_chan not 32 or 64. */
 typedef struct {
     const uint16_t* W1; /* bf16 [64][96] */
     const float* b1;    /* [64] */
     const uint16_t* W2; /* bf16 [64][64] */
     const float* b2;    /* [64] */
-    const uint16_t* W3; /* bf16 [128][64]: rows 0..63 amplitudes, 64..127 phases */
-    const float* b3;    /* [128] */
+    const uint16_t* W3; /* bf16 [2F][64]: rows 0..F-1 amplitudes, F..2F-1 phases */
+    const float* b3;    /* [2F] */
     float box_lo[3], box_hi[3]; /* (host values) encoding box */
     float r_near;               /* distance floor of the log-distance bias, m */
+    int32_t n_chan;             /* F: 32 or 64 */
 } gs_mlp;
 
 /* Rows to evaluate: for set s, the Gaussians list[s*list_stride + i],
@@ -386,8 +470,8 @@ typedef struct {
 /* Z1 = E W1[:, :32]^T: the query-independent part of the first layer.
  * E: bf16 [n][32]; Z1: FP32 [n][64]. */
 gs_status gs_mlp_embed(const gs_mlp* net, const uint16_t* E, int32_t n, float* Z1, void* stream);
-/* Attributes of the listed rows into attr[s * attr_stride + g*128 ...]
- * ([S][n][64][2] for attr_stride = n*128); other rows untouched.  With
+/* Attributes of the listed rows into attr[s * attr_stride + g*2F ...]
+ * ([S][n][F][2] for attr_stride = n*2F); other rows untouched.  With
  * st->save_h1/save_h2 set, keeps the activations for gs_mlp_backward(). */
 gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, int32_t n,
                          const gs_mlp_rows* rows, float* attr, int64_t attr_stride, gs_mlp_state* st,
@@ -399,9 +483,6 @@ gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, 
 gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mean, int32_t n,
                           const gs_mlp_rows* rows, float* d_attr, int64_t attr_stride, int32_t clear_d_attr,
                           gs_mlp_state* st, gs_mlp_grads* grads, void* stream);
-/* One 16x16x32 BF16 matrix-core product C = A B (A [16][32], B [32][16]
- * bf16 row-major, C [16][16] FP32): checks the operand layout. */
-gs_status gs_mfma_probe(const uint16_t* A, const uint16_t* B, float* C, void* stream);
 
 /* ---- fused Adam over parameter segments (Kingma and Ba) ----
  * For each segment: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
@@ -425,6 +506,21 @@ typedef struct {
 } gs_adam_segment;
 gs_status gs_adam_step(const gs_adam_segment* segs /*(host)*/, int32_t n_segs, int32_t step, float beta1,
                        float beta2, float eps, const uint32_t* skip_if, uint32_t* skip_count, void* stream);
+
+/* gs_adam_step() with the step number and learning-rate schedule on the
+ * device, so that a captured graph of a training step replays correctly:
+ * *step_counter (device) holds the number of completed steps t; the update
+ * uses bias corrections for step t + 1 and, for segment k with
+ * lr_final[k] != segs[k].lr (lr_final a host array, or NULL for constant
+ * rates), the rate lr (lr_final / lr)^u with u = min((t + 1) / (total_steps - 1), 1)
+ * (the log-linear decay of the position rate, Table 2); then *step_counter
+ * is incremented (also when skip_if skips the update).  Errors as for
+ * gs_adam_step(), and GS_ERR_INVALID_ARG for a null step_counter,
+ * total_steps < 1 or a scheduled rate that is not positive. */
+gs_status gs_adam_step_scheduled(const gs_adam_segment* segs /*(host)*/, const float* lr_final /*(host)*/,
+                                 int32_t n_segs, int32_t total_steps, uint32_t* step_counter, float beta1,
+                                 float beta2, float eps, const uint32_t* skip_if, uint32_t* skip_count,
+                                 void* stream);
 
 /* Device address of query q's overflow word in a workspace laid out for
  * (n, n_queries, grid, prm): for gs_adam_step's skip_if.  Host-side only. */
@@ -539,6 +635,7 @@ gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, siz
  */
 #define GS_TIMER_BLEND 0
 #define GS_TIMER_BLEND_BWD 1
+#define GS_TIMER_TRAIN 2 /* the fused kernels of gs_render_train() (both, as one interval) */
 gs_status gs_timing_enable(int32_t on);
 gs_status gs_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
 
@@ -551,6 +648,17 @@ gs_status gs_wall_clock_khz(int32_t* khz);
  */
 gs_status gs_read_flags(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries,
                         const gs_grid* grid, const gs_params* prm, gs_flags* out, void* stream);
+
+/*
+ * Synchronises `stream` and reports the device-side conditions of the last
+ * prepare/forward on the workspace: GS_ERR_CAPACITY if any query's pair
+ * buffer overflowed (its outputs are undefined; raise pair_capacity), else
+ * GS_ERR_NONFINITE if any Gaussian was dropped for non-finite or degenerate
+ * parameters (the rest rendered normally), else GS_OK.  Argument errors as
+ * for gs_read_flags().
+ */
+gs_status gs_check(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries, const gs_grid* grid,
+                   const gs_params* prm, void* stream);
 
 #ifdef __cplusplus
 }

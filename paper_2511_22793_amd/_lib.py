@@ -53,7 +53,7 @@ class GsFlags(ctypes.Structure):
 
 class GsMlp(ctypes.Structure):
     _fields_ = [("W1", c_p), ("b1", c_p), ("W2", c_p), ("b2", c_p), ("W3", c_p), ("b3", c_p),
-                ("box_lo", c_f32 * 3), ("box_hi", c_f32 * 3), ("r_near", c_f32)]
+                ("box_lo", c_f32 * 3), ("box_hi", c_f32 * 3), ("r_near", c_f32), ("n_chan", c_i32)]
 
 
 class GsMlpRows(ctypes.Structure):
@@ -77,6 +77,15 @@ class GsAdamSegment(ctypes.Structure):
 
 class GsL2Grad(ctypes.Structure):
     _fields_ = [("partial", c_p), ("target", c_p), ("mean_grad", c_p), ("scale", c_f32)]
+
+
+class GsTrainTarget(ctypes.Structure):
+    _fields_ = [("target", c_p), ("target_mean", c_p), ("lambda_ch", c_f32), ("loss", c_p), ("h_hat", c_p)]
+
+
+GS_BWD_ATTR_GRAD_ZEROED = 1
+GS_TRAIN_WRITE_SPECTRUM = 2
+GS_TIMER_BLEND, GS_TIMER_BLEND_BWD, GS_TIMER_TRAIN = 0, 1, 2
 
 
 class GsBatchJob(ctypes.Structure):
@@ -124,6 +133,14 @@ SIGNATURES = {
                                       ctypes.POINTER(GsL2Grad), c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz, c_p]),
     "gs_loss_spectrum_stats": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_p,
                                        c_sz, c_p]),
+    "gs_loss_l1_ssim_scratch_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i32]),
+    "gs_loss_l1_ssim": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_spatial_mean": (c_i32, [c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_p, c_p]),
+    "gs_train_scratch_bytes": (c_sz, [c_i32, c_i32, ctypes.POINTER(GsGrid)]),
+    "gs_render_train": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsAttrs), ctypes.POINTER(GsQueries), c_i32,
+                                ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p,
+                                ctypes.POINTER(GsTrainTarget), c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz, c_p,
+                                c_sz, c_p]),
     "gs_render_live": (c_i32, [c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_sz, c_p,
                                c_i64, c_p, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,
@@ -134,8 +151,9 @@ SIGNATURES = {
                                ctypes.POINTER(GsMlpState), c_p]),
     "gs_mlp_backward": (c_i32, [ctypes.POINTER(GsMlp), c_p, c_p, c_i32, ctypes.POINTER(GsMlpRows), c_p, c_i64,
                                 c_i32, ctypes.POINTER(GsMlpState), ctypes.POINTER(GsMlpGrads), c_p]),
-    "gs_mfma_probe": (c_i32, [c_p, c_p, c_p, c_p]),
     "gs_adam_step": (c_i32, [ctypes.POINTER(GsAdamSegment), c_i32, c_i32, c_f32, c_f32, c_f32, c_p, c_p, c_p]),
+    "gs_adam_step_scheduled": (c_i32, [ctypes.POINTER(GsAdamSegment), ctypes.POINTER(c_f32), c_i32, c_i32, c_p,
+                                       c_f32, c_f32, c_f32, c_p, c_p, c_p]),
     "gs_overflow_word": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_i32,
                                  ctypes.POINTER(c_p)]),
     "gs_emission_forward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p]),
@@ -148,6 +166,7 @@ SIGNATURES = {
     "gs_wall_clock_khz": (c_i32, [ctypes.POINTER(c_i32)]),
     "gs_timing_enable": (c_i32, [c_i32]),
     "gs_timing_read": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64)]),
+    "gs_check": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p]),
     "gs_read_flags": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams),
                               ctypes.POINTER(GsFlags), c_p]),
 }

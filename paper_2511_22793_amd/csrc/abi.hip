@@ -72,6 +72,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->s_g2d = fwd_only ? 0 : align256((size_t)n * 8 * 4);
     L->s_live = fwd_only ? 0 : align256((size_t)n * 4);
     L->s_gacc = fwd_only ? 0 : align256((size_t)cap * 8 * 4);
+    L->s_wtot = fwd_only ? 0 : align256((size_t)n * 4);
 
     size_t off = 0;
     auto take = [&](size_t stride) {
@@ -102,6 +103,7 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->g2d = take(L->s_g2d);
     L->live = take(L->s_live);
     L->gacc = take(L->s_gacc);
+    L->wtot = take(L->s_wtot);
     L->total = off;
     return GS_OK;
 }
@@ -418,6 +420,21 @@ gs_status gs_read_flags(const void* workspace, size_t ws_bytes, int32_t n, int32
         out[q].n_invalid = w[FL_INVALID];
     }
     return GS_OK;
+}
+
+gs_status gs_check(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries, const gs_grid* grid,
+                   const gs_params* prm, void* stream)
+{
+    if (n_queries < 1 || n_queries > (1 << 20)) return GS_ERR_INVALID_ARG;
+    std::vector<gs_flags> f((size_t)n_queries);
+    const gs_status st = gs_read_flags(workspace, ws_bytes, n, n_queries, grid, prm, f.data(), stream);
+    if (st != GS_OK) return st;
+    bool invalid = false;
+    for (const gs_flags& q : f) {
+        if (q.overflow) return GS_ERR_CAPACITY;
+        invalid = invalid || q.n_invalid != 0;
+    }
+    return invalid ? GS_ERR_NONFINITE : GS_OK;
 }
 
 }  // extern "C"

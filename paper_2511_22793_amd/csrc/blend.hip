@@ -387,7 +387,8 @@ __global__ __launch_bounds__(256) void k_live(
     const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
     const uint2* __restrict__ ranges, size_t s_ranges, int H, int W, int tw, int th, int TX, float amin, float amax,
     float tmin, uint32_t* __restrict__ flags_live, size_t s_live, float* __restrict__ T_final,
-    uint32_t* __restrict__ n_last, uint32_t* __restrict__ n_contrib, size_t s_pix)
+    uint32_t* __restrict__ n_last, uint32_t* __restrict__ n_contrib, size_t s_pix, float* __restrict__ wtot,
+    size_t s_wtot)
 {
     const int tile = blockIdx.x, q = blockIdx.z;
     const int nthr = tw * th;
@@ -401,8 +402,10 @@ __global__ __launch_bounds__(256) void k_live(
     plist += q * s_plist;
     flags_live += q * s_live;
     __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
-    __shared__ float s_sig[256];
+    __shared__ float s_sig[256], s_att[256], s_wsum[256];
     __shared__ uint32_t s_g[256];
+    if (wtot) wtot += q * s_wtot;
+    s_wsum[threadIdx.x] = 0.0f;
     float T = 1.0f;
     uint32_t last = 0, cnt = 0;
     bool done = !inside;
@@ -418,25 +421,45 @@ __global__ __launch_bounds__(256) void k_live(
             s_cb[threadIdx.x] = r.cb;
             s_cc[threadIdx.x] = r.cc;
             s_sig[threadIdx.x] = r.sigma;
+            s_att[threadIdx.x] = r.att;
             s_g[threadIdx.x] = g;
         }
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, rg.y - b0);
-        for (int j = 0; j < m && !done; ++j) {
-            double dx = pcx - s_px[j];
-            dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
-            const double dy = pcy - s_py[j];
-            const double qv = s_ca[j] * dx * dx + 2.0 * s_cb[j] * dx * dy + s_cc[j] * dy * dy;
-            const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
-            const float alpha = fminf(amax, s_sig[j] * G);
-            const float Tn = T * (1.0f - alpha);
-            const bool stop = alpha >= amin && Tn < tmin;
-            const bool take = alpha >= amin && !stop;
-            done = stop;
-            if (take) flags_live[s_g[j]] = 1u;
-            T = take ? Tn : T;
-            last = take ? b0 + j + 1 - rg.x : last;
-            cnt += take ? 1u : 0u;
+        // (the loop runs while any lane of the wave walks, so that the
+        // wave can sum the pixel weights of each entry)
+        for (int j = 0; j < m; ++j) {
+            if (__ballot(!done) == 0ull) break;
+            float wgt = 0.0f;
+            if (!done) {
+                double dx = pcx - s_px[j];
+                dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
+                const double dy = pcy - s_py[j];
+                const double qv = s_ca[j] * dx * dx + 2.0 * s_cb[j] * dx * dy + s_cc[j] * dy * dy;
+                const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E * qv));
+                const float alpha = fminf(amax, s_sig[j] * G);
+                const float Tn = T * (1.0f - alpha);
+                const bool stop = alpha >= amin && Tn < tmin;
+                const bool take = alpha >= amin && !stop;
+                done = stop;
+                if (take) flags_live[s_g[j]] = 1u;
+                wgt = take ? T * alpha * s_att[j] : 0.0f;
+                T = take ? Tn : T;
+                last = take ? b0 + j + 1 - rg.x : last;
+                cnt += take ? 1u : 0u;
+            }
+            if (wtot) {
+                // the entry's weight summed over the wave's pixels
+                for (int o = 32; o > 0; o >>= 1) wgt += __shfl_xor(wgt, o, 64);
+                if ((threadIdx.x & 63) == 0 && wgt != 0.0f) atomicAdd(&s_wsum[j], wgt);
+            }
+        }
+        if (wtot) {
+            __syncthreads();
+            if ((int)threadIdx.x < m && s_wsum[threadIdx.x] != 0.0f) {
+                unsafeAtomicAdd(&wtot[s_g[threadIdx.x]], s_wsum[threadIdx.x]);
+                s_wsum[threadIdx.x] = 0.0f;
+            }
         }
     }
     if (!inside) return;
@@ -468,11 +491,13 @@ void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, 
     uint32_t* fl = (uint32_t*)(ws + L.live);
     launch_fill_u32(fl, (size_t)L.n, L.s_live / 4, L.nq, 0u, s);
     launch_fill_u32(count, 1, 1, L.nq, 0u, s);
+    launch_fill_u32((uint32_t*)(ws + L.wtot), (size_t)L.n, L.s_wtot / 4, L.nq, 0u, s);
     hipLaunchKernelGGL(k_live, dim3(L.T, 1, L.nq), dim3(L.tw * L.th), 0, s, (const GRec*)(ws + L.rec),
                        L.s_rec / sizeof(GRec), (const uint32_t*)(ws + L.plist), L.s_plist / 4,
                        (const uint2*)(ws + L.ranges), L.s_ranges / sizeof(uint2), L.H, L.W, L.tw, L.th, L.TX,
                        p.alpha_min, p.alpha_max, p.T_min, fl, L.s_live / 4, (float*)(ws + L.T_final),
-                       (uint32_t*)(ws + L.n_last), (uint32_t*)(ws + L.n_contrib), L.s_pix / 4);
+                       (uint32_t*)(ws + L.n_last), (uint32_t*)(ws + L.n_contrib), L.s_pix / 4,
+                       (float*)(ws + L.wtot), L.s_wtot / 4);
     hipLaunchKernelGGL(k_compact_live, dim3((L.n + 255) / 256, L.nq), dim3(256), 0, s, fl, L.s_live / 4, L.n, list,
                        s_list, count);
 }
@@ -540,7 +565,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const GRec* __restrict__ rec, const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
     const float* __restrict__ attr, int64_t a_stride, int S, int Fc, int H, int W, int tw, int th, int TX,
     float amin, float amax, float tmin, float* __restrict__ out, float* __restrict__ T_final,
-    uint32_t* __restrict__ n_last, uint32_t* __restrict__ n_contrib)
+    uint32_t* __restrict__ n_last, uint32_t* __restrict__ n_contrib, int min_walk)
 {
     const int tile = blockIdx.x, pg = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -548,6 +573,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int txi = tile % TX, tyi = tile / TX;
     const int vw = min(tw, W - txi * tw), vh = min(th, H - tyi * th);
     if (pg * SGF_PIX >= vw * vh) return;
+    if (min_walk > 0) {
+        // only groups whose walk (the stop positions a live pass recorded)
+        // is longer than min_walk entries
+        const int k = pg * SGF_PIX + lane;
+        const uint32_t st = k < vw * vh ? n_last[(tyi * th + k / vw) * W + txi * tw + k % vw] : 0u;
+        uint32_t mx = st;
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        if (mx <= (uint32_t)min_walk) return;
+    }
     const uint2 rg = ranges[tile];
     const size_t HW = (size_t)H * W;
     const int F = Fc >> CS;
@@ -749,7 +783,7 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
                            (const GRec*)(ws + L.rec), (const uint32_t*)(ws + L.plist), (const uint2*)(ws + L.ranges),
                            a.data, a.query_stride, n_sets, Fc, L.H, L.W, L.tw, L.th, L.TX, p.alpha_min, p.alpha_max,
                            p.T_min, out, (float*)(ws + L.T_final), (uint32_t*)(ws + L.n_last),
-                           (uint32_t*)(ws + L.n_contrib));
+                           (uint32_t*)(ws + L.n_contrib), 0);
         timing_end(tok, s);
         return GS_OK;
     }
@@ -785,6 +819,19 @@ gs_status launch_blend(const gs_attrs& a, const gs_params& p, const Layout& L, i
     timing_end(tok, s);
 #undef ARGS
     return GS_OK;
+}
+
+// k_blend_sg over the groups whose walk (live-pass stop positions) is longer
+// than min_walk entries only
+void launch_blend_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
+                          int min_walk, hipStream_t s)
+{
+    auto kern = a.is_complex ? k_blend_sg<1> : k_blend_sg<0>;
+    hipLaunchKernelGGL(kern, dim3(L.T, (L.tw * L.th) / SGF_PIX), dim3(64 * SGF_WAVES), 0, s,
+                       (const GRec*)(ws + L.rec), (const uint32_t*)(ws + L.plist), (const uint2*)(ws + L.ranges),
+                       a.data, a.query_stride, n_sets, a.n_chan * (a.is_complex ? 2 : 1), L.H, L.W, L.tw, L.th, L.TX,
+                       p.alpha_min, p.alpha_max, p.T_min, out, (float*)(ws + L.T_final), (uint32_t*)(ws + L.n_last),
+                       (uint32_t*)(ws + L.n_contrib), min_walk);
 }
 
 void launch_blend_persist(const BlendJob* jobs, int njobs, uint32_t total, uint32_t* counter,

@@ -451,7 +451,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const GRec* __restrict__ rec, const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
     const float* __restrict__ attr, int64_t a_stride, int S, int Fc, int H, int W, int tw_log, int th, int TX,
     float amin, float amax, SgUp up, const uint32_t* __restrict__ n_last, float* __restrict__ gacc,
-    float* __restrict__ d_attr, int64_t da_stride)
+    float* __restrict__ d_attr, int64_t da_stride, int min_walk, float* __restrict__ lacc)
 {
     const int tw = 1 << tw_log;
     const int tile = blockIdx.x, pg = blockIdx.y;
@@ -499,6 +499,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __syncthreads();
     if (stop) atomicMax(&s_maxstop, stop);
     __syncthreads();
+    // (min_walk > 0: only groups whose walk is longer than min_walk entries)
+    if (min_walk > 0 && s_maxstop <= (uint32_t)min_walk) return;
     const uint32_t end = __builtin_amdgcn_readfirstlane(rg.x + s_maxstop);
     // one batch holds the whole walk of the group (the common case): D is
     // then the walk's own final prefix sum_k w_k GV_k (out = sum_k w_k v_k),
@@ -516,6 +518,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             float mk[4];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) mk[kk] = mg[((size_t)s * Fc + ch + kk) * mstr];
+            float ls = 0.0f;  // squared error of the block (with lacc)
 #pragma unroll
             for (int pb = 0; pb < 4; ++pb) {
                 const int px = pixB[pb];
@@ -523,8 +526,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const size_t i = (((size_t)(s * F + ((ch + kk) >> CS)) * HW + px) << CS) + ((ch + kk) & CS);
-                    dp[pb] += (sg_value<TGT>(up, sg_fetch<TGT>(up, i)) + mk[kk]) * up.out[i];
+                    const SgRaw<TGT> raw = sg_fetch<TGT>(up, i);
+                    dp[pb] += (sg_value<TGT>(up, raw) + mk[kk]) * up.out[i];
+                    if constexpr (TGT) {
+                        const float d = raw.a - raw.b;
+                        ls = fmaf(d, d, ls);
+                    }
                 }
+            }
+            if (TGT && lacc) {
+                for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o, 64);
+                if (lane == 0 && ls != 0.0f) atomicAdd(lacc + s, ls);
             }
         }
 #pragma unroll
@@ -868,6 +880,33 @@ static void bwd_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, cons
                        (float*)(ws + L.gacc), L.s_gacc / 4, d_attr, da_stride, shared);
 }
 
+// k_blend_bwd_sg with g = scale (out - target) + mean_grad over the groups
+// whose walk is longer than min_walk entries only; the squared error of
+// their pixels is added to lacc[set]
+void launch_blend_bwd_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
+                              const float* out, const float* target, const float* mean_grad, float scale,
+                              float* d_attr, int min_walk, float* lacc, hipStream_t s)
+{
+    int tw_log = 0;
+    while ((1 << tw_log) < L.tw) ++tw_log;
+    const SgUp sup{out, nullptr, target, mean_grad, scale};
+    const int Fc = a.n_chan * (a.is_complex ? 2 : 1);
+    auto kern = a.is_complex ? k_blend_bwd_sg<1, true> : k_blend_bwd_sg<0, true>;
+    hipLaunchKernelGGL(kern, dim3(L.T, (L.tw * L.th) / SG_PIX), dim3(SG_WAVES * 64), 0, s, (const GRec*)(ws + L.rec),
+                       (const uint32_t*)(ws + L.plist), (const uint2*)(ws + L.ranges), a.data, a.query_stride, n_sets,
+                       Fc, L.H, L.W, tw_log, L.th, L.TX, p.alpha_min, p.alpha_max, sup,
+                       (const uint32_t*)(ws + L.n_last), (float*)(ws + L.gacc), d_attr, a.query_stride, min_walk,
+                       lacc);
+}
+
+void launch_geo_fold(const Layout& L, char* ws, hipStream_t s)
+{
+    const int64_t fb = (L.cap * 8 + 255) / 256;
+    hipLaunchKernelGGL(k_geo_fold, dim3((unsigned)(fb < 2048 ? fb : 2048), L.nq), dim3(256), 0, s,
+                       (float*)(ws + L.gacc), L.s_gacc / 4, (const uint32_t*)(ws + L.plist), L.s_plist / 4,
+                       (const uint32_t*)(ws + L.flags), L.s_flags / 4, (float*)(ws + L.g2d), L.s_g2d / 4);
+}
+
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                            const float* out, const BwdUpstream& up, float* d_attr, hipStream_t s)
 {
@@ -888,7 +927,7 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
         hipLaunchKernelGGL(kern, grid, block, 0, s, (const GRec*)(ws + L.rec), (const uint32_t*)(ws + L.plist),
                            (const uint2*)(ws + L.ranges), a.data, a.query_stride, n_sets, Fc, L.H, L.W, tw_log,
                            L.th, L.TX, p.alpha_min, p.alpha_max, sup, (const uint32_t*)(ws + L.n_last),
-                           (float*)(ws + L.gacc), d_attr, a.query_stride);
+                           (float*)(ws + L.gacc), d_attr, a.query_stride, 0, (float*)nullptr);
         timing_end(tok, s);
     } else {
     int cg = choose_chan_group(Fc, p.chan_group);

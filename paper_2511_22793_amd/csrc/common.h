@@ -122,9 +122,9 @@ struct Layout {
     int sort_blocks;      // max sort workgroups for n keys
     int pair_blocks;      // max sort workgroups for cap keys
     size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;
-    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live, gacc;
+    size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live, gacc, wtot;
     size_t s_flags, s_rec, s_rect, s_status, s_tinfo, s_keys, s_partial, s_pkeys, s_plist, s_ranges,
-        s_counts, s_totals, s_pix, s_g2d, s_live, s_gacc;
+        s_counts, s_totals, s_pix, s_g2d, s_live, s_gacc, s_wtot;
     size_t total;
 };
 
@@ -178,12 +178,21 @@ struct BwdUpstream {
     float scale;
 };
 // kernel timing (timing.hip): event pairs around launches when enabled
-enum { TK_BLEND = GS_TIMER_BLEND, TK_BLEND_BWD = GS_TIMER_BLEND_BWD, TK_COUNT = 2 };
+enum { TK_BLEND = GS_TIMER_BLEND, TK_BLEND_BWD = GS_TIMER_BLEND_BWD, TK_TRAIN = GS_TIMER_TRAIN, TK_COUNT = 3 };
 bool timing_on();
 void timing_begin(int kernel, hipStream_t s, void** token);
 void timing_end(void* token, hipStream_t s);
 gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                            const float* out, const BwdUpstream& up, float* d_attr, hipStream_t s);
+// the shared-geometry compositing / backward over the groups whose walk is
+// longer than min_walk entries only (the long-walk part of the fused
+// training pass); the per-pair geometric accumulators folded per Gaussian
+void launch_blend_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws, float* out,
+                          int min_walk, hipStream_t s);
+void launch_blend_bwd_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
+                              const float* out, const float* target, const float* mean_grad, float scale,
+                              float* d_attr, int min_walk, float* lacc, hipStream_t s);
+void launch_geo_fold(const Layout& L, char* ws, hipStream_t s);
 void launch_project_bwd(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,
                         const Layout& L, char* ws, float* d_mean, float* d_log_scale, float* d_quat, float* d_opac,
                         hipStream_t s);

@@ -47,23 +47,6 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* p)  // 16-byte aligned
     return r;
 }
 
-// ---- layout probe: C = A B for one 16x16x32 tile (A, B row-major bf16) ----
-__global__ void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* C)
-{
-    const int l = threadIdx.x;
-    uint16_t a[8], b[8];
-    for (int j = 0; j < 8; ++j) {
-        a[j] = A[(l % 16) * 32 + 8 * (l / 16) + j];
-        b[j] = B[(8 * (l / 16) + j) * 16 + (l % 16)];
-    }
-    bf16x8 av, bv;
-    __builtin_memcpy(&av, a, 16);
-    __builtin_memcpy(&bv, b, 16);
-    f32x4 c = {0, 0, 0, 0};
-    c = mfma(av, bv, c);
-    for (int i = 0; i < 4; ++i) C[(4 * (l / 16) + i) * 16 + (l % 16)] = c[i];
-}
-
 // ---- Z1 = E W1e^T, one wave per 16 Gaussians -----------------------------
 __global__ __launch_bounds__(256) void k_mlp_embed(const uint16_t* __restrict__ E, int n,
                                                    const uint16_t* __restrict__ W1, float* __restrict__ Z1)
@@ -171,6 +154,7 @@ __device__ __forceinline__ int row_gauss(const uint32_t* list, uint32_t count, i
     return i < (int)count ? (int)list[i] : -1;
 }
 
+template <int NF>
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
 {
     const int s = blockIdx.y;
@@ -193,7 +177,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
         layer_mfma(s_h1[w], A.W2, 4, acc, lane);
         store_hidden(acc, A.b2, s_h2[w], lane);
         __syncthreads();
-        layer_mfma(s_h2[w], A.W3, 8, acc, lane);
+        layer_mfma(s_h2[w], A.W3, 2 * NF / 16, acc, lane);
         // save activations for the backward (row-compact order r = s*cap + i)
         if (A.save_h1) {
             const int r = lane & 15, c0 = (lane >> 4) * 16;
@@ -216,12 +200,12 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
             const float e0 = A.mean[g] - tx0, e1 = A.mean[A.n + g] - tx1, e2 = A.mean[2 * A.n + g] - tx2;
             const float d = fmaxf(sqrtf(e0 * e0 + e1 * e1 + e2 * e2), A.r_near);
             const float lnd = logf(d);
-            float* out = A.attr + (size_t)s * A.attr_stride + (size_t)g * (2 * MLP_F);
+            float* out = A.attr + (size_t)s * A.attr_stride + (size_t)g * (2 * NF);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < NF / 16; ++nt) {
                 const int f = nt * 16 + (lane & 15);
                 const float oa = acc[nt][i] + A.b3[f] - lnd;
-                const float op = acc[nt + 4][i] + A.b3[MLP_F + f];
+                const float op = acc[nt + NF / 16][i] + A.b3[NF + f];
                 const float amp = 1.0f / (1.0f + expf(-oa));
                 float sn, cs_;
                 sincosf(op, &sn, &cs_);
@@ -234,6 +218,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
 // Backward through the epilogue and the three layers for each row.  Writes
 // the rounded products' operands (d_o, dZ2, dZ1 as bf16) for the weight
 // gradients, bias sums, per-set dZ1 sums and dE (atomics).
+template <int NF>
 __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
 {
     const int s = blockIdx.y;
@@ -241,11 +226,11 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
     const uint32_t* list = A.list + (size_t)s * A.list_stride;
     const uint32_t count = A.count[A.count_stride ? s : 0];
     __shared__ __attribute__((aligned(16))) uint16_t s_h2[4][16 * MLP_HID];
-    __shared__ __attribute__((aligned(16))) uint16_t s_do[4][16 * 2 * MLP_F];
+    __shared__ __attribute__((aligned(16))) uint16_t s_do[4][16 * 2 * NF];
     __shared__ __attribute__((aligned(16))) uint16_t s_dz[4][16 * MLP_HID];
     __shared__ int s_rows[4][16];
-    __shared__ float s_db3[2 * MLP_F], s_db2[MLP_HID], s_dc[MLP_HID];
-    for (int k = threadIdx.x; k < 2 * MLP_F; k += 256) s_db3[k] = 0.0f;
+    __shared__ float s_db3[2 * NF], s_db2[MLP_HID], s_dc[MLP_HID];
+    for (int k = threadIdx.x; k < 2 * NF; k += 256) s_db3[k] = 0.0f;
     if (threadIdx.x < MLP_HID) {
         s_db2[threadIdx.x] = 0.0f;
         s_dc[threadIdx.x] = 0.0f;
@@ -266,7 +251,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
         }
         __syncthreads();
         f32x4 acc[8];
-        layer_mfma(s_h2[w], A.W3, 8, acc, lane);  // recompute o
+        layer_mfma(s_h2[w], A.W3, 2 * NF / 16, acc, lane);  // recompute o
         // d_o from d_attr
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -277,33 +262,33 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
                 const float e0 = A.mean[g] - tx0, e1 = A.mean[A.n + g] - tx1, e2 = A.mean[2 * A.n + g] - tx2;
                 lnd = logf(fmaxf(sqrtf(e0 * e0 + e1 * e1 + e2 * e2), A.r_near));
             }
-            const float* dat = A.d_attr + (size_t)s * A.attr_stride + (size_t)(g < 0 ? 0 : g) * (2 * MLP_F);
+            const float* dat = A.d_attr + (size_t)s * A.attr_stride + (size_t)(g < 0 ? 0 : g) * (2 * NF);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < NF / 16; ++nt) {
                 const int f = nt * 16 + (lane & 15);
                 float da = 0.0f, dp = 0.0f;
                 if (g >= 0) {
                     const float oa = acc[nt][i] + A.b3[f] - lnd;
-                    const float op = acc[nt + 4][i] + A.b3[MLP_F + f];
+                    const float op = acc[nt + NF / 16][i] + A.b3[NF + f];
                     const float amp = 1.0f / (1.0f + expf(-oa));
                     float sn, cs_;
                     sincosf(op, &sn, &cs_);
                     const float2 gg = *(const float2*)(dat + 2 * f);
                     if (A.clear)
-                        *(float2*)(A.clear + (size_t)s * A.attr_stride + (size_t)g * (2 * MLP_F) + 2 * f) =
+                        *(float2*)(A.clear + (size_t)s * A.attr_stride + (size_t)g * (2 * NF) + 2 * f) =
                             make_float2(0.0f, 0.0f);
                     da = (gg.x * cs_ + gg.y * sn) * amp * (1.0f - amp);
                     dp = amp * (-gg.x * sn + gg.y * cs_);
                 }
-                s_do[w][rr * 2 * MLP_F + f] = f2bf(da);
-                s_do[w][rr * 2 * MLP_F + MLP_F + f] = f2bf(dp);
+                s_do[w][rr * 2 * NF + f] = f2bf(da);
+                s_do[w][rr * 2 * NF + NF + f] = f2bf(dp);
                 acc[nt][i] = da;
-                acc[nt + 4][i] = dp;
+                acc[nt + NF / 16][i] = dp;
             }
         }
         // db3: FP32 sums of d_o
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
+        for (int nt = 0; nt < 2 * NF / 16; ++nt) {
             float v = acc[nt][0] + acc[nt][1] + acc[nt][2] + acc[nt][3];
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
@@ -315,18 +300,18 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
             const int r = lane & 15;
             const int i = r0 + r;
             if (i < (int)count)
-                for (int j = (lane >> 4) * 32; j < (lane >> 4) * 32 + 32; ++j)
-                    A.save_do[((size_t)s * A.row_cap + i) * 2 * MLP_F + j] = s_do[w][r * 2 * MLP_F + j];
+                for (int j = (lane >> 4) * (NF / 2); j < (lane >> 4) * (NF / 2) + NF / 2; ++j)
+                    A.save_do[((size_t)s * A.row_cap + i) * 2 * NF + j] = s_do[w][r * 2 * NF + j];
         }
-        // dh2 = d_o W3  (K = 128: four 32-wide chunks; B from W3^T [64][128])
+        // dh2 = d_o W3  (K = 2 NF in 32-wide chunks; B from W3^T [64][2 NF])
         f32x4 dh[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             f32x4 c = {0, 0, 0, 0};
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc) {
-                const bf16x8 a = load8(&s_do[w][(lane & 15) * 2 * MLP_F + kc * 32 + 8 * (lane >> 4)]);
-                const bf16x8 b = load8(A.W3T + (size_t)(nt * 16 + (lane & 15)) * 2 * MLP_F + kc * 32 + 8 * (lane >> 4));
+            for (int kc = 0; kc < 2 * NF / 32; ++kc) {
+                const bf16x8 a = load8(&s_do[w][(lane & 15) * 2 * NF + kc * 32 + 8 * (lane >> 4)]);
+                const bf16x8 b = load8(A.W3T + (size_t)(nt * 16 + (lane & 15)) * 2 * NF + kc * 32 + 8 * (lane >> 4));
                 c = mfma(a, b, c);
             }
             dh[nt] = c;
@@ -413,7 +398,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
     // only workgroups that had rows flush (the grid is sized for the largest
     // row count; the others would add zeros into the same few addresses)
     if (blockIdx.x * 64 >= (int)count) return;
-    for (int k = threadIdx.x; k < 2 * MLP_F; k += 256) unsafeAtomicAdd(A.db3 + k, s_db3[k]);
+    for (int k = threadIdx.x; k < 2 * NF; k += 256) unsafeAtomicAdd(A.db3 + k, s_db3[k]);
     if (threadIdx.x < MLP_HID) {
         unsafeAtomicAdd(A.db2 + threadIdx.x, s_db2[threadIdx.x]);
         unsafeAtomicAdd(A.dc + s * MLP_HID + threadIdx.x, s_dc[threadIdx.x]);
@@ -506,15 +491,18 @@ struct WgradArgs {
     float* partial;
 };
 
-constexpr int WG3_LEN0 = 2 * MLP_F * MLP_HID, WG3_LEN1 = MLP_HID * MLP_HID, WG3_LEN2 = MLP_HID * MLP_EMB;
+constexpr int WG3_LEN1 = MLP_HID * MLP_HID, WG3_LEN2 = MLP_HID * MLP_EMB;
+__host__ __device__ constexpr int wg3_len0(int nf) { return 2 * nf * MLP_HID; }
 
+template <int NF>
 __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs A)
 {
     __shared__ WgradLds L;
     const int P = gridDim.x;
+    constexpr int WG3_LEN0 = wg3_len0(NF);
     // y = 0: dW3 = d_o^T h2; 1: dW2 = dZ2^T h1; 2: dW1e = dZ1^T E[g]
     const int y = blockIdx.y;
-    const int M = y == 0 ? 2 * MLP_F : MLP_HID, N = y == 2 ? MLP_EMB : MLP_HID;
+    const int M = y == 0 ? 2 * NF : MLP_HID, N = y == 2 ? MLP_EMB : MLP_HID;
     const uint16_t* a = y == 0 ? A.do_ : (y == 1 ? A.dz2 : A.dz1);
     const uint16_t* b = y == 0 ? A.h2 : (y == 1 ? A.h1 : nullptr);
     float* part = A.partial + (y == 0 ? 0 : (y == 1 ? (size_t)P * WG3_LEN0 : (size_t)P * (WG3_LEN0 + WG3_LEN1)));
@@ -524,9 +512,11 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs A)
 
 // Sums the partials of the three weight gradients into dW3, dW2 and the
 // embedding columns of dW1.
+template <int NF>
 __global__ void k_reduce3(const float* __restrict__ partial, int nparts, float* __restrict__ dW3,
                           float* __restrict__ dW2, float* __restrict__ dW1)
 {
+    constexpr int WG3_LEN0 = wg3_len0(NF);
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     const float* base = partial;
     int len = WG3_LEN0, ncols = MLP_HID, ld = MLP_HID;
@@ -567,7 +557,7 @@ __global__ void k_mlp_bias_grad(const float* __restrict__ dc, const uint16_t* __
 // bf16 transposes of the weights used as B operands in the backward
 __global__ void k_mlp_transpose(const uint16_t* __restrict__ W1, const uint16_t* __restrict__ W2,
                                 const uint16_t* __restrict__ W3, uint16_t* __restrict__ W1eT,
-                                uint16_t* __restrict__ W2T, uint16_t* __restrict__ W3T)
+                                uint16_t* __restrict__ W2T, uint16_t* __restrict__ W3T, int NF)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < MLP_EMB * MLP_HID) {  // W1eT[n][k] = W1[k][n], n < 32
@@ -578,8 +568,8 @@ __global__ void k_mlp_transpose(const uint16_t* __restrict__ W1, const uint16_t*
         const int n = e / MLP_HID, k = e % MLP_HID;
         W2T[e] = W2[(size_t)k * MLP_HID + n];
     }
-    if (e < MLP_HID * 2 * MLP_F) {  // W3T[n][k] = W3[k][n], n < 64, k < 128
-        const int n = e / (2 * MLP_F), k = e % (2 * MLP_F);
+    if (e < MLP_HID * 2 * NF) {  // W3T[n][k] = W3[k][n], n < 64, k < 2 NF
+        const int n = e / (2 * NF), k = e % (2 * NF);
         W3T[e] = W3[(size_t)k * MLP_HID + n];
     }
 }
@@ -589,14 +579,6 @@ __global__ void k_mlp_transpose(const uint16_t* __restrict__ W1, const uint16_t*
 using namespace gs;
 
 extern "C" {
-
-gs_status gs_mfma_probe(const uint16_t* A, const uint16_t* B, float* C, void* stream)
-{
-    if (!A || !B || !C) return GS_ERR_INVALID_ARG;
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, C);
-    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
-}
 
 gs_status gs_mlp_embed(const gs_mlp* net, const uint16_t* E, int32_t n, float* Z1, void* stream)
 {
@@ -610,6 +592,7 @@ gs_status gs_mlp_embed(const gs_mlp* net, const uint16_t* E, int32_t n, float* Z
 static gs_status check_rows(const gs_mlp* net, const gs_mlp_rows* rows, const float* mean, int32_t n)
 {
     if (!net || !rows || !mean || n < 1) return GS_ERR_INVALID_ARG;
+    if (net->n_chan != 32 && net->n_chan != 64) return GS_ERR_INVALID_ARG;
     if (!net->W1 || !net->b1 || !net->W2 || !net->b2 || !net->W3 || !net->b3) return GS_ERR_INVALID_ARG;
     if (!rows->tx || !rows->list || !rows->count || rows->n_sets < 1 || rows->n_sets > 65535) return GS_ERR_INVALID_ARG;
     if (rows->row_cap < 1 || !(net->r_near > 0.0f)) return GS_ERR_INVALID_ARG;
@@ -623,7 +606,8 @@ gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, 
 {
     gs_status e = check_rows(net, rows, mean, n);
     if (e != GS_OK) return e;
-    if (!Z1 || !attr || !st || !st->cb || attr_stride < (int64_t)n * 2 * MLP_F) return GS_ERR_INVALID_ARG;
+    const int NF = net->n_chan;
+    if (!Z1 || !attr || !st || !st->cb || attr_stride < (int64_t)n * 2 * NF) return GS_ERR_INVALID_ARG;
     if ((st->save_h1 == nullptr) != (st->save_h2 == nullptr)) return GS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();
@@ -637,7 +621,8 @@ gs_status gs_mlp_forward(const gs_mlp* net, const float* Z1, const float* mean, 
     A.row_cap = rows->row_cap; A.attr = attr; A.attr_stride = attr_stride;
     A.save_h1 = st->save_h1; A.save_h2 = st->save_h2;
     const int gx = rows->grid_x > 0 ? rows->grid_x : 32;
-    hipLaunchKernelGGL(k_mlp_fwd, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
+    if (NF == 64) hipLaunchKernelGGL(k_mlp_fwd<64>, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(k_mlp_fwd<32>, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
@@ -651,16 +636,18 @@ gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mea
         !st->save_dz1 || !st->genc || !st->dc || !st->wT || !st->partial || st->n_partial < 1)
         return GS_ERR_INVALID_ARG;
     if (!gr->dW1 || !gr->db1 || !gr->dW2 || !gr->db2 || !gr->dW3 || !gr->db3 || !gr->dE) return GS_ERR_INVALID_ARG;
+    const int NF = net->n_chan;
+    if (attr_stride < (int64_t)n * 2 * NF) return GS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();
     uint16_t* W1eT = st->wT;
     uint16_t* W2T = W1eT + MLP_EMB * MLP_HID;
     uint16_t* W3T = W2T + MLP_HID * MLP_HID;
     hipLaunchKernelGGL(k_mlp_transpose, dim3((MLP_HID * 2 * MLP_F + 255) / 256), dim3(256), 0, s, net->W1, net->W2,
-                       net->W3, W1eT, W2T, W3T);
+                       net->W3, W1eT, W2T, W3T, NF);
     {
         FillSegs f{};
-        f.p[0] = (uint32_t*)gr->db3; f.count[0] = 2 * MLP_F;
+        f.p[0] = (uint32_t*)gr->db3; f.count[0] = 2 * NF;
         f.p[1] = (uint32_t*)gr->db2; f.count[1] = MLP_HID;
         f.p[2] = (uint32_t*)gr->dW1; f.count[2] = (size_t)MLP_HID * MLP_IN;
         f.p[3] = (uint32_t*)st->dc; f.count[3] = (size_t)rows->n_sets * MLP_HID;
@@ -678,14 +665,20 @@ gs_status gs_mlp_backward(const gs_mlp* net, const uint16_t* E, const float* mea
     A.save_h1 = st->save_h1; A.save_h2 = st->save_h2; A.save_do = st->save_do; A.save_dz2 = st->save_dz2;
     A.save_dz1 = st->save_dz1; A.db3 = gr->db3; A.db2 = gr->db2; A.dc = st->dc; A.dE = gr->dE;
     const int gx = rows->grid_x > 0 ? rows->grid_x : 32;
-    hipLaunchKernelGGL(k_mlp_bwd_data, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
+    if (NF == 64) hipLaunchKernelGGL(k_mlp_bwd_data<64>, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(k_mlp_bwd_data<32>, dim3(gx, rows->n_sets), dim3(256), 0, s, A);
     const int P = st->n_partial;
     // dW3 = d_o^T h2, dW2 = dZ2^T h1, dW1e = dZ1^T E: one split-K launch, one reduction
     WgradArgs W{st->save_do, st->save_h2, st->save_dz2, st->save_h1, st->save_dz1, E, rows->list, (size_t)rows->list_stride,
                 rows->count, rows->count_stride, rows->n_sets, (size_t)rows->row_cap, st->partial};
-    hipLaunchKernelGGL(k_wgrad3, dim3(P, 3), dim3(256), 0, s, W);
-    hipLaunchKernelGGL(k_reduce3, dim3((WG3_LEN0 + WG3_LEN1 + WG3_LEN2 + 255) / 256), dim3(256), 0, s, st->partial, P,
-                       gr->dW3, gr->dW2, gr->dW1);
+    const unsigned rb = (unsigned)((wg3_len0(NF) + WG3_LEN1 + WG3_LEN2 + 255) / 256);
+    if (NF == 64) {
+        hipLaunchKernelGGL(k_wgrad3<64>, dim3(P, 3), dim3(256), 0, s, W);
+        hipLaunchKernelGGL(k_reduce3<64>, dim3(rb), dim3(256), 0, s, st->partial, P, gr->dW3, gr->dW2, gr->dW1);
+    } else {
+        hipLaunchKernelGGL(k_wgrad3<32>, dim3(P, 3), dim3(256), 0, s, W);
+        hipLaunchKernelGGL(k_reduce3<32>, dim3(rb), dim3(256), 0, s, st->partial, P, gr->dW3, gr->dW2, gr->dW1);
+    }
     hipLaunchKernelGGL(k_mlp_bias_grad, dim3(MLP_ENC + 1), dim3(MLP_HID), 0, s, st->dc, st->genc, rows->n_sets,
                        gr->dW1, gr->db1);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;

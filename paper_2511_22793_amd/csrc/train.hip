@@ -1,0 +1,764 @@
+// One fused training pass over attribute sets that share one geometry (a
+// fixed receiver, S transmitters whose effect is in the attributes):
+// compositing (Eq. (3)), the training loss (the Eq. (2) spatial mean with
+// the Eq. (4) channel term, and the pixel term) and the compositing backward,
+// without writing the spectra or their gradient to memory.
+//
+// Per pixel p the weight of list entry k, w_k(p) = T_k alpha_k a_k, and the
+// walk's decisions do not depend on the set, so for every column c = (set,
+// channel, re/im):
+//   zhat(p, c)  = sum_k w_k(p) v(k, c)                 (forward, Eq. (3))
+//   g(p, c)     = e (zhat - z)(p, c) + m(c)            (dL/dzhat)
+//   GV_k(p)     = sum_c v(k, c) g(p, c)                (geometric backward)
+//   dL/dv(k, c) = sum_p w_k(p) g(p, c)                 (attribute gradient)
+// with e = 2 / (F H W S) and m(c) = lambda 2 (hhat - h)(c) / (H W S).  m needs
+// the spatial mean hhat before any pixel is formed: by linearity,
+// hhat(c) = (1/HW) sum_g Wtot_g v(g, c) with Wtot_g = sum_p w_g(p), which the
+// live pass accumulates per Gaussian; h, the target's channel (Eq. (2) of the
+// target spectrum), is an input.
+//
+// Work units: (64-pixel group of a tile, column range).  A unit evaluates
+// alpha for every (entry, pixel) of the group's walk (all four waves), forms
+// the prefix transmittance and the weights (one wave), then walks its column
+// range in rounds of four 16-column blocks, one per wave:
+//   (F) zhat on the FP32 matrix cores (the product of k_blend_sg, same
+//       operands and K order, so an optional spectrum store is bit-identical
+//       to the compositing kernel's), the target read, g, the loss partial;
+//   (D) dL/dv over the group's 64 pixels from g in registers, one atomic per
+//       (entry, column) of the unit;
+//   (G) g of all four blocks goes through LDS so that each wave adds GV for
+//       its 16 pixels over the round's 64 columns.
+// GV partials (per unit) go to memory; a second kernel sums the column
+// ranges of each group and walks the backward recurrence (Eq. (3)
+// differentiated): the running prefix P_k = sum_{m<=k} w_m GV_m, dL/dalpha_k
+// = T_k a_k GV_k - (D - P_k) / (1 - alpha_k) with D = P_last, and the seven
+// geometric terms of each entry reduced over the group's pixels.
+// Both kernels come in variants for walks of at most 64, 128 and 256 list
+// entries (the weights of the whole walk stay in LDS); a group takes the
+// smallest that holds its walk.  Walks grow as training makes Gaussians
+// fainter.  Groups whose walk is longer than 256 entries are left to the
+// unfused kernels (compositing, then the backward forming g from the stored
+// spectrum and the target).
+#include <type_traits>
+
+#include "common.h"
+
+namespace gs {
+
+constexpr double LOG2E_T = 1.4426950408889634;
+constexpr int TR_PIX = 64;     // pixels per group
+constexpr int TR_WAVES = 4;
+constexpr int TR_PAD = 68;     // padded LDS row (pixels)
+constexpr int TR_CH = 64;      // entries per alpha chunk
+constexpr int TR_EMAX = 256;   // longest group walk the fused kernels take
+
+typedef float f32x4t __attribute__((ext_vector_type(4)));
+
+// pixel k (0 <= k < vw*vh, row-major inside the tile's in-image part) of
+// tile (txi, tyi) as an image offset, or -1
+__device__ __forceinline__ int tr_pixel(int k, int vw, int vh, int txi, int tyi, int tw, int th, int W)
+{
+    return k < vw * vh ? (tyi * th + k / vw) * W + txi * tw + k % vw : -1;
+}
+
+// The group's pixels, stop positions (the live pass's) and the records of
+// the entries its walk reaches, for walks of at most E entries.
+template <int E>
+struct TrLds {
+    double px[E], py[E], ca[E], cb[E], cc[E];
+    float sig[E], att[E];
+    uint32_t g[E];
+    int pix[TR_PIX];
+    uint32_t maxstop;
+};
+
+// Shared start of both kernels: returns the walk length m of the group when
+// lo < m <= E (lo = 0: 0 <= m <= E), else -1 (another variant, or the
+// unfused kernels beyond TR_EMAX, takes the group).
+template <int E>
+__device__ __forceinline__ int tr_group(TrLds<E>& L, const GRec* __restrict__ rec,
+                                        const uint32_t* __restrict__ plist, uint2 rg,
+                                        const uint32_t* __restrict__ n_last, int pg, int vw, int vh, int txi, int tyi,
+                                        int tw, int th, int W, int lo, uint32_t& stop)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) L.maxstop = 0;
+    if (threadIdx.x < TR_PIX) L.pix[threadIdx.x] = tr_pixel(pg * TR_PIX + threadIdx.x, vw, vh, txi, tyi, tw, th, W);
+    __syncthreads();
+    const int mypix = L.pix[lane];
+    stop = mypix >= 0 ? n_last[mypix] : 0u;
+    if (wave == 0 && stop) atomicMax(&L.maxstop, stop);
+    __syncthreads();
+    const uint32_t ms = L.maxstop;
+    if (ms > (uint32_t)E || (lo > 0 && ms <= (uint32_t)lo)) return -1;
+    const int m = (int)ms;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        const uint32_t g = plist[rg.x + t];
+        const GRec r = rec[g];
+        L.px[t] = r.px;
+        L.py[t] = r.py;
+        L.ca[t] = r.ca;
+        L.cb[t] = r.cb;
+        L.cc[t] = r.cc;
+        L.sig[t] = r.sigma;
+        L.att[t] = r.att;
+        L.g[t] = g;
+    }
+    __syncthreads();
+    return m;
+}
+
+// alpha of entries k0 .. k0 + 63 at the lane's pixel, with the walk's
+// decisions applied (0 where the pixel does not take the entry, and beyond
+// the walk), into rows row0 + (k - k0) of s_a; all four waves, no barrier
+template <int E>
+__device__ __forceinline__ void tr_alpha(const TrLds<E>& L, float (*s_a)[TR_PAD], int row0, int k0, int m,
+                                         uint32_t stop, int W, float amin, float amax)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mypix = L.pix[lane];
+    const double pcx = (mypix >= 0 ? mypix % W : 0) + 0.5, pcy = (mypix >= 0 ? mypix / W : 0) + 0.5;
+    const double halfW = 0.5 * W;
+    for (int kk = wave; kk < TR_CH; kk += TR_WAVES) {
+        const int k = k0 + kk;
+        float a = 0.0f;
+        if (k < m && (uint32_t)k < stop) {
+            double dx = pcx - L.px[k];
+            dx += dx >= halfW ? -(double)W : (dx < -halfW ? (double)W : 0.0);
+            const double dy = pcy - L.py[k];
+            const double qv = L.ca[k] * dx * dx + 2.0 * L.cb[k] * dx * dy + L.cc[k] * dy * dy;
+            const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E_T * qv));
+            const float alpha = fminf(amax, L.sig[k] * G);
+            a = alpha >= amin ? alpha : 0.0f;
+        }
+        s_a[row0 + kk][lane] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: forward products, loss partial, attribute gradient, GV partials.
+// ---------------------------------------------------------------------------
+struct TrArgs {
+    const GRec* rec;
+    const uint32_t* plist;
+    const uint2* ranges;
+    const uint32_t* n_last;
+    const float* attr;
+    int64_t a_stride;
+    const float* tgt;
+    const float* mgrad;  // m [S][Fc]
+    float escale;        // e
+    float* out;          // spectrum, or null
+    float* d_attr;
+    int64_t da_stride;
+    float* gvp;          // GV partials [group][R][TR_EMAX][TR_PIX]
+    float* lpart;        // squared-error partials [group * R + r][S]
+    float* gacc;         // per-pair geometric accumulators [pairs][8]
+    int S, Fc, H, W, tw, th, TX, gpt, R;
+    float amin, amax;
+};
+
+// occupancy per variant: the LDS of E = 64 fits four workgroups per CU, of
+// 128 two, of 256 one
+template <int E>
+struct TrOcc {
+    static constexpr int waves = E <= 64 ? 4 : (E <= 128 ? 2 : 1);
+};
+
+template <int E>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::waves))) void k_train_fb(TrArgs A,
+                                                                                                      int lo)
+{
+    const int grp = blockIdx.x, r = blockIdx.y;
+    const int tile = grp / A.gpt, pg = grp % A.gpt;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j4 = lane >> 4, l16 = lane & 15;
+    const int txi = tile % A.TX, tyi = tile / A.TX;
+    const int vw = min(A.tw, A.W - txi * A.tw), vh = min(A.th, A.H - tyi * A.th);
+    if (pg * TR_PIX >= vw * vh) return;
+    const uint2 rg = A.ranges[tile];
+    const size_t HW = (size_t)A.H * A.W;
+    const int F = A.Fc >> 1;
+    const int ncb = A.S * A.Fc / 16;
+    const int cb_lo = r * ncb / A.R, cb_hi = (r + 1) * ncb / A.R;
+
+    __shared__ TrLds<E> L;
+    __shared__ __align__(16) float s_a[TR_CH][TR_PAD];  // alpha of a chunk, then the exchange of g
+    __shared__ __align__(16) float s_w[E][TR_PAD];      // weights w_k(p)
+    uint32_t stop;
+    const int m = tr_group<E>(L, A.rec, A.plist, rg, A.n_last, pg, vw, vh, txi, tyi, A.tw, A.th, A.W, lo, stop);
+    if (m < 0) return;
+    const int nks = (m + 3) >> 2;  // K-steps of 4 entries
+    const int mp = nks * 4;
+
+    // prefix transmittance and weights chunk by chunk: alpha by all waves,
+    // the walk by one (lane = pixel, in list order: the operations of the
+    // compositing kernel)
+    float T = 1.0f;
+    for (int k0 = 0; k0 < mp; k0 += TR_CH) {
+        tr_alpha<E>(L, s_a, 0, k0, m, stop, A.W, A.amin, A.amax);
+        __syncthreads();
+        if (wave == 0) {
+            const int kn = min(TR_CH, mp - k0);
+            for (int kk = 0; kk < kn; ++kk) {
+                const float a = s_a[kk][lane];
+                const float w = a > 0.0f ? T * a * L.att[k0 + kk] : 0.0f;
+                T = a > 0.0f ? T * (1.0f - a) : T;
+                s_w[k0 + kk][lane] = w;
+            }
+        }
+        __syncthreads();
+    }
+
+    // the lanes' pixels in the (F)/(D) layout (lane holds rows
+    // 16 pb + 4 j4 + i of a 64-pixel column), read from LDS where used
+    auto pixY = [&](int pb, int i) -> int { return L.pix[16 * pb + 4 * j4 + i]; };
+    const uint32_t gfirst = m > 0 ? L.g[0] : 0u;
+    auto gid = [&](int k) -> uint32_t { return k < m ? L.g[k] : gfirst; };
+
+    constexpr int NEB = E / 16;
+    f32x4t gv[NEB];  // GV[16 eb + 4 j4 + i][16 wave + l16], over this unit's columns
+#pragma unroll
+    for (int eb = 0; eb < NEB; ++eb) gv[eb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
+    const int neb = (m + 15) >> 4;
+    float lsum = 0.0f;
+    int lset = -1;
+    float* lp = A.lpart + (size_t)(grp * A.R + r) * A.S;
+
+    const int nrounds = (cb_hi - cb_lo + TR_WAVES - 1) / TR_WAVES;
+    // target words of this wave's block in a round, one round ahead (their
+    // HBM latency hides behind the previous round's products)
+    auto tgt_load = [&](int rd_, float* t) {
+        const int cb_ = cb_lo + rd_ * TR_WAVES + wave;
+        if (rd_ >= nrounds || cb_ >= cb_hi) return;
+        const int s_ = cb_ * 16 / A.Fc;
+        const int c_ = cb_ * 16 - s_ * A.Fc + l16;
+        const size_t plane = ((size_t)(s_ * F + (c_ >> 1)) * HW) * 2 + (c_ & 1);
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = pixY(pb, i);
+                t[4 * pb + i] = px >= 0 ? A.tgt[plane + ((size_t)px << 1)] : 0.0f;
+            }
+    };
+    float tcur[16], tnext[16];
+    tgt_load(0, tcur);
+    constexpr int KCH = (E < 128 ? E : 128) / 4;  // K-steps of one chain
+    for (int rd = 0; rd < nrounds; ++rd) {
+        const int cb = cb_lo + rd * TR_WAVES + wave;
+        const bool own = cb < cb_hi;
+        const int s = own ? cb * 16 / A.Fc : 0;
+        const int c0 = own ? cb * 16 - s * A.Fc : 0;
+        f32x4t z[4];  // zhat, then g: [pixel 16 pb + 4 j4 + i][column c0 + l16]
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) z[pb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
+        if (own) {
+            // (F) zhat = W^T V, in chains of 128 entries added in list order
+            // (the compositing kernel's buffer flushes, so that the stored
+            // spectrum is bit-identical to it); the chain's V words first
+            const float* vb = A.attr + s * A.a_stride + c0 + l16;
+            for (int kc = 0; kc < nks; kc += KCH) {
+                float bq[KCH];
+#pragma unroll
+                for (int q = 0; q < KCH; ++q)
+                    if (kc + q < nks) bq[q] = vb[(size_t)gid(4 * (kc + q) + j4) * A.Fc];
+                f32x4t zc[4];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) zc[pb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int q = 0; q < KCH; ++q) {
+                    if (kc + q < nks) {
+                        const int ks = kc + q;
+#pragma unroll
+                        for (int pb = 0; pb < 4; ++pb)
+                            zc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_w[4 * ks + j4][16 * pb + l16], bq[q],
+                                                                          zc[pb], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) z[pb] = kc == 0 ? zc[pb] : zc[pb] + z[pb];
+            }
+        }
+        tgt_load(rd + 1, tnext);
+        if (own) {
+            // target, g, loss partial (column c0 + l16 = channel f, re/im)
+            const int c = c0 + l16;
+            const size_t plane = ((size_t)(s * F + (c >> 1)) * HW) * 2 + (c & 1);
+            const float mc = A.mgrad[(size_t)s * A.Fc + c];
+            float ls = 0.0f;
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int px = pixY(pb, i);
+                    if (px >= 0) {
+                        if (A.out) A.out[plane + ((size_t)px << 1)] = z[pb][i];
+                        const float d = z[pb][i] - tcur[4 * pb + i];
+                        ls = fmaf(d, d, ls);
+                        z[pb][i] = fmaf(A.escale, d, mc);
+                    } else {
+                        z[pb][i] = 0.0f;
+                    }
+                }
+            if (s != lset) {
+                if (lset >= 0) {
+                    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+                    if (lane == 0) atomicAdd(lp + lset, lsum);
+                }
+                lset = s;
+                lsum = 0.0f;
+            }
+            lsum += ls;
+            // g to LDS for (G): s_a[16 wave + j][p] = g(p, c0 + j)
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s_a[16 * wave + l16][16 * pb + 4 * j4 + i] = z[pb][i];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) tcur[q] = tnext[q];
+        __syncthreads();
+        // (G) GV[k][16 wave + l16] += sum over the round's columns of v(k, c) g(p, c)
+#pragma unroll 1
+        for (int ow = 0; ow < TR_WAVES; ++ow) {
+            const int ocb = cb_lo + rd * TR_WAVES + ow;
+            if (ocb >= cb_hi) break;
+            const int os = ocb * 16 / A.Fc;
+            const int oc0 = ocb * 16 - os * A.Fc;
+            const float* va = A.attr + os * A.a_stride + oc0 + 4 * j4;
+            float bg[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) bg[kk] = s_a[16 * ow + 4 * j4 + kk][16 * wave + l16];
+#pragma unroll
+            for (int eb = 0; eb < NEB; ++eb) {
+                if (eb < neb) {
+                    const float4 v4 = *(const float4*)(va + (size_t)gid(16 * eb + l16) * A.Fc);
+                    __builtin_amdgcn_sched_barrier(0);
+                    gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.x, bg[0], gv[eb], 0, 0, 0);
+                    gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.y, bg[1], gv[eb], 0, 0, 0);
+                    gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.z, bg[2], gv[eb], 0, 0, 0);
+                    gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.w, bg[3], gv[eb], 0, 0, 0);
+                }
+            }
+        }
+        // (D) dL/dv[k][c0 + l16] = sum_p w_k(p) g(p, c0 + l16): K-step (pb, i)
+        // pairs lane group j4 with pixel 16 pb + 4 j4 + i
+        if (own) {
+            float* dA = A.d_attr + s * A.da_stride + c0 + l16;
+            for (int eb = 0; eb < neb; ++eb) {
+                f32x4t acc = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) {
+                    const float4 w4 = *(const float4*)&s_w[16 * eb + l16][16 * pb + 4 * j4];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[pb][0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[pb][1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[pb][2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[pb][3], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * eb + 4 * j4 + i;
+                    if (k < m && acc[i] != 0.0f) unsafeAtomicAdd(dA + (size_t)L.g[k] * A.Fc, acc[i]);
+                }
+            }
+        }
+        __syncthreads();  // before the next round's g overwrites s_a
+    }
+    if (lset >= 0) {
+        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+        if (lane == 0) atomicAdd(lp + lset, lsum);
+    }
+    // GV partial of this column range: lane holds entries 16 eb + 4 j4 + i at
+    // pixel 16 wave + l16
+    float* gp = A.gvp + (size_t)(grp * A.R + r) * TR_EMAX * TR_PIX;
+#pragma unroll
+    for (int eb = 0; eb < NEB; ++eb)
+        if (eb < neb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gp[(16 * eb + 4 * j4 + i) * TR_PIX + 16 * wave + l16] = gv[eb][i];
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: per group, GV summed over the column ranges, the backward walk
+// and the geometric terms of each entry reduced over the group's pixels into
+// the per-pair accumulators (folded per Gaussian afterwards).
+// ---------------------------------------------------------------------------
+
+// reduce-scatter of 8 values over the wave: lane l ends with the wave total
+// of value l >> 3 (permlane swaps, then DPP; as in the compositing backward)
+__device__ __forceinline__ float tr_dpp(float v, int sel)
+{
+    const int iv = __float_as_int(v);
+    int rr;
+    switch (sel) {
+        case 0: rr = __builtin_amdgcn_update_dpp(0, iv, 0x128, 0xF, 0xF, true); break;  // row_ror:8
+        case 1: rr = __builtin_amdgcn_update_dpp(0, iv, 0xB1, 0xF, 0xF, true); break;   // quad_perm [1,0,3,2]
+        case 2: rr = __builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xF, 0xF, true); break;   // quad_perm [2,3,0,1]
+        default: rr = __builtin_amdgcn_update_dpp(0, iv, 0x141, 0xF, 0xF, true); break; // row_half_mirror
+    }
+    return __int_as_float(rr);
+}
+
+__device__ __forceinline__ void tr_reduce_scatter8(float* x, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i + 4]), false, false);
+        x[i] = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[i + 2]), false, false);
+        x[i] = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    }
+    const float t0 = x[0] + tr_dpp(x[0], 0), t1 = x[1] + tr_dpp(x[1], 0);
+    float v = (lane & 8) ? t1 : t0;
+    v += tr_dpp(v, 1);
+    v += tr_dpp(v, 2);
+    v += tr_dpp(v, 3);
+    x[0] = v;
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void k_train_walk(TrArgs A, int lo)
+{
+    const int grp = blockIdx.x;
+    const int tile = grp / A.gpt, pg = grp % A.gpt;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int txi = tile % A.TX, tyi = tile / A.TX;
+    const int vw = min(A.tw, A.W - txi * A.tw), vh = min(A.th, A.H - tyi * A.th);
+    if (pg * TR_PIX >= vw * vh) return;
+    const uint2 rg = A.ranges[tile];
+
+    __shared__ TrLds<E> L;
+    __shared__ float s_a[E][TR_PAD];   // alpha, then dL/d(sigma G)
+    __shared__ float s_gv[E][TR_PAD];  // GV, then T alpha GV
+    uint32_t stop;
+    const int m = tr_group<E>(L, A.rec, A.plist, rg, A.n_last, pg, vw, vh, txi, tyi, A.tw, A.th, A.W, lo, stop);
+    if (m <= 0) return;
+    for (int k0 = 0; k0 < m; k0 += TR_CH) tr_alpha<E>(L, s_a, k0, k0, m, stop, A.W, A.amin, A.amax);
+    const float* gp = A.gvp + (size_t)grp * A.R * TR_EMAX * TR_PIX;
+    for (int e = threadIdx.x; e < m * TR_PIX; e += blockDim.x) {
+        float v = 0.0f;
+        for (int rr = 0; rr < A.R; ++rr) v += gp[(size_t)rr * TR_EMAX * TR_PIX + e];
+        s_gv[e / TR_PIX][e % TR_PIX] = v;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // D = sum_k w_k GV_k (the forward output contracted with g), then the
+        // recurrence front to back
+        float T = 1.0f, P = 0.0f;
+        for (int k = 0; k < m; ++k) {
+            const float a = s_a[k][lane];
+            const float Ta = a > 0.0f ? T * a : 0.0f;
+            P = P + Ta * (L.att[k] * s_gv[k][lane]);
+            T = a > 0.0f ? T * (1.0f - a) : T;
+        }
+        const float D = P;
+        T = 1.0f;
+        P = 0.0f;
+        for (int k = 0; k < m; ++k) {
+            const float a = s_a[k][lane];
+            const bool take = a > 0.0f;
+            const float gvk = s_gv[k][lane];
+            const float cA = L.att[k] * gvk;
+            const float Ta = take ? T * a : 0.0f;
+            const float Pn = P + Ta * cA;
+            const float dalpha = T * cA - (D - Pn) * __builtin_amdgcn_rcpf(1.0f - a);
+            s_a[k][lane] = (take && a < A.amax) ? dalpha : 0.0f;
+            s_gv[k][lane] = Ta * gvk;
+            T = take ? T * (1.0f - a) : T;
+            P = Pn;
+        }
+    }
+    __syncthreads();
+    // geometric terms of entry k at this lane's pixel, reduced over the pixels
+    const int mypix = L.pix[lane];
+    const double pcx = (mypix >= 0 ? mypix % A.W : 0) + 0.5, pcy = (mypix >= 0 ? mypix / A.W : 0) + 0.5;
+    const double halfW = 0.5 * A.W;
+    for (int k = wave; k < m; k += TR_WAVES) {
+        const float dsg = s_a[k][lane];
+        const float tg = s_gv[k][lane];
+        if (__ballot(dsg != 0.0f || tg != 0.0f) == 0ull) continue;
+        double dx = pcx - L.px[k];
+        dx += dx >= halfW ? -(double)A.W : (dx < -halfW ? (double)A.W : 0.0);
+        const double dy = pcy - L.py[k];
+        const double qv = L.ca[k] * dx * dx + 2.0 * L.cb[k] * dx * dy + L.cc[k] * dy * dy;
+        const float G = __builtin_amdgcn_exp2f((float)(-0.5 * LOG2E_T * qv));
+        const float dq = -0.5f * dsg * L.sig[k] * G;
+        const float dxf = (float)dx, dyf = (float)dy;
+        const float caf = (float)L.ca[k], cbf = (float)L.cb[k], ccf = (float)L.cc[k];
+        const float dq2 = -2.0f * dq;
+        float geo[8];
+        geo[0] = dq2 * fmaf(caf, dxf, cbf * dyf);
+        geo[1] = dq2 * fmaf(cbf, dxf, ccf * dyf);
+        geo[2] = dq * (dxf * dxf);
+        geo[3] = dq * (2.0f * dxf * dyf);
+        geo[4] = dq * (dyf * dyf);
+        geo[5] = dsg * G;
+        geo[6] = tg;
+        geo[7] = 0.0f;
+        tr_reduce_scatter8(geo, lane);
+        if ((lane & 7) == 0 && lane < 56 && geo[0] != 0.0f)
+            unsafeAtomicAdd(A.gacc + (size_t)(rg.x + k) * 8 + (lane >> 3), geo[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// hhat from the per-Gaussian weight totals, the channel-mean gradient term
+// and the channel part of the loss.
+// ---------------------------------------------------------------------------
+// hs[s][c] += sum over a chunk of the live list of Wtot_g v(g, c)
+__global__ __launch_bounds__(256) void k_train_hsum(const uint32_t* __restrict__ live, const uint32_t* __restrict__ count,
+                                                    const float* __restrict__ wtot, const float* __restrict__ attr,
+                                                    int64_t a_stride, int Fc, float* __restrict__ hs)
+{
+    const int s = blockIdx.y;
+    const uint32_t nl = *count;
+    const uint32_t lo = blockIdx.x * 1024u;
+    if (lo >= nl) return;
+    const uint32_t hi = min(nl, lo + 1024u);
+    const float* a = attr + s * a_stride;
+    for (int c = threadIdx.x; c < Fc; c += blockDim.x) {
+        float acc = 0.0f;
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t g = live[i];
+            acc = fmaf(wtot[g], a[(size_t)g * Fc + c], acc);
+        }
+        unsafeAtomicAdd(&hs[(size_t)s * Fc + c], acc);
+    }
+}
+
+// h_hat = hs / HW; m = lambda 2 (h_hat - h) / (HW S); loss[s] = lambda sum_c
+// (h_hat - h)^2 (the pixel term is added by k_train_loss_add)
+__global__ __launch_bounds__(256) void k_train_hfinish(const float* __restrict__ hs, const float* __restrict__ h,
+                                                       int S, int Fc, float inv_hw, float lambda,
+                                                       float* __restrict__ h_hat, float* __restrict__ mgrad,
+                                                       float* __restrict__ loss)
+{
+    const int s = blockIdx.x;
+    float part = 0.0f;
+    for (int c = threadIdx.x; c < Fc; c += blockDim.x) {
+        const size_t i = (size_t)s * Fc + c;
+        const float hh = hs[i] * inv_hw;
+        const float d = hh - h[i];
+        h_hat[i] = hh;
+        mgrad[i] = lambda * 2.0f * d * inv_hw / (float)S;
+        part = fmaf(d, d, part);
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[s] = lambda * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// loss[s] += lscale * sum over units of the squared-error partials
+__global__ __launch_bounds__(256) void k_train_loss_add(const float* __restrict__ lpart, int nunits, int S,
+                                                        float lscale, float* __restrict__ loss)
+{
+    const int s = blockIdx.x;
+    float v = 0.0f;
+    for (int u = threadIdx.x; u < nunits; u += blockDim.x) v += lpart[(size_t)u * S + s];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[s] += lscale * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// Eq. (2): h[s][c] = (1/HW) sum_p z(s, c, p); one workgroup per (set,
+// channel), both components of a complex channel (summed in FP32 per thread,
+// then over the workgroup; deterministic)
+__global__ __launch_bounds__(256) void k_spatial_mean(const float* __restrict__ z, int Fc, int C, size_t HW,
+                                                      float* __restrict__ h)
+{
+    const int s = blockIdx.y, f = blockIdx.x;
+    const int F = Fc / C;
+    const float* zb = z + ((size_t)s * F + f) * HW * C;
+    float a0 = 0.0f, a1 = 0.0f;
+    if (C == 2) {
+        const float2* z2 = (const float2*)zb;
+        for (size_t p = threadIdx.x; p < HW; p += blockDim.x) {
+            const float2 v = z2[p];
+            a0 += v.x;
+            a1 += v.y;
+        }
+    } else {
+        for (size_t p = threadIdx.x; p < HW; p += blockDim.x) a0 += zb[p];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+    }
+    __shared__ float red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a0;
+        red[1][threadIdx.x >> 6] = a1;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)C) {
+        const float t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        h[((size_t)s * F + f) * C + threadIdx.x] = t / (float)HW;
+    }
+}
+
+// column ranges per group: enough units to spread the groups over the chip
+int train_ranges(int ncb) { return ncb >= 32 ? 4 : (ncb >= 8 ? 2 : 1); }
+
+size_t train_scratch_floats(int groups, int R, int S, int Fc)
+{
+    // GV partials, squared-error partials (+ one slot per set for the
+    // long-walk path), hsum, mgrad
+    return align256((size_t)groups * R * TR_EMAX * TR_PIX * 4) / 4 + align256((size_t)(groups * R + 1) * S * 4) / 4 +
+           2 * (align256((size_t)S * Fc * 4) / 4);
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+gs_status gs_spatial_mean(const float* spectrum, int32_t n_sets, int32_t n_chan, int32_t is_complex, int32_t H,
+                          int32_t W, float* h, void* stream)
+{
+    if (!spectrum || !h || n_sets < 1 || n_chan < 1 || H < 1 || W < 1 || (is_complex != 0 && is_complex != 1))
+        return GS_ERR_INVALID_ARG;
+    if (n_chan > 65535 || n_sets > 65535) return GS_ERR_CAPACITY;
+    const int C = is_complex ? 2 : 1;
+    if (C == 2 && ((uintptr_t)spectrum & 7)) return GS_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_spatial_mean, dim3(n_chan, n_sets), dim3(256), 0, (hipStream_t)stream, spectrum, n_chan * C,
+                       C, (size_t)H * W, h);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries, int32_t n_sets,
+                          const gs_grid* grid, const gs_params* prm, const uint32_t* live_list,
+                          const uint32_t* live_count, const gs_train_target* tt, float* spectrum, float* d_mean,
+                          float* d_log_scale, float* d_quat, float* d_opacity_logit, float* d_attr, int32_t flags,
+                          void* workspace, size_t ws_bytes, void* scratch, size_t scratch_bytes, void* stream)
+{
+    if (!tt || !tt->target || !tt->target_mean || !tt->loss || !tt->h_hat || !(tt->lambda_ch >= 0.0f) ||
+        !live_list || !live_count || !d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !d_attr)
+        return GS_ERR_INVALID_ARG;
+    if (flags & ~(GS_BWD_ATTR_GRAD_ZEROED | GS_TRAIN_WRITE_SPECTRUM)) return GS_ERR_INVALID_ARG;
+    Layout L;
+    gs_status st = check_forward(scene, attrs, queries, grid, prm, spectrum, workspace, ws_bytes, &L);
+    if (st != GS_OK) return st;
+    if (prm->options & GS_OPT_FORWARD_ONLY) return GS_ERR_INVALID_ARG;
+    // one prepared receiver shared by every set (attenuation to the receiver)
+    if (queries->count != 1 || prm->atten_ref != 0 || n_sets < 1 || attrs->is_complex != 1) return GS_ERR_INVALID_ARG;
+    const int Fc = attrs->n_chan * 2;
+    if (Fc % 16 != 0) return GS_ERR_INVALID_ARG;
+    // (the long-walk backward addresses one set's spectrum with 32-bit offsets)
+    if ((uint64_t)Fc * L.H * L.W >= (1ull << 30)) return GS_ERR_CAPACITY;
+    if (n_sets > 1 && attrs->query_stride != 0 && attrs->query_stride < (int64_t)scene->n * Fc)
+        return GS_ERR_INVALID_ARG;
+    const int gpt = (L.tw * L.th) / TR_PIX;
+    const int groups = L.T * gpt;
+    const int ncb = n_sets * Fc / 16;
+    const int R = train_ranges(ncb);
+    if ((int64_t)groups * R > 0x7FFFFFFF / (TR_EMAX * TR_PIX) || groups > 0x7FFFFFFF / 4) return GS_ERR_CAPACITY;
+    const size_t need = train_scratch_floats(groups, R, n_sets, Fc) * 4;
+    if (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < need) return GS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    (void)hipGetLastError();
+
+    float* gvp = (float*)scratch;
+    float* lpart = gvp + align256((size_t)groups * R * TR_EMAX * TR_PIX * 4) / 4;
+    const int nunits = groups * R;
+    float* hs = lpart + align256((size_t)(nunits + 1) * n_sets * 4) / 4;
+    float* mg = hs + align256((size_t)n_sets * Fc * 4) / 4;
+    const size_t HW = (size_t)L.H * L.W;
+    const float escale = 2.0f / ((float)attrs->n_chan * (float)HW * (float)n_sets);
+    const float lscale = 1.0f / ((float)attrs->n_chan * (float)HW);
+
+    FillSegs fs{};
+    fs.p[0] = (uint32_t*)lpart;
+    fs.count[0] = (size_t)(nunits + 1) * n_sets;
+    fs.p[1] = (uint32_t*)hs;
+    fs.count[1] = (size_t)n_sets * Fc;
+    fs.p[2] = (uint32_t*)(ws + L.g2d);
+    fs.count[2] = (size_t)L.n * 8;
+    fs.n = 3;
+    if (!(flags & GS_BWD_ATTR_GRAD_ZEROED)) {
+        fs.p[3] = (uint32_t*)d_attr;
+        fs.count[3] = (size_t)(attrs->query_stride ? n_sets : 1) * scene->n * Fc;
+        fs.n = 4;
+    }
+    launch_fill_segs(fs, s);
+    launch_fill_dev((uint32_t*)(ws + L.gacc), (size_t)L.cap * 8, L.s_gacc / 4, L.nq,
+                    (const uint32_t*)(ws + L.flags) + FL_PUSED, L.s_flags / 4, 8u, s);
+    // hhat, the mean term of g and the channel part of the loss
+    hipLaunchKernelGGL(k_train_hsum, dim3((scene->n + 1023) / 1024, n_sets), dim3(128), 0, s, live_list, live_count,
+                       (const float*)(ws + L.wtot), attrs->data, attrs->query_stride, Fc, hs);
+    hipLaunchKernelGGL(k_train_hfinish, dim3(n_sets), dim3(256), 0, s, hs, tt->target_mean, n_sets, Fc,
+                       1.0f / (float)HW, tt->lambda_ch, tt->h_hat, mg, tt->loss);
+
+    TrArgs A{};
+    A.rec = (const GRec*)(ws + L.rec);
+    A.plist = (const uint32_t*)(ws + L.plist);
+    A.ranges = (const uint2*)(ws + L.ranges);
+    A.n_last = (const uint32_t*)(ws + L.n_last);
+    A.attr = attrs->data;
+    A.a_stride = attrs->query_stride;
+    A.tgt = tt->target;
+    A.mgrad = mg;
+    A.escale = escale;
+    A.out = (flags & GS_TRAIN_WRITE_SPECTRUM) ? spectrum : nullptr;
+    A.d_attr = d_attr;
+    A.da_stride = attrs->query_stride;
+    A.gvp = gvp;
+    A.lpart = lpart;
+    A.gacc = (float*)(ws + L.gacc);
+    A.S = n_sets;
+    A.Fc = Fc;
+    A.H = L.H;
+    A.W = L.W;
+    A.tw = L.tw;
+    A.th = L.th;
+    A.TX = L.TX;
+    A.gpt = gpt;
+    A.R = R;
+    A.amin = prm->alpha_min;
+    A.amax = prm->alpha_max;
+    void* tok;
+    timing_begin(TK_TRAIN, s, &tok);
+    // each group goes to the variant of the smallest walk bound that holds
+    // its walk (the others leave at once)
+    hipLaunchKernelGGL(k_train_fb<64>, dim3(groups, R), dim3(256), 0, s, A, 0);
+    hipLaunchKernelGGL(k_train_fb<128>, dim3(groups, R), dim3(256), 0, s, A, 64);
+    hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(groups, R), dim3(256), 0, s, A, 128);
+    hipLaunchKernelGGL(k_train_walk<64>, dim3(groups), dim3(256), 0, s, A, 0);
+    hipLaunchKernelGGL(k_train_walk<128>, dim3(groups), dim3(256), 0, s, A, 64);
+    hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(groups), dim3(256), 0, s, A, 128);
+    timing_end(tok, s);
+    // groups whose walk is longer than the fused kernels take: compositing
+    // into the spectrum, then the backward forming g from it and the target
+    launch_blend_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, TR_EMAX, s);
+    launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, d_attr, TR_EMAX,
+                             lpart + (size_t)nunits * n_sets, s);
+    hipLaunchKernelGGL(k_train_loss_add, dim3(n_sets), dim3(256), 0, s, lpart, nunits + 1, n_sets, lscale, tt->loss);
+    launch_geo_fold(L, ws, s);
+    launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+size_t gs_train_scratch_bytes(int32_t n_sets, int32_t n_chan, const gs_grid* grid)
+{
+    if (!grid || n_sets < 1 || n_chan < 1 || grid->H < 1 || grid->W < 1 || grid->tile_h < 1 || grid->tile_w < 1)
+        return 0;
+    const int TX = (grid->W + grid->tile_w - 1) / grid->tile_w, TY = (grid->H + grid->tile_h - 1) / grid->tile_h;
+    const int gpt = (grid->tile_w * grid->tile_h + TR_PIX - 1) / TR_PIX;
+    const int Fc = n_chan * 2;
+    const int R = train_ranges(n_sets * Fc / 16);
+    return train_scratch_floats(TX * TY * gpt, R, n_sets, Fc) * 4;
+}
+
+}  // extern "C"

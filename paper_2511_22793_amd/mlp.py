@@ -39,6 +39,10 @@ class AttributeNet:
         self.w = {k: torch.tensor(np.asarray(weights[k], np.float32), device=self.device) for k in WEIGHTS}
         self.bf = {k: torch.from_numpy(bf16_bits(weights[k]).view(np.int16)).to(self.device) for k in BF16_WEIGHTS}
         self.box_lo, self.box_hi, self.r_near = list(box_lo), list(box_hi), float(r_near)
+        # subcarriers: W3 has 2F rows (F amplitudes, F phases), F in {32, 64}
+        self.F = int(self.w["W3"].shape[0]) // 2
+        if self.F not in (32, 64) or tuple(self.w["W3"].shape) != (2 * self.F, HID):
+            raise ValueError("W3 must be [2F, 64] with F = 32 or 64")
 
     def c(self) -> GsMlp:
         m = GsMlp()
@@ -48,6 +52,7 @@ class AttributeNet:
         for k in range(3):
             m.box_lo[k], m.box_hi[k] = self.box_lo[k], self.box_hi[k]
         m.r_near = self.r_near
+        m.n_chan = self.F
         return m
 
 
@@ -71,7 +76,8 @@ class Rows:
 class State:
     """Scratch of the network calls for S sets and row_cap rows per set."""
 
-    def __init__(self, S: int, row_cap: int, training: bool = True, n_partial: int = 16, device="cuda"):
+    def __init__(self, S: int, row_cap: int, training: bool = True, n_partial: int = 16, device="cuda",
+                 n_chan: int = F):
         dev = torch.device(device)
         u16 = torch.int16
         self.cb = torch.empty(S, HID, device=dev)
@@ -80,7 +86,7 @@ class State:
         if training:
             self.h1 = torch.empty(S, row_cap, HID, dtype=u16, device=dev)
             self.h2 = torch.empty(S, row_cap, HID, dtype=u16, device=dev)
-            self.do = torch.empty(S, row_cap, 2 * F, dtype=u16, device=dev)
+            self.do = torch.empty(S, row_cap, 2 * n_chan, dtype=u16, device=dev)  # rows of 2F d_o values
             self.dz2 = torch.empty(S, row_cap, HID, dtype=u16, device=dev)
             self.dz1 = torch.empty(S, row_cap, HID, dtype=u16, device=dev)
             self.dc = torch.empty(S, HID, device=dev)
@@ -113,12 +119,12 @@ def embed(net: AttributeNet, E_bf: torch.Tensor, Z1: Optional[torch.Tensor] = No
 
 def forward(net: AttributeNet, Z1: torch.Tensor, mean: torch.Tensor, rows: Rows, attr: torch.Tensor,
             state: State) -> torch.Tensor:
-    """attr: [S, n, 64, 2] float32, written for the listed rows."""
+    """attr: [S, n, F, 2] float32, written for the listed rows."""
     n = mean.shape[1]
     m, r, s = net.c(), rows.c(), state.c()
     if not state.training:
         s.save_h1 = s.save_h2 = None
-    check(lib().gs_mlp_forward(ctypes.byref(m), _p(Z1), _p(mean), n, ctypes.byref(r), _p(attr), n * 2 * F,
+    check(lib().gs_mlp_forward(ctypes.byref(m), _p(Z1), _p(mean), n, ctypes.byref(r), _p(attr), n * 2 * net.F,
                                ctypes.byref(s), _stream(mean.device)), "gs_mlp_forward")
     return attr
 
@@ -130,12 +136,12 @@ def backward(net: AttributeNet, E_bf: torch.Tensor, mean: torch.Tensor, rows: Ro
     if grads is None:
         grads = {"W1": torch.empty(HID, IN_PAD, device=dev), "b1": torch.empty(HID, device=dev),
                  "W2": torch.empty(HID, HID, device=dev), "b2": torch.empty(HID, device=dev),
-                 "W3": torch.empty(2 * F, HID, device=dev), "b3": torch.empty(2 * F, device=dev),
+                 "W3": torch.empty(2 * net.F, HID, device=dev), "b3": torch.empty(2 * net.F, device=dev),
                  "E": torch.empty(n, EMB, device=dev)}
     g = GsMlpGrads(_p(grads["W1"]), _p(grads["b1"]), _p(grads["W2"]), _p(grads["b2"]), _p(grads["W3"]),
                    _p(grads["b3"]), _p(grads["E"]))
     m, r, s = net.c(), rows.c(), state.c()
-    check(lib().gs_mlp_backward(ctypes.byref(m), _p(E_bf), _p(mean), n, ctypes.byref(r), _p(d_attr), n * 2 * F,
+    check(lib().gs_mlp_backward(ctypes.byref(m), _p(E_bf), _p(mean), n, ctypes.byref(r), _p(d_attr), n * 2 * net.F,
                                 int(clear_d_attr), ctypes.byref(s), ctypes.byref(g), _stream(dev)),
           "gs_mlp_backward")
     return grads
@@ -156,7 +162,17 @@ def adam_step(segments, step: int, beta1=0.9, beta2=0.999, eps=1e-15, skip_if=No
           "gs_adam_step")
 
 
-def mfma_probe(A_bits: torch.Tensor, B_bits: torch.Tensor) -> torch.Tensor:
-    C = torch.empty(16, 16, device=A_bits.device)
-    check(lib().gs_mfma_probe(_p(A_bits), _p(B_bits), _p(C), _stream(A_bits.device)), "gs_mfma_probe")
-    return C
+def adam_step_scheduled(segments, lr_final, total_steps: int, step_counter: torch.Tensor, beta1=0.9, beta2=0.999,
+                        eps=1e-15, skip_if=None, skip_count: Optional[torch.Tensor] = None):
+    """adam_step() with the step number read from (and advanced in)
+    step_counter (int32 device tensor of completed steps) and rate k decaying
+    log-linearly from segments[k] lr to lr_final[k] over total_steps, on the
+    device (capturable)."""
+    arr = (GsAdamSegment * len(segments))()
+    dev = segments[0][0].device
+    for k, (p, g, m, v, sh, lr) in enumerate(segments):
+        arr[k] = GsAdamSegment(_p(p), _p(g), _p(m), _p(v), _p(sh), p.numel(), float(lr))
+    fin = (ctypes.c_float * len(segments))(*[float(x) for x in lr_final])
+    check(lib().gs_adam_step_scheduled(arr, fin, len(segments), int(total_steps), _p(step_counter), beta1, beta2,
+                                       eps, None if skip_if is None else ctypes.c_void_p(skip_if), _p(skip_count),
+                                       _stream(dev)), "gs_adam_step_scheduled")

@@ -16,7 +16,8 @@ from typing import Optional
 
 import torch
 
-from ._lib import GS_OPT_BLEND_PER_GROUP, GS_OPT_BWD_PER_GROUP, GS_OPT_FORWARD_ONLY, GsAttrs, GsL2Grad, GsFlags, GsGrid, GsLayout, GsParams, GsQueries, GsScene, check, lib
+from ._lib import (GS_OPT_BLEND_PER_GROUP, GS_OPT_BWD_PER_GROUP, GS_OPT_FORWARD_ONLY, GS_TRAIN_WRITE_SPECTRUM, GsAttrs,
+                   GsFlags, GsGrid, GsL2Grad, GsLayout, GsParams, GsQueries, GsScene, GsTrainTarget, check, lib)
 
 DEFAULT_VIEW = (0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0)
 
@@ -110,6 +111,14 @@ class Workspace:
         check(lib().gs_overflow_word(ctypes.c_void_p(self.ptr), self.nbytes, self.n, self.nq, ctypes.byref(g),
                                      ctypes.byref(p), q, ctypes.byref(w)), "gs_overflow_word")
         return w.value
+
+    def check(self, stream=None) -> int:
+        """gs_check: synchronises; GS_OK, GS_ERR_CAPACITY (a pair buffer
+        overflowed) or GS_ERR_NONFINITE (invalid Gaussians were dropped)."""
+        g, p = self.grid.c(), self.params.c()
+        st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        return int(lib().gs_check(ctypes.c_void_p(self.ptr), self.nbytes, self.n, self.nq, ctypes.byref(g),
+                                  ctypes.byref(p), ctypes.c_void_p(st)))
 
     def flags(self, stream=None):
         out = (GsFlags * self.nq)()
@@ -402,3 +411,102 @@ def loss_stats(spectrum: torch.Tensor, target: torch.Tensor, is_complex: bool, l
                                        _ptr(loss), _ptr(hhat), _ptr(mgrad), _ptr(partial), ctypes.c_void_p(base + off),
                                        scratch.numel() - off, ctypes.c_void_p(stream)), "gs_loss_spectrum_stats")
     return loss, hhat, mgrad, 2.0 / (F * H * W * B)
+
+
+def spatial_mean(spectrum: torch.Tensor, is_complex: bool, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Eq. (2): the coherent spatial mean of each channel, [B,F(,2)]."""
+    _check_f32("spectrum", spectrum)
+    B, F, H, W = spectrum.shape[:4]
+    shape = (B, F, 2) if is_complex else (B, F)
+    if out is None:
+        out = torch.empty(shape, device=spectrum.device)
+    else:
+        _check_f32("out", out, shape)
+    stream = torch.cuda.current_stream(spectrum.device).cuda_stream
+    check(lib().gs_spatial_mean(_ptr(spectrum), B, F, int(is_complex), H, W, _ptr(out), ctypes.c_void_p(stream)),
+          "gs_spatial_mean")
+    return out
+
+
+class TrainScratch:
+    """Caller-owned scratch of train_pass() for (n_sets, F, grid)."""
+
+    def __init__(self, n_sets: int, n_chan: int, grid: Grid, device=None):
+        g = grid.c()
+        self.key = (n_sets, n_chan, grid)
+        self.nbytes = int(lib().gs_train_scratch_bytes(n_sets, n_chan, ctypes.byref(g)))
+        if self.nbytes == 0:
+            raise ValueError("no training scratch size for these shapes")
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+        base = self.buf.data_ptr()
+        self.ptr = base + (-base) % 256
+
+
+def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.Tensor, live_list: torch.Tensor,
+               live_count: torch.Tensor, target: torch.Tensor, target_mean: torch.Tensor, lambda_ch: float = 1.0,
+               spectrum: Optional[torch.Tensor] = None, write_spectrum: bool = False,
+               d_attr: Optional[torch.Tensor] = None, out: Optional[dict] = None,
+               scratch: Optional[TrainScratch] = None, loss: Optional[torch.Tensor] = None,
+               h_hat: Optional[torch.Tensor] = None):
+    """Fused compositing + loss + backward over S complex attribute sets
+    sharing the workspace's one prepared receiver (gs_render_train), after
+    live().  attr [S,n,F,2]; target [S,F,H,W,2]; target_mean [S,F,2]
+    (spatial_mean of the target).  Returns (loss [S], h_hat [S,F,2],
+    gradients dict, spectrum)."""
+    sc = _scene_c(scene)
+    n = sc.n
+    if attr.dim() != 4:
+        raise ValueError("attr must be [S, n, F, 2]")
+    S = attr.shape[0]
+    a = _attrs_c(attr, n, S, True)
+    F, H, W = a.n_chan, workspace.grid.H, workspace.grid.W
+    dev = attr.device
+    shape = (S, F, H, W, 2)
+    _check_f32("target", target, shape)
+    _check_f32("target_mean", target_mean, (S, F, 2))
+    if spectrum is None:
+        spectrum = torch.empty(shape, device=dev)
+    else:
+        _check_f32("spectrum", spectrum, shape)
+    if scratch is None or scratch.key != (S, F, workspace.grid):
+        scratch = TrainScratch(S, F, workspace.grid, device=dev)
+    loss = torch.empty(S, device=dev) if loss is None else loss
+    h_hat = torch.empty(S, F, 2, device=dev) if h_hat is None else h_hat
+    g = out if out is not None else {
+        "d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+        "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+    flags = (1 if d_attr is not None else 0) | (GS_TRAIN_WRITE_SPECTRUM if write_spectrum else 0)
+    g["d_attr"] = d_attr if d_attr is not None else torch.empty_like(attr)
+    tt = GsTrainTarget(_ptr(target), _ptr(target_mean), float(lambda_ch), _ptr(loss), _ptr(h_hat))
+    q = GsQueries(1, _ptr(rx), None)
+    gr, p = workspace.grid.c(), workspace.params.c()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_render_train(ctypes.byref(sc), ctypes.byref(a), ctypes.byref(q), S, ctypes.byref(gr),
+                                ctypes.byref(p), _ptr(live_list), _ptr(live_count), ctypes.byref(tt),
+                                _ptr(spectrum), _ptr(g["d_mean"]), _ptr(g["d_log_scale"]), _ptr(g["d_quat"]),
+                                _ptr(g["d_opacity_logit"]), _ptr(g["d_attr"]), flags,
+                                ctypes.c_void_p(workspace.ptr), workspace.nbytes, ctypes.c_void_p(scratch.ptr),
+                                scratch.nbytes, ctypes.c_void_p(stream)), "gs_render_train")
+    return loss, h_hat, g, spectrum
+
+
+def loss_l1_ssim(spectrum: torch.Tensor, target: torch.Tensor, lambda_1: float = 0.2, grad: bool = True):
+    """Eq. (5) on real spectra [S,F,H,W]: returns (loss [S], ssim [S], l1 [S],
+    dL/dspectrum of the mean over sets, or None)."""
+    _check_f32("spectrum", spectrum)
+    _check_f32("target", target, tuple(spectrum.shape))
+    if spectrum.dim() != 4:
+        raise ValueError("spectrum must be [S, F, H, W] (real)")
+    S, F, H, W = spectrum.shape
+    dev = spectrum.device
+    loss, ssim, l1 = (torch.empty(S, device=dev) for _ in range(3))
+    d = torch.empty_like(spectrum) if grad else None
+    nbytes = int(lib().gs_loss_l1_ssim_scratch_bytes(S, F, H, W))
+    scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().gs_loss_l1_ssim(_ptr(spectrum), _ptr(target), S, F, H, W, float(lambda_1), _ptr(loss), _ptr(ssim),
+                                _ptr(l1), _ptr(d), ctypes.c_void_p(base + off), nbytes, ctypes.c_void_p(stream)),
+          "gs_loss_l1_ssim")
+    return loss, ssim, l1, d

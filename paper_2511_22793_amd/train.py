@@ -3,26 +3,26 @@ shared attribute network, a fixed receiver and a batch of transmitters).
 
 One step, all on the device with no host synchronisation:
   prepare (projection, depth sort, tile binning) for the receiver
-  live pass: Gaussians that reach some pixel
+  live pass: Gaussians that reach some pixel (and their weight sums)
   network forward for (transmitter, live Gaussian) rows -> attributes
-  blend of the batch's attribute sets over the shared geometry -> spectra
-  loss (spectrum L2 + Eq. (4) on the Eq. (2) mean) -> dL/dspectrum
+  the fused training pass over the shared geometry: blend of the batch's
+  attribute sets, loss (spectrum L2 + Eq. (4) on the Eq. (2) mean) and the
   blend + projection backward -> Gaussian-parameter and attribute gradients
+  (other loss modes run blend, loss and backward as separate passes)
   network backward -> weight, bias and embedding gradients
   fused Adam over every parameter group (Table 2 learning rates; the
   position rate decays exponentially)
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass
 
 import numpy as np
 import torch
 
 from . import mlp as gm
-from .render import (Grid, Params, Workspace, backward, backward_l2, blend, blend_loss, live, loss_spectrum,
-                     loss_stats, prepare)
+from .render import (Grid, Params, TrainScratch, Workspace, backward, backward_l2, blend, blend_loss, live,
+                     loss_spectrum, loss_stats, prepare, spatial_mean, train_pass)
 
 F = gm.F
 
@@ -38,16 +38,16 @@ class Rates:
     embedding: float = 0.005
 
 
-def init_weights(seed: int = 0) -> dict:
+def init_weights(seed: int = 0, n_chan: int = F) -> dict:
     """He-normal initial weights in [out, in] layout (W1 [64, 96] with zero
-    columns beyond the 83 inputs), zero biases."""
+    columns beyond the 83 inputs, W3 [2 n_chan, 64]), zero biases."""
     rng = np.random.default_rng(seed)
     fan1 = gm.EMB + gm.ENC
     W1 = np.zeros((gm.HID, gm.IN_PAD))
     W1[:, :fan1] = rng.normal(0, np.sqrt(2.0 / fan1), size=(gm.HID, fan1))
     return {"W1": W1, "b1": np.zeros(gm.HID),
             "W2": rng.normal(0, np.sqrt(2.0 / gm.HID), size=(gm.HID, gm.HID)), "b2": np.zeros(gm.HID),
-            "W3": rng.normal(0, np.sqrt(2.0 / gm.HID), size=(2 * F, gm.HID)), "b3": np.zeros(2 * F)}
+            "W3": rng.normal(0, np.sqrt(2.0 / gm.HID), size=(2 * n_chan, gm.HID)), "b3": np.zeros(2 * n_chan)}
 
 
 class LearnedScene:
@@ -56,28 +56,36 @@ class LearnedScene:
 
     def __init__(self, scene: dict, embeddings: np.ndarray, weights: dict, rx, batch: int, box_lo, box_hi,
                  grid: Grid = Grid(), params: Params = Params(), rates: Rates = Rates(), total_steps: int = 1000,
-                 train_geometry: bool = True, lambda_ch: float = 1.0, loss_mode: str = "partial", device="cuda"):
+                 train_geometry: bool = True, lambda_ch: float = 1.0, loss_mode: str = "train_pass",
+                 keep_spectra: bool = False, device="cuda"):
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
-        if loss_mode not in ("fused", "partial", "target", "two_pass"):
-            raise ValueError("loss_mode is 'fused', 'partial', 'target' or 'two_pass'")
+        if loss_mode not in ("train_pass", "fused", "partial", "target", "two_pass"):
+            raise ValueError("loss_mode is 'train_pass', 'fused', 'partial', 'target' or 'two_pass'")
         self.loss_mode = loss_mode
+        # train_pass: also store the step's spectra in self.spec (the other
+        # modes always do)
+        self.keep_spectra = keep_spectra
         self.n = n = scene["opacity_logit"].shape[0]
         self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
         self.E = torch.tensor(np.asarray(embeddings, np.float32), device=dev)
         self.E_bf = torch.from_numpy(gm.bf16_bits(embeddings).view(np.int16)).to(dev)
         self.net = gm.AttributeNet(weights, box_lo, box_hi, params.r_near, device=dev)
+        self.F = F = self.net.F
         self.rx = torch.tensor(np.asarray(rx, np.float32).reshape(1, 3), device=dev)
         self.ws = Workspace(n, 1, grid, params, device=dev)
         # attribute rows never written stay zero (the blend multiplies them by 0)
         self.attr = torch.zeros(batch, n, F, 2, device=dev)
         self.d_attr = torch.zeros(batch, n, F, 2, device=dev)
         self.spec = torch.empty(batch, F, grid.H, grid.W, 2, device=dev)
-        self.dpart = torch.empty_like(self.spec)
+        self.dpart = torch.empty_like(self.spec) if loss_mode in ("partial", "fused") else None
+        self.loss = torch.empty(batch, device=dev)
+        self.h_hat = torch.empty(batch, F, 2, device=dev)
+        self.tscratch = TrainScratch(batch, F, grid, device=dev) if loss_mode == "train_pass" else None
         self.live_list = torch.empty(1, n, dtype=torch.int32, device=dev)
         self.live_count = torch.empty(1, dtype=torch.int32, device=dev)
-        self.state = gm.State(batch, n, training=True, device=dev)
+        self.state = gm.State(batch, n, training=True, device=dev, n_chan=F)
         self.Z1 = torch.empty(n, gm.HID, device=dev)
         self.ggrads = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
                        "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
@@ -87,6 +95,9 @@ class LearnedScene:
         # steps whose pair buffer overflowed: their spectra and gradients are
         # undefined, so Adam skips them (guarded on the device) and counts them
         self.skipped = torch.zeros(1, dtype=torch.int32, device=dev)
+        # completed steps, on the device: Adam reads its step number and the
+        # position rate's schedule from it (so a captured step replays)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def _rows(self, tx):
         return gm.Rows(tx, self.live_list[0], self.live_count, row_cap=self.n)
@@ -106,15 +117,13 @@ class LearnedScene:
             self.moments[key] = (torch.zeros_like(like), torch.zeros_like(like))
         return self.moments[key]
 
-    def position_lr(self):
-        t = min(self.step_count / max(self.total_steps - 1, 1), 1.0)
-        r = self.rates
-        return math.exp((1 - t) * math.log(r.position) + t * math.log(r.position_final))
-
-    def train_step(self, tx: torch.Tensor, target: torch.Tensor, marks=None) -> torch.Tensor:
+    def train_step(self, tx: torch.Tensor, target: torch.Tensor, marks=None,
+                   target_mean: torch.Tensor = None) -> torch.Tensor:
         """One step on transmitters tx [B,3] with target spectra [B,F,H,W,2];
         returns the per-set losses (device tensor, before the update).
-        marks: optional callable(name) invoked between stages (timing)."""
+        marks: optional callable(name) invoked between stages (timing).
+        target_mean: the targets' channels (Eq. (2) of each target, [B,F,2]),
+        a property of the training samples; formed here when not given."""
         mark = marks or (lambda name: None)
         sc = self.g
         mark("start")
@@ -125,7 +134,17 @@ class LearnedScene:
         gm.embed(self.net, self.E_bf, self.Z1)
         gm.forward(self.net, self.Z1, sc["mean"], self._rows(tx), self.attr, self.state)
         mark("mlp_fwd")
-        if self.loss_mode == "fused":
+        if self.loss_mode == "train_pass":
+            # compositing, loss and backward in one fused pass (no spectra
+            # or spectrum gradients in memory)
+            if target_mean is None:
+                target_mean = spatial_mean(target, True)
+            loss, _, _, _ = train_pass(self.ws, sc, self.attr, self.rx, self.live_list[0], self.live_count, target,
+                                       target_mean, self.lambda_ch, spectrum=self.spec,
+                                       write_spectrum=self.keep_spectra, d_attr=self.d_attr, out=self.ggrads,
+                                       scratch=self.tscratch, loss=self.loss, h_hat=self.h_hat)
+            mark("train_pass")
+        elif self.loss_mode == "fused":
             # the loss pass folded into the compositing kernel's output stage:
             # loss, channel means and the elementwise gradient part written
             # as the spectrum is written; the backward adds the channel-mean
@@ -158,25 +177,30 @@ class LearnedScene:
                 mark("loss")
                 backward(self.ws, sc, self.attr, self.rx, spec, dspec, is_complex=True, n_sets=self.B,
                          d_attr=self.d_attr, out=self.ggrads)
-        mark("render_bwd")
+        if self.loss_mode != "train_pass":
+            mark("render_bwd")
         self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
                                   self.mgrads, clear_d_attr=True)
         mark("mlp_bwd")
         self.step_count += 1
         r = self.rates
-        segs = []
+        segs, final = [], []
         for k, lr, sh in (("W1", r.mlp, self.net.bf["W1"]), ("b1", r.mlp, None), ("W2", r.mlp, self.net.bf["W2"]),
                           ("b2", r.mlp, None), ("W3", r.mlp, self.net.bf["W3"]), ("b3", r.mlp, None)):
             m, v = self._moment(k, self.net.w[k])
             segs.append((self.net.w[k], self.mgrads[k], m, v, sh, lr))
+            final.append(lr)
         m, v = self._moment("E", self.E)
         segs.append((self.E, self.mgrads["E"], m, v, self.E_bf, r.embedding))
+        final.append(r.embedding)
         if self.train_geometry:
-            for k, lr in (("mean", self.position_lr()), ("log_scale", r.scaling), ("quat", r.rotation),
-                          ("opacity_logit", r.opacity)):
+            for k, lr, lr1 in (("mean", r.position, r.position_final), ("log_scale", r.scaling, r.scaling),
+                               ("quat", r.rotation, r.rotation), ("opacity_logit", r.opacity, r.opacity)):
                 m, v = self._moment(k, sc[k])
                 segs.append((sc[k], self.ggrads["d_" + k], m, v, None, lr))
-        gm.adam_step(segs, self.step_count, skip_if=self.ws.overflow_word(0), skip_count=self.skipped)
+                final.append(lr1)
+        gm.adam_step_scheduled(segs, final, self.total_steps, self.step_dev, skip_if=self.ws.overflow_word(0),
+                               skip_count=self.skipped)
         mark("adam")
         return loss
 

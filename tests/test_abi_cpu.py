@@ -143,7 +143,8 @@ def test_kernel_timing_api_on_host():
     assert L.gs_timing_enable(0) == _lib.GS_OK
     assert L.gs_timing_read(0, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_OK and cnt.value == 0
     assert L.gs_timing_read(1, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_OK and tot.value == 0.0
-    assert L.gs_timing_read(2, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_ERR_INVALID_ARG
+    assert L.gs_timing_read(2, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_OK and cnt.value == 0
+    assert L.gs_timing_read(3, ctypes.byref(tot), ctypes.byref(cnt)) == _lib.GS_ERR_INVALID_ARG
     assert L.gs_timing_read(0, None, ctypes.byref(cnt)) == _lib.GS_ERR_INVALID_ARG
 
 
@@ -153,3 +154,65 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def _train(sc, at, q, S, g, p, tt, flags=0, ws_bytes=None, scratch_bytes=None):
+    L = _lib.lib()
+    out = GsLayout()
+    assert L.gs_workspace_layout(sc.n, q.count, ctypes.byref(g), ctypes.byref(p), ctypes.byref(out)) == 0
+    ws_bytes = out.total if ws_bytes is None else ws_bytes
+    need = L.gs_train_scratch_bytes(S, at.n_chan, ctypes.byref(g))
+    scratch_bytes = need if scratch_bytes is None else scratch_bytes
+    return L.gs_render_train(ctypes.byref(sc), ctypes.byref(at), ctypes.byref(q), S, ctypes.byref(g),
+                             ctypes.byref(p), FAKE, FAKE, tt, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, flags,
+                             ctypes.c_void_p(0x100000), ws_bytes, ctypes.c_void_p(0x200000), scratch_bytes, None)
+
+
+def test_train_pass_rejects_bad_arguments_on_host():
+    sc = GsScene(100, FAKE, FAKE, FAKE, FAKE)
+    q = GsQueries(1, FAKE, None)
+    g, p = grid(), params()
+    at = GsAttrs(8, 1, FAKE, 100 * 16)
+    tt = ctypes.byref(_lib.GsTrainTarget(FAKE, FAKE, 1.0, FAKE, FAKE))
+    L = _lib.lib()
+    # scratch size: GV partials per (64-pixel group, column range) dominate
+    need = L.gs_train_scratch_bytes(4, 8, ctypes.byref(g))
+    assert need >= 138 * 4 * 64 * 64 * 4 and need % 256 == 0
+    assert L.gs_train_scratch_bytes(0, 8, ctypes.byref(g)) == 0
+    assert _train(sc, at, q, 4, g, p, None) == _lib.GS_ERR_INVALID_ARG
+    assert _train(sc, GsAttrs(8, 0, FAKE, 800), q, 4, g, p, tt) == _lib.GS_ERR_INVALID_ARG      # real attributes
+    assert _train(sc, GsAttrs(4, 1, FAKE, 800), q, 4, g, p, tt) == _lib.GS_ERR_INVALID_ARG      # 2F not 16k
+    assert _train(sc, at, GsQueries(2, FAKE, None), 4, g, p, tt) == _lib.GS_ERR_INVALID_ARG     # two receivers
+    assert _train(sc, at, q, 4, g, params(atten_ref=1), tt) == _lib.GS_ERR_INVALID_ARG
+    assert _train(sc, at, q, 4, g, params(options=_lib.GS_OPT_FORWARD_ONLY), tt) == _lib.GS_ERR_INVALID_ARG
+    assert _train(sc, at, q, 4, g, p, tt, flags=8) == _lib.GS_ERR_INVALID_ARG
+    bad_tt = ctypes.byref(_lib.GsTrainTarget(FAKE, None, 1.0, FAKE, FAKE))
+    assert _train(sc, at, q, 4, g, p, bad_tt) == _lib.GS_ERR_INVALID_ARG
+    assert _train(sc, at, q, 4, g, p, tt, scratch_bytes=need - 1) == _lib.GS_ERR_WORKSPACE
+    assert _train(sc, at, q, 4, g, p, tt, ws_bytes=100) == _lib.GS_ERR_WORKSPACE
+
+
+def test_spatial_mean_rejects_bad_arguments_on_host():
+    L = _lib.lib()
+    assert L.gs_spatial_mean(None, 1, 1, 0, 4, 4, FAKE, None) == _lib.GS_ERR_INVALID_ARG
+    assert L.gs_spatial_mean(FAKE, 1, 0, 0, 4, 4, FAKE, None) == _lib.GS_ERR_INVALID_ARG
+    assert L.gs_spatial_mean(ctypes.c_void_p(0x10004), 1, 1, 1, 4, 4, FAKE, None) == _lib.GS_ERR_INVALID_ARG
+    assert L.gs_spatial_mean(FAKE, 1, 70000, 0, 4, 4, FAKE, None) == _lib.GS_ERR_CAPACITY
+
+
+def test_l1_ssim_rejects_bad_arguments_on_host():
+    L = _lib.lib()
+    need = L.gs_loss_l1_ssim_scratch_bytes(2, 3, 90, 360)
+    assert need == 2 * 3 * 12 * 6 * 2 * 4 + (-(2 * 3 * 12 * 6 * 2 * 4) % 256)
+    args = lambda **kw: dict(dict(sp=FAKE, tg=FAKE, S=2, F=3, H=90, W=360, lam=0.2, sc=ctypes.c_void_p(0x100000),
+                                  nb=need), **kw)
+
+    def call(a):
+        return L.gs_loss_l1_ssim(a["sp"], a["tg"], a["S"], a["F"], a["H"], a["W"], a["lam"], FAKE, None, None, None,
+                                 a["sc"], a["nb"], None)
+    assert call(args(sp=None)) == _lib.GS_ERR_INVALID_ARG
+    assert call(args(lam=1.5)) == _lib.GS_ERR_INVALID_ARG
+    assert call(args(H=0)) == _lib.GS_ERR_INVALID_ARG
+    assert call(args(nb=need - 1)) == _lib.GS_ERR_WORKSPACE
+    assert call(args(sc=ctypes.c_void_p(0x100010))) == _lib.GS_ERR_WORKSPACE
+    assert call(args(S=300, F=300)) == _lib.GS_ERR_CAPACITY

@@ -162,6 +162,7 @@ def test_empty_scene_and_invalid_inputs_render_zero():
     sc["opacity_logit"][:] = -30.0
     got, ws = gpu_forward(sc, synth.rss_attrs(n), np.zeros((1, 3), np.float32))
     assert np.all(got == 0) and ws.flags()[0]["n_visible"] == 0
+    assert ws.check() == gs._lib.GS_OK
     sc = synth.scene(n, seed=62)
     sc["mean"][0, :50] = np.nan
     sc["quat"][:, 50:60] = 0.0
@@ -169,6 +170,7 @@ def test_empty_scene_and_invalid_inputs_render_zero():
     attr = synth.rss_attrs(n, seed=63)
     got, ws = gpu_forward(sc, attr, np.zeros((1, 3), np.float32))
     assert ws.flags()[0]["n_invalid"] == 70
+    assert ws.check() == gs._lib.GS_ERR_NONFINITE
     assert np.all(np.isfinite(got))
     ref = oracle.render(sc, attr, [0, 0, 0], 90, 360)
     check_parity(got[0], ref, "invalid")
@@ -181,6 +183,7 @@ def test_pair_capacity_overflow_is_flagged_not_faulted():
     got, ws = gpu_forward(sc, synth.rss_attrs(n), np.zeros((1, 3), np.float32), prm=prm)
     f = ws.flags()[0]
     assert f["overflow"] == 1 and f["n_pairs"] > 1000
+    assert ws.check() == gs._lib.GS_ERR_CAPACITY
     assert np.all(np.isfinite(got))
 
 

@@ -51,21 +51,33 @@ def check_codes(gpu, ref_pre, label, max_frac=0.01, scale=None):
 
 
 def test_mfma_operand_layout_probe():
+    # the operand layout the network kernels assume, checked by a test-only
+    # probe library (tests/probe) on small integers (exact in BF16 and FP32)
+    import ctypes
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "probe", "libgsprobe.so")
+    probe = ctypes.CDLL(path)
+    probe.probe_mfma_bf16.restype = ctypes.c_int
     rng = np.random.default_rng(0)
     A = rng.integers(-8, 9, size=(16, 32)).astype(np.float32)
     B = rng.integers(-8, 9, size=(32, 16)).astype(np.float32)
     Ab = torch.from_numpy(gm.bf16_bits(A).view(np.int16)).cuda()
     Bb = torch.from_numpy(gm.bf16_bits(B).view(np.int16)).cuda()
-    C = gm.mfma_probe(Ab, Bb).cpu().numpy()
-    assert np.array_equal(C, A @ B)
+    C = torch.empty(16, 16, device="cuda")
+    torch.cuda.synchronize()
+    assert probe.probe_mfma_bf16(ctypes.c_void_p(Ab.data_ptr()), ctypes.c_void_p(Bb.data_ptr()),
+                                 ctypes.c_void_p(C.data_ptr())) == 0
+    assert np.array_equal(C.cpu().numpy(), A @ B)
 
 
-def setup(n=300, S=3, seed=0, shared=True):
+def setup(n=300, S=3, seed=0, shared=True, F=64):
     w = mlp_ref.init(seed)
     rng = np.random.default_rng(seed + 1)
     w["b1"] = rng.normal(0, 0.1, 64)
     w["b2"] = rng.normal(0, 0.1, 64)
-    w["b3"] = rng.normal(0, 0.3, 128)
+    w["b3"] = rng.normal(0, 0.3, 2 * F)
+    if F != 64:  # a network with F complex subcarriers: W3 [2F, 64]
+        w["W3"] = rng.normal(0, np.sqrt(2.0 / 64), size=(2 * F, 64))
     E = synth.embeddings(n, seed=seed + 2)
     sc = synth.scene(n, seed=seed + 3)
     tx = synth.points(S, seed=seed + 4)
@@ -86,18 +98,18 @@ def setup(n=300, S=3, seed=0, shared=True):
         L = torch.from_numpy(arr.view(np.int32)).cuda()
         cnt = torch.tensor([len(x) for x in lists], dtype=torch.int32).cuda()
     rows = gm.Rows(torch.from_numpy(tx).cuda(), L, cnt, row_cap=n // 2)
-    return dict(w=w, E=E, sc=sc, tx=tx, net=net, E_bf=E_bf, mean=mean, rows=rows, lists=lists, n=n, S=S)
+    return dict(w=w, E=E, sc=sc, tx=tx, net=net, E_bf=E_bf, mean=mean, rows=rows, lists=lists, n=n, S=S, F=F)
 
 
-@pytest.mark.parametrize("shared", [True, False])
-def test_forward_layers_reanchored_and_end_to_end(shared):
-    d = setup(shared=shared)
+@pytest.mark.parametrize("shared,F", [(True, 64), (False, 64), (True, 32)])
+def test_forward_layers_reanchored_and_end_to_end(shared, F):
+    d = setup(shared=shared, F=F)
     n, S = d["n"], d["S"]
     st = gm.State(S, n // 2)
     for t in (st.h1, st.h2):  # rows past a set's count are never written: keep them defined
         t.zero_()
     Z1 = gm.embed(d["net"], d["E_bf"])
-    attr = torch.zeros(S, n, 64, 2, device="cuda")
+    attr = torch.zeros(S, n, F, 2, device="cuda")
     gm.forward(d["net"], Z1, d["mean"], d["rows"], attr, st)
     torch.cuda.synchronize()
     w = d["w"]
@@ -107,7 +119,7 @@ def test_forward_layers_reanchored_and_end_to_end(shared):
     h1g, h2g = bits_to_f64(st.h1), bits_to_f64(st.h2)
     A = attr.cpu().numpy().astype(np.float64)
     full = mlp_ref.forward(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], d["E"], d["tx"], d["sc"]["mean"],
-                           0.2, LO, HI)
+                           0.2, LO, HI, F=F)
     for s in range(S):
         lst = d["lists"][s]
         m = len(lst)
@@ -118,8 +130,8 @@ def test_forward_layers_reanchored_and_end_to_end(shared):
         check_codes(h2g[s, :m], np.maximum(z2, 0.0), "h2")
         o = h2g[s, :m] @ W3r.T + w["b3"]
         dd = np.maximum(np.linalg.norm(d["sc"]["mean"][:, lst].T.astype(np.float64) - d["tx"][s].astype(np.float64), axis=1), 0.2)
-        amp = 1 / (1 + np.exp(-(o[:, :64] - np.log(dd)[:, None])))
-        ref = np.stack([amp * np.cos(o[:, 64:]), amp * np.sin(o[:, 64:])], -1)
+        amp = 1 / (1 + np.exp(-(o[:, :F] - np.log(dd)[:, None])))
+        ref = np.stack([amp * np.cos(o[:, F:]), amp * np.sin(o[:, F:])], -1)
         err = np.abs(A[s, lst] - ref) / np.maximum(amp[..., None], 1e-6)
         assert err.max() <= 2e-5, "attr re-anchored err %.3g" % err.max()
         # end to end against the unanchored oracle: BF16 flip bound
@@ -131,17 +143,18 @@ def test_forward_layers_reanchored_and_end_to_end(shared):
     assert np.all(A[0, mask] == 0)
 
 
-def test_backward_reanchored():
-    d = setup(n=256, S=3, seed=5)
+@pytest.mark.parametrize("F", [64, 32])
+def test_backward_reanchored(F):
+    d = setup(n=256, S=3, seed=5, F=F)
     n, S = d["n"], d["S"]
-    st = gm.State(S, n // 2, n_partial=8)
+    st = gm.State(S, n // 2, n_partial=8, n_chan=F)
     for t in (st.h1, st.h2, st.do, st.dz2, st.dz1):
         t.zero_()
     Z1 = gm.embed(d["net"], d["E_bf"])
-    attr = torch.zeros(S, n, 64, 2, device="cuda")
+    attr = torch.zeros(S, n, F, 2, device="cuda")
     gm.forward(d["net"], Z1, d["mean"], d["rows"], attr, st)
     rng = np.random.default_rng(9)
-    dA = rng.normal(size=(S, n, 64, 2)).astype(np.float32)
+    dA = rng.normal(size=(S, n, F, 2)).astype(np.float32)
     gr = gm.backward(d["net"], d["E_bf"], d["mean"], d["rows"], torch.from_numpy(dA).cuda(), st)
     torch.cuda.synchronize()
     w = d["w"]
@@ -158,8 +171,8 @@ def test_backward_reanchored():
     for s in range(S):
         o = h2g[s, :m] @ W3r.T + w["b3"]
         dd = np.maximum(np.linalg.norm(d["sc"]["mean"][:, lst].T.astype(np.float64) - d["tx"][s].astype(np.float64), axis=1), 0.2)
-        amp = 1 / (1 + np.exp(-(o[:, :64] - np.log(dd)[:, None])))
-        ph = o[:, 64:]
+        amp = 1 / (1 + np.exp(-(o[:, :F] - np.log(dd)[:, None])))
+        ph = o[:, F:]
         gre, gim = dA[s, lst, :, 0].astype(np.float64), dA[s, lst, :, 1].astype(np.float64)
         do = np.concatenate([(gre * np.cos(ph) + gim * np.sin(ph)) * amp * (1 - amp),
                              amp * (-gre * np.sin(ph) + gim * np.cos(ph))], 1)
@@ -195,10 +208,10 @@ def test_backward_reanchored():
     assert np.all(gr["W1"].cpu().numpy()[:, 83:] == 0)
     # end to end against the unanchored oracle (flip bound)
     full = mlp_ref.forward(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], d["E"], d["tx"], d["sc"]["mean"],
-                           0.2, LO, HI)
+                           0.2, LO, HI, F=F)
     dmask = np.zeros_like(dA, dtype=np.float64)
     dmask[:, lst] = dA[:, lst]
-    gfull = mlp_ref.backward(full, dmask)
+    gfull = mlp_ref.backward(full, dmask, F=F)
     for k in ("W1", "W2", "W3", "b3", "E"):
         want = gfull[k]
         got = gr[k].cpu().numpy()

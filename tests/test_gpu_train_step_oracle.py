@@ -64,7 +64,7 @@ def test_whole_training_step_matches_oracle_chain():
     tx = synth.points(B, seed=115)
     target = synth.normal((B, F, H, W, 2), 0.05, seed=116)
     total = 10
-    model = train.LearnedScene(sc, E, w, [0, 0, 0], B, LO, HI, total_steps=total)
+    model = train.LearnedScene(sc, E, w, [0, 0, 0], B, LO, HI, total_steps=total, keep_spectra=True)
     loss = model.train_step(torch.from_numpy(tx).cuda(), torch.from_numpy(target).cuda())
     torch.cuda.synchronize()
     assert model.ws.flags()[0]["overflow"] == 0
