@@ -359,14 +359,16 @@ gs_status gs_spatial_mean(const float* spectrum, int32_t n_sets, int32_t n_chan,
  *                weight sums: h_hat = (1/HW) sum_g (sum_p w_g(p)) v_g).
  * spectrum: [S][F][H][W][2], written in full with GS_TRAIN_WRITE_SPECTRUM
  *   (bit-identical to gs_render_blend()), else used only for the groups of
- *   64 pixels whose walk exceeds 64 list entries (those take the unfused
+ *   64 pixels whose walk exceeds 256 list entries (those take the unfused
  *   compositing and backward kernels inside this call).
  * Gradient outputs as for gs_render_backward() for L = (1/S) sum_b L_b
  * (d_attr cleared first unless GS_BWD_ATTR_GRAD_ZEROED).
  * scratch: >= gs_train_scratch_bytes(n_sets, F, grid) bytes, 256-byte
  *   aligned, caller-owned (GV partials, loss partials, the mean term).
  * Errors: GS_ERR_INVALID_ARG (null pointer, an unsupported shape above,
- * unknown flag bits), GS_ERR_WORKSPACE, GS_ERR_CAPACITY; nothing is enqueued
+ * unknown flag bits), GS_ERR_WORKSPACE, GS_ERR_CAPACITY (also when one set's
+ * attributes, n 2F floats, or one set's spectrum, 2F H W floats, reach 2^29:
+ * the kernels address them with 32-bit byte offsets); nothing is enqueued
  * on an argument error.  Float atomics make the last bits of the gradients
  * vary between runs.
  */

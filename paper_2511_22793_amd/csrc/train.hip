@@ -28,17 +28,26 @@
 //       (entry, column) of the unit;
 //   (G) g of all four blocks goes through LDS so that each wave adds GV for
 //       its 16 pixels over the round's 64 columns.
-// GV partials (per unit) go to memory; a second kernel sums the column
-// ranges of each group and walks the backward recurrence (Eq. (3)
+// Each unit adds its GV (its columns' share) into the group's accumulator; a
+// second kernel walks the backward recurrence per group (Eq. (3)
 // differentiated): the running prefix P_k = sum_{m<=k} w_m GV_m, dL/dalpha_k
 // = T_k a_k GV_k - (D - P_k) / (1 - alpha_k) with D = P_last, and the seven
 // geometric terms of each entry reduced over the group's pixels.
 // Both kernels come in variants for walks of at most 64, 128 and 256 list
-// entries (the weights of the whole walk stay in LDS); a group takes the
-// smallest that holds its walk.  Walks grow as training makes Gaussians
-// fainter.  Groups whose walk is longer than 256 entries are left to the
-// unfused kernels (compositing, then the backward forming g from the stored
-// spectrum and the target).
+// entries (the weights of the whole walk stay in LDS, so the wider variants
+// hold fewer workgroups per CU); a group takes the smallest that holds its
+// walk.  A classification kernel sorts the groups into those three classes
+// (and clears their GV rows); each variant then runs as a persistent grid of
+// the workgroups that fit the chip at once, taking units from its class's
+// list through an atomic counter.  The column split R of a class is chosen
+// on the device from its group count: enough units to fill that grid, so a
+// class of a few long walks is spread over many CUs instead of running as a
+// few long units.  Walks grow as training makes Gaussians fainter.  Groups
+// whose walk is longer than 256 entries are left to the unfused kernels
+// (compositing, then the backward forming g from the stored spectrum and the
+// target).
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -68,6 +77,8 @@ struct TrLds {
     double px[E], py[E], ca[E], cb[E], cc[E];
     float sig[E], att[E];
     uint32_t g[E];
+    uint32_t voff[E];      // float offset of the entry's attribute row (g Fc; entry 0's row past the walk)
+    uint32_t nzb[E / 16];  // per block of 16 entries: bit b set if one of them weighs at a pixel of block b
     int pix[TR_PIX];
     uint32_t maxstop;
 };
@@ -135,6 +146,22 @@ __device__ __forceinline__ void tr_alpha(const TrLds<E>& L, float (*s_a)[TR_PAD]
     }
 }
 
+// Raw buffer resource over `base` (32-bit byte offsets from it; no range
+// check): per-lane offsets then need one 32-bit add instead of 64-bit
+// address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tr_rsrc(const void* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7FFFFFFF, 0x00020000);
+}
+
+// One float at byte offset `off` of the buffer; offsets at or past 2^31 - 1
+// (beyond the resource's range) read 0.0f without touching memory.
+constexpr uint32_t TR_OOB = 0x80000000u;
+__device__ __forceinline__ float tr_ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 1: forward products, loss partial, attribute gradient, GV partials.
 // ---------------------------------------------------------------------------
@@ -151,12 +178,51 @@ struct TrArgs {
     float* out;          // spectrum, or null
     float* d_attr;
     int64_t da_stride;
-    float* gvp;          // GV partials [group][R][TR_EMAX][TR_PIX]
-    float* lpart;        // squared-error partials [group * R + r][S]
+    float* gv;           // GV accumulators [group][TR_EMAX][TR_PIX] (rows of the walk cleared by the classification)
+    double* lacc;        // squared-error sums [S]
+    uint32_t* cls;       // group lists of the three walk classes [3][groups]
+    uint32_t* ctr;       // class sizes, then the work counters of both kernels
     float* gacc;         // per-pair geometric accumulators [pairs][8]
-    int S, Fc, H, W, tw, th, TX, gpt, R;
+    int S, Fc, H, W, tw, th, TX, gpt, groups;
+    int rmin, rmax;      // bounds of a class's column split
     float amin, amax;
 };
+
+// counters: class sizes at TR_CNT + c, units taken by the forward/backward
+// products at TR_WK_FB + c, groups taken by the backward walk at TR_WK_WALK + c
+constexpr int TR_CNT = 0, TR_WK_FB = 4, TR_WK_WALK = 8, TR_NCTR = 16;
+
+// shortest walk of class c (exclusive; class 0 takes empty walks too)
+__device__ __forceinline__ int tr_lo(int c) { return c == 0 ? 0 : (c == 1 ? 64 : 128); }
+
+// Column split of a class of `cnt` groups over a persistent grid of `slots`
+// workgroups: enough units to fill the grid, within [rmin, rmax].
+__device__ __forceinline__ int tr_split(const TrArgs& A, uint32_t cnt, int slots)
+{
+    const int r = cnt ? (int)((slots + cnt - 1) / cnt) : A.rmin;
+    return min(A.rmax, max(A.rmin, r));
+}
+
+// One wave per group: its walk length (the largest stop position of its
+// pixels), its class, and the GV rows of its walk cleared for the products'
+// atomics.  Groups of no class (walks past TR_EMAX) are left alone.
+__global__ __launch_bounds__(64) void k_train_classify(TrArgs A)
+{
+    const int grp = blockIdx.x;
+    const int tile = grp / A.gpt, pg = grp % A.gpt;
+    const int lane = threadIdx.x;
+    const int txi = tile % A.TX, tyi = tile / A.TX;
+    const int vw = min(A.tw, A.W - txi * A.tw), vh = min(A.th, A.H - tyi * A.th);
+    if (pg * TR_PIX >= vw * vh) return;
+    const int px = tr_pixel(pg * TR_PIX + lane, vw, vh, txi, tyi, A.tw, A.th, A.W);
+    int m = px >= 0 ? (int)A.n_last[px] : 0;
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if (m > TR_EMAX) return;
+    const int c = m <= 64 ? 0 : (m <= 128 ? 1 : 2);
+    float4* gv = (float4*)(A.gv + (size_t)grp * TR_EMAX * TR_PIX);
+    for (int i = lane; i < m * (TR_PIX / 4); i += 64) gv[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (lane == 0) A.cls[c * A.groups + atomicAdd(A.ctr + TR_CNT + c, 1u)] = (uint32_t)grp;
+}
 
 // occupancy per variant: the LDS of E = 64 fits four workgroups per CU, of
 // 128 two, of 256 one
@@ -165,11 +231,12 @@ struct TrOcc {
     static constexpr int waves = E <= 64 ? 4 : (E <= 128 ? 2 : 1);
 };
 
+// One unit (group grp, column range r of R) of kernel 1.  Returns early only
+// for the whole workgroup.
 template <int E>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::waves))) void k_train_fb(TrArgs A,
-                                                                                                      int lo)
+__device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (*s_a)[TR_PAD], float (*s_w)[TR_PAD],
+                                           int grp, int r, int R, int lo)
 {
-    const int grp = blockIdx.x, r = blockIdx.y;
     const int tile = grp / A.gpt, pg = grp % A.gpt;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int j4 = lane >> 4, l16 = lane & 15;
@@ -180,31 +247,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
     const size_t HW = (size_t)A.H * A.W;
     const int F = A.Fc >> 1;
     const int ncb = A.S * A.Fc / 16;
-    const int cb_lo = r * ncb / A.R, cb_hi = (r + 1) * ncb / A.R;
-
-    __shared__ TrLds<E> L;
-    __shared__ __align__(16) float s_a[TR_CH][TR_PAD];  // alpha of a chunk, then the exchange of g
-    __shared__ __align__(16) float s_w[E][TR_PAD];      // weights w_k(p)
+    const int cb_lo = r * ncb / R, cb_hi = (r + 1) * ncb / R;
     uint32_t stop;
     const int m = tr_group<E>(L, A.rec, A.plist, rg, A.n_last, pg, vw, vh, txi, tyi, A.tw, A.th, A.W, lo, stop);
     if (m < 0) return;
     const int nks = (m + 3) >> 2;  // K-steps of 4 entries
     const int mp = nks * 4;
+    const int neb = (m + 15) >> 4;
+    for (int t = threadIdx.x; t < 16 * neb; t += blockDim.x) L.voff[t] = (t < m ? L.g[t] : L.g[0]) * (uint32_t)A.Fc;
 
     // prefix transmittance and weights chunk by chunk: alpha by all waves,
     // the walk by one (lane = pixel, in list order: the operations of the
-    // compositing kernel)
+    // compositing kernel); the walk also marks which (entries, 16-pixel
+    // block) tiles of the weights hold a nonzero value: the products skip
+    // the others (their terms are exact zeros)
     float T = 1.0f;
     for (int k0 = 0; k0 < mp; k0 += TR_CH) {
         tr_alpha<E>(L, s_a, 0, k0, m, stop, A.W, A.amin, A.amax);
         __syncthreads();
         if (wave == 0) {
             const int kn = min(TR_CH, mp - k0);
+            unsigned long long nz = 0ull;
             for (int kk = 0; kk < kn; ++kk) {
                 const float a = s_a[kk][lane];
                 const float w = a > 0.0f ? T * a * L.att[k0 + kk] : 0.0f;
                 T = a > 0.0f ? T * (1.0f - a) : T;
                 s_w[k0 + kk][lane] = w;
+                nz |= __ballot(w != 0.0f);
+                const int k = k0 + kk;
+                if ((k & 15) == 15 || k == mp - 1) {
+                    if (lane == 0)
+                        L.nzb[k >> 4] = ((nz & 0xFFFFull) ? 1u : 0u) | ((nz & 0xFFFF0000ull) ? 2u : 0u) |
+                                        ((nz & 0xFFFF00000000ull) ? 4u : 0u) | ((nz >> 48) ? 8u : 0u);
+                    nz = 0ull;
+                }
             }
         }
         __syncthreads();
@@ -213,17 +289,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
     // the lanes' pixels in the (F)/(D) layout (lane holds rows
     // 16 pb + 4 j4 + i of a 64-pixel column), read from LDS where used
     auto pixY = [&](int pb, int i) -> int { return L.pix[16 * pb + 4 * j4 + i]; };
-    const uint32_t gfirst = m > 0 ? L.g[0] : 0u;
-    auto gid = [&](int k) -> uint32_t { return k < m ? L.g[k] : gfirst; };
-
     constexpr int NEB = E / 16;
     f32x4t gv[NEB];  // GV[16 eb + 4 j4 + i][16 wave + l16], over this unit's columns
 #pragma unroll
     for (int eb = 0; eb < NEB; ++eb) gv[eb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
-    const int neb = (m + 15) >> 4;
     float lsum = 0.0f;
     int lset = -1;
-    float* lp = A.lpart + (size_t)(grp * A.R + r) * A.S;
 
     const int nrounds = (cb_hi - cb_lo + TR_WAVES - 1) / TR_WAVES;
     // target words of this wave's block in a round, one round ahead (their
@@ -233,13 +304,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
         if (rd_ >= nrounds || cb_ >= cb_hi) return;
         const int s_ = cb_ * 16 / A.Fc;
         const int c_ = cb_ * 16 - s_ * A.Fc + l16;
-        const size_t plane = ((size_t)(s_ * F + (c_ >> 1)) * HW) * 2 + (c_ & 1);
+        const __amdgpu_buffer_rsrc_t rt = tr_rsrc(A.tgt + (size_t)s_ * F * HW * 2);
+        const uint32_t plane = (uint32_t)((c_ >> 1) * HW * 2 + (c_ & 1));
 #pragma unroll
         for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int px = pixY(pb, i);
-                t[4 * pb + i] = px >= 0 ? A.tgt[plane + ((size_t)px << 1)] : 0.0f;
+                t[4 * pb + i] = tr_ld(rt, px >= 0 ? (plane + 2u * px) * 4u : TR_OOB);
             }
     };
     float tcur[16], tnext[16];
@@ -257,12 +329,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
             // (F) zhat = W^T V, in chains of 128 entries added in list order
             // (the compositing kernel's buffer flushes, so that the stored
             // spectrum is bit-identical to it); the chain's V words first
-            const float* vb = A.attr + s * A.a_stride + c0 + l16;
+            const __amdgpu_buffer_rsrc_t rv = tr_rsrc(A.attr + s * A.a_stride);
             for (int kc = 0; kc < nks; kc += KCH) {
                 float bq[KCH];
 #pragma unroll
                 for (int q = 0; q < KCH; ++q)
-                    if (kc + q < nks) bq[q] = vb[(size_t)gid(4 * (kc + q) + j4) * A.Fc];
+                    if (kc + q < nks) bq[q] = tr_ld(rv, (L.voff[4 * (kc + q) + j4] + (uint32_t)(c0 + l16)) * 4u);
                 f32x4t zc[4];
 #pragma unroll
                 for (int pb = 0; pb < 4; ++pb) zc[pb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
@@ -304,7 +376,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
             if (s != lset) {
                 if (lset >= 0) {
                     for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-                    if (lane == 0) atomicAdd(lp + lset, lsum);
+                    if (lane == 0) unsafeAtomicAdd(A.lacc + lset, (double)lsum);
                 }
                 lset = s;
                 lsum = 0.0f;
@@ -326,14 +398,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
             if (ocb >= cb_hi) break;
             const int os = ocb * 16 / A.Fc;
             const int oc0 = ocb * 16 - os * A.Fc;
-            const float* va = A.attr + os * A.a_stride + oc0 + 4 * j4;
+            const __amdgpu_buffer_rsrc_t rv = tr_rsrc(A.attr + os * A.a_stride);
             float bg[4];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) bg[kk] = s_a[16 * ow + 4 * j4 + kk][16 * wave + l16];
 #pragma unroll
             for (int eb = 0; eb < NEB; ++eb) {
-                if (eb < neb) {
-                    const float4 v4 = *(const float4*)(va + (size_t)gid(16 * eb + l16) * A.Fc);
+                if (eb < neb && (__builtin_amdgcn_readfirstlane(L.nzb[eb]) & (1u << wave))) {
+                    const float4 v4 = __builtin_bit_cast(
+                        float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                    rv, (L.voff[16 * eb + l16] + (uint32_t)(oc0 + 4 * j4)) * 4u, 0, 0));
                     __builtin_amdgcn_sched_barrier(0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.x, bg[0], gv[eb], 0, 0, 0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.y, bg[1], gv[eb], 0, 0, 0);
@@ -345,21 +419,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
         // (D) dL/dv[k][c0 + l16] = sum_p w_k(p) g(p, c0 + l16): K-step (pb, i)
         // pairs lane group j4 with pixel 16 pb + 4 j4 + i
         if (own) {
-            float* dA = A.d_attr + s * A.da_stride + c0 + l16;
+            const __amdgpu_buffer_rsrc_t rd_attr = tr_rsrc(A.d_attr + s * A.da_stride);
             for (int eb = 0; eb < neb; ++eb) {
+                const uint32_t fl = __builtin_amdgcn_readfirstlane(L.nzb[eb]);
+                if (!fl) continue;
                 f32x4t acc = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int pb = 0; pb < 4; ++pb) {
-                    const float4 w4 = *(const float4*)&s_w[16 * eb + l16][16 * pb + 4 * j4];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[pb][0], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[pb][1], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[pb][2], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[pb][3], acc, 0, 0, 0);
+                    if (fl & (1u << pb)) {
+                        const float4 w4 = *(const float4*)&s_w[16 * eb + l16][16 * pb + 4 * j4];
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[pb][0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[pb][1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[pb][2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[pb][3], acc, 0, 0, 0);
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = 16 * eb + 4 * j4 + i;
-                    if (k < m && acc[i] != 0.0f) unsafeAtomicAdd(dA + (size_t)L.g[k] * A.Fc, acc[i]);
+                    if (k < m && acc[i] != 0.0f)
+                        __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(
+                            acc[i], rd_attr, (L.voff[k] + (uint32_t)(c0 + l16)) * 4u, 0, 0);
                 }
             }
         }
@@ -367,16 +447,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
     }
     if (lset >= 0) {
         for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-        if (lane == 0) atomicAdd(lp + lset, lsum);
+        if (lane == 0) unsafeAtomicAdd(A.lacc + lset, (double)lsum);
     }
-    // GV partial of this column range: lane holds entries 16 eb + 4 j4 + i at
+    // this column range's share of GV: lane holds entries 16 eb + 4 j4 + i at
     // pixel 16 wave + l16
-    float* gp = A.gvp + (size_t)(grp * A.R + r) * TR_EMAX * TR_PIX;
+    // (byte offset: the entry block in the scalar offset, the entry inside
+    // it as an immediate, one per-lane register)
+    const __amdgpu_buffer_rsrc_t rg_gv = tr_rsrc(A.gv + (size_t)grp * TR_EMAX * TR_PIX);
+    const uint32_t lane_off = (uint32_t)(4 * j4 * TR_PIX + 16 * wave + l16) * 4u;
 #pragma unroll
     for (int eb = 0; eb < NEB; ++eb)
         if (eb < neb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) gp[(16 * eb + 4 * j4 + i) * TR_PIX + 16 * wave + l16] = gv[eb][i];
+            for (int i = 0; i < 4; ++i) {
+                const int k = 16 * eb + 4 * j4 + i;
+                if (k < m && gv[eb][i] != 0.0f)
+                    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(gv[eb][i], rg_gv, lane_off + i * TR_PIX * 4,
+                                                                    eb * 16 * TR_PIX * 4, 0);
+            }
+}
+
+// Kernel 1 as a persistent grid over the units of walk class c.
+template <int E>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::waves))) void k_train_fb(TrArgs A,
+                                                                                                      int c)
+{
+    __shared__ TrLds<E> L;
+    __shared__ __align__(16) float s_a[TR_CH][TR_PAD];  // alpha of a chunk, then the exchange of g
+    __shared__ __align__(16) float s_w[E][TR_PAD];      // weights w_k(p)
+    __shared__ uint32_t s_item;
+    const uint32_t cnt = A.ctr[TR_CNT + c];
+    const int R = tr_split(A, cnt, (int)gridDim.x);
+    const uint32_t total = cnt * (uint32_t)R;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(A.ctr + TR_WK_FB + c, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        tr_fb_unit<E>(A, L, s_a, s_w, (int)A.cls[c * A.groups + item / R], (int)(item % R), R, tr_lo(c));
+        __syncthreads();  // the next unit reuses the LDS
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -421,29 +532,22 @@ __device__ __forceinline__ void tr_reduce_scatter8(float* x, int lane)
 }
 
 template <int E>
-__global__ __launch_bounds__(256) void k_train_walk(TrArgs A, int lo)
+__device__ __forceinline__ void tr_walk_group(const TrArgs& A, TrLds<E>& L, float (*s_a)[TR_PAD],
+                                              float (*s_gv)[TR_PAD], int grp, int lo)
 {
-    const int grp = blockIdx.x;
     const int tile = grp / A.gpt, pg = grp % A.gpt;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int txi = tile % A.TX, tyi = tile / A.TX;
     const int vw = min(A.tw, A.W - txi * A.tw), vh = min(A.th, A.H - tyi * A.th);
     if (pg * TR_PIX >= vw * vh) return;
     const uint2 rg = A.ranges[tile];
-
-    __shared__ TrLds<E> L;
-    __shared__ float s_a[E][TR_PAD];   // alpha, then dL/d(sigma G)
-    __shared__ float s_gv[E][TR_PAD];  // GV, then T alpha GV
     uint32_t stop;
     const int m = tr_group<E>(L, A.rec, A.plist, rg, A.n_last, pg, vw, vh, txi, tyi, A.tw, A.th, A.W, lo, stop);
     if (m <= 0) return;
     for (int k0 = 0; k0 < m; k0 += TR_CH) tr_alpha<E>(L, s_a, k0, k0, m, stop, A.W, A.amin, A.amax);
-    const float* gp = A.gvp + (size_t)grp * A.R * TR_EMAX * TR_PIX;
-    for (int e = threadIdx.x; e < m * TR_PIX; e += blockDim.x) {
-        float v = 0.0f;
-        for (int rr = 0; rr < A.R; ++rr) v += gp[(size_t)rr * TR_EMAX * TR_PIX + e];
-        s_gv[e / TR_PIX][e % TR_PIX] = v;
-    }
+    const float4* gp = (const float4*)(A.gv + (size_t)grp * TR_EMAX * TR_PIX);
+    for (int e = threadIdx.x; e < m * (TR_PIX / 4); e += blockDim.x)
+        *(float4*)&s_gv[e / (TR_PIX / 4)][4 * (e % (TR_PIX / 4))] = gp[e];
     __syncthreads();
     if (wave == 0) {
         // D = sum_k w_k GV_k (the forward output contracted with g), then the
@@ -505,6 +609,26 @@ __global__ __launch_bounds__(256) void k_train_walk(TrArgs A, int lo)
     }
 }
 
+// Kernel 2 as a persistent grid over the groups of walk class c.
+template <int E>
+__global__ __launch_bounds__(256) void k_train_walk(TrArgs A, int c)
+{
+    __shared__ TrLds<E> L;
+    __shared__ __align__(16) float s_a[E][TR_PAD];   // alpha, then dL/d(sigma G)
+    __shared__ __align__(16) float s_gv[E][TR_PAD];  // GV, then T alpha GV
+    __shared__ uint32_t s_item;
+    const uint32_t cnt = A.ctr[TR_CNT + c];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(A.ctr + TR_WK_WALK + c, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= cnt) break;
+        tr_walk_group<E>(A, L, s_a, s_gv, (int)A.cls[c * A.groups + item], tr_lo(c));
+        __syncthreads();  // the next group reuses the LDS
+    }
+}
+
 // ---------------------------------------------------------------------------
 // hhat from the per-Gaussian weight totals, the channel-mean gradient term
 // and the channel part of the loss.
@@ -554,18 +678,14 @@ __global__ __launch_bounds__(256) void k_train_hfinish(const float* __restrict__
     if (threadIdx.x == 0) loss[s] = lambda * (red[0] + red[1] + red[2] + red[3]);
 }
 
-// loss[s] += lscale * sum over units of the squared-error partials
-__global__ __launch_bounds__(256) void k_train_loss_add(const float* __restrict__ lpart, int nunits, int S,
-                                                        float lscale, float* __restrict__ loss)
+// loss[s] += lscale * (squared-error sum of the fused kernels + that of the
+// long-walk kernels)
+__global__ __launch_bounds__(64) void k_train_loss_add(const double* __restrict__ lacc,
+                                                       const float* __restrict__ llong, int S, float lscale,
+                                                       float* __restrict__ loss)
 {
-    const int s = blockIdx.x;
-    float v = 0.0f;
-    for (int u = threadIdx.x; u < nunits; u += blockDim.x) v += lpart[(size_t)u * S + s];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    __shared__ float red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) loss[s] += lscale * (red[0] + red[1] + red[2] + red[3]);
+    for (int s = threadIdx.x; s < S; s += blockDim.x)
+        loss[s] += lscale * (float)(lacc[s] + (double)llong[s]);
 }
 
 // Eq. (2): h[s][c] = (1/HW) sum_p z(s, c, p); one workgroup per (set,
@@ -604,15 +724,56 @@ __global__ __launch_bounds__(256) void k_spatial_mean(const float* __restrict__ 
     }
 }
 
-// column ranges per group: enough units to spread the groups over the chip
-int train_ranges(int ncb) { return ncb >= 32 ? 4 : (ncb >= 8 ? 2 : 1); }
-
-size_t train_scratch_floats(int groups, int R, int S, int Fc)
+// Scratch layout of gs_render_train (byte offsets from its start).
+struct TrScratch {
+    size_t gv, lacc, llong, hs, mg, cls, ctr, total;
+};
+TrScratch train_scratch(int groups, int S, int Fc)
 {
-    // GV partials, squared-error partials (+ one slot per set for the
-    // long-walk path), hsum, mgrad
-    return align256((size_t)groups * R * TR_EMAX * TR_PIX * 4) / 4 + align256((size_t)(groups * R + 1) * S * 4) / 4 +
-           2 * (align256((size_t)S * Fc * 4) / 4);
+    TrScratch t;
+    t.gv = 0;
+    t.lacc = t.gv + align256((size_t)groups * TR_EMAX * TR_PIX * 4);
+    t.llong = t.lacc + align256((size_t)S * 8);
+    t.hs = t.llong + align256((size_t)S * 4);
+    t.mg = t.hs + align256((size_t)S * Fc * 4);
+    t.cls = t.mg + align256((size_t)S * Fc * 4);
+    t.ctr = t.cls + align256((size_t)3 * groups * 4);
+    t.total = t.ctr + align256((size_t)TR_NCTR * 4);
+    return t;
+}
+
+// Workgroups of each variant resident on the whole device at once (the
+// persistent grids), per device.
+struct TrSlots {
+    int fb[3], walk[3];
+};
+hipError_t train_slots(TrSlots* out)
+{
+    static std::mutex mu;
+    static int have[64] = {};
+    static TrSlots cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!have[dev]) {
+        int cus = 0;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        const void* fb[3] = {(const void*)k_train_fb<64>, (const void*)k_train_fb<128>, (const void*)k_train_fb<256>};
+        const void* wk[3] = {(const void*)k_train_walk<64>, (const void*)k_train_walk<128>,
+                             (const void*)k_train_walk<256>};
+        for (int c = 0; c < 3; ++c) {
+            int a = 0, b = 0;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, fb[c], 256, 0)) != hipSuccess) return e;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, wk[c], 256, 0)) != hipSuccess) return e;
+            cache[dev].fb[c] = std::max(1, a) * std::max(1, cus);
+            cache[dev].walk[c] = std::max(1, b) * std::max(1, cus);
+        }
+        have[dev] = 1;
+    }
+    *out = cache[dev];
+    return hipSuccess;
 }
 
 }  // namespace gs
@@ -654,35 +815,38 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     if (queries->count != 1 || prm->atten_ref != 0 || n_sets < 1 || attrs->is_complex != 1) return GS_ERR_INVALID_ARG;
     const int Fc = attrs->n_chan * 2;
     if (Fc % 16 != 0) return GS_ERR_INVALID_ARG;
-    // (the long-walk backward addresses one set's spectrum with 32-bit offsets)
-    if ((uint64_t)Fc * L.H * L.W >= (1ull << 30)) return GS_ERR_CAPACITY;
+    // (one set's spectrum, target and attributes are addressed with 32-bit
+    // byte offsets)
+    if ((uint64_t)Fc * L.H * L.W >= (1ull << 29) || (uint64_t)scene->n * Fc >= (1ull << 29)) return GS_ERR_CAPACITY;
     if (n_sets > 1 && attrs->query_stride != 0 && attrs->query_stride < (int64_t)scene->n * Fc)
         return GS_ERR_INVALID_ARG;
     const int gpt = (L.tw * L.th) / TR_PIX;
     const int groups = L.T * gpt;
     const int ncb = n_sets * Fc / 16;
-    const int R = train_ranges(ncb);
-    if ((int64_t)groups * R > 0x7FFFFFFF / (TR_EMAX * TR_PIX) || groups > 0x7FFFFFFF / 4) return GS_ERR_CAPACITY;
-    const size_t need = train_scratch_floats(groups, R, n_sets, Fc) * 4;
-    if (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < need) return GS_ERR_WORKSPACE;
+    if (groups > 0x7FFFFFFF / (TR_EMAX * TR_PIX) || (int64_t)groups * ncb > 0x7FFFFFFF) return GS_ERR_CAPACITY;
+    const TrScratch ts = train_scratch(groups, n_sets, Fc);
+    if (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < ts.total) return GS_ERR_WORKSPACE;
+    TrSlots slots;
+    if (train_slots(&slots) != hipSuccess) return GS_ERR_HIP;
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)workspace;
+    char* sc = (char*)scratch;
     (void)hipGetLastError();
 
-    float* gvp = (float*)scratch;
-    float* lpart = gvp + align256((size_t)groups * R * TR_EMAX * TR_PIX * 4) / 4;
-    const int nunits = groups * R;
-    float* hs = lpart + align256((size_t)(nunits + 1) * n_sets * 4) / 4;
-    float* mg = hs + align256((size_t)n_sets * Fc * 4) / 4;
+    double* lacc = (double*)(sc + ts.lacc);
+    float* llong = (float*)(sc + ts.llong);
+    float* hs = (float*)(sc + ts.hs);
+    float* mg = (float*)(sc + ts.mg);
+    uint32_t* ctr = (uint32_t*)(sc + ts.ctr);
     const size_t HW = (size_t)L.H * L.W;
     const float escale = 2.0f / ((float)attrs->n_chan * (float)HW * (float)n_sets);
     const float lscale = 1.0f / ((float)attrs->n_chan * (float)HW);
 
     FillSegs fs{};
-    fs.p[0] = (uint32_t*)lpart;
-    fs.count[0] = (size_t)(nunits + 1) * n_sets;
-    fs.p[1] = (uint32_t*)hs;
-    fs.count[1] = (size_t)n_sets * Fc;
+    fs.p[0] = (uint32_t*)lacc;  // lacc, llong, hs (adjacent)
+    fs.count[0] = (ts.mg - ts.lacc) / 4;
+    fs.p[1] = ctr;
+    fs.count[1] = TR_NCTR;
     fs.p[2] = (uint32_t*)(ws + L.g2d);
     fs.count[2] = (size_t)L.n * 8;
     fs.n = 3;
@@ -713,8 +877,10 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     A.out = (flags & GS_TRAIN_WRITE_SPECTRUM) ? spectrum : nullptr;
     A.d_attr = d_attr;
     A.da_stride = attrs->query_stride;
-    A.gvp = gvp;
-    A.lpart = lpart;
+    A.gv = (float*)(sc + ts.gv);
+    A.lacc = lacc;
+    A.cls = (uint32_t*)(sc + ts.cls);
+    A.ctr = ctr;
     A.gacc = (float*)(ws + L.gacc);
     A.S = n_sets;
     A.Fc = Fc;
@@ -724,26 +890,32 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     A.th = L.th;
     A.TX = L.TX;
     A.gpt = gpt;
-    A.R = R;
+    A.groups = groups;
+    // each wave owns a 16-column block per round: at least one round of
+    // four blocks per unit, and at least four units per group where the
+    // columns allow
+    A.rmax = std::max(1, ncb / TR_WAVES);
+    A.rmin = std::min(A.rmax, 4);
     A.amin = prm->alpha_min;
     A.amax = prm->alpha_max;
     void* tok;
     timing_begin(TK_TRAIN, s, &tok);
-    // each group goes to the variant of the smallest walk bound that holds
-    // its walk (the others leave at once)
-    hipLaunchKernelGGL(k_train_fb<64>, dim3(groups, R), dim3(256), 0, s, A, 0);
-    hipLaunchKernelGGL(k_train_fb<128>, dim3(groups, R), dim3(256), 0, s, A, 64);
-    hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(groups, R), dim3(256), 0, s, A, 128);
-    hipLaunchKernelGGL(k_train_walk<64>, dim3(groups), dim3(256), 0, s, A, 0);
-    hipLaunchKernelGGL(k_train_walk<128>, dim3(groups), dim3(256), 0, s, A, 64);
-    hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(groups), dim3(256), 0, s, A, 128);
+    // the groups sorted by walk length into the variants' lists, then each
+    // variant over its list (the longest walks first)
+    hipLaunchKernelGGL(k_train_classify, dim3(groups), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(slots.fb[2]), dim3(256), 0, s, A, 2);
+    hipLaunchKernelGGL(k_train_fb<128>, dim3(slots.fb[1]), dim3(256), 0, s, A, 1);
+    hipLaunchKernelGGL(k_train_fb<64>, dim3(slots.fb[0]), dim3(256), 0, s, A, 0);
+    hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(slots.walk[2]), dim3(256), 0, s, A, 2);
+    hipLaunchKernelGGL(k_train_walk<128>, dim3(slots.walk[1]), dim3(256), 0, s, A, 1);
+    hipLaunchKernelGGL(k_train_walk<64>, dim3(slots.walk[0]), dim3(256), 0, s, A, 0);
     timing_end(tok, s);
     // groups whose walk is longer than the fused kernels take: compositing
     // into the spectrum, then the backward forming g from it and the target
     launch_blend_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, TR_EMAX, s);
-    launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, d_attr, TR_EMAX,
-                             lpart + (size_t)nunits * n_sets, s);
-    hipLaunchKernelGGL(k_train_loss_add, dim3(n_sets), dim3(256), 0, s, lpart, nunits + 1, n_sets, lscale, tt->loss);
+    launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, d_attr, TR_EMAX, llong,
+                             s);
+    hipLaunchKernelGGL(k_train_loss_add, dim3(1), dim3(64), 0, s, lacc, llong, n_sets, lscale, tt->loss);
     launch_geo_fold(L, ws, s);
     launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);
     GS_CHECK_LAUNCH();
@@ -756,9 +928,7 @@ size_t gs_train_scratch_bytes(int32_t n_sets, int32_t n_chan, const gs_grid* gri
         return 0;
     const int TX = (grid->W + grid->tile_w - 1) / grid->tile_w, TY = (grid->H + grid->tile_h - 1) / grid->tile_h;
     const int gpt = (grid->tile_w * grid->tile_h + TR_PIX - 1) / TR_PIX;
-    const int Fc = n_chan * 2;
-    const int R = train_ranges(n_sets * Fc / 16);
-    return train_scratch_floats(TX * TY * gpt, R, n_sets, Fc) * 4;
+    return train_scratch(TX * TY * gpt, n_sets, n_chan * 2).total;
 }
 
 }  // extern "C"
