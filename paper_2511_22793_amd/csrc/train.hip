@@ -297,26 +297,35 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
     int lset = -1;
 
     const int nrounds = (cb_hi - cb_lo + TR_WAVES - 1) / TR_WAVES;
-    // target words of this wave's block in a round, one round ahead (their
-    // HBM latency hides behind the previous round's products)
-    auto tgt_load = [&](int rd_, float* t) {
+    // Memory operations complete in issue order for the wait counter, so a
+    // wait for a load also waits for every atomic issued before it.  A round
+    // therefore issues the next round's (F) operands (first chain) and target
+    // words before its own attribute-gradient atomics: the next round's first
+    // wait leaves those atomics in flight.
+    constexpr int KCH = (E < 128 ? E : 128) / 4;  // K-steps of one chain
+    float bq[KCH];   // V words of the next chain
+    float tcur[16];  // target words of this wave's block
+    auto round_load = [&](int rd_) {
         const int cb_ = cb_lo + rd_ * TR_WAVES + wave;
         if (rd_ >= nrounds || cb_ >= cb_hi) return;
         const int s_ = cb_ * 16 / A.Fc;
-        const int c_ = cb_ * 16 - s_ * A.Fc + l16;
+        const int c_ = cb_ * 16 - s_ * A.Fc;
+        const __amdgpu_buffer_rsrc_t rv_ = tr_rsrc(A.attr + s_ * A.a_stride);
+#pragma unroll
+        for (int q = 0; q < KCH; ++q)
+            if (q < nks) bq[q] = tr_ld(rv_, (L.voff[4 * q + j4] + (uint32_t)(c_ + l16)) * 4u);
         const __amdgpu_buffer_rsrc_t rt = tr_rsrc(A.tgt + (size_t)s_ * F * HW * 2);
-        const uint32_t plane = (uint32_t)((c_ >> 1) * HW * 2 + (c_ & 1));
+        const int cl = c_ + l16;
+        const uint32_t plane = (uint32_t)((cl >> 1) * HW * 2 + (cl & 1));
 #pragma unroll
         for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int px = pixY(pb, i);
-                t[4 * pb + i] = tr_ld(rt, px >= 0 ? (plane + 2u * px) * 4u : TR_OOB);
+                tcur[4 * pb + i] = tr_ld(rt, px >= 0 ? (plane + 2u * px) * 4u : TR_OOB);
             }
     };
-    float tcur[16], tnext[16];
-    tgt_load(0, tcur);
-    constexpr int KCH = (E < 128 ? E : 128) / 4;  // K-steps of one chain
+    round_load(0);
     for (int rd = 0; rd < nrounds; ++rd) {
         const int cb = cb_lo + rd * TR_WAVES + wave;
         const bool own = cb < cb_hi;
@@ -328,13 +337,15 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
         if (own) {
             // (F) zhat = W^T V, in chains of 128 entries added in list order
             // (the compositing kernel's buffer flushes, so that the stored
-            // spectrum is bit-identical to it); the chain's V words first
+            // spectrum is bit-identical to it); the first chain's V words
+            // were loaded with the previous round
             const __amdgpu_buffer_rsrc_t rv = tr_rsrc(A.attr + s * A.a_stride);
             for (int kc = 0; kc < nks; kc += KCH) {
-                float bq[KCH];
+                if (kc > 0) {
 #pragma unroll
-                for (int q = 0; q < KCH; ++q)
-                    if (kc + q < nks) bq[q] = tr_ld(rv, (L.voff[4 * (kc + q) + j4] + (uint32_t)(c0 + l16)) * 4u);
+                    for (int q = 0; q < KCH; ++q)
+                        if (kc + q < nks) bq[q] = tr_ld(rv, (L.voff[4 * (kc + q) + j4] + (uint32_t)(c0 + l16)) * 4u);
+                }
                 f32x4t zc[4];
 #pragma unroll
                 for (int pb = 0; pb < 4; ++pb) zc[pb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
@@ -351,13 +362,24 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
 #pragma unroll
                 for (int pb = 0; pb < 4; ++pb) z[pb] = kc == 0 ? zc[pb] : zc[pb] + z[pb];
             }
-        }
-        tgt_load(rd + 1, tnext);
-        if (own) {
             // target, g, loss partial (column c0 + l16 = channel f, re/im)
             const int c = c0 + l16;
-            const size_t plane = ((size_t)(s * F + (c >> 1)) * HW) * 2 + (c & 1);
             const float mc = A.mgrad[(size_t)s * A.Fc + c];
+            if (A.out) {
+                // the spectrum, on request (one set's spectrum: 32-bit offsets)
+                const __amdgpu_buffer_rsrc_t ro = tr_rsrc(A.out + (size_t)s * F * HW * 2);
+                const uint32_t plane = (uint32_t)((c >> 1) * HW * 2 + (c & 1));
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int px = pixY(pb, i);
+                        const float zv = z[pb][i];
+                        if (px >= 0)
+                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zv), ro, (plane + 2u * px) * 4u, 0,
+                                                                  0);
+                    }
+            }
             float ls = 0.0f;
 #pragma unroll
             for (int pb = 0; pb < 4; ++pb)
@@ -365,7 +387,6 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
                 for (int i = 0; i < 4; ++i) {
                     const int px = pixY(pb, i);
                     if (px >= 0) {
-                        if (A.out) A.out[plane + ((size_t)px << 1)] = z[pb][i];
                         const float d = z[pb][i] - tcur[4 * pb + i];
                         ls = fmaf(d, d, ls);
                         z[pb][i] = fmaf(A.escale, d, mc);
@@ -385,11 +406,8 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
             // g to LDS for (G): s_a[16 wave + j][p] = g(p, c0 + j)
 #pragma unroll
             for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) s_a[16 * wave + l16][16 * pb + 4 * j4 + i] = z[pb][i];
+                *(float4*)&s_a[16 * wave + l16][16 * pb + 4 * j4] = float4{z[pb][0], z[pb][1], z[pb][2], z[pb][3]};
         }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) tcur[q] = tnext[q];
         __syncthreads();
         // (G) GV[k][16 wave + l16] += sum over the round's columns of v(k, c) g(p, c)
 #pragma unroll 1
@@ -408,7 +426,7 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
                     const float4 v4 = __builtin_bit_cast(
                         float4, __builtin_amdgcn_raw_buffer_load_b128(
                                     rv, (L.voff[16 * eb + l16] + (uint32_t)(oc0 + 4 * j4)) * 4u, 0, 0));
-                    __builtin_amdgcn_sched_barrier(0);
+                    if constexpr (E > 64) __builtin_amdgcn_sched_barrier(0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.x, bg[0], gv[eb], 0, 0, 0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.y, bg[1], gv[eb], 0, 0, 0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.z, bg[2], gv[eb], 0, 0, 0);
@@ -417,31 +435,38 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
             }
         }
         // (D) dL/dv[k][c0 + l16] = sum_p w_k(p) g(p, c0 + l16): K-step (pb, i)
-        // pairs lane group j4 with pixel 16 pb + 4 j4 + i
-        if (own) {
-            const __amdgpu_buffer_rsrc_t rd_attr = tr_rsrc(A.d_attr + s * A.da_stride);
-            for (int eb = 0; eb < neb; ++eb) {
-                const uint32_t fl = __builtin_amdgcn_readfirstlane(L.nzb[eb]);
-                if (!fl) continue;
-                f32x4t acc = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
+        // pairs lane group j4 with pixel 16 pb + 4 j4 + i; all entry blocks'
+        // sums first, then the next round's loads, then the atomics
+        f32x4t acc[NEB];
+#pragma unroll
+        for (int eb = 0; eb < NEB; ++eb) {
+            acc[eb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
+            const uint32_t fl = __builtin_amdgcn_readfirstlane(L.nzb[eb < neb ? eb : 0]);
+            if (own && eb < neb && fl) {
 #pragma unroll
                 for (int pb = 0; pb < 4; ++pb) {
                     if (fl & (1u << pb)) {
                         const float4 w4 = *(const float4*)&s_w[16 * eb + l16][16 * pb + 4 * j4];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[pb][0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[pb][1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[pb][2], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[pb][3], acc, 0, 0, 0);
+                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[pb][0], acc[eb], 0, 0, 0);
+                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[pb][1], acc[eb], 0, 0, 0);
+                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[pb][2], acc[eb], 0, 0, 0);
+                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[pb][3], acc[eb], 0, 0, 0);
                     }
                 }
+            }
+        }
+        round_load(rd + 1);
+        if (own) {
+            const __amdgpu_buffer_rsrc_t rd_attr = tr_rsrc(A.d_attr + s * A.da_stride);
+#pragma unroll
+            for (int eb = 0; eb < NEB; ++eb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = 16 * eb + 4 * j4 + i;
-                    if (k < m && acc[i] != 0.0f)
+                    if (k < m && acc[eb][i] != 0.0f)
                         __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(
-                            acc[i], rd_attr, (L.voff[k] + (uint32_t)(c0 + l16)) * 4u, 0, 0);
+                            acc[eb][i], rd_attr, (L.voff[k] + (uint32_t)(c0 + l16)) * 4u, 0, 0);
                 }
-            }
         }
         __syncthreads();  // before the next round's g overwrites s_a
     }
