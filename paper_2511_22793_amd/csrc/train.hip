@@ -286,9 +286,12 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
         __syncthreads();
     }
 
-    // the lanes' pixels in the (F)/(D) layout (lane holds rows
-    // 16 pb + 4 j4 + i of a 64-pixel column), read from LDS where used
-    auto pixY = [&](int pb, int i) -> int { return L.pix[16 * pb + 4 * j4 + i]; };
+    // The (F) products take the group's pixels in an interleaved order:
+    // row m of output block pb is pixel 4 m + pb, so that a lane's four A
+    // operands of one K-step (one entry, pixels 4 l16 .. 4 l16 + 3) are one
+    // 16-byte LDS read.  A lane then holds rows 4 j4 + i of each block, i.e.
+    // pixel 16 j4 + 4 i + pb (read from LDS where used).
+    auto pixY = [&](int pb, int i) -> int { return L.pix[16 * j4 + 4 * i + pb]; };
     constexpr int NEB = E / 16;
     f32x4t gv[NEB];  // GV[16 eb + 4 j4 + i][16 wave + l16], over this unit's columns
 #pragma unroll
@@ -331,7 +334,7 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
         const bool own = cb < cb_hi;
         const int s = own ? cb * 16 / A.Fc : 0;
         const int c0 = own ? cb * 16 - s * A.Fc : 0;
-        f32x4t z[4];  // zhat, then g: [pixel 16 pb + 4 j4 + i][column c0 + l16]
+        f32x4t z[4];  // zhat, then g: [pixel 16 j4 + 4 i + pb][column c0 + l16]
 #pragma unroll
         for (int pb = 0; pb < 4; ++pb) z[pb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
         if (own) {
@@ -353,10 +356,11 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
                 for (int q = 0; q < KCH; ++q) {
                     if (kc + q < nks) {
                         const int ks = kc + q;
-#pragma unroll
-                        for (int pb = 0; pb < 4; ++pb)
-                            zc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_w[4 * ks + j4][16 * pb + l16], bq[q],
-                                                                          zc[pb], 0, 0, 0);
+                        const float4 wa = *(const float4*)&s_w[4 * ks + j4][4 * l16];
+                        zc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.x, bq[q], zc[0], 0, 0, 0);
+                        zc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.y, bq[q], zc[1], 0, 0, 0);
+                        zc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.z, bq[q], zc[2], 0, 0, 0);
+                        zc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.w, bq[q], zc[3], 0, 0, 0);
                     }
                 }
 #pragma unroll
@@ -405,8 +409,10 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
             lsum += ls;
             // g to LDS for (G): s_a[16 wave + j][p] = g(p, c0 + j)
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb)
-                *(float4*)&s_a[16 * wave + l16][16 * pb + 4 * j4] = float4{z[pb][0], z[pb][1], z[pb][2], z[pb][3]};
+            for (int i = 0; i < 4; ++i) {
+                const float g0 = z[0][i], g1 = z[1][i], g2 = z[2][i], g3 = z[3][i];
+                *(float4*)&s_a[16 * wave + l16][16 * j4 + 4 * i] = float4{g0, g1, g2, g3};
+            }
         }
         __syncthreads();
         // (G) GV[k][16 wave + l16] += sum over the round's columns of v(k, c) g(p, c)
@@ -434,24 +440,21 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
                 }
             }
         }
-        // (D) dL/dv[k][c0 + l16] = sum_p w_k(p) g(p, c0 + l16): K-step (pb, i)
-        // pairs lane group j4 with pixel 16 pb + 4 j4 + i; all entry blocks'
+        // (D) dL/dv[k][c0 + l16] = sum_p w_k(p) g(p, c0 + l16): K-step (i, pb)
+        // pairs lane group j4 with pixel 16 j4 + 4 i + pb; all entry blocks'
         // sums first, then the next round's loads, then the atomics
         f32x4t acc[NEB];
 #pragma unroll
         for (int eb = 0; eb < NEB; ++eb) {
             acc[eb] = f32x4t{0.0f, 0.0f, 0.0f, 0.0f};
-            const uint32_t fl = __builtin_amdgcn_readfirstlane(L.nzb[eb < neb ? eb : 0]);
-            if (own && eb < neb && fl) {
+            if (own && eb < neb && __builtin_amdgcn_readfirstlane(L.nzb[eb])) {
 #pragma unroll
-                for (int pb = 0; pb < 4; ++pb) {
-                    if (fl & (1u << pb)) {
-                        const float4 w4 = *(const float4*)&s_w[16 * eb + l16][16 * pb + 4 * j4];
-                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[pb][0], acc[eb], 0, 0, 0);
-                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[pb][1], acc[eb], 0, 0, 0);
-                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[pb][2], acc[eb], 0, 0, 0);
-                        acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[pb][3], acc[eb], 0, 0, 0);
-                    }
+                for (int i = 0; i < 4; ++i) {
+                    const float4 w4 = *(const float4*)&s_w[16 * eb + l16][16 * j4 + 4 * i];
+                    acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.x, z[0][i], acc[eb], 0, 0, 0);
+                    acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.y, z[1][i], acc[eb], 0, 0, 0);
+                    acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.z, z[2][i], acc[eb], 0, 0, 0);
+                    acc[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4.w, z[3][i], acc[eb], 0, 0, 0);
                 }
             }
         }
