@@ -416,6 +416,40 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
         }
         __syncthreads();
         // (G) GV[k][16 wave + l16] += sum over the round's columns of v(k, c) g(p, c)
+        if constexpr (E == 64) {
+            // The round's V block is the four waves' (F) operands: it goes
+            // through s_a too (after each wave has taken its g words), so
+            // that no wave reads the other waves' columns from memory.
+            const int nown = min(TR_WAVES, cb_hi - (cb_lo + rd * TR_WAVES));
+            float bg[TR_WAVES][4];
+#pragma unroll
+            for (int ow = 0; ow < TR_WAVES; ++ow)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) bg[ow][kk] = s_a[16 * ow + 4 * j4 + kk][16 * wave + l16];
+            __syncthreads();
+            // s_a[k][16 ow + j] = v(k, column j of owner ow's block)
+            if (own) {
+#pragma unroll
+                for (int q = 0; q < KCH; ++q)
+                    if (q < nks) s_a[4 * q + j4][16 * wave + l16] = bq[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int eb = 0; eb < NEB; ++eb) {
+                if (eb < neb && (__builtin_amdgcn_readfirstlane(L.nzb[eb]) & (1u << wave))) {
+#pragma unroll
+                    for (int ow = 0; ow < TR_WAVES; ++ow) {
+                        if (ow < nown) {
+                            const float4 v4 = *(const float4*)&s_a[16 * eb + l16][16 * ow + 4 * j4];
+                            gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.x, bg[ow][0], gv[eb], 0, 0, 0);
+                            gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.y, bg[ow][1], gv[eb], 0, 0, 0);
+                            gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.z, bg[ow][2], gv[eb], 0, 0, 0);
+                            gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.w, bg[ow][3], gv[eb], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        } else {
 #pragma unroll 1
         for (int ow = 0; ow < TR_WAVES; ++ow) {
             const int ocb = cb_lo + rd * TR_WAVES + ow;
@@ -432,13 +466,14 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
                     const float4 v4 = __builtin_bit_cast(
                         float4, __builtin_amdgcn_raw_buffer_load_b128(
                                     rv, (L.voff[16 * eb + l16] + (uint32_t)(oc0 + 4 * j4)) * 4u, 0, 0));
-                    if constexpr (E > 64) __builtin_amdgcn_sched_barrier(0);
+                    __builtin_amdgcn_sched_barrier(0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.x, bg[0], gv[eb], 0, 0, 0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.y, bg[1], gv[eb], 0, 0, 0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.z, bg[2], gv[eb], 0, 0, 0);
                     gv[eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v4.w, bg[3], gv[eb], 0, 0, 0);
                 }
             }
+        }
         }
         // (D) dL/dv[k][c0 + l16] = sum_p w_k(p) g(p, c0 + l16): K-step (i, pb)
         // pairs lane group j4 with pixel 16 j4 + 4 i + pb; all entry blocks'
