@@ -79,8 +79,9 @@ def parse():
                          "from the target (target), or loss + stored gradient (two_pass)")
     ap.add_argument("--mix-only", action="store_true", help="run only the uneven serving mix (for profiling)")
     ap.add_argument("--pmc-run", action="store_true",
-                    help="short run for hardware-counter passes: 2 training steps, then a 256 MiB copy that "
-                         "calibrates the byte counters")
+                    help="short run for hardware-counter passes: 2 training steps, one serving render, one "
+                         "network forward over all n Gaussians, then a 256 MiB copy that calibrates the byte "
+                         "counters")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON) for the serving mix")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (plain 2k render, 50k fwd+bwd, 300k training step, N sweep)")
@@ -159,6 +160,16 @@ def main():
     for a, b in zip(names[:-1], names[1:]):
         stages[b] = float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))
     if args.pmc_run:
+        # the counter runs also cover the serving render of the same batch
+        # (the shared-geometry forward blend) and one network forward over
+        # every Gaussian (all n rows listed), where the matrix cores bind
+        from paper_2511_22793_amd import mlp as gmlp
+        model.render(tx)
+        all_rows = torch.arange(n, dtype=torch.int32, device=dev)
+        n_all = torch.full((1,), n, dtype=torch.int32, device=dev)
+        gmlp.forward(model.net, model.Z1, model.g["mean"], gmlp.Rows(tx, all_rows, n_all, row_cap=n), model.attr,
+                     model.state)
+        torch.cuda.synchronize()
         # calibration: a plain device copy of exactly 256 MiB (read 256, write 256)
         src = torch.ones(64 << 20, device=dev)
         dst = torch.empty_like(src)
@@ -323,7 +334,8 @@ def replay_times(g, reps):
     return np.array([a.elapsed_time(b) for a, b in ev])
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "compositing_traffic_100k_90x360_f64c_b16.md")
+TRAFFIC_PROFILES = [os.path.join(ROOT, "profiles", f) for f in ("fused_train_pass_traffic_100k_90x360_f64c_b16.md",
+                                                                  "compositing_traffic_100k_90x360_f64c_b16.md")]
 
 
 def kernel_source_hash(path):
@@ -340,20 +352,22 @@ def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
     when there is none or the kernel's source changed since it was taken."""
-    if not os.path.exists(TRAFFIC_PROFILE):
-        return None
-    text = open(TRAFFIC_PROFILE).read()
-    start = text.find("```json")
-    if start < 0:
-        return None
-    data = json.loads(text[start + 7:text.index("```", start + 7)])
-    k = data.get("kernels", {}).get(kernel)
-    if not k:
-        return None
-    src = os.path.join(ROOT, "paper_2511_22793_amd", "csrc", k["source"])
-    if kernel_source_hash(src) != k["source_sha256"]:
-        return None
-    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    for path in TRAFFIC_PROFILES:
+        if not os.path.exists(path):
+            continue
+        text = open(path).read()
+        start = text.find("```json")
+        if start < 0:
+            continue
+        data = json.loads(text[start + 7:text.index("```", start + 7)])
+        k = data.get("kernels", {}).get(kernel)
+        if not k:
+            continue
+        src = os.path.join(ROOT, "paper_2511_22793_amd", "csrc", k["source"])
+        if kernel_source_hash(src) != k["source_sha256"]:
+            return None
+        return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    return None
 
 
 # confidence head + Eq. (6) per sample: layer 1 (3x32 FMA), layer 2 (32 FMA),
