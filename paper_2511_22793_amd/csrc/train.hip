@@ -229,6 +229,10 @@ __global__ __launch_bounds__(64) void k_train_classify(TrArgs A)
 template <int E>
 struct TrOcc {
     static constexpr int waves = E <= 64 ? 4 : (E <= 128 ? 2 : 1);
+    // rows of s_a: the round's V block goes through it for walks of up to
+    // 128 entries (E = 128 keeps two workgroups per CU with it; E = 256
+    // would not fit, so it reads the other waves' columns from memory)
+    static constexpr int sa_rows = E <= 128 ? E : TR_CH;
 };
 
 // One unit (group grp, column range r of R) of kernel 1.  Returns early only
@@ -255,6 +259,45 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
     const int mp = nks * 4;
     const int neb = (m + 15) >> 4;
     for (int t = threadIdx.x; t < 16 * neb; t += blockDim.x) L.voff[t] = (t < m ? L.g[t] : L.g[0]) * (uint32_t)A.Fc;
+    __syncthreads();
+
+    // The (F) products take the group's pixels in an interleaved order:
+    // row m of output block pb is pixel 4 m + pb, so that a lane's four A
+    // operands of one K-step (one entry, pixels 4 l16 .. 4 l16 + 3) are one
+    // 16-byte LDS read.  A lane then holds rows 4 j4 + i of each block, i.e.
+    // pixel 16 j4 + 4 i + pb (read from LDS where used).
+    auto pixY = [&](int pb, int i) -> int { return L.pix[16 * j4 + 4 * i + pb]; };
+    const int nrounds = (cb_hi - cb_lo + TR_WAVES - 1) / TR_WAVES;
+    // Memory operations complete in issue order for the wait counter, so a
+    // wait for a load also waits for every atomic issued before it.  A round
+    // therefore issues the next round's (F) operands (first chain) and target
+    // words before its own attribute-gradient atomics: the next round's first
+    // wait leaves those atomics in flight.
+    constexpr int KCH = (E < 128 ? E : 128) / 4;  // K-steps of one chain
+    float bq[KCH];   // V words of the next chain
+    float tcur[16];  // target words of this wave's block
+    auto round_load = [&](int rd_) {
+        const int cb_ = cb_lo + rd_ * TR_WAVES + wave;
+        if (rd_ >= nrounds || cb_ >= cb_hi) return;
+        const int s_ = cb_ * 16 / A.Fc;
+        const int c_ = cb_ * 16 - s_ * A.Fc;
+        const __amdgpu_buffer_rsrc_t rv_ = tr_rsrc(A.attr + s_ * A.a_stride);
+#pragma unroll
+        for (int q = 0; q < KCH; ++q)
+            if (q < nks) bq[q] = tr_ld(rv_, (L.voff[4 * q + j4] + (uint32_t)(c_ + l16)) * 4u);
+        const __amdgpu_buffer_rsrc_t rt = tr_rsrc(A.tgt + (size_t)s_ * F * HW * 2);
+        const int cl = c_ + l16;
+        const uint32_t plane = (uint32_t)((cl >> 1) * HW * 2 + (cl & 1));
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = pixY(pb, i);
+                tcur[4 * pb + i] = tr_ld(rt, px >= 0 ? (plane + 2u * px) * 4u : TR_OOB);
+            }
+    };
+    // the first round's loads fly during the weights' walk
+    round_load(0);
 
     // prefix transmittance and weights chunk by chunk: alpha by all waves,
     // the walk by one (lane = pixel, in list order: the operations of the
@@ -286,12 +329,6 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
         __syncthreads();
     }
 
-    // The (F) products take the group's pixels in an interleaved order:
-    // row m of output block pb is pixel 4 m + pb, so that a lane's four A
-    // operands of one K-step (one entry, pixels 4 l16 .. 4 l16 + 3) are one
-    // 16-byte LDS read.  A lane then holds rows 4 j4 + i of each block, i.e.
-    // pixel 16 j4 + 4 i + pb (read from LDS where used).
-    auto pixY = [&](int pb, int i) -> int { return L.pix[16 * j4 + 4 * i + pb]; };
     constexpr int NEB = E / 16;
     f32x4t gv[NEB];  // GV[16 eb + 4 j4 + i][16 wave + l16], over this unit's columns
 #pragma unroll
@@ -299,36 +336,6 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
     float lsum = 0.0f;
     int lset = -1;
 
-    const int nrounds = (cb_hi - cb_lo + TR_WAVES - 1) / TR_WAVES;
-    // Memory operations complete in issue order for the wait counter, so a
-    // wait for a load also waits for every atomic issued before it.  A round
-    // therefore issues the next round's (F) operands (first chain) and target
-    // words before its own attribute-gradient atomics: the next round's first
-    // wait leaves those atomics in flight.
-    constexpr int KCH = (E < 128 ? E : 128) / 4;  // K-steps of one chain
-    float bq[KCH];   // V words of the next chain
-    float tcur[16];  // target words of this wave's block
-    auto round_load = [&](int rd_) {
-        const int cb_ = cb_lo + rd_ * TR_WAVES + wave;
-        if (rd_ >= nrounds || cb_ >= cb_hi) return;
-        const int s_ = cb_ * 16 / A.Fc;
-        const int c_ = cb_ * 16 - s_ * A.Fc;
-        const __amdgpu_buffer_rsrc_t rv_ = tr_rsrc(A.attr + s_ * A.a_stride);
-#pragma unroll
-        for (int q = 0; q < KCH; ++q)
-            if (q < nks) bq[q] = tr_ld(rv_, (L.voff[4 * q + j4] + (uint32_t)(c_ + l16)) * 4u);
-        const __amdgpu_buffer_rsrc_t rt = tr_rsrc(A.tgt + (size_t)s_ * F * HW * 2);
-        const int cl = c_ + l16;
-        const uint32_t plane = (uint32_t)((cl >> 1) * HW * 2 + (cl & 1));
-#pragma unroll
-        for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int px = pixY(pb, i);
-                tcur[4 * pb + i] = tr_ld(rt, px >= 0 ? (plane + 2u * px) * 4u : TR_OOB);
-            }
-    };
-    round_load(0);
     for (int rd = 0; rd < nrounds; ++rd) {
         const int cb = cb_lo + rd * TR_WAVES + wave;
         const bool own = cb < cb_hi;
@@ -416,7 +423,7 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
         }
         __syncthreads();
         // (G) GV[k][16 wave + l16] += sum over the round's columns of v(k, c) g(p, c)
-        if constexpr (E == 64) {
+        if constexpr (E <= 128) {
             // The round's V block is the four waves' (F) operands: it goes
             // through s_a too (after each wave has taken its g words), so
             // that no wave reads the other waves' columns from memory.
@@ -536,7 +543,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TrOcc<E>::w
                                                                                                       int c)
 {
     __shared__ TrLds<E> L;
-    __shared__ __align__(16) float s_a[TR_CH][TR_PAD];  // alpha of a chunk, then the exchange of g
+    // alpha of a chunk, then the exchange of g, then (E <= 128) the round's V block
+    __shared__ __align__(16) float s_a[TrOcc<E>::sa_rows][TR_PAD];
     __shared__ __align__(16) float s_w[E][TR_PAD];      // weights w_k(p)
     __shared__ uint32_t s_item;
     const uint32_t cnt = A.ctr[TR_CNT + c];
