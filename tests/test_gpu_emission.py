@@ -43,7 +43,10 @@ def dev(a):
 
 
 @pytest.mark.parametrize("n,Q,seed,H", [(1, 1, 1, 16), (1000, 1, 2, 16), (1000, 16, 3, 16), (257, 7, 4, 16),
-                                       (100_000, 16, 5, 16), (1000, 16, 7, 8), (1000, 16, 8, 64)])
+                                       (100_000, 16, 5, 16), (1000, 16, 7, 8), (1000, 16, 8, 64),
+                                       # width 64 takes eight lanes per Gaussian: a ragged last wave and
+                                       # workgroup (261 = 8 * 32 + 5), and one Gaussian
+                                       (261, 5, 9, 64), (1, 3, 10, 64)])
 def test_emission_matches_oracle(n, Q, seed, H):
     P, mean, rx, tx = case(n, Q, seed, H)
     Pt = dev(np.ascontiguousarray(P.T))      # [98, n]
