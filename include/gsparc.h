@@ -357,6 +357,10 @@ gs_status gs_spatial_mean(const float* spectrum, int32_t n_sets, int32_t n_chan,
  *   loss [S], h_hat [S][F][2]: outputs (per-set loss, Eq. (2) of the
  *                rendered spectra, formed from the live pass's per-Gaussian
  *                weight sums: h_hat = (1/HW) sum_g (sum_p w_g(p)) v_g).
+ *   grad_scale   NULL, or a device float c: every gradient output is that
+ *                of c L (the loss outputs stay those of L).  The
+ *                confidence-weighted objective of Eq. (6) with the sets'
+ *                shared receiver: c = C(x_rx) from gs_confidence_loss().
  * spectrum: [S][F][H][W][2], written in full with GS_TRAIN_WRITE_SPECTRUM
  *   (bit-identical to gs_render_blend()), else used only for the groups of
  *   64 pixels whose walk exceeds 256 list entries (those take the unfused
@@ -378,6 +382,7 @@ typedef struct {
     float lambda_ch;
     float* loss;
     float* h_hat;
+    const float* grad_scale;
 } gs_train_target;
 #define GS_TRAIN_WRITE_SPECTRUM 2 /* flags: also store the spectra */
 size_t gs_train_scratch_bytes(int32_t n_sets, int32_t n_chan, const gs_grid* grid);
@@ -537,10 +542,16 @@ gs_status gs_overflow_word(const void* workspace, size_t ws_bytes, int32_t n, in
  *   d loss[b] / d task_loss[b] (the factor on the task loss gradient).
  * Gradients of sum_b loss[b]: dW1 [32][3], db1 [32], dw2 [32], db2 [1],
  * overwritten.  Layout: W1 row-major [32][3], all FP32 device pointers,
- * caller-owned; the paper's alpha is 0.3.  One workgroup; the weight
- * gradients are summed in a fixed order (deterministic).
+ * caller-owned; the paper's alpha is 0.3.  Up to 4096 samples one
+ * workgroup does everything (scratch may be NULL); beyond, up to 1024
+ * workgroups write partial gradient sums to `scratch` (>=
+ * gs_confidence_scratch_bytes(n) bytes, 256-byte aligned, caller-owned
+ * device memory, its contents not needed before or after the call) and one
+ * more workgroup adds them.  Either way the weight gradients are summed in
+ * an order fixed by n alone (deterministic).
  * Errors: GS_ERR_INVALID_ARG for a null pointer, n < 1 or alpha negative or
- * not finite; GS_ERR_CAPACITY for n > 65536. */
+ * not finite; GS_ERR_CAPACITY for n > 2^24; GS_ERR_WORKSPACE for missing,
+ * misaligned or short scratch when n > 4096. */
 /* ---- the paper's own emission form: one network per Gaussian (Sec. 4.1, Eq. (1)) ----
  * Gaussian i owns a 3 -> H -> 2 network, H = hidden in {8, 16, 64} (16 in
  * the paper, 8 and 64 in its width ablation): 6H + 2 FP32 parameters, stored
@@ -567,9 +578,11 @@ gs_status gs_emission_backward(const float* params, int64_t param_stride, int32_
                                const float* d_attr, int64_t attr_query_stride, float* d_params, float* d_mean,
                                void* stream);
 
+size_t gs_confidence_scratch_bytes(int32_t n); /* 0 when n <= 4096 or n > 2^24 */
 gs_status gs_confidence_loss(const float* x_rx, const float* task_loss, int32_t n, const float* W1,
                              const float* b1, const float* w2, const float* b2, float alpha, float* conf,
-                             float* loss, float* dW1, float* db1, float* dw2, float* db2, void* stream);
+                             float* loss, float* dW1, float* db1, float* dw2, float* db2, void* scratch,
+                             size_t scratch_bytes, void* stream);
 
 /*
  * Batched serving: many queries over several scenes of uneven size, grid,

@@ -80,7 +80,8 @@ class GsL2Grad(ctypes.Structure):
 
 
 class GsTrainTarget(ctypes.Structure):
-    _fields_ = [("target", c_p), ("target_mean", c_p), ("lambda_ch", c_f32), ("loss", c_p), ("h_hat", c_p)]
+    _fields_ = [("target", c_p), ("target_mean", c_p), ("lambda_ch", c_f32), ("loss", c_p), ("h_hat", c_p),
+                ("grad_scale", c_p)]
 
 
 GS_BWD_ATTR_GRAD_ZEROED = 1
@@ -159,7 +160,9 @@ SIGNATURES = {
     "gs_emission_forward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p]),
     "gs_emission_backward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p, c_p,
                                      c_p]),
-    "gs_confidence_loss": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_f32, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "gs_confidence_scratch_bytes": (c_sz, [c_i32]),
+    "gs_confidence_loss": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_f32, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
+                                   c_sz, c_p]),
     "gs_batch_plan_bytes": (c_sz, [c_i32]),
     "gs_batch_plan": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, ctypes.POINTER(GsBatchInfo), c_p]),
     "gs_batch_run": (c_i32, [ctypes.POINTER(GsBatchJob), c_i32, c_p, c_sz, c_i32, c_p, c_p]),

@@ -412,6 +412,7 @@ struct SgUp {  // upstream gradient g = upstream + mean term
     const float* tgt;
     const float* mgrad;
     float scale;
+    const float* gscale;  // with tgt: device factor on scale (the mean term carries it already), or null
 };
 
 // Raw upstream words of one element: dout, or (out, target) with TGT.
@@ -450,9 +451,11 @@ template <int CS, bool TGT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_bwd_sg(
     const GRec* __restrict__ rec, const uint32_t* __restrict__ plist, const uint2* __restrict__ ranges,
     const float* __restrict__ attr, int64_t a_stride, int S, int Fc, int H, int W, int tw_log, int th, int TX,
-    float amin, float amax, SgUp up, const uint32_t* __restrict__ n_last, float* __restrict__ gacc,
+    float amin, float amax, SgUp up_in, const uint32_t* __restrict__ n_last, float* __restrict__ gacc,
     float* __restrict__ d_attr, int64_t da_stride, int min_walk, float* __restrict__ lacc)
 {
+    SgUp up = up_in;
+    if (TGT && up.gscale) up.scale *= *up.gscale;
     const int tw = 1 << tw_log;
     const int tile = blockIdx.x, pg = blockIdx.y;
     // (wave-uniform values go through readfirstlane so that they live in
@@ -885,11 +888,11 @@ static void bwd_cg(dim3 grid, dim3 block, hipStream_t s, const gs_attrs& a, cons
 // their pixels is added to lacc[set]
 void launch_blend_bwd_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                               const float* out, const float* target, const float* mean_grad, float scale,
-                              float* d_attr, int min_walk, float* lacc, hipStream_t s)
+                              const float* gscale, float* d_attr, int min_walk, float* lacc, hipStream_t s)
 {
     int tw_log = 0;
     while ((1 << tw_log) < L.tw) ++tw_log;
-    const SgUp sup{out, nullptr, target, mean_grad, scale};
+    const SgUp sup{out, nullptr, target, mean_grad, scale, gscale};
     const int Fc = a.n_chan * (a.is_complex ? 2 : 1);
     auto kern = a.is_complex ? k_blend_bwd_sg<1, true> : k_blend_bwd_sg<0, true>;
     hipLaunchKernelGGL(kern, dim3(L.T, (L.tw * L.th) / SG_PIX), dim3(SG_WAVES * 64), 0, s, (const GRec*)(ws + L.rec),
@@ -918,7 +921,7 @@ gs_status launch_blend_bwd(const gs_attrs& a, const gs_params& p, const Layout& 
         // one geometry for every set: the factorised backward
         int tw_log = 0;
         while ((1 << tw_log) < L.tw) ++tw_log;
-        const SgUp sup{out, up.dout, up.target, up.mean_grad, up.scale};
+        const SgUp sup{out, up.dout, up.target, up.mean_grad, up.scale, nullptr};
         const dim3 grid(L.T, (L.tw * L.th) / SG_PIX), block(SG_WAVES * 64);
         void* tok;
         timing_begin(TK_BLEND_BWD, s, &tok);

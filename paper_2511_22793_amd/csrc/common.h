@@ -191,7 +191,7 @@ void launch_blend_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L
                           int min_walk, hipStream_t s);
 void launch_blend_bwd_sg_long(const gs_attrs& a, const gs_params& p, const Layout& L, int n_sets, char* ws,
                               const float* out, const float* target, const float* mean_grad, float scale,
-                              float* d_attr, int min_walk, float* lacc, hipStream_t s);
+                              const float* gscale, float* d_attr, int min_walk, float* lacc, hipStream_t s);
 void launch_geo_fold(const Layout& L, char* ws, hipStream_t s);
 void launch_project_bwd(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,
                         const Layout& L, char* ws, float* d_mean, float* d_log_scale, float* d_quat, float* d_opac,

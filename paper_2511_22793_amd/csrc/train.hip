@@ -183,6 +183,7 @@ struct TrArgs {
     uint32_t* cls;       // group lists of the three walk classes [3][groups]
     uint32_t* ctr;       // class sizes, then the work counters of both kernels
     float* gacc;         // per-pair geometric accumulators [pairs][8]
+    const float* gscale; // device scale c of every gradient, or null
     int S, Fc, H, W, tw, th, TX, gpt, groups;
     int rmin, rmax;      // bounds of a class's column split
     float amin, amax;
@@ -252,6 +253,9 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
     const int F = A.Fc >> 1;
     const int ncb = A.S * A.Fc / 16;
     const int cb_lo = r * ncb / R, cb_hi = (r + 1) * ncb / R;
+    // e, times the gradient scale c when one is given (the mean term m
+    // carries c already)
+    const float escale = A.gscale ? A.escale * *A.gscale : A.escale;
     uint32_t stop;
     const int m = tr_group<E>(L, A.rec, A.plist, rg, A.n_last, pg, vw, vh, txi, tyi, A.tw, A.th, A.W, lo, stop);
     if (m < 0) return;
@@ -400,7 +404,7 @@ __device__ __forceinline__ void tr_fb_unit(const TrArgs& A, TrLds<E>& L, float (
                     if (px >= 0) {
                         const float d = z[pb][i] - tcur[4 * pb + i];
                         ls = fmaf(d, d, ls);
-                        z[pb][i] = fmaf(A.escale, d, mc);
+                        z[pb][i] = fmaf(escale, d, mc);
                     } else {
                         z[pb][i] = 0.0f;
                     }
@@ -725,21 +729,24 @@ __global__ __launch_bounds__(256) void k_train_hsum(const uint32_t* __restrict__
     }
 }
 
-// h_hat = hs / HW; m = lambda 2 (h_hat - h) / (HW S); loss[s] = lambda sum_c
-// (h_hat - h)^2 (the pixel term is added by k_train_loss_add)
+// h_hat = hs / HW; m = c lambda 2 (h_hat - h) / (HW S) (c = the gradient
+// scale, 1 without one); loss[s] = lambda sum_c (h_hat - h)^2 (the pixel
+// term is added by k_train_loss_add)
 __global__ __launch_bounds__(256) void k_train_hfinish(const float* __restrict__ hs, const float* __restrict__ h,
                                                        int S, int Fc, float inv_hw, float lambda,
+                                                       const float* __restrict__ gscale,
                                                        float* __restrict__ h_hat, float* __restrict__ mgrad,
                                                        float* __restrict__ loss)
 {
     const int s = blockIdx.x;
+    const float cs = gscale ? *gscale : 1.0f;
     float part = 0.0f;
     for (int c = threadIdx.x; c < Fc; c += blockDim.x) {
         const size_t i = (size_t)s * Fc + c;
         const float hh = hs[i] * inv_hw;
         const float d = hh - h[i];
         h_hat[i] = hh;
-        mgrad[i] = lambda * 2.0f * d * inv_hw / (float)S;
+        mgrad[i] = cs * (lambda * 2.0f * d * inv_hw / (float)S);
         part = fmaf(d, d, part);
     }
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
@@ -933,7 +940,7 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     hipLaunchKernelGGL(k_train_hsum, dim3((scene->n + 1023) / 1024, n_sets), dim3(128), 0, s, live_list, live_count,
                        (const float*)(ws + L.wtot), attrs->data, attrs->query_stride, Fc, hs);
     hipLaunchKernelGGL(k_train_hfinish, dim3(n_sets), dim3(256), 0, s, hs, tt->target_mean, n_sets, Fc,
-                       1.0f / (float)HW, tt->lambda_ch, tt->h_hat, mg, tt->loss);
+                       1.0f / (float)HW, tt->lambda_ch, tt->grad_scale, tt->h_hat, mg, tt->loss);
 
     TrArgs A{};
     A.rec = (const GRec*)(ws + L.rec);
@@ -953,6 +960,7 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     A.cls = (uint32_t*)(sc + ts.cls);
     A.ctr = ctr;
     A.gacc = (float*)(ws + L.gacc);
+    A.gscale = tt->grad_scale;
     A.S = n_sets;
     A.Fc = Fc;
     A.H = L.H;
@@ -984,8 +992,8 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     // groups whose walk is longer than the fused kernels take: compositing
     // into the spectrum, then the backward forming g from it and the target
     launch_blend_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, TR_EMAX, s);
-    launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, d_attr, TR_EMAX, llong,
-                             s);
+    launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, tt->grad_scale, d_attr,
+                             TR_EMAX, llong, s);
     hipLaunchKernelGGL(k_train_loss_add, dim3(1), dim3(64), 0, s, lacc, llong, n_sets, lscale, tt->loss);
     launch_geo_fold(L, ws, s);
     launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);

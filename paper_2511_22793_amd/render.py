@@ -447,12 +447,13 @@ def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.
                spectrum: Optional[torch.Tensor] = None, write_spectrum: bool = False,
                d_attr: Optional[torch.Tensor] = None, out: Optional[dict] = None,
                scratch: Optional[TrainScratch] = None, loss: Optional[torch.Tensor] = None,
-               h_hat: Optional[torch.Tensor] = None):
+               h_hat: Optional[torch.Tensor] = None, grad_scale: Optional[torch.Tensor] = None):
     """Fused compositing + loss + backward over S complex attribute sets
     sharing the workspace's one prepared receiver (gs_render_train), after
     live().  attr [S,n,F,2]; target [S,F,H,W,2]; target_mean [S,F,2]
-    (spatial_mean of the target).  Returns (loss [S], h_hat [S,F,2],
-    gradients dict, spectrum)."""
+    (spatial_mean of the target); grad_scale: optional device float c, every
+    gradient then that of c L.  Returns (loss [S], h_hat [S,F,2], gradients
+    dict, spectrum)."""
     sc = _scene_c(scene)
     n = sc.n
     if attr.dim() != 4:
@@ -464,6 +465,9 @@ def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.
     shape = (S, F, H, W, 2)
     _check_f32("target", target, shape)
     _check_f32("target_mean", target_mean, (S, F, 2))
+    if grad_scale is not None and (not grad_scale.is_cuda or grad_scale.dtype != torch.float32 or
+                                   grad_scale.numel() < 1):
+        raise ValueError("grad_scale: a float32 CUDA tensor expected")
     if spectrum is None:
         spectrum = torch.empty(shape, device=dev)
     else:
@@ -477,7 +481,8 @@ def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.
         "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
     flags = (1 if d_attr is not None else 0) | (GS_TRAIN_WRITE_SPECTRUM if write_spectrum else 0)
     g["d_attr"] = d_attr if d_attr is not None else torch.empty_like(attr)
-    tt = GsTrainTarget(_ptr(target), _ptr(target_mean), float(lambda_ch), _ptr(loss), _ptr(h_hat))
+    tt = GsTrainTarget(_ptr(target), _ptr(target_mean), float(lambda_ch), _ptr(loss), _ptr(h_hat),
+                       _ptr(grad_scale) if grad_scale is not None else None)
     q = GsQueries(1, _ptr(rx), None)
     gr, p = workspace.grid.c(), workspace.params.c()
     stream = torch.cuda.current_stream(dev).cuda_stream

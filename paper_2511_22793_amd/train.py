@@ -12,6 +12,9 @@ One step, all on the device with no host synchronisation:
   network backward -> weight, bias and embedding gradients
   fused Adam over every parameter group (Table 2 learning rates; the
   position rate decays exponentially)
+Optionally (confidence=True) the confidence-weighted objective of Eq. (6):
+the head's C for the receiver scales every gradient of the pass, and the
+head itself trains on the step's task losses.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
+from . import confidence as gc
 from . import mlp as gm
 from .render import (Grid, Params, TrainScratch, Workspace, backward, backward_l2, blend, blend_loss, live,
                      loss_spectrum, loss_stats, prepare, spatial_mean, train_pass)
@@ -57,13 +61,16 @@ class LearnedScene:
     def __init__(self, scene: dict, embeddings: np.ndarray, weights: dict, rx, batch: int, box_lo, box_hi,
                  grid: Grid = Grid(), params: Params = Params(), rates: Rates = Rates(), total_steps: int = 1000,
                  train_geometry: bool = True, lambda_ch: float = 1.0, loss_mode: str = "train_pass",
-                 keep_spectra: bool = False, device="cuda"):
+                 keep_spectra: bool = False, confidence: bool = False, conf_alpha: float = gc.ALPHA,
+                 conf_weights: dict = None, device="cuda"):
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
         if loss_mode not in ("train_pass", "fused", "partial", "target", "two_pass"):
             raise ValueError("loss_mode is 'train_pass', 'fused', 'partial', 'target' or 'two_pass'")
         self.loss_mode = loss_mode
+        if confidence and loss_mode != "train_pass":
+            raise ValueError("the confidence-weighted objective (Eq. (6)) runs with loss_mode 'train_pass'")
         # train_pass: also store the step's spectra in self.spec (the other
         # modes always do)
         self.keep_spectra = keep_spectra
@@ -98,6 +105,18 @@ class LearnedScene:
         # completed steps, on the device: Adam reads its step number and the
         # position rate's schedule from it (so a captured step replays)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        # Eq. (6): the confidence head C = 1 + exp(g(x_rx)) on the receiver;
+        # every set of the batch is one sample with the shared receiver, so C
+        # is one number per step and scales every task-loss gradient
+        self.confidence, self.conf_alpha = confidence, conf_alpha
+        if confidence:
+            w = conf_weights if conf_weights is not None else gc.init_weights(0, device=dev)
+            self.conf_w = {k: v.to(dev, torch.float32).contiguous().clone() for k, v in w.items()}
+            self.conf_x = self.rx.expand(batch, 3).contiguous()
+            self.conf_zero = torch.zeros(batch, device=dev)
+            self.conf_c = torch.empty(batch, device=dev)
+            self.conf_loss = torch.empty(batch, device=dev)
+            self.conf_grads = {k: torch.empty_like(v) for k, v in self.conf_w.items()}
 
     def _rows(self, tx):
         return gm.Rows(tx, self.live_list[0], self.live_count, row_cap=self.n)
@@ -139,10 +158,23 @@ class LearnedScene:
             # or spectrum gradients in memory)
             if target_mean is None:
                 target_mean = spatial_mean(target, True)
+            scale = None
+            if self.confidence:
+                # C first (it does not depend on the task loss): it scales the
+                # pass's gradients
+                gc.confidence_loss(self.conf_x, self.conf_zero, self.conf_w, self.conf_alpha,
+                                   out=(self.conf_c, self.conf_loss, self.conf_grads))
+                scale = self.conf_c[:1]
             loss, _, _, _ = train_pass(self.ws, sc, self.attr, self.rx, self.live_list[0], self.live_count, target,
                                        target_mean, self.lambda_ch, spectrum=self.spec,
                                        write_spectrum=self.keep_spectra, d_attr=self.d_attr, out=self.ggrads,
-                                       scratch=self.tscratch, loss=self.loss, h_hat=self.h_hat)
+                                       scratch=self.tscratch, loss=self.loss, h_hat=self.h_hat, grad_scale=scale)
+            if self.confidence:
+                # Eq. (6) per sample with the step's task losses: the
+                # confidence-weighted loss and the head's gradients (of the
+                # batch sum; Adam does not see the constant factor)
+                gc.confidence_loss(self.conf_x, self.loss, self.conf_w, self.conf_alpha,
+                                   out=(self.conf_c, self.conf_loss, self.conf_grads))
             mark("train_pass")
         elif self.loss_mode == "fused":
             # the loss pass folded into the compositing kernel's output stage:
@@ -193,6 +225,11 @@ class LearnedScene:
         m, v = self._moment("E", self.E)
         segs.append((self.E, self.mgrads["E"], m, v, self.E_bf, r.embedding))
         final.append(r.embedding)
+        if self.confidence:
+            for k in ("W1", "b1", "w2", "b2"):
+                m, v = self._moment("conf_" + k, self.conf_w[k])
+                segs.append((self.conf_w[k], self.conf_grads[k], m, v, None, r.mlp))
+                final.append(r.mlp)
         if self.train_geometry:
             for k, lr, lr1 in (("mean", r.position, r.position_final), ("log_scale", r.scaling, r.scaling),
                                ("quat", r.rotation, r.rotation), ("opacity_logit", r.opacity, r.opacity)):

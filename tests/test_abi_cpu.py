@@ -216,3 +216,22 @@ def test_l1_ssim_rejects_bad_arguments_on_host():
     assert call(args(nb=need - 1)) == _lib.GS_ERR_WORKSPACE
     assert call(args(sc=ctypes.c_void_p(0x100010))) == _lib.GS_ERR_WORKSPACE
     assert call(args(S=300, F=300)) == _lib.GS_ERR_CAPACITY
+
+
+def test_confidence_rejects_bad_arguments_on_host():
+    L = _lib.lib()
+    assert L.gs_confidence_scratch_bytes(4096) == 0
+    need = L.gs_confidence_scratch_bytes(4097)
+    assert need == 17 * 192 * 4  # 17 chunks of 256 samples, one workgroup each: their partials
+    assert L.gs_confidence_scratch_bytes(1 << 24) == 1024 * 192 * 4
+    w = [FAKE] * 4
+
+    def call(n, sc=ctypes.c_void_p(0x100000), nb=None, alpha=0.3):
+        return L.gs_confidence_loss(FAKE, FAKE, n, *w, alpha, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, sc,
+                                    need if nb is None else nb, None)
+    assert call(0) == _lib.GS_ERR_INVALID_ARG
+    assert call(10, alpha=-1.0) == _lib.GS_ERR_INVALID_ARG
+    assert call((1 << 24) + 1) == _lib.GS_ERR_CAPACITY
+    assert call(4097, sc=None) == _lib.GS_ERR_WORKSPACE
+    assert call(4097, nb=need - 1) == _lib.GS_ERR_WORKSPACE
+    assert call(4097, sc=ctypes.c_void_p(0x100010)) == _lib.GS_ERR_WORKSPACE

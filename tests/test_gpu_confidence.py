@@ -44,7 +44,11 @@ def run(x, L, w, alpha):
 
 
 @pytest.mark.parametrize("n,seed,alpha", [(1, 1, 0.3), (7, 2, 0.3), (16, 3, 0.3), (1000, 4, 0.3), (777, 5, 0.0),
-                                          (65536, 6, 0.3)])
+                                          (4096, 10, 0.3),
+                                          # the multi-workgroup path: one chunk past the single
+                                          # workgroup's limit, a ragged last chunk, and more chunks
+                                          # than workgroups (1024 x 256 = 262144)
+                                          (4097, 11, 0.3), (65536, 6, 0.3), (300_001, 12, 0.3)])
 def test_confidence_matches_oracle(n, seed, alpha):
     x, L, w = case(n, seed)
     conf, loss, g = run(x, L, w, alpha)
@@ -66,9 +70,12 @@ def test_deterministic_and_input_checks():
         assert np.array_equal(a[2][k], b[2][k])
     d = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).cuda()  # noqa: E731
     wt = {k: d(v) for k, v in w.items()}
-    with pytest.raises(GsError) as e:
-        gs.confidence_loss(d(np.zeros((65537, 3), np.float32)), d(np.zeros(65537, np.float32)), wt)
-    assert e.value.status == GS_ERR_CAPACITY
+    # the multi-workgroup path is deterministic too
+    x2, L2, w2 = case(20_000, 13)
+    a = run(x2, L2, w2, 0.3)
+    b = run(x2, L2, w2, 0.3)
+    for k in a[2]:
+        assert np.array_equal(a[2][k], b[2][k])
     with pytest.raises(GsError) as e:
         gs.confidence_loss(d(x), d(L), wt, alpha=-0.1)
     assert e.value.status == GS_ERR_INVALID_ARG
