@@ -295,7 +295,8 @@ def main():
     if not args.no_configs:
         res["configs"] = other_configs(args, gs, train, dev)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(gt, rho, tx_all, H, W, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(gt, rho, tx_all, H, W, args.cpu_seconds,
+                                           gpu_forward=res.get("serving", {}).get("spectra_per_s"))
     print(json.dumps(res), flush=True)
 
 
@@ -661,25 +662,62 @@ def plain(args, gs, train, scene, emb, gt, rho, tx_all, grid, targets, target_me
             "training": "one-query training steps, same stages"}
 
 
-def cpu_baseline(gt, rho, tx_all, H, W, seconds):
+def cpu_baseline(gt, rho, tx_all, H, W, seconds, gpu_forward=None):
     """The FP64 oracle on the host cores: full spectra (64 complex
     subcarriers, fixed attributes) of the same scene size, as many queries
-    as fit in `seconds`."""
+    as fit in `seconds`, with every host thread; then the same at one thread
+    and at T_min = 0 (every walk to the end of its list), a third of the time
+    each.  The oracle renders forward only (it has no batched backward), so
+    the headline's training unit has no oracle counterpart: the forward-only
+    GPU rate of the same workload (`gpu_forward`, spectra/s) stands beside
+    it, with the ratio."""
     import oracle
-    from paper_2511_22793_amd import train
     threads = min(os.cpu_count() or 1, 64)
-    t = time.perf_counter()
-    k = 0
-    while True:
-        attr = synth.ground_truth_attributes(gt, rho, tx_all[k % len(tx_all):k % len(tx_all) + 1])[0]
-        oracle.render(gt, attr, [0, 0, 0], H, W, nthreads=threads)
-        k += 1
-        if time.perf_counter() - t >= seconds and k >= 2:
-            break
-    dt = time.perf_counter() - t
-    return {"value": round(k / dt, 4), "unit": "spectra/s", "cores": threads, "kind": "oracle",
-            "sample": "%d full %dx%d forward spectra (64 complex subcarriers, fixed attributes) of a %d-Gaussian "
-                      "scene; the oracle has no batched backward" % (k, H, W, gt["opacity_logit"].shape[0])}
+
+    # the inputs (attributes for a few transmitters) are formed outside the
+    # timed region
+    attrs = [synth.ground_truth_attributes(gt, rho, tx_all[i:i + 1])[0] for i in range(min(4, len(tx_all)))]
+
+    def run(nthreads, budget, prm=None, stride=1):
+        # stride > 1: the per-pixel compositing over every stride-th pixel
+        # only, its time scaled by stride (the work per pixel is the same);
+        # projection and depth order run in full and count once
+        pix = None if stride == 1 else np.arange(0, H * W, stride, dtype=np.int32)
+        t_all = 0.0  # estimated time of k whole spectra
+        k = 0
+        start = time.perf_counter()
+        while True:
+            attr = attrs[k % len(attrs)]
+            t0 = time.perf_counter()
+            proj = oracle.project(gt, [0, 0, 0], H, W, prm)
+            order = oracle.depth_order(proj)
+            t1 = time.perf_counter()
+            oracle.composite(proj, order, attr, H, W, prm, pixels=pix, nthreads=nthreads)
+            t2 = time.perf_counter()
+            t_all += (t1 - t0) + (t2 - t1) * stride
+            k += 1
+            if time.perf_counter() - start >= budget and k >= 2:
+                break
+        return k, t_all
+
+    k, dt = run(threads, seconds)
+    out = {"value": round(k / dt, 4), "unit": "spectra/s", "cores": threads, "kind": "oracle",
+           "sample": "%d full %dx%d forward spectra (64 complex subcarriers, fixed attributes) of a %d-Gaussian "
+                     "scene (projection, depth order, compositing; attributes formed beforehand); the oracle "
+                     "has no batched backward" % (k, H, W, gt["opacity_logit"].shape[0])}
+    k1, dt1 = run(1, seconds / 3.0, stride=16)
+    out["one_thread"] = {"value": round(k1 / dt1, 4), "unit": "spectra/s", "cores": 1,
+                         "sample": "%d spectra, compositing timed at every 16th pixel and scaled" % k1}
+    k0, dt0 = run(threads, seconds / 3.0, prm=oracle.params(T_min=0.0), stride=64)
+    out["t_min_0"] = {"value": round(k0 / dt0, 4), "unit": "spectra/s", "cores": threads,
+                      "sample": "%d spectra with T_min = 0 (every walk to the end of its list), compositing "
+                                "timed at every 64th pixel and scaled" % k0}
+    if gpu_forward:
+        out["gpu_forward_same_workload"] = {"value": gpu_forward, "unit": "spectra/s",
+                                            "ratio_to_oracle": round(gpu_forward / out["value"], 1),
+                                            "what": "the serving forward (network + prepare + live + blend) of "
+                                                    "the same scene and grid, per spectrum"}
+    return out
 
 
 if __name__ == "__main__":
