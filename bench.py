@@ -612,7 +612,9 @@ def serving_mix(args, gs, dev):
     e1.synchronize()
     ms_plain = e0.elapsed_time(e1)
     nq = batch.n_queries
+    ws_bytes = sum(w.nbytes for w in batch.workspaces)
     return {"queries": nq, "scenes": [j.signature() for j in batch.jobs],
+            "workspace_bytes": ws_bytes, "pair_capacity": [int(j.params.pair_capacity) for j in batch.jobs],
             "tuned": {"block": tuner.choice["block"], "workgroups": tuner.choice.get("workgroups"),
                       "tiles_and_groups": [list(x[1:]) for x in tuner.choice["jobs"]], "tune_s": round(tune_s, 2)},
             "ms_per_batch": round(ms_batch, 4), "makespan_ms_device": round(float(np.mean(spans)), 4),

@@ -208,6 +208,24 @@ def prepare(scene: dict, rx: torch.Tensor, tx: Optional[torch.Tensor] = None, gr
     return workspace
 
 
+def fit_pair_capacity(scene: dict, rx: torch.Tensor, tx: Optional[torch.Tensor] = None, grid: Grid = Grid(),
+                      params: Params = Params(), headroom: float = 2.0) -> Params:
+    """Params whose pair_capacity fits these queries of a static scene: one
+    prepare with the default capacity (n min(tiles, 64) + 4096 pairs per
+    query, several times what scenes of the benchmark's kind need), then
+    headroom times the largest measured pair count plus 4096.  The workspace
+    of a static serving scene shrinks accordingly; a scene whose geometry
+    changes keeps the default (an overflow is detected and flagged, see
+    gs_read_flags)."""
+    from dataclasses import replace
+    ws = prepare(scene, rx, tx=tx, grid=grid, params=replace(params, pair_capacity=0))
+    fl = ws.flags()
+    if any(f["overflow"] for f in fl):
+        return replace(params, pair_capacity=0)
+    need = max(f["n_pairs"] for f in fl)
+    return replace(params, pair_capacity=int(headroom * need) + 4096)
+
+
 def blend(workspace: Workspace, attr: torch.Tensor, n_sets: Optional[int] = None, is_complex: bool = False,
           out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Compositing over a prepared workspace.  attr: [n_sets, n, F(,2)] (or

@@ -25,7 +25,7 @@ import numpy as np
 import torch
 
 from ._lib import GsBatchInfo, GsBatchJob, GsQueries, check, lib
-from .render import Grid, Params, Workspace, _attrs_c, _check_f32, _ptr, _scene_c
+from .render import Grid, Params, Workspace, _attrs_c, _check_f32, _ptr, _scene_c, fit_pair_capacity
 
 
 @dataclass
@@ -67,9 +67,15 @@ class Job:
 class Batch:
     """Device state of one batch; the jobs' order is the service order."""
 
-    def __init__(self, jobs: list, workgroups: Optional[int] = None, device=None):
+    def __init__(self, jobs: list, workgroups: Optional[int] = None, device=None, fit_capacity: bool = True):
+        """fit_capacity: size each job's pair buffer from one prepare of its
+        queries (fit_pair_capacity; jobs whose params already set
+        pair_capacity keep it)."""
         if not jobs:
             raise ValueError("a batch needs at least one job")
+        if fit_capacity:
+            jobs = [replace(j, params=fit_pair_capacity(j.scene, j.rx, j.tx, j.grid, j.params))
+                    if j.params.pair_capacity == 0 else j for j in jobs]
         self.jobs = list(jobs)
         dev = device or jobs[0].rx.device
         self.device = dev

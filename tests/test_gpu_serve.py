@@ -155,6 +155,14 @@ def test_full_size_serving_mix_sampled():
     torch.cuda.synchronize()
     check_timestamps(batch)
     rng = np.random.default_rng(29)
+    # each job's pair buffer was fitted to its queries (twice the largest
+    # pair count): no overflow, and below the default capacity
+    # (n min(tiles, 64) + 4096)
+    for i, (j, ws) in enumerate(zip(batch.jobs, batch.workspaces)):
+        T = -(-j.grid.H // j.grid.tile_h) * -(-j.grid.W // j.grid.tile_w)
+        assert 0 < j.params.pair_capacity < j.n * min(T, 64) + 4096, j.signature()
+        assert ws.layout.pair_capacity == j.params.pair_capacity
+        assert max(f["n_pairs"] for f in batch.flags()[i]) <= j.params.pair_capacity
     for i, (sc, attr, rx, cplx, H, W) in enumerate(arrs):
         assert all(f["overflow"] == 0 for f in batch.flags()[i])
         q = int(rng.integers(0, rx.shape[0]))
