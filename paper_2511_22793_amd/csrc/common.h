@@ -140,7 +140,8 @@ struct FillSegs {
     int n;
 };
 void launch_fill_segs(const FillSegs& f, hipStream_t s);  // zero-fills f.n buffers (words)
-// fills [0, per_query * n_dev[q]) of each query, n_dev read on the device
+// fills [0, min(per_query * n_dev[q], max_count)) of each query, n_dev read
+// on the device
 void launch_fill_dev(uint32_t* p, size_t max_count, size_t q_stride, int nq, const uint32_t* n_dev, size_t n_stride,
                      uint32_t per_query, hipStream_t s);
 void launch_project(const gs_scene& sc, const gs_queries& qs, const gs_grid& g, const gs_params& p,

@@ -48,9 +48,11 @@ void launch_fill_u32(uint32_t* p, size_t count, size_t q_stride, int nq, uint32_
     hipLaunchKernelGGL(k_fill_u32, grid, dim3(256), 0, s, p, count, q_stride, v);
 }
 
-__global__ void k_fill_dev(uint32_t* p, size_t q_stride, const uint32_t* n_dev, size_t n_stride, uint32_t mult)
+__global__ void k_fill_dev(uint32_t* p, size_t q_stride, const uint32_t* n_dev, size_t n_stride, uint32_t mult,
+                           size_t max_count)
 {
-    const size_t n = (size_t)n_dev[blockIdx.y * n_stride] * mult;
+    size_t n = (size_t)n_dev[blockIdx.y * n_stride] * mult;
+    n = n < max_count ? n : max_count;  // never past the buffer
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[blockIdx.y * q_stride + i] = 0u;
 }
@@ -60,7 +62,7 @@ void launch_fill_dev(uint32_t* p, size_t max_count, size_t q_stride, int nq, con
 {
     const size_t blocks = (max_count + 255) / 256;
     dim3 grid((unsigned)(blocks < 2048 ? (blocks ? blocks : 1) : 2048), nq);
-    hipLaunchKernelGGL(k_fill_dev, grid, dim3(256), 0, s, p, q_stride, n_dev, n_stride, per_query);
+    hipLaunchKernelGGL(k_fill_dev, grid, dim3(256), 0, s, p, q_stride, n_dev, n_stride, per_query, max_count);
 }
 
 __device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int q)
