@@ -584,6 +584,68 @@ gs_status gs_confidence_loss(const float* x_rx, const float* task_loss, int32_t 
                              float* loss, float* dW1, float* db1, float* dw2, float* db2, void* scratch,
                              size_t scratch_bytes, void* stream);
 
+/* ---- adaptive densification, pruning and opacity reset (Sec. 4.2, Algorithm 1) ----
+ * Statistics (gs_densify_stats, after a step's backward): for every Gaussian
+ * i in the live list, grad_acc[i] += |d_mean[:, i]| (d_mean [3][n]) and
+ * grad_cnt[i] += 1.  The caller zeroes both after each densification.
+ *
+ * Plan (gs_densify_plan): per Gaussian i (scene arrays in the scene's
+ * layout; screen_radius [n] from gs_screen_radius, or NULL for no size
+ * pruning), with FP32 decisions
+ *   densify = grad_cnt > 0 and grad_acc / grad_cnt >= grad_threshold,
+ *   small   = max_c exp(log_scale[c]) <= clone_extent (epsilon r_scene),
+ *   faint   = sigmoid(opacity_logit) < opacity_min,
+ *   large   = screen_radius > radius_max,
+ * i yields: not densified: itself unless faint or large; small: itself
+ * unless faint or large, then its clone unless faint; otherwise split_n
+ * children unless faint (i leaves).  (Reading: Algorithm 1's prune runs over
+ * the densified set and the new Gaussians have no screen radius yet.)
+ * Output slot j: src[j] = parent, kind[j] = -1 (the parent itself), -2 (a
+ * clone) or the child number; slots in parent order (deterministic).
+ * n_out (device u32) = the new count.  src, kind: device int32 arrays of
+ * out_capacity >= n * split_n entries; scratch >=
+ * gs_densify_scratch_bytes(n), 256-byte aligned.
+ *
+ * Apply (gs_densify_apply, n_out read back by the caller): the new scene
+ * arrays ([3][n_out], [4][n_out], [n_out]): copies of the parents, split
+ * children at mean + R(q) (exp(log_scale) * xi) with xi [n][split_n][3] the
+ * caller's standard normals (parent i, child k), log_scale - log(0.8
+ * split_n) (the paper's Sigma / (0.8 N), read as on the scale).
+ * Gather (gs_densify_gather): any per-Gaussian array [comps][n][width_words]
+ * of 32-bit words to [comps][n_out][width_words] in the new order; with
+ * zero_new, the rows of clones and children are zero (fresh Adam moments).
+ * Opacity reset (gs_opacity_reset): opacity_logit <- min(opacity_logit,
+ * logit(opacity_cap)), the paper's sigma <- min(sigma, 0.01).
+ * All pointers are caller-owned device memory.  Errors: GS_ERR_INVALID_ARG
+ * for a null pointer, n < 1, split_n outside [2, 64] or a threshold that is
+ * not positive (grad_threshold, radius_max) or negative (clone_extent,
+ * opacity_min); GS_ERR_CAPACITY when n * split_n >= 2^31; GS_ERR_WORKSPACE
+ * for a short src/kind capacity or scratch. */
+typedef struct {
+    float grad_threshold; /* tau_grad on the mean |dL/dmu| over the steps a Gaussian was live */
+    float clone_extent;   /* epsilon * r_scene */
+    int32_t split_n;      /* N children of a split */
+    float opacity_min;    /* sigma_min */
+    float radius_max;     /* r_max, pixels */
+} gs_densify_params;
+gs_status gs_densify_stats(const float* d_mean, int32_t n, const uint32_t* live_list, const uint32_t* live_count,
+                           float* grad_acc, uint32_t* grad_cnt, void* stream);
+size_t gs_densify_scratch_bytes(int32_t n);
+gs_status gs_densify_plan(int32_t n, const float* log_scale, const float* opacity_logit, const float* grad_acc,
+                          const uint32_t* grad_cnt, const float* screen_radius, const gs_densify_params* prm,
+                          int32_t* src, int32_t* kind, int64_t out_capacity, uint32_t* n_out, void* scratch,
+                          size_t scratch_bytes, void* stream);
+gs_status gs_densify_apply(int32_t n, int32_t n_out, const int32_t* src, const int32_t* kind, const gs_scene* scene,
+                           const float* xi, int32_t split_n, float* o_mean, float* o_log_scale, float* o_quat,
+                           float* o_opacity_logit, void* stream);
+gs_status gs_densify_gather(int32_t n, int32_t n_out, const int32_t* src, const int32_t* kind, const void* in,
+                            void* out, int32_t comps, int32_t width_words, int32_t zero_new, void* stream);
+gs_status gs_opacity_reset(int32_t n, float* opacity_logit, float opacity_cap, void* stream);
+/* Screen radius of every Gaussian for query q of a prepared workspace: half
+ * the larger side of its support rectangle in pixels, 0 if culled. */
+gs_status gs_screen_radius(const void* workspace, size_t ws_bytes, int32_t n, int32_t n_queries,
+                           const gs_grid* grid, const gs_params* prm, int32_t q, float* radius, void* stream);
+
 /*
  * Batched serving: many queries over several scenes of uneven size, grid,
  * tile shape and channel count in one persistent blend launch.

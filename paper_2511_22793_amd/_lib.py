@@ -25,6 +25,11 @@ class GsScene(ctypes.Structure):
     _fields_ = [("n", c_i32), ("mean", c_p), ("log_scale", c_p), ("quat", c_p), ("opacity_logit", c_p)]
 
 
+class GsDensifyParams(ctypes.Structure):
+    _fields_ = [("grad_threshold", c_f32), ("clone_extent", c_f32), ("split_n", c_i32), ("opacity_min", c_f32),
+                ("radius_max", c_f32)]
+
+
 class GsAttrs(ctypes.Structure):
     _fields_ = [("n_chan", c_i32), ("is_complex", c_i32), ("data", c_p), ("query_stride", c_i64)]
 
@@ -161,6 +166,16 @@ SIGNATURES = {
     "gs_emission_backward": (c_i32, [c_p, c_i64, c_i32, c_p, c_i32, c_p, c_p, c_i32, c_f32, c_p, c_i64, c_p, c_p,
                                      c_p]),
     "gs_confidence_scratch_bytes": (c_sz, [c_i32]),
+    "gs_densify_stats": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_p, c_p]),
+    "gs_densify_scratch_bytes": (c_sz, [c_i32]),
+    "gs_densify_plan": (c_i32, [c_i32, c_p, c_p, c_p, c_p, c_p, ctypes.POINTER(GsDensifyParams), c_p, c_p, c_i64,
+                                c_p, c_p, c_sz, c_p]),
+    "gs_densify_apply": (c_i32, [c_i32, c_i32, c_p, c_p, ctypes.POINTER(GsScene), c_p, c_i32, c_p, c_p, c_p, c_p,
+                                 c_p]),
+    "gs_densify_gather": (c_i32, [c_i32, c_i32, c_p, c_p, c_p, c_p, c_i32, c_i32, c_i32, c_p]),
+    "gs_opacity_reset": (c_i32, [c_i32, c_p, c_f32, c_p]),
+    "gs_screen_radius": (c_i32, [c_p, c_sz, c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_i32,
+                                 c_p, c_p]),
     "gs_confidence_loss": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_f32, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
                                    c_sz, c_p]),
     "gs_batch_plan_bytes": (c_sz, [c_i32]),

@@ -24,6 +24,7 @@ import numpy as np
 import torch
 
 from . import confidence as gc
+from . import densify as gd
 from . import mlp as gm
 from .render import (Grid, Params, TrainScratch, Workspace, backward, backward_l2, blend, blend_loss, live,
                      loss_spectrum, loss_stats, prepare, spatial_mean, train_pass)
@@ -62,7 +63,7 @@ class LearnedScene:
                  grid: Grid = Grid(), params: Params = Params(), rates: Rates = Rates(), total_steps: int = 1000,
                  train_geometry: bool = True, lambda_ch: float = 1.0, loss_mode: str = "train_pass",
                  keep_spectra: bool = False, confidence: bool = False, conf_alpha: float = gc.ALPHA,
-                 conf_weights: dict = None, device="cuda"):
+                 conf_weights: dict = None, densify_stats: bool = False, device="cuda"):
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
@@ -74,28 +75,20 @@ class LearnedScene:
         # train_pass: also store the step's spectra in self.spec (the other
         # modes always do)
         self.keep_spectra = keep_spectra
-        self.n = n = scene["opacity_logit"].shape[0]
         self.g = {k: torch.tensor(np.asarray(v, np.float32), device=dev) for k, v in scene.items()}
         self.E = torch.tensor(np.asarray(embeddings, np.float32), device=dev)
         self.E_bf = torch.from_numpy(gm.bf16_bits(embeddings).view(np.int16)).to(dev)
         self.net = gm.AttributeNet(weights, box_lo, box_hi, params.r_near, device=dev)
         self.F = F = self.net.F
         self.rx = torch.tensor(np.asarray(rx, np.float32).reshape(1, 3), device=dev)
-        self.ws = Workspace(n, 1, grid, params, device=dev)
-        # attribute rows never written stay zero (the blend multiplies them by 0)
-        self.attr = torch.zeros(batch, n, F, 2, device=dev)
-        self.d_attr = torch.zeros(batch, n, F, 2, device=dev)
         self.spec = torch.empty(batch, F, grid.H, grid.W, 2, device=dev)
         self.dpart = torch.empty_like(self.spec) if loss_mode in ("partial", "fused") else None
         self.loss = torch.empty(batch, device=dev)
         self.h_hat = torch.empty(batch, F, 2, device=dev)
         self.tscratch = TrainScratch(batch, F, grid, device=dev) if loss_mode == "train_pass" else None
-        self.live_list = torch.empty(1, n, dtype=torch.int32, device=dev)
-        self.live_count = torch.empty(1, dtype=torch.int32, device=dev)
-        self.state = gm.State(batch, n, training=True, device=dev, n_chan=F)
-        self.Z1 = torch.empty(n, gm.HID, device=dev)
-        self.ggrads = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
-                       "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+        # Algorithm 1's per-Gaussian positional-gradient statistics (for densify())
+        self.densify_stats = densify_stats
+        self._size_buffers(scene["opacity_logit"].shape[0])
         self.mgrads = None
         self.moments = {}
         self.step_count = 0
@@ -117,6 +110,58 @@ class LearnedScene:
             self.conf_c = torch.empty(batch, device=dev)
             self.conf_loss = torch.empty(batch, device=dev)
             self.conf_grads = {k: torch.empty_like(v) for k, v in self.conf_w.items()}
+
+    def _size_buffers(self, n: int):
+        """Every buffer whose size is the Gaussian count."""
+        dev, B, F = self.dev, self.B, self.F
+        self.n = n
+        self.ws = Workspace(n, 1, self.grid, self.params, device=dev)
+        # attribute rows never written stay zero (the blend multiplies them by 0)
+        self.attr = torch.zeros(B, n, F, 2, device=dev)
+        self.d_attr = torch.zeros(B, n, F, 2, device=dev)
+        self.live_list = torch.empty(1, n, dtype=torch.int32, device=dev)
+        self.live_count = torch.empty(1, dtype=torch.int32, device=dev)
+        self.state = gm.State(B, n, training=True, device=dev, n_chan=F)
+        self.Z1 = torch.empty(n, gm.HID, device=dev)
+        self.ggrads = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
+                       "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
+        self.grad_acc = torch.zeros(n, device=dev) if self.densify_stats else None
+        self.grad_cnt = torch.zeros(n, dtype=torch.int32, device=dev) if self.densify_stats else None
+
+    def densify(self, prm: "gd.DensifyParams" = None, seed: int = 0) -> int:
+        """Algorithm 1's densify branch on the statistics gathered since the
+        last call: clone / split / prune (gd.plan) into a new Gaussian set;
+        the scene, the embeddings (and their BF16 copy) follow, Adam moments
+        of kept Gaussians follow and those of new ones start at zero, every
+        per-Gaussian buffer is rebuilt and the statistics restart.  Child
+        positions draw standard normals from a seeded generator.  Returns the
+        new count (one synchronisation; a captured step must be captured
+        again afterwards)."""
+        if not self.densify_stats:
+            raise ValueError("densify() needs LearnedScene(densify_stats=True)")
+        prm = prm or gd.DensifyParams()
+        n = self.n
+        # the screen radius from the last prepare of the receiver
+        radius = gd.screen_radius(self.ws, 0)
+        src, kind, n_out = gd.plan(self.g, self.grad_acc, self.grad_cnt, radius, prm)
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        xi = torch.randn(n, prm.split_n, 3, generator=gen).to(self.dev)
+        self.g = gd.apply(self.g, src, kind, n_out, xi, prm.split_n)
+        self.E = gd.gather(self.E, src, kind, n, n_out, 1, zero_new=False)
+        self.E_bf = gd.gather(self.E_bf, src, kind, n, n_out, 1, zero_new=False)
+        comps = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "E": 1}
+        for k, c in comps.items():
+            if k in self.moments:
+                m, v = self.moments[k]
+                self.moments[k] = (gd.gather(m, src, kind, n, n_out, c, zero_new=True),
+                                   gd.gather(v, src, kind, n, n_out, c, zero_new=True))
+        self._size_buffers(n_out)
+        self.mgrads = None  # (the embedding gradient has a row per Gaussian)
+        return n_out
+
+    def opacity_reset(self, cap: float = 0.01):
+        """sigma <- min(sigma, cap) for every Gaussian (Algorithm 1)."""
+        gd.opacity_reset(self.g["opacity_logit"], cap)
 
     def _rows(self, tx):
         return gm.Rows(tx, self.live_list[0], self.live_count, row_cap=self.n)
@@ -211,6 +256,8 @@ class LearnedScene:
                          d_attr=self.d_attr, out=self.ggrads)
         if self.loss_mode != "train_pass":
             mark("render_bwd")
+        if self.densify_stats:
+            gd.stats(self.ggrads["d_mean"], self.live_list[0], self.live_count, self.grad_acc, self.grad_cnt)
         self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
                                   self.mgrads, clear_d_attr=True)
         mark("mlp_bwd")
