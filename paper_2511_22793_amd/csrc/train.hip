@@ -708,20 +708,34 @@ __global__ __launch_bounds__(256) void k_train_walk(TrArgs A, int c)
 // hhat from the per-Gaussian weight totals, the channel-mean gradient term
 // and the channel part of the loss.
 // ---------------------------------------------------------------------------
-// hs[s][c] += sum over a chunk of the live list of Wtot_g v(g, c)
-__global__ __launch_bounds__(256) void k_train_hsum(const uint32_t* __restrict__ live, const uint32_t* __restrict__ count,
+// hs[s][c] += sum over live entries i = blockIdx.x + k gridDim.x of
+// Wtot_g v(g, c): a fixed grid of TR_HSUM_BLOCKS per set whatever the live
+// count (it is only known on the device), each thread a column, four
+// entries' loads in flight at a time
+constexpr int TR_HSUM_BLOCKS = 64;
+__global__ __launch_bounds__(128) void k_train_hsum(const uint32_t* __restrict__ live, const uint32_t* __restrict__ count,
                                                     const float* __restrict__ wtot, const float* __restrict__ attr,
                                                     int64_t a_stride, int Fc, float* __restrict__ hs)
 {
     const int s = blockIdx.y;
     const uint32_t nl = *count;
-    const uint32_t lo = blockIdx.x * 1024u;
-    if (lo >= nl) return;
-    const uint32_t hi = min(nl, lo + 1024u);
+    if (blockIdx.x >= nl) return;
     const float* a = attr + s * a_stride;
+    const uint32_t G = gridDim.x;
     for (int c = threadIdx.x; c < Fc; c += blockDim.x) {
         float acc = 0.0f;
-        for (uint32_t i = lo; i < hi; ++i) {
+        uint32_t i = blockIdx.x;
+        for (; i + 3 * G < nl; i += 4 * G) {
+            const uint32_t g0 = live[i], g1 = live[i + G], g2 = live[i + 2 * G], g3 = live[i + 3 * G];
+            const float w0 = wtot[g0], w1 = wtot[g1], w2 = wtot[g2], w3 = wtot[g3];
+            const float v0 = a[(size_t)g0 * Fc + c], v1 = a[(size_t)g1 * Fc + c];
+            const float v2 = a[(size_t)g2 * Fc + c], v3 = a[(size_t)g3 * Fc + c];
+            acc = fmaf(w0, v0, acc);
+            acc = fmaf(w1, v1, acc);
+            acc = fmaf(w2, v2, acc);
+            acc = fmaf(w3, v3, acc);
+        }
+        for (; i < nl; i += G) {
             const uint32_t g = live[i];
             acc = fmaf(wtot[g], a[(size_t)g * Fc + c], acc);
         }
@@ -937,7 +951,7 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     launch_fill_dev((uint32_t*)(ws + L.gacc), (size_t)L.cap * 8, L.s_gacc / 4, L.nq,
                     (const uint32_t*)(ws + L.flags) + FL_PUSED, L.s_flags / 4, 8u, s);
     // hhat, the mean term of g and the channel part of the loss
-    hipLaunchKernelGGL(k_train_hsum, dim3((scene->n + 1023) / 1024, n_sets), dim3(128), 0, s, live_list, live_count,
+    hipLaunchKernelGGL(k_train_hsum, dim3(TR_HSUM_BLOCKS, n_sets), dim3(128), 0, s, live_list, live_count,
                        (const float*)(ws + L.wtot), attrs->data, attrs->query_stride, Fc, hs);
     hipLaunchKernelGGL(k_train_hfinish, dim3(n_sets), dim3(256), 0, s, hs, tt->target_mean, n_sets, Fc,
                        1.0f / (float)HW, tt->lambda_ch, tt->grad_scale, tt->h_hat, mg, tt->loss);

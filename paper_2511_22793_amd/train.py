@@ -121,7 +121,9 @@ class LearnedScene:
         self.d_attr = torch.zeros(B, n, F, 2, device=dev)
         self.live_list = torch.empty(1, n, dtype=torch.int32, device=dev)
         self.live_count = torch.empty(1, dtype=torch.int32, device=dev)
-        self.state = gm.State(B, n, training=True, device=dev, n_chan=F)
+        # 64 split-K workgroups for the weight gradients: the live rows are few
+        # (a few hundred per set), so more workgroups shorten each one's chain
+        self.state = gm.State(B, n, training=True, device=dev, n_chan=F, n_partial=64)
         self.Z1 = torch.empty(n, gm.HID, device=dev)
         self.ggrads = {"d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
                        "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
