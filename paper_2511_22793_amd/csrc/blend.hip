@@ -383,7 +383,11 @@ __global__ void k_stamp(unsigned long long* ts)
 // (alpha >= alpha_min before the pixel stops) and records the per-pixel
 // state.  Its output decides which (set, Gaussian) rows the attribute
 // network must evaluate: no other Gaussian can change a pixel.
-__global__ __launch_bounds__(256) void k_live(
+// One wave per 64 pixels of a tile (the tile's pixels row-major, in groups of
+// 64): the groups of a tile walk the same list independently, so every CU
+// has work (a tile per workgroup left half the chip idle at 138 tiles).
+constexpr int LIVE_PIX = 64;
+__global__ __launch_bounds__(LIVE_PIX) void k_live(
     const GRec* __restrict__ rec, size_t s_rec, const uint32_t* __restrict__ plist, size_t s_plist,
     const uint2* __restrict__ ranges, size_t s_ranges, int H, int W, int tw, int th, int TX, float amin, float amax,
     float tmin, uint32_t* __restrict__ flags_live, size_t s_live, float* __restrict__ T_final,
@@ -391,19 +395,21 @@ __global__ __launch_bounds__(256) void k_live(
     size_t s_wtot)
 {
     const int tile = blockIdx.x, q = blockIdx.z;
-    const int nthr = tw * th;
+    constexpr int nthr = LIVE_PIX;
     const int txi = tile % TX, tyi = tile / TX;
-    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+    const int k = blockIdx.y * LIVE_PIX + threadIdx.x;  // pixel of the tile
+    const int lx = k % tw, ly = k / tw;
     const int col = txi * tw + lx, row = tyi * th + ly;
-    const bool inside = col < W && row < H;
+    const bool inside = ly < th && col < W && row < H;
+    if (__syncthreads_count(inside) == 0) return;  // a group past the image
     const uint2 rg = ranges[q * s_ranges + tile];
     const double pcx = col + 0.5, pcy = row + 0.5, halfW = 0.5 * W;
     rec += q * s_rec;
     plist += q * s_plist;
     flags_live += q * s_live;
-    __shared__ double s_px[256], s_py[256], s_ca[256], s_cb[256], s_cc[256];
-    __shared__ float s_sig[256], s_att[256], s_wsum[256];
-    __shared__ uint32_t s_g[256];
+    __shared__ double s_px[LIVE_PIX], s_py[LIVE_PIX], s_ca[LIVE_PIX], s_cb[LIVE_PIX], s_cc[LIVE_PIX];
+    __shared__ float s_sig[LIVE_PIX], s_att[LIVE_PIX], s_wsum[LIVE_PIX];
+    __shared__ uint32_t s_g[LIVE_PIX];
     if (wtot) wtot += q * s_wtot;
     s_wsum[threadIdx.x] = 0.0f;
     float T = 1.0f;
@@ -492,7 +498,8 @@ void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, 
     launch_fill_u32(fl, (size_t)L.n, L.s_live / 4, L.nq, 0u, s);
     launch_fill_u32(count, 1, 1, L.nq, 0u, s);
     launch_fill_u32((uint32_t*)(ws + L.wtot), (size_t)L.n, L.s_wtot / 4, L.nq, 0u, s);
-    hipLaunchKernelGGL(k_live, dim3(L.T, 1, L.nq), dim3(L.tw * L.th), 0, s, (const GRec*)(ws + L.rec),
+    hipLaunchKernelGGL(k_live, dim3(L.T, (L.tw * L.th + LIVE_PIX - 1) / LIVE_PIX, L.nq), dim3(LIVE_PIX), 0, s,
+                       (const GRec*)(ws + L.rec),
                        L.s_rec / sizeof(GRec), (const uint32_t*)(ws + L.plist), L.s_plist / 4,
                        (const uint2*)(ws + L.ranges), L.s_ranges / sizeof(uint2), L.H, L.W, L.tw, L.th, L.TX,
                        p.alpha_min, p.alpha_max, p.T_min, fl, L.s_live / 4, (float*)(ws + L.T_final),
