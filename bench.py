@@ -576,7 +576,7 @@ def serving_mix(args, gs, dev):
     for _ in range(args.warmup):
         batch.replay()
     torch.cuda.synchronize()
-    lat, spans = [], []
+    lat, spans, preps = [], [], []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = max(3, min(args.steps, 10))
     total_ms = 0.0
@@ -589,6 +589,7 @@ def serving_mix(args, gs, dev):
         L = batch.latencies_ms()
         lat.append(L["per_query"])
         spans.append(L["makespan"])
+        preps.append(L["prepare"])
     lat = np.concatenate(lat)
     ms_batch = total_ms / reps
     # plain: one forward per query, each on its own scene, back to back
@@ -618,6 +619,7 @@ def serving_mix(args, gs, dev):
             "tuned": {"block": tuner.choice["block"], "workgroups": tuner.choice.get("workgroups"),
                       "tiles_and_groups": [list(x[1:]) for x in tuner.choice["jobs"]], "tune_s": round(tune_s, 2)},
             "ms_per_batch": round(ms_batch, 4), "makespan_ms_device": round(float(np.mean(spans)), 4),
+            "prepare_ms_device": round(float(np.mean(preps)), 4),
             "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
             "queries_per_s": round(nq / (ms_batch / 1e3), 2), "replays": reps,
             "plain_ms_per_batch": round(ms_plain, 4), "plain_queries_per_s": round(nq / (ms_plain / 1e3), 2),

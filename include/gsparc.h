@@ -653,29 +653,39 @@ gs_status gs_screen_radius(const void* workspace, size_t ws_bytes, int32_t n, in
  * A job is one scene with a group of queries (receiver positions; n_sets =
  * queries.count, set q seen from query q) and its own grid, params, output
  * and workspace, exactly as for gs_render_forward() (GS_OPT_FORWARD_ONLY is
- * allowed and saves memory).  gs_batch_run() enqueues, for job 0, 1, ...:
- * the prepare steps of gs_render_prepare(), then one persistent blend kernel
- * whose workgroups pull (job, query, channel group, tile) items from a device
- * counter in job order, so the job order is the service order.  Spectra and
- * workspace state are those that gs_render_forward() leaves for the same
- * job, bit for bit.
+ * allowed and saves memory); no two jobs may share a workspace.
+ * gs_batch_run() enqueues the prepare steps of gs_render_prepare() for every
+ * job, spread over the caller's stream and up to three side streams of the
+ * library (each job to the stream with the least Gaussians x queries so far;
+ * forked from and joined back into the caller's stream with events, so a
+ * graph capture records them as parallel branches), then one persistent
+ * blend kernel whose workgroups pull (job, query, channel group, tile) items
+ * from a device counter in job order, so the job order is the service order.
+ * Spectra and workspace state are those that gs_render_forward() leaves for
+ * the same job, bit for bit.
  *
  *  gs_batch_plan_bytes(n_jobs): size of the plan buffer (device, 256-byte
  *    aligned, caller-owned).
  *  gs_batch_plan: validates the jobs (host array), writes the job table into
  *    the plan buffer and fills *info (host).  Synchronises `stream` (the
- *    table is copied from host memory).  Call again whenever any job field
- *    changes; the plan holds device pointers of the jobs' buffers.
+ *    table is copied from host memory).  Creates the side streams of the
+ *    current device on its first call there (kept until the process ends).
+ *    Call again whenever any job field changes; the plan holds device
+ *    pointers of the jobs' buffers.
  *  gs_batch_run: enqueues the batch for a plan made from the same jobs.
  *    Enqueues kernels only (no copies, no memset, no allocation, no host
  *    synchronisation), so it can be captured into a HIP graph and replayed.
  *    workgroups: persistent workgroups (> 0; info->workgroups fills the
  *    device at the kernel's occupancy).  timestamps: NULL, or a device array
- *    of info->n_queries + 2 uint64 values written as device wall-clock ticks
+ *    of info->n_queries + 3 uint64 values written as device wall-clock ticks
  *    (gs_wall_clock_khz()): [0] batch start (before the first prepare),
  *    [1 + k] completion of the k-th query's spectrum (queries numbered job
- *    by job), [n_queries + 1] batch end.
- *  Concurrent runs of one plan race on its work counter.
+ *    by job), [n_queries + 1] batch end, [n_queries + 2] end of the prepare
+ *    steps (start of the blend).  Without a prior gs_batch_plan() on the
+ *    device, or with one job, every prepare runs on `stream`.
+ *  Concurrent runs of one plan race on its work counter; runs enqueued from
+ *  several host threads take turns on the side streams (a lock), and runs on
+ *  different caller streams of one device are ordered through them.
  */
 typedef struct {
     gs_scene scene;

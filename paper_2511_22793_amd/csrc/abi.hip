@@ -41,9 +41,15 @@ gs_status make_layout(int32_t n, int32_t nq, const gs_grid* g, const gs_params* 
     L->pair_passes = L->tile_bits <= TILE_PASS_MAX_BITS ? 1 : (L->tile_bits + RADIX_BITS - 1) / RADIX_BITS;
     const int digits = L->tile_bits <= RADIX_BITS ? RADIX
                        : (L->tile_bits <= TILE_PASS_MAX_BITS ? (1 << TILE_PASS_MAX_BITS) : RADIX);
-    L->sort_blocks = (n + SORT_TILE - 1) / SORT_TILE;
-    L->pair_blocks = (int)((cap + SORT_TILE - 1) / SORT_TILE);
-    const int64_t ttile = (int64_t)SORT_THREADS * TILE_PASS_ITEMS;
+    const int64_t wide = SORT_WIDE_WAVES / (SORT_THREADS / 64);  // keys-per-block factor of a wide block
+    L->sort_wide = (n + wide * SORT_TILE - 1) / (wide * SORT_TILE) * nq >= SORT_WIDE_MIN_BLOCKS;
+    L->pair_wide = (cap + wide * SORT_TILE - 1) / (wide * SORT_TILE) * nq >= SORT_WIDE_MIN_BLOCKS;
+    const int64_t stile = L->sort_wide ? wide * SORT_TILE : SORT_TILE;
+    const int64_t ptile = L->pair_wide ? wide * SORT_TILE : SORT_TILE;
+    const int64_t ttile = L->pair_wide ? (int64_t)64 * SORT_WIDE_WAVES * TILE_PASS_WIDE_ITEMS
+                                       : (int64_t)SORT_THREADS * TILE_PASS_ITEMS;
+    L->sort_blocks = (int)((n + stile - 1) / stile);
+    L->pair_blocks = (int)((cap + ptile - 1) / ptile);
     L->tile_blocks = (int)((cap + ttile - 1) / ttile);
     const size_t HW = (size_t)g->H * g->W;
 

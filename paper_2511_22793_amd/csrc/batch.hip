@@ -1,10 +1,43 @@
-// Batched serving: the prepare steps of every job, then one persistent
-// blend launch over all jobs' (query, channel group, tile) items.
+// Batched serving: the prepare steps of every job, spread over a few
+// streams so that small jobs' launches overlap, then one persistent blend
+// launch over all jobs' (query, channel group, tile) items.
+#include <mutex>
+
 #include "common.h"
 
 namespace gs {
 
 constexpr size_t PLAN_HEAD = 256;  // work counter, then the job table
+
+// Prepare lanes: the caller's stream plus BATCH_SIDE side streams (default
+// priority, non-blocking), created once per device by gs_batch_plan().  A
+// run forks them from the caller's stream with an event and joins them back
+// before the blend, so the whole run stays one capturable sequence.
+constexpr int BATCH_SIDE = 3;
+constexpr int BATCH_MAX_DEVICES = 64;
+struct Lanes {
+    hipStream_t side[BATCH_SIDE];
+    hipEvent_t fork;
+    hipEvent_t join[BATCH_SIDE];
+    bool ready;
+};
+std::mutex g_lanes_mu;
+Lanes g_lanes[BATCH_MAX_DEVICES] = {};
+
+static gs_status lanes_init(int dev)
+{
+    if (dev < 0 || dev >= BATCH_MAX_DEVICES) return GS_ERR_CAPACITY;
+    std::lock_guard<std::mutex> lk(g_lanes_mu);
+    Lanes& l = g_lanes[dev];
+    if (l.ready) return GS_OK;
+    for (int i = 0; i < BATCH_SIDE; ++i) {
+        if (hipStreamCreateWithFlags(&l.side[i], hipStreamNonBlocking) != hipSuccess) return GS_ERR_HIP;
+        if (hipEventCreateWithFlags(&l.join[i], hipEventDisableTiming) != hipSuccess) return GS_ERR_HIP;
+    }
+    if (hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) != hipSuccess) return GS_ERR_HIP;
+    l.ready = true;
+    return GS_OK;
+}
 
 static gs_status build_table(const gs_batch_job* jobs, int n_jobs, std::vector<BlendJob>& table, gs_batch_info* info)
 {
@@ -69,6 +102,8 @@ gs_status gs_batch_plan(const gs_batch_job* jobs, int32_t n_jobs, void* plan, si
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return GS_ERR_HIP;
     if (persist_occupancy(info->block, &per_cu) != hipSuccess) return GS_ERR_HIP;
+    st = lanes_init(dev);
+    if (st != GS_OK) return st;
     info->workgroups = std::max(1, cus * std::max(1, per_cu));
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync((char*)plan + PLAN_HEAD, table.data(), table.size() * sizeof(BlendJob),
@@ -93,16 +128,47 @@ gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, siz
     unsigned long long* ts = (unsigned long long*)timestamps;
     launch_fill_u32(counter, 1, 0, 1, 0u, s);
     if (ts) {
-        launch_fill_u32((uint32_t*)ts, 2 * ((size_t)info.n_queries + 2), 0, 1, 0u, s);
+        launch_fill_u32((uint32_t*)ts, 2 * ((size_t)info.n_queries + 3), 0, 1, 0u, s);
         launch_stamp(ts, s);
     }
+    std::vector<Layout> lay(n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
         const gs_batch_job& b = jobs[j];
-        Layout L;
-        st = make_layout(b.scene.n, b.queries.count, &b.grid, &b.params, &L);
+        st = make_layout(b.scene.n, b.queries.count, &b.grid, &b.params, &lay[j]);
         if (st != GS_OK) return st;
-        enqueue_prepare(&b.scene, &b.queries, &b.grid, &b.params, L, (char*)b.workspace, s);
     }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
+    const Lanes* ln = (dev >= 0 && dev < BATCH_MAX_DEVICES && g_lanes[dev].ready && n_jobs > 1) ? &g_lanes[dev] : nullptr;
+    if (!ln) {
+        for (int j = 0; j < n_jobs; ++j) {
+            const gs_batch_job& b = jobs[j];
+            enqueue_prepare(&b.scene, &b.queries, &b.grid, &b.params, lay[j], (char*)b.workspace, s);
+        }
+    } else {
+        // each job to the lane with the least projected work so far
+        // (Gaussians x queries), in job order
+        std::lock_guard<std::mutex> lk(g_lanes_mu);
+        const int nl = std::min(n_jobs, BATCH_SIDE + 1);
+        double load[BATCH_SIDE + 1] = {};
+        if (hipEventRecord(ln->fork, s) != hipSuccess) return GS_ERR_HIP;
+        for (int i = 1; i < nl; ++i)
+            if (hipStreamWaitEvent(ln->side[i - 1], ln->fork, 0) != hipSuccess) return GS_ERR_HIP;
+        for (int j = 0; j < n_jobs; ++j) {
+            const gs_batch_job& b = jobs[j];
+            int best = 0;
+            for (int i = 1; i < nl; ++i)
+                if (load[i] < load[best]) best = i;
+            load[best] += (double)b.scene.n * (double)b.queries.count;
+            enqueue_prepare(&b.scene, &b.queries, &b.grid, &b.params, lay[j], (char*)b.workspace,
+                            best ? ln->side[best - 1] : s);
+        }
+        for (int i = 1; i < nl; ++i) {
+            if (hipEventRecord(ln->join[i - 1], ln->side[i - 1]) != hipSuccess) return GS_ERR_HIP;
+            if (hipStreamWaitEvent(s, ln->join[i - 1], 0) != hipSuccess) return GS_ERR_HIP;
+        }
+    }
+    if (ts) launch_stamp(ts + 2 + info.n_queries, s);
     launch_blend_persist((const BlendJob*)((char*)plan + PLAN_HEAD), n_jobs, (uint32_t)info.items, counter,
                          ts ? ts + 1 : nullptr, workgroups, info.block, s);
     if (ts) launch_stamp(ts + 1 + info.n_queries, s);

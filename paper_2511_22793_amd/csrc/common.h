@@ -102,6 +102,12 @@ __device__ __forceinline__ void wave_reduce_scatter(float* x, int lane)
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 8;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per sort workgroup
+// Wide sort workgroups: 16 waves, so 4x the keys per block.  A block's
+// output runs per digit are 4x longer (fewer partly written lines) and the
+// digit-by-block count matrix 4x smaller; taken while the launch still has
+// at least SORT_WIDE_MIN_BLOCKS workgroups.
+constexpr int SORT_WIDE_WAVES = 16;
+constexpr int SORT_WIDE_MIN_BLOCKS = 256;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 // tile ids up to this many bits are sorted in one counting pass
@@ -109,6 +115,9 @@ constexpr int TILE_PASS_MAX_BITS = 10;
 // keys per thread of that pass: large blocks keep its digit-by-block count
 // matrix (up to 1024 rows) small
 constexpr int TILE_PASS_ITEMS = 32;
+// keys per thread of that pass in wide workgroups (2x the keys per block
+// within the 128 registers a 1024-thread workgroup allows)
+constexpr int TILE_PASS_WIDE_ITEMS = 16;
 
 // Byte layout of the caller's workspace (all sub-buffers 256-byte aligned,
 // each an array over queries with the given stride).
@@ -121,6 +130,8 @@ struct Layout {
     int tile_blocks;      // workgroups of the single tile pass
     int sort_blocks;      // max sort workgroups for n keys
     int pair_blocks;      // max sort workgroups for cap keys
+    int sort_wide;        // depth sort in wide workgroups
+    int pair_wide;        // pair sorts (tile pass included) in wide workgroups
     size_t flags, rec, rect, status, tinfo, keys_a, keys_b, vals_a, vals_b, partial;
     size_t pkeys_a, pkeys_b, plist, ranges, counts, totals, T_final, n_last, n_contrib, g2d, live, gacc, wtot;
     size_t s_flags, s_rec, s_rect, s_status, s_tinfo, s_keys, s_partial, s_pkeys, s_plist, s_ranges,

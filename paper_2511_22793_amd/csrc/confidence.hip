@@ -145,15 +145,27 @@ __global__ __launch_bounds__(CONF_WAVES * 64) void k_confidence_part(const float
         for (int k = 0; k < 6; ++k) part[((size_t)blockIdx.x * 6 + k) * CONF_HIDDEN + j] = r[k];
 }
 
-// the G workgroups' partials added in workgroup order (thread k*32 + j)
+// the G workgroups' partials added in workgroup order (thread k*32 + j);
+// CONF_SUM_BATCH loads in flight ahead of the additions, which keep the order
+constexpr int CONF_SUM_BATCH = 16;
 __global__ __launch_bounds__(CONF_NPART) void k_confidence_sum(const float* __restrict__ part, int G,
                                                                float* __restrict__ dW1, float* __restrict__ db1,
                                                                float* __restrict__ dw2, float* __restrict__ db2)
 {
     __shared__ float r[6][CONF_HIDDEN];
     const int k = threadIdx.x / CONF_HIDDEN, j = threadIdx.x % CONF_HIDDEN;
+    const float* p = part + (size_t)k * CONF_HIDDEN + j;
+    constexpr size_t STEP = 6 * CONF_HIDDEN;  // one workgroup's partials
     float v = 0.0f;
-    for (int w = 0; w < G; ++w) v += part[((size_t)w * 6 + k) * CONF_HIDDEN + j];
+    int w = 0;
+    for (; w + CONF_SUM_BATCH <= G; w += CONF_SUM_BATCH) {
+        float b[CONF_SUM_BATCH];
+#pragma unroll
+        for (int u = 0; u < CONF_SUM_BATCH; ++u) b[u] = p[(size_t)(w + u) * STEP];
+#pragma unroll
+        for (int u = 0; u < CONF_SUM_BATCH; ++u) v += b[u];
+    }
+    for (; w < G; ++w) v += p[(size_t)w * STEP];
     r[k][j] = v;
     __syncthreads();
     if (threadIdx.x < CONF_HIDDEN) {

@@ -70,36 +70,37 @@ __device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_st
     return n_dev ? n_dev[q * n_stride] : n_fixed;
 }
 
-// Per-workgroup digit histogram (RB-bit digits); counts laid out
-// [digit][block] per query.
-template <int RB, int IT = SORT_ITEMS>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_count(
+// Per-workgroup digit histogram (RB-bit digits) of a block of 64*WV*IT
+// keys; counts laid out [digit][block] per query.
+template <int RB, int IT = SORT_ITEMS, int WV = SORT_THREADS / 64>
+__global__ __launch_bounds__(64 * WV) void k_sort_count(
     const uint32_t* __restrict__ keys, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, uint32_t* __restrict__ counts, size_t s_counts, int max_blocks)
 {
     constexpr int R = 1 << RB;
-    constexpr uint32_t TILE = SORT_THREADS * IT;
+    constexpr int NT = 64 * WV;
+    constexpr uint32_t TILE = NT * IT;
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
     const uint32_t base = blockIdx.x * TILE;
     if (base >= n) return;
     __shared__ uint32_t hist[R];
-    for (int d = threadIdx.x; d < R; d += SORT_THREADS) hist[d] = 0;
+    for (int d = threadIdx.x; d < R; d += NT) hist[d] = 0;
     __syncthreads();
     keys += q * s_keys;
     uint32_t kv[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-        const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
+        const uint32_t e = base + i * NT + threadIdx.x;
         kv[i] = e < n ? keys[e] : 0u;
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-        const uint32_t e = base + i * SORT_THREADS + threadIdx.x;
+        const uint32_t e = base + i * NT + threadIdx.x;
         if (e < n) atomicAdd(&hist[(kv[i] >> shift) & (R - 1)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < R; d += SORT_THREADS)
+    for (int d = threadIdx.x; d < R; d += NT)
         counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x] = hist[d];
 }
 
@@ -141,15 +142,15 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ counts
     if (threadIdx.x == 0) totals[q * s_totals + d] = carry;
 }
 
-// Stable scatter of RB-bit digits.  Wave w of the workgroup owns keys
-// [w*1024, (w+1)*1024) of the block, consumed as 16 rounds of 64 consecutive
-// keys.  A key's rank is (digit base) + (same digit in earlier blocks) +
-// (in earlier waves) + (in earlier rounds of this wave) + (lanes below it
-// with the same digit in this round, from an RB-ballot match mask).
+// Stable scatter of RB-bit digits.  Wave w of the WV-wave workgroup owns
+// keys [w*64*IT, (w+1)*64*IT) of the block, consumed as IT rounds of 64
+// consecutive keys.  A key's rank is (digit base) + (same digit in earlier
+// blocks) + (in earlier waves) + (in earlier rounds of this wave) + (lanes
+// below it with the same digit in this round, from an RB-ballot match mask).
 // With `order` set (the single tile pass over pair keys) the output is the
 // pair's Gaussian, order[key & rank_mask], instead of the key.
-template <int RB, int IT = SORT_ITEMS, bool KV = true>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
+template <int RB, int IT = SORT_ITEMS, bool KV = true, int WV = SORT_THREADS / 64>
+__global__ __launch_bounds__(64 * WV) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, const uint32_t* __restrict__ counts, size_t s_counts,
@@ -157,15 +158,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     size_t s_order, uint32_t* __restrict__ plist, size_t s_plist, uint32_t rank_mask)
 {
     constexpr int R = 1 << RB;
-    constexpr int DPT = R / SORT_THREADS;  // digits per thread in the digit scans
-    constexpr uint32_t TILE = SORT_THREADS * IT;
+    constexpr int NT = 64 * WV;
+    constexpr int DPT = R >= NT ? R / NT : 1;  // digits per thread in the digit scans
+    constexpr int NDT = R / DPT;               // threads owning digits
+    constexpr uint32_t TILE = NT * IT;
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
     const uint32_t base = blockIdx.x * TILE;
     if (base >= n) return;
     __shared__ uint32_t s_goff[R];
-    __shared__ uint32_t s_wcnt[4][R];
-    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_wcnt[WV][R];
+    __shared__ uint32_t s_wsum[WV];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     kin += q * s_keys;
     if (!order) kout += q * s_keys;
@@ -173,13 +176,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
         vin += q * s_keys;
         vout += q * s_keys;
     }
-    // digit bases: exclusive scan of the totals over digits (thread tid owns
-    // digits [tid*DPT, tid*DPT + DPT))
+    // digit bases: exclusive scan of the totals over digits (thread tid <
+    // NDT owns digits [tid*DPT, tid*DPT + DPT))
     {
+        const bool own = tid < NDT;
         uint32_t t[DPT], tsum = 0;
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
-            t[k] = totals[q * s_totals + tid * DPT + k];
+            t[k] = own ? totals[q * s_totals + tid * DPT + k] : 0u;
             tsum += t[k];
         }
         uint32_t x = tsum;
@@ -189,16 +193,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
             if (lane >= o) x += y;
         }
         if (lane == 63) s_wsum[w] = x;
+        for (int d = tid; d < WV * R; d += NT) s_wcnt[d / R][d % R] = 0;
         __syncthreads();
         uint32_t run = x - tsum;
         for (int k = 0; k < w; ++k) run += s_wsum[k];
+        if (own) {
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) {
-            const int d = tid * DPT + k;
-            s_goff[d] = run + counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x];
-            run += t[k];
-#pragma unroll
-            for (int ww = 0; ww < 4; ++ww) s_wcnt[ww][d] = 0;
+            for (int k = 0; k < DPT; ++k) {
+                const int d = tid * DPT + k;
+                s_goff[d] = run + counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x];
+                run += t[k];
+            }
         }
     }
     __syncthreads();
@@ -207,13 +212,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     // issue every load before the rank chain so that they overlap
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-        const uint32_t e = base + w * (TILE / 4) + j * 64 + lane;
+        const uint32_t e = base + w * (TILE / WV) + j * 64 + lane;
         key[j] = e < n ? kin[e] : 0u;
         if constexpr (KV) val[j] = (e < n && vin) ? vin[e] : 0u;
     }
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-        const uint32_t e = base + w * (TILE / 4) + j * 64 + lane;
+        const uint32_t e = base + w * (TILE / WV) + j * 64 + lane;
         const bool valid = e < n;
         const uint32_t dig = (key[j] >> shift) & (R - 1);
         unsigned long long m = __ballot(valid);
@@ -232,10 +237,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    for (int d = tid; d < R; d += SORT_THREADS) {
+    for (int d = tid; d < R; d += NT) {
         uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < WV; ++k) {
             const uint32_t c = s_wcnt[k][d];
             s_wcnt[k][d] = run;
             run += c;
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-        const uint32_t e = base + w * (TILE / 4) + j * 64 + lane;
+        const uint32_t e = base + w * (TILE / WV) + j * 64 + lane;
         if (e < n) {
             const uint32_t dig = (key[j] >> shift) & (R - 1);
             const uint32_t dst = s_goff[dig] + s_wcnt[w][dig] + pos[j];
@@ -262,26 +267,44 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     }
 }
 
-// Sorts `passes` digits starting at bit 0; returns the buffer index (0 = a,
-// 1 = b) that holds the result.
-static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, size_t s_keys,
-                      const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int first_bit, int passes,
-                      int blocks, const Layout& L, char* ws, hipStream_t s)
+// One counting pass over the RB-bit digits at `shift`: per-block counts,
+// their scan over blocks, the stable scatter.  `blocks` is the count-row
+// stride (the layout sizes the rows for it).
+template <int RB, int IT, bool KV, int WV>
+static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, size_t s_keys,
+                      const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int shift, int blocks,
+                      const Layout& L, char* ws, const uint32_t* order, size_t s_order, uint32_t* plist,
+                      size_t s_plist, uint32_t rank_mask, hipStream_t s)
 {
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* totals = (uint32_t*)(ws + L.totals);
     const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
-    const int maxb = blocks;  // count-row stride of this sort (the layout sizes rows for it)
+    hipLaunchKernelGGL((k_sort_count<RB, IT, WV>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, s_keys, n_dev,
+                       n_stride, n_fixed, shift, counts, sc, blocks);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1 << RB, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev, n_stride,
+                       n_fixed, blocks, (uint32_t)(64 * WV * IT));
+    hipLaunchKernelGGL((k_sort_scatter<RB, IT, KV, WV>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, vin, kout,
+                       vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, blocks, order, s_order,
+                       plist, s_plist, rank_mask);
+}
+
+// Sorts `passes` digits starting at bit 0; returns the buffer index (0 = a,
+// 1 = b) that holds the result.
+static int radix_sort(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, size_t s_keys,
+                      const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int first_bit, int passes,
+                      int blocks, bool wide, const Layout& L, char* ws, hipStream_t s)
+{
     uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
         const int shift = first_bit + p * RADIX_BITS;
-        hipLaunchKernelGGL(k_sort_count<RADIX_BITS>, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, s_keys,
-                           n_dev, n_stride, n_fixed, shift, counts, sc, maxb);
-        hipLaunchKernelGGL(k_sort_scan, dim3(RADIX, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev,
-                           n_stride, n_fixed, maxb, (uint32_t)SORT_TILE);
-        hipLaunchKernelGGL(k_sort_scatter<RADIX_BITS>, dim3(blocks, L.nq), dim3(SORT_THREADS), 0, s, kin, vin,
-                           kout, vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, maxb,
-                           nullptr, (size_t)0, nullptr, (size_t)0, 0u);
+        if (wide)
+            sort_pass<RADIX_BITS, SORT_ITEMS, true, SORT_WIDE_WAVES>(kin, vin, kout, vout, s_keys, n_dev, n_stride,
+                                                                     n_fixed, shift, blocks, L, ws, nullptr, 0,
+                                                                     nullptr, 0, 0u, s);
+        else
+            sort_pass<RADIX_BITS, SORT_ITEMS, true, SORT_THREADS / 64>(kin, vin, kout, vout, s_keys, n_dev, n_stride,
+                                                                       n_fixed, shift, blocks, L, ws, nullptr, 0,
+                                                                       nullptr, 0, 0u, s);
         uint32_t* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
@@ -292,7 +315,8 @@ void launch_depth_sort(const Layout& L, char* ws, hipStream_t s)
 {
     // keys a -> ... -> a after 4 passes (even), values follow
     radix_sort((uint32_t*)(ws + L.keys_a), (uint32_t*)(ws + L.keys_b), (uint32_t*)(ws + L.vals_a),
-               (uint32_t*)(ws + L.vals_b), L.s_keys / 4, nullptr, 0, (uint32_t)L.n, 0, 4, L.sort_blocks, L, ws, s);
+               (uint32_t*)(ws + L.vals_b), L.s_keys / 4, nullptr, 0, (uint32_t)L.n, 0, 4, L.sort_blocks,
+               L.sort_wide != 0, L, ws, s);
 }
 
 // ---- tiles-touched scan and pair emission -------------------------------
@@ -499,42 +523,41 @@ void launch_binning(const Layout& L, char* ws, hipStream_t s)
         // one counting pass over all tile digits: the scatter writes each
         // pair's Gaussian straight into the list, and the tile ranges are
         // the scan of the per-tile totals
-        uint32_t* counts = (uint32_t*)(ws + L.counts);
-        uint32_t* totals = (uint32_t*)(ws + L.totals);
-        const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
         const uint32_t* nd = flags + FL_PUSED;
         const uint32_t rmask = (1u << L.rank_bits) - 1u;
         uint32_t* plist = (uint32_t*)(ws + L.plist);
         const size_t spl = L.s_plist / 4;
+        constexpr int WN = SORT_THREADS / 64, WW = SORT_WIDE_WAVES;
         if (L.tile_bits <= RADIX_BITS) {
             // 256 digits: the usual blocks of SORT_ITEMS keys per thread
-            const int pb = L.pair_blocks;
-            hipLaunchKernelGGL((k_sort_count<RADIX_BITS>), dim3(pb, L.nq), dim3(SORT_THREADS), 0, s, pa, spk, nd, sf,
-                               0u, L.rank_bits, counts, sc, pb);
-            hipLaunchKernelGGL(k_sort_scan, dim3(1 << RADIX_BITS, L.nq), dim3(256), 0, s, counts, sc, totals, st,
-                               nd, sf, 0u, pb, (uint32_t)SORT_TILE);
-            hipLaunchKernelGGL((k_sort_scatter<RADIX_BITS, SORT_ITEMS, false>), dim3(pb, L.nq), dim3(SORT_THREADS),
-                               0, s, pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits, counts, sc, totals,
-                               st, pb, order, so, plist, spl, rmask);
+            if (L.pair_wide)
+                sort_pass<RADIX_BITS, SORT_ITEMS, false, WW>(pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u,
+                                                             L.rank_bits, L.pair_blocks, L, ws, order, so, plist,
+                                                             spl, rmask, s);
+            else
+                sort_pass<RADIX_BITS, SORT_ITEMS, false, WN>(pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u,
+                                                             L.rank_bits, L.pair_blocks, L, ws, order, so, plist,
+                                                             spl, rmask, s);
         } else {
-            // 1024 digits: blocks of TILE_PASS_ITEMS keys per thread keep the
-            // digit-by-block count matrix small
-            const int tb = L.tile_blocks;
-            const uint32_t ttile = (uint32_t)(SORT_THREADS * TILE_PASS_ITEMS);
-            hipLaunchKernelGGL((k_sort_count<TILE_PASS_MAX_BITS, TILE_PASS_ITEMS>), dim3(tb, L.nq),
-                               dim3(SORT_THREADS), 0, s, pa, spk, nd, sf, 0u, L.rank_bits, counts, sc, tb);
-            hipLaunchKernelGGL(k_sort_scan, dim3(1 << TILE_PASS_MAX_BITS, L.nq), dim3(256), 0, s, counts, sc,
-                               totals, st, nd, sf, 0u, tb, ttile);
-            hipLaunchKernelGGL((k_sort_scatter<TILE_PASS_MAX_BITS, TILE_PASS_ITEMS, false>), dim3(tb, L.nq),
-                               dim3(SORT_THREADS), 0, s, pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u, L.rank_bits,
-                               counts, sc, totals, st, tb, order, so, plist, spl, rmask);
+            // 1024 digits: blocks of TILE_PASS_ITEMS (TILE_PASS_WIDE_ITEMS)
+            // keys per thread keep the digit-by-block count matrix small
+            if (L.pair_wide)
+                sort_pass<TILE_PASS_MAX_BITS, TILE_PASS_WIDE_ITEMS, false, WW>(pa, nullptr, nullptr, nullptr, spk, nd,
+                                                                          sf, 0u, L.rank_bits, L.tile_blocks, L, ws,
+                                                                          order, so, plist, spl, rmask, s);
+            else
+                sort_pass<TILE_PASS_MAX_BITS, TILE_PASS_ITEMS, false, WN>(pa, nullptr, nullptr, nullptr, spk, nd,
+                                                                          sf, 0u, L.rank_bits, L.tile_blocks, L, ws,
+                                                                          order, so, plist, spl, rmask, s);
         }
+        const uint32_t* totals = (const uint32_t*)(ws + L.totals);
+        const size_t st = L.s_totals / 4;
         hipLaunchKernelGGL(k_tile_ranges, dim3(L.nq), dim3(256), 0, s, totals, st, ranges,
                            L.s_ranges / sizeof(uint2), L.T);
         return;
     }
     const int which = radix_sort(pa, pb, nullptr, nullptr, spk, flags + FL_PUSED, sf, 0, L.rank_bits,
-                                 L.pair_passes, L.pair_blocks, L, ws, s);
+                                 L.pair_passes, L.pair_blocks, L.pair_wide != 0, L, ws, s);
     uint32_t* sorted = which ? pb : pa;
     launch_fill_u32((uint32_t*)ranges, (size_t)L.T * 2, L.s_ranges / 4, L.nq, 0u, s);
     const int64_t rblocks = (L.cap + 255) / 256;

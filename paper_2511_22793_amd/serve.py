@@ -109,7 +109,7 @@ class Batch:
                               ctypes.byref(self.info), ctypes.c_void_p(stream)), "gs_batch_plan")
         self.n_queries = self.info.n_queries
         self.workgroups = int(workgroups) if workgroups else int(self.info.workgroups)
-        self.timestamps = torch.zeros(self.n_queries + 2, dtype=torch.int64, device=dev)
+        self.timestamps = torch.zeros(self.n_queries + 3, dtype=torch.int64, device=dev)
         khz = ctypes.c_int32()
         check(L.gs_wall_clock_khz(ctypes.byref(khz)), "gs_wall_clock_khz")
         self.clock_khz = khz.value
@@ -142,8 +142,10 @@ class Batch:
         the batch makespan, from the device timestamps of the last run."""
         ts = self.timestamps.cpu().numpy().astype(np.float64)
         per_tick = 1.0 / self.clock_khz  # ms
-        lat = (ts[1:-1] - ts[0]) * per_tick
-        return {"per_query": lat, "makespan": (ts[-1] - ts[0]) * per_tick,
+        nq = self.n_queries
+        lat = (ts[1:nq + 1] - ts[0]) * per_tick
+        return {"per_query": lat, "makespan": (ts[nq + 1] - ts[0]) * per_tick,
+                "prepare": (ts[nq + 2] - ts[0]) * per_tick,
                 "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
 
     def flags(self):

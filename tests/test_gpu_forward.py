@@ -50,21 +50,11 @@ def test_projection_records_match_oracle():
         assert np.array_equal(g["rect"][vis], p["rect"][vis])
 
 
-# tile counts 138 (one 8-bit pass), 540 and 276 (one 10-bit pass) and 2070
-# (12 bits: two 8-bit passes, then the range/list pass)
-@pytest.mark.parametrize("n,H,W,tile", [(2048, 90, 360, (16, 16)), (5000, 90, 360, (8, 8)),
-                                        (4097, 180, 720, (16, 16)), (3000, 90, 360, (8, 16)),
-                                        (3000, 180, 720, (8, 8))])
-def test_depth_order_and_tile_lists_bit_exact(n, H, W, tile):
-    sc = synth.scene(n, seed=1)
-    rx = np.array([[0.0, 0.0, 0.0], [-2.0, 1.5, 0.3]], np.float32)
-    # small tiles on the fine grid need more than the default 64 pairs per Gaussian
-    prm = gs.Params(pair_capacity=n * 512 + 4096)
-    _, ws = gpu_forward(sc, synth.rss_attrs(n), rx, H=H, W=W, tile=tile, prm=prm)
+def _check_order_and_lists(sc, rx, ws, n, H, W, tile, queries):
     flags = ws.flags()
     th, tw = tile
     TX, TY = oracle.tile_grid(H, W, tw, th)
-    for q in range(2):
+    for q in queries:
         g = _proj_from_ws(ws, q, n)
         p = oracle.project(sc, rx[q], H, W)
         order = oracle.depth_order(p)
@@ -82,6 +72,37 @@ def test_depth_order_and_tile_lists_bit_exact(n, H, W, tile):
             got = plist[rng[t, 0]:rng[t, 1]] if rng[t, 1] > rng[t, 0] else plist[:0]
             assert np.array_equal(got, lst_i[off_i[t]:off_i[t + 1]]), (q, t)
         assert np.array_equal(off_i, off_o) and np.array_equal(lst_i, lst_o)
+
+
+# Tile counts 138 (one 8-bit pass), 540 and 276 (one 10-bit pass) and 2070
+# (12 bits: two 8-bit passes, then the range/list pass).  The pair sorts run
+# in 16-wave workgroups when ceil(capacity / 8192) x queries >= 256 (here
+# 512 pairs per Gaussian), else in 4-wave ones (the cases with fewer pairs
+# per Gaussian).
+@pytest.mark.parametrize("n,H,W,tile,per", [(2048, 90, 360, (16, 16), 512), (5000, 90, 360, (8, 8), 512),
+                                            (4097, 180, 720, (16, 16), 512), (3000, 90, 360, (8, 16), 512),
+                                            (3000, 180, 720, (8, 8), 512), (2048, 90, 360, (16, 16), 64),
+                                            (4097, 180, 720, (16, 16), 200), (3000, 180, 720, (8, 8), 200)])
+def test_depth_order_and_tile_lists_bit_exact(n, H, W, tile, per):
+    sc = synth.scene(n, seed=1)
+    rx = np.array([[0.0, 0.0, 0.0], [-2.0, 1.5, 0.3]], np.float32)
+    wide = -(-(n * per + 4096) // 8192) * 2 >= 256
+    assert wide == (per == 512)
+    prm = gs.Params(pair_capacity=n * per + 4096)
+    _, ws = gpu_forward(sc, synth.rss_attrs(n), rx, H=H, W=W, tile=tile, prm=prm)
+    _check_order_and_lists(sc, rx, ws, n, H, W, tile, range(2))
+
+
+def test_wide_depth_sort_bit_exact():
+    # 40000 Gaussians x 52 receivers: ceil(40000 / 8192) x 52 = 260 >= 256
+    # blocks, so the depth sort runs in 16-wave workgroups of 8192 keys (a
+    # ragged last block of 7232); checked on the first, a middle and the last
+    # receiver
+    n, nq = 40_000, 52
+    sc = synth.scene(n, seed=4)
+    rx = synth.points(nq, seed=12)
+    _, ws = gpu_forward(sc, synth.rss_attrs(n), rx)
+    _check_order_and_lists(sc, rx, ws, n, 90, 360, (16, 16), (0, 25, nq - 1))
 
 
 @pytest.mark.parametrize("n,seed,rx", [(2048, 0, (0.0, 0.0, 0.0)), (777, 5, (0.5, -0.5, 1.0)),

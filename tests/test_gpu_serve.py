@@ -60,9 +60,13 @@ def assert_batch_equals_single(batch):
 
 def check_timestamps(batch):
     ts = batch.timestamps.cpu().numpy()
-    assert ts[0] > 0 and np.all(ts[1:-1] >= ts[0]) and np.all(ts[1:-1] <= ts[-1])
+    nq = batch.n_queries
+    assert ts.shape == (nq + 3,)
+    # start <= end of the prepare steps <= every completion <= end
+    assert ts[0] > 0 and ts[0] <= ts[nq + 2]
+    assert np.all(ts[1:nq + 1] >= ts[nq + 2]) and np.all(ts[1:nq + 1] <= ts[nq + 1])
     lat = batch.latencies_ms()
-    assert 0 < lat["p50"] <= lat["p99"] <= lat["makespan"]
+    assert 0 < lat["prepare"] <= lat["p50"] <= lat["p99"] <= lat["makespan"]
     return lat
 
 
