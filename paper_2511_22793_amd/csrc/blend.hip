@@ -408,10 +408,12 @@ __global__ __launch_bounds__(LIVE_PIX) void k_live(
     plist += q * s_plist;
     flags_live += q * s_live;
     __shared__ double s_px[LIVE_PIX], s_py[LIVE_PIX], s_ca[LIVE_PIX], s_cb[LIVE_PIX], s_cc[LIVE_PIX];
-    __shared__ float s_sig[LIVE_PIX], s_att[LIVE_PIX], s_wsum[LIVE_PIX];
+    __shared__ float s_sig[LIVE_PIX], s_att[LIVE_PIX];
     __shared__ uint32_t s_g[LIVE_PIX];
+    // per-pixel weights of the batch's entries, [entry][pixel] (a row of 65
+    // keeps both the per-pixel writes and the per-entry sums conflict-free)
+    __shared__ float s_w[LIVE_PIX][LIVE_PIX + 1];
     if (wtot) wtot += q * s_wtot;
-    s_wsum[threadIdx.x] = 0.0f;
     float T = 1.0f;
     uint32_t last = 0, cnt = 0;
     bool done = !inside;
@@ -432,10 +434,10 @@ __global__ __launch_bounds__(LIVE_PIX) void k_live(
         }
         __syncthreads();
         const int m = (int)min((uint32_t)nthr, rg.y - b0);
-        // (the loop runs while any lane of the wave walks, so that the
-        // wave can sum the pixel weights of each entry)
+        int jend = 0;  // entries walked by some pixel of the wave
         for (int j = 0; j < m; ++j) {
             if (__ballot(!done) == 0ull) break;
+            jend = j + 1;
             float wgt = 0.0f;
             if (!done) {
                 double dx = pcx - s_px[j];
@@ -454,17 +456,16 @@ __global__ __launch_bounds__(LIVE_PIX) void k_live(
                 last = take ? b0 + j + 1 - rg.x : last;
                 cnt += take ? 1u : 0u;
             }
-            if (wtot) {
-                // the entry's weight summed over the wave's pixels
-                for (int o = 32; o > 0; o >>= 1) wgt += __shfl_xor(wgt, o, 64);
-                if ((threadIdx.x & 63) == 0 && wgt != 0.0f) atomicAdd(&s_wsum[j], wgt);
-            }
+            if (wtot) s_w[j][threadIdx.x] = wgt;
         }
         if (wtot) {
+            // thread t sums entry t's weight over the 64 pixels
             __syncthreads();
-            if ((int)threadIdx.x < m && s_wsum[threadIdx.x] != 0.0f) {
-                unsafeAtomicAdd(&wtot[s_g[threadIdx.x]], s_wsum[threadIdx.x]);
-                s_wsum[threadIdx.x] = 0.0f;
+            if ((int)threadIdx.x < jend) {
+                float ws = 0.0f;
+#pragma unroll 8
+                for (int i = 0; i < LIVE_PIX; ++i) ws += s_w[threadIdx.x][i];
+                if (ws != 0.0f) unsafeAtomicAdd(&wtot[s_g[threadIdx.x]], ws);
             }
         }
     }
