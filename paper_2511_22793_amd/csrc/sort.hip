@@ -221,12 +221,18 @@ __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
         const uint32_t e = base + w * (TILE / WV) + j * 64 + lane;
         const bool valid = e < n;
         const uint32_t dig = (key[j] >> shift) & (R - 1);
-        unsigned long long m = __ballot(valid);
+        // lanes whose digit differs from this lane's in some bit: per bit,
+        // the ballot of the bit, inverted where this lane's bit is set
+        // (bm: the bit as an all-ones or all-zeros word)
+        uint32_t dlo = 0u, dhi = 0u;
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            const unsigned long long bb = __ballot((dig >> b) & 1u);
-            m &= ((dig >> b) & 1u) ? bb : ~bb;
+            const int32_t bm = (int32_t)(dig << (31 - b)) >> 31;
+            const unsigned long long bb = __ballot(bm != 0);
+            dlo |= (uint32_t)bb ^ (uint32_t)bm;
+            dhi |= (uint32_t)(bb >> 32) ^ (uint32_t)bm;
         }
+        const unsigned long long m = __ballot(valid) & ~(((unsigned long long)dhi << 32) | dlo);
         const uint32_t r = (uint32_t)__popcll(m & lt);
         const uint32_t c = s_wcnt[w][dig];
         pos[j] = c + r;
