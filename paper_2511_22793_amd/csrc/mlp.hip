@@ -121,18 +121,66 @@ __device__ __forceinline__ void layer_mfma(const uint16_t* __restrict__ act /*LD
     }
 }
 
+// Weights staged in LDS for the row kernels: rows of 64 bf16 padded to
+// WROW (16-byte aligned rows, fewer bank conflicts in the B-operand reads).
+constexpr int WROW = MLP_HID + 8;
+
+// layer_mfma with the weights' B operands from LDS rows of `ws` bf16
+__device__ __forceinline__ void layer_mfma_lds(const uint16_t* act /*LDS [16][64]*/, const uint16_t* W /*LDS [N][ws]*/,
+                                               int ws, int ntiles, f32x4* acc, int lane)
+{
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) {
+        if (nt < ntiles) {
+            f32x4 c = {0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                const bf16x8 a = load8(act + (lane & 15) * MLP_HID + kc * 32 + 8 * (lane >> 4));
+                const bf16x8 b = load8(W + (nt * 16 + (lane & 15)) * ws + kc * 32 + 8 * (lane >> 4));
+                c = mfma(a, b, c);
+            }
+            acc[nt] = c;
+        }
+    }
+}
+
+// dst[r][k] = W[r * 64 + k] for r < rows (LDS rows of WROW), in 16-byte chunks
+__device__ __forceinline__ void stage_rows(uint16_t* dst, const uint16_t* __restrict__ W, int rows)
+{
+    for (int c = threadIdx.x; c < rows * (MLP_HID / 8); c += blockDim.x) {
+        const int r = c / (MLP_HID / 8), k = (c % (MLP_HID / 8)) * 8;
+        *(uint4*)(dst + r * WROW + k) = *(const uint4*)(W + (size_t)r * MLP_HID + k);
+    }
+}
+
+// 16 consecutive bf16 (32 bytes, 16-byte aligned) between global and LDS
+__device__ __forceinline__ void copy16(uint16_t* dst, const uint16_t* src)
+{
+    ((uint4*)dst)[0] = ((const uint4*)src)[0];
+    ((uint4*)dst)[1] = ((const uint4*)src)[1];
+}
+
 // Loads h1 = relu(Z1[g] + c[s]) for the wave's 16 rows into LDS (bf16).
 __device__ __forceinline__ void load_h1(const float* __restrict__ Z1, const float* __restrict__ cs, const int* rows,
                                         uint16_t* h1s, int lane)
 {
     const int r = lane & 15, c0 = (lane >> 4) * 16;
     const int g = rows[r];
+    float z[16], c[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        float v = 0.0f;
-        if (g >= 0) v = fmaxf(Z1[(size_t)g * MLP_HID + c0 + j] + cs[c0 + j], 0.0f);
-        h1s[r * MLP_HID + c0 + j] = f2bf(v);
+    for (int j = 0; j < 16; j += 4) {
+        const float4 zz = g >= 0 ? *(const float4*)(Z1 + (size_t)g * MLP_HID + c0 + j) : make_float4(0, 0, 0, 0);
+        const float4 cc = *(const float4*)(cs + c0 + j);
+        z[j] = zz.x; z[j + 1] = zz.y; z[j + 2] = zz.z; z[j + 3] = zz.w;
+        c[j] = cc.x; c[j + 1] = cc.y; c[j + 2] = cc.z; c[j + 3] = cc.w;
     }
+    uint16_t h[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) h[j] = f2bf(g >= 0 ? fmaxf(z[j] + c[j], 0.0f) : 0.0f);
+    uint4 v[2];
+    __builtin_memcpy(v, h, 32);
+    ((uint4*)(h1s + r * MLP_HID + c0))[0] = v[0];
+    ((uint4*)(h1s + r * MLP_HID + c0))[1] = v[1];
 }
 
 // C layout (16 x 64 as 4 tiles) + bias -> relu -> bf16 -> LDS [16][64]
@@ -161,9 +209,14 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t* list = A.list + (size_t)s * A.list_stride;
     const uint32_t count = A.count[A.count_stride ? s : 0];
+    if (blockIdx.x * 64 >= (int)count) return;  // no rows for this workgroup
     __shared__ __attribute__((aligned(16))) uint16_t s_h1[4][16 * MLP_HID];
     __shared__ __attribute__((aligned(16))) uint16_t s_h2[4][16 * MLP_HID];
+    __shared__ __attribute__((aligned(16))) uint16_t s_W2[MLP_HID * WROW];
+    __shared__ __attribute__((aligned(16))) uint16_t s_W3[2 * NF * WROW];
     __shared__ int s_rows[4][16];
+    stage_rows(s_W2, A.W2, MLP_HID);
+    stage_rows(s_W3, A.W3, 2 * NF);
     const float* cs = A.cb + s * MLP_HID;
     const float tx0 = A.tx[3 * s], tx1 = A.tx[3 * s + 1], tx2 = A.tx[3 * s + 2];
     for (int base = blockIdx.x * 64; base < (int)count; base += gridDim.x * 64) {
@@ -174,21 +227,17 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs A)
         load_h1(A.Z1, cs, s_rows[w], s_h1[w], lane);
         __syncthreads();
         f32x4 acc[8];
-        layer_mfma(s_h1[w], A.W2, 4, acc, lane);
+        layer_mfma_lds(s_h1[w], s_W2, WROW, 4, acc, lane);
         store_hidden(acc, A.b2, s_h2[w], lane);
         __syncthreads();
-        layer_mfma(s_h2[w], A.W3, 2 * NF / 16, acc, lane);
+        layer_mfma_lds(s_h2[w], s_W3, WROW, 2 * NF / 16, acc, lane);
         // save activations for the backward (row-compact order r = s*cap + i)
         if (A.save_h1) {
             const int r = lane & 15, c0 = (lane >> 4) * 16;
             const int i = r0 + r;
             if (i < (int)count) {
-                uint16_t* d1 = A.save_h1 + ((size_t)s * A.row_cap + i) * MLP_HID + c0;
-                uint16_t* d2 = A.save_h2 + ((size_t)s * A.row_cap + i) * MLP_HID + c0;
-                for (int j = 0; j < 16; ++j) {
-                    d1[j] = s_h1[w][r * MLP_HID + c0 + j];
-                    d2[j] = s_h2[w][r * MLP_HID + c0 + j];
-                }
+                copy16(A.save_h1 + ((size_t)s * A.row_cap + i) * MLP_HID + c0, &s_h1[w][r * MLP_HID + c0]);
+                copy16(A.save_h2 + ((size_t)s * A.row_cap + i) * MLP_HID + c0, &s_h2[w][r * MLP_HID + c0]);
             }
         }
         // epilogue: amplitude / phase -> complex attribute
@@ -225,6 +274,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t* list = A.list + (size_t)s * A.list_stride;
     const uint32_t count = A.count[A.count_stride ? s : 0];
+    __shared__ __attribute__((aligned(16))) uint16_t s_h1[4][16 * MLP_HID];
     __shared__ __attribute__((aligned(16))) uint16_t s_h2[4][16 * MLP_HID];
     __shared__ __attribute__((aligned(16))) uint16_t s_do[4][16 * 2 * NF];
     __shared__ __attribute__((aligned(16))) uint16_t s_dz[4][16 * MLP_HID];
@@ -241,13 +291,20 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
         const int r0 = base + w * 16;
         if (lane < 16) s_rows[w][lane] = row_gauss(list, count, r0 + lane);
         __syncthreads();
-        // saved h2 of the 16 rows
+        // saved h1 and h2 of the 16 rows
         {
             const int r = lane & 15, c0 = (lane >> 4) * 16;
             const int i = r0 + r;
-            for (int j = 0; j < 16; ++j)
-                s_h2[w][r * MLP_HID + c0 + j] =
-                    i < (int)count ? A.save_h2[((size_t)s * A.row_cap + i) * MLP_HID + c0 + j] : (uint16_t)0;
+            if (i < (int)count) {
+                copy16(&s_h1[w][r * MLP_HID + c0], A.save_h1 + ((size_t)s * A.row_cap + i) * MLP_HID + c0);
+                copy16(&s_h2[w][r * MLP_HID + c0], A.save_h2 + ((size_t)s * A.row_cap + i) * MLP_HID + c0);
+            } else {
+                const uint4 z = make_uint4(0, 0, 0, 0);
+                ((uint4*)&s_h1[w][r * MLP_HID + c0])[0] = z;
+                ((uint4*)&s_h1[w][r * MLP_HID + c0])[1] = z;
+                ((uint4*)&s_h2[w][r * MLP_HID + c0])[0] = z;
+                ((uint4*)&s_h2[w][r * MLP_HID + c0])[1] = z;
+            }
         }
         __syncthreads();
         f32x4 acc[8];
@@ -300,8 +357,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
             const int r = lane & 15;
             const int i = r0 + r;
             if (i < (int)count)
-                for (int j = (lane >> 4) * (NF / 2); j < (lane >> 4) * (NF / 2) + NF / 2; ++j)
-                    A.save_do[((size_t)s * A.row_cap + i) * 2 * NF + j] = s_do[w][r * 2 * NF + j];
+                for (int j = (lane >> 4) * (NF / 2); j < (lane >> 4) * (NF / 2) + NF / 2; j += 16)
+                    copy16(A.save_do + ((size_t)s * A.row_cap + i) * 2 * NF + j, &s_do[w][r * 2 * NF + j]);
         }
         // dh2 = d_o W3  (K = 2 NF in 32-wide chunks; B from W3^T [64][2 NF])
         f32x4 dh[4];
@@ -343,8 +400,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
             const int r = lane & 15, c0 = (lane >> 4) * 16;
             const int i = r0 + r;
             if (i < (int)count)
-                for (int j = 0; j < 16; ++j)
-                    A.save_dz2[((size_t)s * A.row_cap + i) * MLP_HID + c0 + j] = s_dz[w][r * MLP_HID + c0 + j];
+                copy16(A.save_dz2 + ((size_t)s * A.row_cap + i) * MLP_HID + c0, &s_dz[w][r * MLP_HID + c0]);
         }
         // dh1 = dZ2 W2 (B from W2^T), dZ1 = dh1 * [h1 > 0]
         f32x4 d1[4];
@@ -357,7 +413,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
                 const int col = nt * 16 + (lane & 15), row = 4 * (lane >> 4) + i;
                 const int rix = r0 + row;
                 float m = 0.0f;
-                if (rix < (int)count) m = bf2f(A.save_h1[((size_t)s * A.row_cap + rix) * MLP_HID + col]) > 0.0f;
+                if (rix < (int)count) m = bf2f(s_h1[w][row * MLP_HID + col]) > 0.0f;
                 d1[nt][i] *= m;
                 s_dz[w][row * MLP_HID + col] = f2bf(d1[nt][i]);
             }
@@ -373,8 +429,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpArgs A)
             const int r = lane & 15, c0 = (lane >> 4) * 16;
             const int i = r0 + r;
             if (i < (int)count)
-                for (int j = 0; j < 16; ++j)
-                    A.save_dz1[((size_t)s * A.row_cap + i) * MLP_HID + c0 + j] = s_dz[w][r * MLP_HID + c0 + j];
+                copy16(A.save_dz1 + ((size_t)s * A.row_cap + i) * MLP_HID + c0, &s_dz[w][r * MLP_HID + c0]);
         }
         // dE[g] += dZ1 W1e  (B from W1e^T [32][64])
 #pragma unroll
