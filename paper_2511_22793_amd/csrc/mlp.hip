@@ -79,15 +79,19 @@ __global__ __launch_bounds__(64) void k_mlp_bias(const uint16_t* __restrict__ W1
 {
     const int s = blockIdx.x, j = threadIdx.x;
     __shared__ float g[MLP_ENC];
+    __shared__ double su[3];
     if (j < 3) {
         const float lo = j == 0 ? lo0 : (j == 1 ? lo1 : lo2), hi = j == 0 ? hi0 : (j == 1 ? hi1 : hi2);
         const double u = 2.0 * ((double)tx[3 * s + j] - lo) / ((double)hi - lo) - 1.0;
+        su[j] = u;
         g[j] = bf2f(f2bf((float)u));
-        for (int k = 0; k < MLP_BANDS; ++k) {
-            const double a = ldexp(M_PI, k) * u;
-            g[3 + 6 * k + j] = bf2f(f2bf((float)sin(a)));
-            g[6 + 6 * k + j] = bf2f(f2bf((float)cos(a)));
-        }
+    }
+    __syncthreads();
+    if (j < 3 * MLP_BANDS) {  // one (band, coordinate) angle per thread
+        const int k = j / 3, d = j % 3;
+        const double a = ldexp(M_PI, k) * su[d];
+        g[3 + 6 * k + d] = bf2f(f2bf((float)sin(a)));
+        g[6 + 6 * k + d] = bf2f(f2bf((float)cos(a)));
     }
     __syncthreads();
     float acc = b1[j];
@@ -591,8 +595,17 @@ __global__ void k_reduce3(const float* __restrict__ partial, int nparts, float* 
             if (e >= WG3_LEN2) return;
         }
     }
+    // the partials added in order, 16 loads in flight ahead of the additions
     float acc = 0.0f;
-    for (int p = 0; p < nparts; ++p) acc += base[(size_t)p * len + e];
+    int p = 0;
+    for (; p + 16 <= nparts; p += 16) {
+        float b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) b[u] = base[(size_t)(p + u) * len + e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += b[u];
+    }
+    for (; p < nparts; ++p) acc += base[(size_t)p * len + e];
     out[(size_t)(e / ncols) * ld + e % ncols] = acc;
 }
 
@@ -602,8 +615,20 @@ __global__ void k_mlp_bias_grad(const float* __restrict__ dc, const uint16_t* __
 {
     const int j = threadIdx.x;  // hidden unit
     for (int k = blockIdx.x; k <= MLP_ENC; k += gridDim.x) {
+        // the sets added in order, 16 sets' loads in flight ahead of the products
         float acc = 0.0f;
-        for (int s = 0; s < S; ++s) acc += dc[s * MLP_HID + j] * (k < MLP_ENC ? bf2f(genc[s * MLP_ENC_PAD + k]) : 1.0f);
+        int s = 0;
+        for (; s + 16 <= S; s += 16) {
+            float d[16], g[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                d[u] = dc[(s + u) * MLP_HID + j];
+                g[u] = k < MLP_ENC ? bf2f(genc[(s + u) * MLP_ENC_PAD + k]) : 1.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += d[u] * g[u];
+        }
+        for (; s < S; ++s) acc += dc[s * MLP_HID + j] * (k < MLP_ENC ? bf2f(genc[s * MLP_ENC_PAD + k]) : 1.0f);
         if (k < MLP_ENC) dW1[(size_t)j * MLP_IN + MLP_EMB + k] = acc;
         else db1[j] = acc;
     }
