@@ -9,34 +9,40 @@ namespace gs {
 
 constexpr size_t PLAN_HEAD = 256;  // work counter, then the job table
 
-// Prepare lanes: the caller's stream plus BATCH_SIDE side streams (default
-// priority, non-blocking), created once per device by gs_batch_plan().  A
-// run forks them from the caller's stream with an event and joins them back
+// Prepare lanes: the caller's stream plus the LANE_SIDE side streams of the
+// device, forked from the caller's stream with an event and joined back
 // before the blend, so the whole run stays one capturable sequence.
-constexpr int BATCH_SIDE = 3;
-constexpr int BATCH_MAX_DEVICES = 64;
-struct Lanes {
-    hipStream_t side[BATCH_SIDE];
-    hipEvent_t fork;
-    hipEvent_t join[BATCH_SIDE];
-    bool ready;
-};
+constexpr int LANES_MAX_DEVICES = 64;
 std::mutex g_lanes_mu;
-Lanes g_lanes[BATCH_MAX_DEVICES] = {};
+Lanes g_lanes[LANES_MAX_DEVICES] = {};
 
-static gs_status lanes_init(int dev)
+std::mutex& lanes_mutex() { return g_lanes_mu; }
+
+gs_status lanes_init(int dev)
 {
-    if (dev < 0 || dev >= BATCH_MAX_DEVICES) return GS_ERR_CAPACITY;
+    if (dev < 0 || dev >= LANES_MAX_DEVICES) return GS_ERR_CAPACITY;
     std::lock_guard<std::mutex> lk(g_lanes_mu);
     Lanes& l = g_lanes[dev];
     if (l.ready) return GS_OK;
-    for (int i = 0; i < BATCH_SIDE; ++i) {
+    for (int i = 0; i < LANE_SIDE; ++i) {
         if (hipStreamCreateWithFlags(&l.side[i], hipStreamNonBlocking) != hipSuccess) return GS_ERR_HIP;
         if (hipEventCreateWithFlags(&l.join[i], hipEventDisableTiming) != hipSuccess) return GS_ERR_HIP;
     }
     if (hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) != hipSuccess) return GS_ERR_HIP;
     l.ready = true;
     return GS_OK;
+}
+
+const Lanes* side_lanes(hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= LANES_MAX_DEVICES) return nullptr;
+    if (!g_lanes[dev].ready) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+        if (lanes_init(dev) != GS_OK) return nullptr;
+    }
+    return &g_lanes[dev];
 }
 
 static gs_status build_table(const gs_batch_job* jobs, int n_jobs, std::vector<BlendJob>& table, gs_batch_info* info)
@@ -137,9 +143,7 @@ gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, siz
         st = make_layout(b.scene.n, b.queries.count, &b.grid, &b.params, &lay[j]);
         if (st != GS_OK) return st;
     }
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
-    const Lanes* ln = (dev >= 0 && dev < BATCH_MAX_DEVICES && g_lanes[dev].ready && n_jobs > 1) ? &g_lanes[dev] : nullptr;
+    const Lanes* ln = n_jobs > 1 ? side_lanes(s) : nullptr;
     if (!ln) {
         for (int j = 0; j < n_jobs; ++j) {
             const gs_batch_job& b = jobs[j];
@@ -149,8 +153,8 @@ gs_status gs_batch_run(const gs_batch_job* jobs, int32_t n_jobs, void* plan, siz
         // each job to the lane with the least projected work so far
         // (Gaussians x queries), in job order
         std::lock_guard<std::mutex> lk(g_lanes_mu);
-        const int nl = std::min(n_jobs, BATCH_SIDE + 1);
-        double load[BATCH_SIDE + 1] = {};
+        const int nl = std::min(n_jobs, LANE_SIDE + 1);
+        double load[LANE_SIDE + 1] = {};
         if (hipEventRecord(ln->fork, s) != hipSuccess) return GS_ERR_HIP;
         for (int i = 1; i < nl; ++i)
             if (hipStreamWaitEvent(ln->side[i - 1], ln->fork, 0) != hipSuccess) return GS_ERR_HIP;

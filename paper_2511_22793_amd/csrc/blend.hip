@@ -496,9 +496,16 @@ void launch_live(const gs_params& p, const Layout& L, char* ws, uint32_t* list, 
                  hipStream_t s)
 {
     uint32_t* fl = (uint32_t*)(ws + L.live);
-    launch_fill_u32(fl, (size_t)L.n, L.s_live / 4, L.nq, 0u, s);
-    launch_fill_u32(count, 1, 1, L.nq, 0u, s);
-    launch_fill_u32((uint32_t*)(ws + L.wtot), (size_t)L.n, L.s_wtot / 4, L.nq, 0u, s);
+    {
+        // the live flags and weight sums of every query (their query
+        // strides included: one contiguous range each) and the counts
+        FillSegs f{};
+        f.p[0] = fl; f.count[0] = (size_t)L.nq * (L.s_live / 4);
+        f.p[1] = count; f.count[1] = (size_t)L.nq;
+        f.p[2] = (uint32_t*)(ws + L.wtot); f.count[2] = (size_t)L.nq * (L.s_wtot / 4);
+        f.n = 3;
+        launch_fill_segs(f, s);
+    }
     hipLaunchKernelGGL(k_live, dim3(L.T, (L.tw * L.th + LIVE_PIX - 1) / LIVE_PIX, L.nq), dim3(LIVE_PIX), 0, s,
                        (const GRec*)(ws + L.rec),
                        L.s_rec / sizeof(GRec), (const uint32_t*)(ws + L.plist), L.s_plist / 4,

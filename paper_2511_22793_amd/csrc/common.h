@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/gsparc.h"
@@ -151,6 +152,22 @@ struct FillSegs {
     int n;
 };
 void launch_fill_segs(const FillSegs& f, hipStream_t s);  // zero-fills f.n buffers (words)
+
+// Side streams of a device for the library's fork/join launch sequences
+// (default priority, non-blocking), created once per device and kept until
+// the process ends, with the events that fork them from and join them into
+// a caller's stream.  Enqueueing on them is serialised by lanes_mutex().
+constexpr int LANE_SIDE = 3;
+struct Lanes {
+    hipStream_t side[LANE_SIDE];
+    hipEvent_t fork;
+    hipEvent_t join[LANE_SIDE];
+    bool ready;
+};
+gs_status lanes_init(int dev);           // creates device dev's lanes (call outside graph capture)
+const Lanes* side_lanes(hipStream_t s);  // the current device's lanes, created unless s is being
+                                         // captured; null: the caller runs serially
+std::mutex& lanes_mutex();
 // fills [0, min(per_query * n_dev[q], max_count)) of each query, n_dev read
 // on the device
 void launch_fill_dev(uint32_t* p, size_t max_count, size_t q_stride, int nq, const uint32_t* n_dev, size_t n_stride,

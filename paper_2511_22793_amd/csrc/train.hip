@@ -996,12 +996,35 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     // the groups sorted by walk length into the variants' lists, then each
     // variant over its list (the longest walks first)
     hipLaunchKernelGGL(k_train_classify, dim3(groups), dim3(64), 0, s, A);
-    hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(slots.fb[2]), dim3(256), 0, s, A, 2);
-    hipLaunchKernelGGL(k_train_fb<128>, dim3(slots.fb[1]), dim3(256), 0, s, A, 1);
-    hipLaunchKernelGGL(k_train_fb<64>, dim3(slots.fb[0]), dim3(256), 0, s, A, 0);
-    hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(slots.walk[2]), dim3(256), 0, s, A, 2);
-    hipLaunchKernelGGL(k_train_walk<128>, dim3(slots.walk[1]), dim3(256), 0, s, A, 1);
-    hipLaunchKernelGGL(k_train_walk<64>, dim3(slots.walk[0]), dim3(256), 0, s, A, 0);
+    // The classes touch disjoint groups (their GV rows, work counters and
+    // lists; the attribute gradients, loss partials and per-pair sums are
+    // atomics), so the 256 and 128 classes run on side streams beside the
+    // 64 class: their few long walks fill the 64 class's tail instead of
+    // running alone.
+    const Lanes* ln = side_lanes(s);
+    if (ln) {
+        std::lock_guard<std::mutex> lk(lanes_mutex());
+        if (hipEventRecord(ln->fork, s) != hipSuccess) return GS_ERR_HIP;
+        for (int i = 0; i < 2; ++i)
+            if (hipStreamWaitEvent(ln->side[i], ln->fork, 0) != hipSuccess) return GS_ERR_HIP;
+        hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(slots.fb[2]), dim3(256), 0, ln->side[0], A, 2);
+        hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(slots.walk[2]), dim3(256), 0, ln->side[0], A, 2);
+        hipLaunchKernelGGL(k_train_fb<128>, dim3(slots.fb[1]), dim3(256), 0, ln->side[1], A, 1);
+        hipLaunchKernelGGL(k_train_walk<128>, dim3(slots.walk[1]), dim3(256), 0, ln->side[1], A, 1);
+        hipLaunchKernelGGL(k_train_fb<64>, dim3(slots.fb[0]), dim3(256), 0, s, A, 0);
+        hipLaunchKernelGGL(k_train_walk<64>, dim3(slots.walk[0]), dim3(256), 0, s, A, 0);
+        for (int i = 0; i < 2; ++i) {
+            if (hipEventRecord(ln->join[i], ln->side[i]) != hipSuccess) return GS_ERR_HIP;
+            if (hipStreamWaitEvent(s, ln->join[i], 0) != hipSuccess) return GS_ERR_HIP;
+        }
+    } else {
+        hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(slots.fb[2]), dim3(256), 0, s, A, 2);
+        hipLaunchKernelGGL(k_train_fb<128>, dim3(slots.fb[1]), dim3(256), 0, s, A, 1);
+        hipLaunchKernelGGL(k_train_fb<64>, dim3(slots.fb[0]), dim3(256), 0, s, A, 0);
+        hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(slots.walk[2]), dim3(256), 0, s, A, 2);
+        hipLaunchKernelGGL(k_train_walk<128>, dim3(slots.walk[1]), dim3(256), 0, s, A, 1);
+        hipLaunchKernelGGL(k_train_walk<64>, dim3(slots.walk[0]), dim3(256), 0, s, A, 0);
+    }
     timing_end(tok, s);
     // groups whose walk is longer than the fused kernels take: compositing
     // into the spectrum, then the backward forming g from it and the target
