@@ -375,6 +375,12 @@ gs_status gs_spatial_mean(const float* spectrum, int32_t n_sets, int32_t n_chan,
  * the kernels address them with 32-bit byte offsets); nothing is enqueued
  * on an argument error.  Float atomics make the last bits of the gradients
  * vary between runs.
+ * Streams: the walk classes of up to 256 and 128 entries run on two of the
+ * library's side streams of the device (those of gs_batch_run(), created on
+ * first use outside graph capture), forked from and joined back into
+ * `stream` with events inside the call; a graph capture of the call records
+ * them as parallel branches.  Before the side streams exist (first call
+ * under capture) everything runs on `stream`.
  */
 typedef struct {
     const float* target;
@@ -681,8 +687,8 @@ gs_status gs_screen_radius(const void* workspace, size_t ws_bytes, int32_t n, in
  *    (gs_wall_clock_khz()): [0] batch start (before the first prepare),
  *    [1 + k] completion of the k-th query's spectrum (queries numbered job
  *    by job), [n_queries + 1] batch end, [n_queries + 2] end of the prepare
- *    steps (start of the blend).  Without a prior gs_batch_plan() on the
- *    device, or with one job, every prepare runs on `stream`.
+ *    steps (start of the blend).  With one job, or under a graph capture
+ *    before the side streams exist, every prepare runs on `stream`.
  *  Concurrent runs of one plan race on its work counter; runs enqueued from
  *  several host threads take turns on the side streams (a lock), and runs on
  *  different caller streams of one device are ordered through them.
