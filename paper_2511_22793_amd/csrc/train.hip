@@ -1001,22 +1001,30 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     // atomics), so the 256 and 128 classes run on side streams beside the
     // 64 class: their few long walks fill the 64 class's tail instead of
     // running alone.
+    // Groups whose walk is longer than the fused kernels take go through
+    // compositing into the spectrum, then the backward forming g from it and
+    // the target (their own loss partial; attribute gradients and per-pair
+    // sums are atomics): a third branch beside the classes.
     const Lanes* ln = side_lanes(s);
     if (ln) {
         std::lock_guard<std::mutex> lk(lanes_mutex());
         if (hipEventRecord(ln->fork, s) != hipSuccess) return GS_ERR_HIP;
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 3; ++i)
             if (hipStreamWaitEvent(ln->side[i], ln->fork, 0) != hipSuccess) return GS_ERR_HIP;
         hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(slots.fb[2]), dim3(256), 0, ln->side[0], A, 2);
         hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(slots.walk[2]), dim3(256), 0, ln->side[0], A, 2);
         hipLaunchKernelGGL(k_train_fb<128>, dim3(slots.fb[1]), dim3(256), 0, ln->side[1], A, 1);
         hipLaunchKernelGGL(k_train_walk<128>, dim3(slots.walk[1]), dim3(256), 0, ln->side[1], A, 1);
+        launch_blend_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, TR_EMAX, ln->side[2]);
+        launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, tt->grad_scale,
+                                 d_attr, TR_EMAX, llong, ln->side[2]);
         hipLaunchKernelGGL(k_train_fb<64>, dim3(slots.fb[0]), dim3(256), 0, s, A, 0);
         hipLaunchKernelGGL(k_train_walk<64>, dim3(slots.walk[0]), dim3(256), 0, s, A, 0);
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < 3; ++i) {
             if (hipEventRecord(ln->join[i], ln->side[i]) != hipSuccess) return GS_ERR_HIP;
             if (hipStreamWaitEvent(s, ln->join[i], 0) != hipSuccess) return GS_ERR_HIP;
         }
+        timing_end(tok, s);
     } else {
         hipLaunchKernelGGL(k_train_fb<TR_EMAX>, dim3(slots.fb[2]), dim3(256), 0, s, A, 2);
         hipLaunchKernelGGL(k_train_fb<128>, dim3(slots.fb[1]), dim3(256), 0, s, A, 1);
@@ -1024,13 +1032,11 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
         hipLaunchKernelGGL(k_train_walk<TR_EMAX>, dim3(slots.walk[2]), dim3(256), 0, s, A, 2);
         hipLaunchKernelGGL(k_train_walk<128>, dim3(slots.walk[1]), dim3(256), 0, s, A, 1);
         hipLaunchKernelGGL(k_train_walk<64>, dim3(slots.walk[0]), dim3(256), 0, s, A, 0);
+        timing_end(tok, s);
+        launch_blend_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, TR_EMAX, s);
+        launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, tt->grad_scale,
+                                 d_attr, TR_EMAX, llong, s);
     }
-    timing_end(tok, s);
-    // groups whose walk is longer than the fused kernels take: compositing
-    // into the spectrum, then the backward forming g from it and the target
-    launch_blend_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, TR_EMAX, s);
-    launch_blend_bwd_sg_long(*attrs, *prm, L, n_sets, ws, spectrum, tt->target, mg, escale, tt->grad_scale, d_attr,
-                             TR_EMAX, llong, s);
     hipLaunchKernelGGL(k_train_loss_add, dim3(1), dim3(64), 0, s, lacc, llong, n_sets, lscale, tt->loss);
     launch_geo_fold(L, ws, s);
     launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);
