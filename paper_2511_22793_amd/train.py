@@ -66,6 +66,7 @@ class LearnedScene:
                  conf_weights: dict = None, densify_stats: bool = False, device="cuda"):
         dev = torch.device(device)
         self.dev, self.grid, self.params, self.rates = dev, grid, params, rates
+        self._side = None  # second stream of the step (created on first use)
         self.B, self.total_steps, self.train_geometry, self.lambda_ch = batch, total_steps, train_geometry, lambda_ch
         if loss_mode not in ("train_pass", "fused", "partial", "target", "two_pass"):
             raise ValueError("loss_mode is 'train_pass', 'fused', 'partial', 'target' or 'two_pass'")
@@ -173,10 +174,26 @@ class LearnedScene:
         sc = self.g
         prepare(sc, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
         live(self.ws, self.live_list, self.live_count)
+        # (one stream here: the second stream of train_step measured slower
+        # for this shorter sequence)
         gm.embed(self.net, self.E_bf, self.Z1)
         gm.forward(self.net, self.Z1, sc["mean"], self._rows(tx), self.attr, self.state)
         blend(self.ws, self.attr, n_sets=self.B, is_complex=True, out=self.spec)
         return self.spec
+
+    def _embed_beside(self) -> torch.cuda.Stream:
+        """Enqueues Z1 = E W1e^T (all rows; it depends on neither the
+        geometry nor the transmitters) on a second stream, forked from the
+        current one, so that it runs beside the prepare and live passes;
+        returns the current stream, which must wait for the second before
+        the network forward."""
+        main = torch.cuda.current_stream(self.dev)
+        if self._side is None:
+            self._side = torch.cuda.Stream(self.dev)
+        self._side.wait_stream(main)
+        with torch.cuda.stream(self._side):
+            gm.embed(self.net, self.E_bf, self.Z1)
+        return main
 
     def _moment(self, key, like):
         if key not in self.moments:
@@ -193,11 +210,12 @@ class LearnedScene:
         mark = marks or (lambda name: None)
         sc = self.g
         mark("start")
+        main = self._embed_beside()
         prepare(sc, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
         mark("prepare")
         live(self.ws, self.live_list, self.live_count)
         mark("live")
-        gm.embed(self.net, self.E_bf, self.Z1)
+        main.wait_stream(self._side)
         gm.forward(self.net, self.Z1, sc["mean"], self._rows(tx), self.attr, self.state)
         mark("mlp_fwd")
         if self.loss_mode == "train_pass":
