@@ -391,12 +391,29 @@ typedef struct {
     const float* grad_scale;
 } gs_train_target;
 #define GS_TRAIN_WRITE_SPECTRUM 2 /* flags: also store the spectra */
+/* flags: leave the per-pair fold and the projection backward (the outputs
+ * d_mean, d_log_scale, d_quat, d_opacity_logit) to a later
+ * gs_render_train_geometry() on the same workspace, e.g. on a second stream
+ * beside the network backward, which needs only d_attr and the loss. */
+#define GS_TRAIN_DEFER_GEOMETRY 4
 size_t gs_train_scratch_bytes(int32_t n_sets, int32_t n_chan, const gs_grid* grid);
 gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs_queries* queries, int32_t n_sets,
                           const gs_grid* grid, const gs_params* prm, const uint32_t* live_list,
                           const uint32_t* live_count, const gs_train_target* tt, float* spectrum, float* d_mean,
                           float* d_log_scale, float* d_quat, float* d_opacity_logit, float* d_attr, int32_t flags,
                           void* workspace, size_t ws_bytes, void* scratch, size_t scratch_bytes, void* stream);
+/* The geometric tail of a gs_render_train() call made with
+ * GS_TRAIN_DEFER_GEOMETRY (Sec. 4.2, the backward through the projection):
+ * folds the per-pair geometric sums that call left in the workspace per
+ * Gaussian and runs the projection backward into d_mean [3][n],
+ * d_log_scale [3][n], d_quat [4][n], d_opacity_logit [n] (overwritten).
+ * Same scene, queries (one receiver), grid, params and workspace as that
+ * call; it must run after it (stream order or an event) and before the
+ * workspace is prepared again.  Errors: GS_ERR_INVALID_ARG,
+ * GS_ERR_WORKSPACE. */
+gs_status gs_render_train_geometry(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
+                                   const gs_params* prm, float* d_mean, float* d_log_scale, float* d_quat,
+                                   float* d_opacity_logit, void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * gs_render_blend() with the loss of gs_loss_spectrum_stats() fused into its

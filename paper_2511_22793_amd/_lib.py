@@ -91,6 +91,7 @@ class GsTrainTarget(ctypes.Structure):
 
 GS_BWD_ATTR_GRAD_ZEROED = 1
 GS_TRAIN_WRITE_SPECTRUM = 2
+GS_TRAIN_DEFER_GEOMETRY = 4
 GS_TIMER_BLEND, GS_TIMER_BLEND_BWD, GS_TIMER_TRAIN = 0, 1, 2
 
 
@@ -147,6 +148,8 @@ SIGNATURES = {
                                 ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_p,
                                 ctypes.POINTER(GsTrainTarget), c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz, c_p,
                                 c_sz, c_p]),
+    "gs_render_train_geometry": (c_i32, [ctypes.POINTER(GsScene), ctypes.POINTER(GsQueries), ctypes.POINTER(GsGrid),
+                                         ctypes.POINTER(GsParams), c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_render_live": (c_i32, [c_i32, c_i32, ctypes.POINTER(GsGrid), ctypes.POINTER(GsParams), c_p, c_sz, c_p,
                                c_i64, c_p, c_p]),
     "gs_loss_spectrum": (c_i32, [c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_p, c_p, c_p, c_p, c_sz,

@@ -898,7 +898,8 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
     if (!tt || !tt->target || !tt->target_mean || !tt->loss || !tt->h_hat || !(tt->lambda_ch >= 0.0f) ||
         !live_list || !live_count || !d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !d_attr)
         return GS_ERR_INVALID_ARG;
-    if (flags & ~(GS_BWD_ATTR_GRAD_ZEROED | GS_TRAIN_WRITE_SPECTRUM)) return GS_ERR_INVALID_ARG;
+    if (flags & ~(GS_BWD_ATTR_GRAD_ZEROED | GS_TRAIN_WRITE_SPECTRUM | GS_TRAIN_DEFER_GEOMETRY))
+        return GS_ERR_INVALID_ARG;
     Layout L;
     gs_status st = check_forward(scene, attrs, queries, grid, prm, spectrum, workspace, ws_bytes, &L);
     if (st != GS_OK) return st;
@@ -1038,6 +1039,31 @@ gs_status gs_render_train(const gs_scene* scene, const gs_attrs* attrs, const gs
                                  d_attr, TR_EMAX, llong, s);
     }
     hipLaunchKernelGGL(k_train_loss_add, dim3(1), dim3(64), 0, s, lacc, llong, n_sets, lscale, tt->loss);
+    if (!(flags & GS_TRAIN_DEFER_GEOMETRY)) {
+        launch_geo_fold(L, ws, s);
+        launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);
+    }
+    GS_CHECK_LAUNCH();
+    return GS_OK;
+}
+
+gs_status gs_render_train_geometry(const gs_scene* scene, const gs_queries* queries, const gs_grid* grid,
+                                   const gs_params* prm, float* d_mean, float* d_log_scale, float* d_quat,
+                                   float* d_opacity_logit, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!d_mean || !d_log_scale || !d_quat || !d_opacity_logit || !queries || !prm) return GS_ERR_INVALID_ARG;
+    if (queries->count != 1 || (prm->options & GS_OPT_FORWARD_ONLY)) return GS_ERR_INVALID_ARG;
+    // the scene, queries, params and workspace checks of a forward (no
+    // attributes or spectrum are touched here)
+    gs_attrs none{};
+    none.data = (const float*)workspace;
+    none.n_chan = 1;
+    Layout L;
+    gs_status st = check_forward(scene, &none, queries, grid, prm, (const float*)workspace, workspace, ws_bytes, &L);
+    if (st != GS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    char* ws = (char*)workspace;
     launch_geo_fold(L, ws, s);
     launch_project_bwd(*scene, *queries, *grid, *prm, L, ws, d_mean, d_log_scale, d_quat, d_opacity_logit, s);
     GS_CHECK_LAUNCH();

@@ -16,7 +16,8 @@ from typing import Optional
 
 import torch
 
-from ._lib import (GS_OPT_BLEND_PER_GROUP, GS_OPT_BWD_PER_GROUP, GS_OPT_FORWARD_ONLY, GS_TRAIN_WRITE_SPECTRUM, GsAttrs,
+from ._lib import (GS_OPT_BLEND_PER_GROUP, GS_OPT_BWD_PER_GROUP, GS_OPT_FORWARD_ONLY, GS_TRAIN_DEFER_GEOMETRY,
+                   GS_TRAIN_WRITE_SPECTRUM, GsAttrs,
                    GsFlags, GsGrid, GsL2Grad, GsLayout, GsParams, GsQueries, GsScene, GsTrainTarget, check, lib)
 
 DEFAULT_VIEW = (0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0)
@@ -465,13 +466,15 @@ def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.
                spectrum: Optional[torch.Tensor] = None, write_spectrum: bool = False,
                d_attr: Optional[torch.Tensor] = None, out: Optional[dict] = None,
                scratch: Optional[TrainScratch] = None, loss: Optional[torch.Tensor] = None,
-               h_hat: Optional[torch.Tensor] = None, grad_scale: Optional[torch.Tensor] = None):
+               h_hat: Optional[torch.Tensor] = None, grad_scale: Optional[torch.Tensor] = None,
+               defer_geometry: bool = False):
     """Fused compositing + loss + backward over S complex attribute sets
     sharing the workspace's one prepared receiver (gs_render_train), after
     live().  attr [S,n,F,2]; target [S,F,H,W,2]; target_mean [S,F,2]
     (spatial_mean of the target); grad_scale: optional device float c, every
-    gradient then that of c L.  Returns (loss [S], h_hat [S,F,2], gradients
-    dict, spectrum)."""
+    gradient then that of c L.  defer_geometry: the scene gradients are left
+    to train_geometry() (GS_TRAIN_DEFER_GEOMETRY).  Returns (loss [S],
+    h_hat [S,F,2], gradients dict, spectrum)."""
     sc = _scene_c(scene)
     n = sc.n
     if attr.dim() != 4:
@@ -497,7 +500,8 @@ def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.
     g = out if out is not None else {
         "d_mean": torch.empty(3, n, device=dev), "d_log_scale": torch.empty(3, n, device=dev),
         "d_quat": torch.empty(4, n, device=dev), "d_opacity_logit": torch.empty(n, device=dev)}
-    flags = (1 if d_attr is not None else 0) | (GS_TRAIN_WRITE_SPECTRUM if write_spectrum else 0)
+    flags = ((1 if d_attr is not None else 0) | (GS_TRAIN_WRITE_SPECTRUM if write_spectrum else 0) |
+             (GS_TRAIN_DEFER_GEOMETRY if defer_geometry else 0))
     g["d_attr"] = d_attr if d_attr is not None else torch.empty_like(attr)
     tt = GsTrainTarget(_ptr(target), _ptr(target_mean), float(lambda_ch), _ptr(loss), _ptr(h_hat),
                        _ptr(grad_scale) if grad_scale is not None else None)
@@ -511,6 +515,24 @@ def train_pass(workspace: Workspace, scene: dict, attr: torch.Tensor, rx: torch.
                                 ctypes.c_void_p(workspace.ptr), workspace.nbytes, ctypes.c_void_p(scratch.ptr),
                                 scratch.nbytes, ctypes.c_void_p(stream)), "gs_render_train")
     return loss, h_hat, g, spectrum
+
+
+def train_geometry(workspace: Workspace, scene: dict, rx: torch.Tensor, out: dict):
+    """The scene gradients of a train_pass(defer_geometry=True) on the same
+    workspace (gs_render_train_geometry), on the current stream: out's
+    d_mean [3,n], d_log_scale [3,n], d_quat [4,n], d_opacity_logit [n]."""
+    sc = _scene_c(scene)
+    n = sc.n
+    for k, shape in (("d_mean", (3, n)), ("d_log_scale", (3, n)), ("d_quat", (4, n)), ("d_opacity_logit", (n,))):
+        _check_f32(k, out[k], shape)
+    q = GsQueries(1, _ptr(rx), None)
+    gr, p = workspace.grid.c(), workspace.params.c()
+    stream = torch.cuda.current_stream(out["d_mean"].device).cuda_stream
+    check(lib().gs_render_train_geometry(ctypes.byref(sc), ctypes.byref(q), ctypes.byref(gr), ctypes.byref(p),
+                                         _ptr(out["d_mean"]), _ptr(out["d_log_scale"]), _ptr(out["d_quat"]),
+                                         _ptr(out["d_opacity_logit"]), ctypes.c_void_p(workspace.ptr),
+                                         workspace.nbytes, ctypes.c_void_p(stream)), "gs_render_train_geometry")
+    return out
 
 
 def loss_l1_ssim(spectrum: torch.Tensor, target: torch.Tensor, lambda_1: float = 0.2, grad: bool = True):

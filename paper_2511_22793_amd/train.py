@@ -27,7 +27,7 @@ from . import confidence as gc
 from . import densify as gd
 from . import mlp as gm
 from .render import (Grid, Params, TrainScratch, Workspace, backward, backward_l2, blend, blend_loss, live,
-                     loss_spectrum, loss_stats, prepare, spatial_mean, train_pass)
+                     loss_spectrum, loss_stats, prepare, spatial_mean, train_geometry, train_pass)
 
 F = gm.F
 
@@ -209,6 +209,7 @@ class LearnedScene:
         a property of the training samples; formed here when not given."""
         mark = marks or (lambda name: None)
         sc = self.g
+        geo_side = False
         mark("start")
         main = self._embed_beside()
         prepare(sc, self.rx, grid=self.grid, params=self.params, workspace=self.ws)
@@ -233,7 +234,14 @@ class LearnedScene:
             loss, _, _, _ = train_pass(self.ws, sc, self.attr, self.rx, self.live_list[0], self.live_count, target,
                                        target_mean, self.lambda_ch, spectrum=self.spec,
                                        write_spectrum=self.keep_spectra, d_attr=self.d_attr, out=self.ggrads,
-                                       scratch=self.tscratch, loss=self.loss, h_hat=self.h_hat, grad_scale=scale)
+                                       scratch=self.tscratch, loss=self.loss, h_hat=self.h_hat, grad_scale=scale,
+                                       defer_geometry=True)
+            # the scene gradients (per-pair fold, projection backward) on the
+            # second stream, beside the network backward below
+            self._side.wait_stream(main)
+            with torch.cuda.stream(self._side):
+                train_geometry(self.ws, sc, self.rx, self.ggrads)
+            geo_side = True
             if self.confidence:
                 # Eq. (6) per sample with the step's task losses: the
                 # confidence-weighted loss and the head's gradients (of the
@@ -276,10 +284,12 @@ class LearnedScene:
                          d_attr=self.d_attr, out=self.ggrads)
         if self.loss_mode != "train_pass":
             mark("render_bwd")
-        if self.densify_stats:
-            gd.stats(self.ggrads["d_mean"], self.live_list[0], self.live_count, self.grad_acc, self.grad_cnt)
         self.mgrads = gm.backward(self.net, self.E_bf, sc["mean"], self._rows(tx), self.d_attr, self.state,
                                   self.mgrads, clear_d_attr=True)
+        if geo_side:
+            main.wait_stream(self._side)  # the scene gradients
+        if self.densify_stats:
+            gd.stats(self.ggrads["d_mean"], self.live_list[0], self.live_count, self.grad_acc, self.grad_cnt)
         mark("mlp_bwd")
         self.step_count += 1
         r = self.rates

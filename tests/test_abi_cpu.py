@@ -192,6 +192,25 @@ def test_train_pass_rejects_bad_arguments_on_host():
     assert _train(sc, at, q, 4, g, p, tt, ws_bytes=100) == _lib.GS_ERR_WORKSPACE
 
 
+def test_train_geometry_rejects_bad_arguments_on_host():
+    L = _lib.lib()
+    sc = GsScene(100, FAKE, FAKE, FAKE, FAKE)
+    q = GsQueries(1, FAKE, None)
+    g, p = grid(), params()
+    out = GsLayout()
+    assert L.gs_workspace_layout(100, 1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(out)) == 0
+
+    def call(sc_=sc, q_=q, p_=p, d=FAKE, ws=ctypes.c_void_p(0x100000), nb=out.total):
+        return L.gs_render_train_geometry(ctypes.byref(sc_), ctypes.byref(q_), ctypes.byref(g), ctypes.byref(p_), d,
+                                          FAKE, FAKE, FAKE, ws, nb, None)
+    assert call(d=None) == _lib.GS_ERR_INVALID_ARG
+    assert call(sc_=GsScene(100, None, FAKE, FAKE, FAKE)) == _lib.GS_ERR_INVALID_ARG
+    assert call(q_=GsQueries(2, FAKE, None)) == _lib.GS_ERR_INVALID_ARG          # one receiver only
+    assert call(p_=params(options=_lib.GS_OPT_FORWARD_ONLY)) == _lib.GS_ERR_INVALID_ARG
+    assert call(nb=out.total - 1) == _lib.GS_ERR_WORKSPACE
+    assert call(ws=ctypes.c_void_p(0x100010)) == _lib.GS_ERR_WORKSPACE           # not 256-byte aligned
+
+
 def test_spatial_mean_rejects_bad_arguments_on_host():
     L = _lib.lib()
     assert L.gs_spatial_mean(None, 1, 1, 0, 4, 4, FAKE, None) == _lib.GS_ERR_INVALID_ARG

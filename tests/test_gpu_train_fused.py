@@ -192,6 +192,46 @@ def test_fused_pass_matches_oracle_loss_and_gradients():
         compare(fused["d_" + k], t[k].grad.numpy(), k)
 
 
+def test_deferred_geometry_on_a_second_stream_matches_the_one_call():
+    # GS_TRAIN_DEFER_GEOMETRY + gs_render_train_geometry on another stream
+    # (the training step's split): the same loss, attribute and scene
+    # gradients as one gs_render_train call (float atomics: to rounding)
+    n, S, F = 3000, 4, 16
+    sc = synth.scene(n, seed=81)
+    attrs = np.stack([synth.channel_attrs(n, F, True, seed=82 + s) for s in range(S)])
+    tgt = _targets(S, F, 90, 360, 83)
+    dev = to_dev(sc)
+    rx_t = torch.zeros(1, 3, device="cuda")
+    ws = gs.prepare(dev, rx_t)
+    lst, cnt = gs.live(ws)
+    a = torch.from_numpy(np.ascontiguousarray(attrs, np.float32)).cuda()
+    z = torch.from_numpy(tgt).cuda()
+    h = gs.spatial_mean(z, True)
+    loss1, _, g1, _ = gs.train_pass(ws, dev, a, rx_t, lst, cnt, z, h, 1.0)
+    torch.cuda.synchronize()
+    one = {k: v.cpu().double().numpy() for k, v in g1.items()}
+    one["loss"] = loss1.cpu().double().numpy()
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    loss2, _, g2, _ = gs.train_pass(ws, dev, a, rx_t, lst, cnt, z, h, 1.0, defer_geometry=True)
+    side.wait_stream(main)
+    with torch.cuda.stream(side):
+        gs.train_geometry(ws, dev, rx_t, g2)
+    main.wait_stream(side)
+    torch.cuda.synchronize()
+    two = {k: v.cpu().double().numpy() for k, v in g2.items()}
+    _close_rel(loss2.cpu().double().numpy(), one["loss"], "loss", 1e-6)
+    for s in range(S):
+        compare(two["d_attr"][s], one["d_attr"][s], "d_attr set %d" % s)
+    for k in NAMES:
+        compare(two["d_" + k], one["d_" + k], k)
+    # argument checks of the tail: wrong shapes are rejected on the host
+    bad = dict(g2)
+    bad["d_mean"] = torch.empty(3, n - 1, device="cuda")
+    with pytest.raises(ValueError):
+        gs.train_geometry(ws, dev, rx_t, bad)
+
+
 def test_spatial_mean_matches_definition():
     rng = np.random.default_rng(3)
     for shape, cplx in (((3, 5, 17, 33, 2), True), ((2, 4, 90, 360), False)):
