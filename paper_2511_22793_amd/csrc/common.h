@@ -109,6 +109,9 @@ constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per sort workgroup
 // at least SORT_WIDE_MIN_BLOCKS workgroups.
 constexpr int SORT_WIDE_WAVES = 16;
 constexpr int SORT_WIDE_MIN_BLOCKS = 256;
+// at most this many blocks per query: the depth sort's scatter scans the
+// per-block counts itself instead of a separate scan launch
+constexpr int SORT_FUSED_SCAN_BLOCKS = 64;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 // tile ids up to this many bits are sorted in one counting pass

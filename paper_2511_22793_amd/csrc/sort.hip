@@ -71,8 +71,9 @@ __device__ __forceinline__ uint32_t seg_count(const uint32_t* n_dev, size_t n_st
 }
 
 // Per-workgroup digit histogram (RB-bit digits) of a block of 64*WV*IT
-// keys; counts laid out [digit][block] per query.
-template <int RB, int IT = SORT_ITEMS, int WV = SORT_THREADS / 64>
+// keys; counts laid out [digit][block] per query, or [block][digit] (BM)
+// for the scatter that scans them itself.
+template <int RB, int IT = SORT_ITEMS, int WV = SORT_THREADS / 64, bool BM = false>
 __global__ __launch_bounds__(64 * WV) void k_sort_count(
     const uint32_t* __restrict__ keys, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, uint32_t* __restrict__ counts, size_t s_counts, int max_blocks)
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(64 * WV) void k_sort_count(
     }
     __syncthreads();
     for (int d = threadIdx.x; d < R; d += NT)
-        counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x] = hist[d];
+        counts[q * s_counts + (BM ? (size_t)blockIdx.x * R + d : (size_t)d * max_blocks + blockIdx.x)] = hist[d];
 }
 
 // Exclusive scan over blocks for one digit (one workgroup per digit and
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ counts
 // below it with the same digit in this round, from an RB-ballot match mask).
 // With `order` set (the single tile pass over pair keys) the output is the
 // pair's Gaussian, order[key & rank_mask], instead of the key.
-template <int RB, int IT = SORT_ITEMS, bool KV = true, int WV = SORT_THREADS / 64>
+template <int RB, int IT = SORT_ITEMS, bool KV = true, int WV = SORT_THREADS / 64, bool FS = false>
 __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
@@ -177,15 +178,41 @@ __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
         vout += q * s_keys;
     }
     // digit bases: exclusive scan of the totals over digits (thread tid <
-    // NDT owns digits [tid*DPT, tid*DPT + DPT))
+    // NDT owns digits [tid*DPT, tid*DPT + DPT)).  FS: the counts are
+    // [block][digit] and this workgroup forms its digits' totals and its
+    // earlier-block prefixes itself (no scan launch; for a few blocks).
     {
         const bool own = tid < NDT;
         uint32_t t[DPT], tsum = 0;
+        uint32_t pre[FS ? DPT : 1];
+        if constexpr (FS) {
+            const int nb = (int)((n + TILE - 1) / TILE);
+            const uint32_t* cq = counts + q * s_counts + (size_t)tid * DPT;
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) {
-            t[k] = own ? totals[q * s_totals + tid * DPT + k] : 0u;
-            tsum += t[k];
+            for (int k = 0; k < DPT; ++k) t[k] = pre[k] = 0u;
+            if (own) {
+                // eight blocks' loads in flight at a time
+                for (int b0 = 0; b0 < nb; b0 += 8) {
+                    uint32_t c[8][DPT];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int k = 0; k < DPT; ++k) c[u][k] = b0 + u < nb ? cq[(size_t)(b0 + u) * R + k] : 0u;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int k = 0; k < DPT; ++k) {
+                            t[k] += c[u][k];
+                            pre[k] += b0 + u < (int)blockIdx.x ? c[u][k] : 0u;
+                        }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) t[k] = own ? totals[q * s_totals + tid * DPT + k] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) tsum += t[k];
         uint32_t x = tsum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -201,7 +228,10 @@ __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
 #pragma unroll
             for (int k = 0; k < DPT; ++k) {
                 const int d = tid * DPT + k;
-                s_goff[d] = run + counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x];
+                if constexpr (FS)
+                    s_goff[d] = run + pre[k];
+                else
+                    s_goff[d] = run + counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x];
                 run += t[k];
             }
         }
@@ -285,6 +315,16 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* totals = (uint32_t*)(ws + L.totals);
     const size_t sc = L.s_counts / 4, st = L.s_totals / 4;
+    if (!n_dev && blocks <= SORT_FUSED_SCAN_BLOCKS) {
+        // a fixed key count (the depth sort) in a few blocks: the scatter
+        // scans the block-major counts itself (the digit totals are not kept)
+        hipLaunchKernelGGL((k_sort_count<RB, IT, WV, true>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, s_keys,
+                           n_dev, n_stride, n_fixed, shift, counts, sc, blocks);
+        hipLaunchKernelGGL((k_sort_scatter<RB, IT, KV, WV, true>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, vin,
+                           kout, vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, blocks,
+                           order, s_order, plist, s_plist, rank_mask);
+        return;
+    }
     hipLaunchKernelGGL((k_sort_count<RB, IT, WV>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, s_keys, n_dev,
                        n_stride, n_fixed, shift, counts, sc, blocks);
     hipLaunchKernelGGL(k_sort_scan, dim3(1 << RB, L.nq), dim3(256), 0, s, counts, sc, totals, st, n_dev, n_stride,
