@@ -156,7 +156,8 @@ __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
     uint32_t* __restrict__ vout, size_t s_keys, const uint32_t* __restrict__ n_dev, size_t n_stride,
     uint32_t n_fixed, int shift, const uint32_t* __restrict__ counts, size_t s_counts,
     const uint32_t* __restrict__ totals, size_t s_totals, int max_blocks, const uint32_t* __restrict__ order,
-    size_t s_order, uint32_t* __restrict__ plist, size_t s_plist, uint32_t rank_mask)
+    size_t s_order, uint32_t* __restrict__ plist, size_t s_plist, uint32_t rank_mask, uint2* __restrict__ ranges,
+    size_t s_ranges, int T)
 {
     constexpr int R = 1 << RB;
     constexpr int NT = 64 * WV;
@@ -166,7 +167,9 @@ __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
     const int q = blockIdx.y;
     const uint32_t n = seg_count(n_dev, n_stride, n_fixed, q);
     const uint32_t base = blockIdx.x * TILE;
-    if (base >= n) return;
+    // (with `ranges`, block 0 always runs: it writes the tile ranges, also
+    // when there are no keys)
+    if (base >= n && !(ranges && blockIdx.x == 0)) return;
     __shared__ uint32_t s_goff[R];
     __shared__ uint32_t s_wcnt[WV][R];
     __shared__ uint32_t s_wsum[WV];
@@ -232,6 +235,8 @@ __global__ __launch_bounds__(64 * WV) void k_sort_scatter(
                     s_goff[d] = run + pre[k];
                 else
                     s_goff[d] = run + counts[q * s_counts + (size_t)d * max_blocks + blockIdx.x];
+                // the tile pass: [start, end) of tile d is its digit range
+                if (ranges && blockIdx.x == 0 && d < T) ranges[q * s_ranges + d] = make_uint2(run, run + t[k]);
                 run += t[k];
             }
         }
@@ -310,7 +315,7 @@ template <int RB, int IT, bool KV, int WV>
 static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, size_t s_keys,
                       const uint32_t* n_dev, size_t n_stride, uint32_t n_fixed, int shift, int blocks,
                       const Layout& L, char* ws, const uint32_t* order, size_t s_order, uint32_t* plist,
-                      size_t s_plist, uint32_t rank_mask, hipStream_t s)
+                      size_t s_plist, uint32_t rank_mask, hipStream_t s, uint2* ranges = nullptr)
 {
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* totals = (uint32_t*)(ws + L.totals);
@@ -322,7 +327,7 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
                            n_dev, n_stride, n_fixed, shift, counts, sc, blocks);
         hipLaunchKernelGGL((k_sort_scatter<RB, IT, KV, WV, true>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, vin,
                            kout, vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, blocks,
-                           order, s_order, plist, s_plist, rank_mask);
+                           order, s_order, plist, s_plist, rank_mask, (uint2*)nullptr, (size_t)0, 0);
         return;
     }
     hipLaunchKernelGGL((k_sort_count<RB, IT, WV>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, s_keys, n_dev,
@@ -331,7 +336,7 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
                        n_fixed, blocks, (uint32_t)(64 * WV * IT));
     hipLaunchKernelGGL((k_sort_scatter<RB, IT, KV, WV>), dim3(blocks, L.nq), dim3(64 * WV), 0, s, kin, vin, kout,
                        vout, s_keys, n_dev, n_stride, n_fixed, shift, counts, sc, totals, st, blocks, order, s_order,
-                       plist, s_plist, rank_mask);
+                       plist, s_plist, rank_mask, ranges, L.s_ranges / sizeof(uint2), L.T);
 }
 
 // Sorts `passes` digits starting at bit 0; returns the buffer index (0 = a,
@@ -368,6 +373,10 @@ void launch_depth_sort(const Layout& L, char* ws, hipStream_t s)
 // ---- tiles-touched scan and pair emission -------------------------------
 // Scan granularity: EMIT_RANKS consecutive depth ranks per workgroup.
 constexpr int EMIT_RANKS = 64;
+// up to this many blocks the emission adds up the block sums itself (each
+// workgroup reads the sums before its own: quadratic, so only for a few
+// thousand blocks)
+constexpr int EMIT_SCAN_BLOCKS = 2048;
 
 __device__ __forceinline__ uint32_t ntiles_at(const uint32_t* order, const uint4* tinfo, uint32_t k, uint32_t nvis)
 {
@@ -440,9 +449,13 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ partial
 // last rank whose first pair slot is <= p; each lane walks forward through
 // the 64 prefix offsets as its p grows by 256), so the stores stay coalesced
 // and the work balanced however unequal the tile counts are.
+// SCAN: `partial` holds the block sums (no k_scan_top): each workgroup adds
+// up the sums before its own (for a few thousand blocks at most), and the
+// last active one records the pair count and overflow.
+template <bool SCAN>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, size_t s_order,
                                              const uint4* __restrict__ tinfo, size_t s_tinfo,
-                                             const uint32_t* __restrict__ flags, size_t s_flags,
+                                             uint32_t* __restrict__ flags, size_t s_flags,
                                              const uint32_t* __restrict__ partial, size_t s_partial,
                                              uint32_t* __restrict__ pkeys, size_t s_pkeys, int64_t cap,
                                              int TX, int rank_bits)
@@ -451,6 +464,26 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     const uint32_t nvis = flags[q * s_flags + FL_NVIS];
     const uint32_t base = blockIdx.x * EMIT_RANKS;
     if (base >= nvis) return;
+    uint32_t o0 = 0;
+    if constexpr (SCAN) {
+        __shared__ unsigned long long s_pre;
+        if (threadIdx.x == 0) s_pre = 0ull;
+        __syncthreads();
+        unsigned long long v = 0ull;
+        for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) v += partial[q * s_partial + b];
+        if (v) atomicAdd(&s_pre, v);
+        __syncthreads();
+        const unsigned long long pre = s_pre;
+        o0 = (uint32_t)pre;
+        if (threadIdx.x == 0 && blockIdx.x == (nvis - 1) / EMIT_RANKS) {
+            const unsigned long long P = pre + partial[q * s_partial + blockIdx.x];
+            flags[q * s_flags + FL_PAIRS] = (uint32_t)(P > 0xFFFFFFFFull ? 0xFFFFFFFFull : P);
+            flags[q * s_flags + FL_OVERFLOW] = P > (unsigned long long)cap ? 1u : 0u;
+            flags[q * s_flags + FL_PUSED] = (uint32_t)(P > (unsigned long long)cap ? (unsigned long long)cap : P);
+        }
+    } else {
+        o0 = partial[q * s_partial + blockIdx.x];
+    }
     order += q * s_order;
     tinfo += q * s_tinfo;
     pkeys += q * s_pkeys;
@@ -474,7 +507,6 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
             s_total = x;
         }
     }
-    const uint32_t o0 = partial[q * s_partial + blockIdx.x];
     __syncthreads();
     const uint32_t total = s_total;
     int j = 0;  // largest j with s_start[j] <= p; only moves forward as p grows
@@ -522,30 +554,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pke
     }
 }
 
-// Tile ranges of the single tile pass: [start, end) = exclusive scan of the
-// per-tile pair totals (tiles beyond T have zero totals).
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ totals, size_t s_totals,
-                                                     uint2* __restrict__ ranges, size_t s_ranges, int T)
-{
-    const int q = blockIdx.x;
-    totals += q * s_totals;
-    ranges += q * s_ranges;
-    __shared__ uint32_t wsum[4];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int t0 = 0; t0 < T; t0 += 256) {
-        const int t = t0 + threadIdx.x;
-        const uint32_t v = t < T ? totals[t] : 0u;
-        const uint32_t ex = block_exclusive_scan_256(v, wsum);
-        const uint32_t c = carry;
-        if (t < T) ranges[t] = make_uint2(c + ex, c + ex + v);
-        __syncthreads();
-        if (threadIdx.x == 255) carry = c + ex + v;
-        __syncthreads();
-    }
-}
-
 void launch_binning(const Layout& L, char* ws, hipStream_t s)
 {
     const uint32_t* order = (const uint32_t*)(ws + L.vals_a);
@@ -556,12 +564,17 @@ void launch_binning(const Layout& L, char* ws, hipStream_t s)
     const int nblk = (L.n + EMIT_RANKS - 1) / EMIT_RANKS;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblk, L.nq), dim3(64), 0, s, order, so, tinfo, sti, flags, sf,
                        partial, sp);
-    hipLaunchKernelGGL(k_scan_top, dim3(L.nq), dim3(256), 0, s, partial, sp, nblk, flags, sf, L.cap);
     uint32_t* pa = (uint32_t*)(ws + L.pkeys_a);
     uint32_t* pb = (uint32_t*)(ws + L.pkeys_b);
     const size_t spk = L.s_pkeys / 4;
-    hipLaunchKernelGGL(k_emit, dim3(nblk, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf, partial, sp,
-                       pa, spk, L.cap, L.TX, L.rank_bits);
+    if (nblk <= EMIT_SCAN_BLOCKS) {
+        hipLaunchKernelGGL(k_emit<true>, dim3(nblk, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf,
+                           partial, sp, pa, spk, L.cap, L.TX, L.rank_bits);
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(L.nq), dim3(256), 0, s, partial, sp, nblk, flags, sf, L.cap);
+        hipLaunchKernelGGL(k_emit<false>, dim3(nblk, L.nq), dim3(256), 0, s, order, so, tinfo, sti, flags, sf,
+                           partial, sp, pa, spk, L.cap, L.TX, L.rank_bits);
+    }
     // pairs are emitted in depth-rank order, so a stable sort on the tile
     // digits alone yields (tile, depth) order
     uint2* ranges = (uint2*)(ws + L.ranges);
@@ -579,27 +592,24 @@ void launch_binning(const Layout& L, char* ws, hipStream_t s)
             if (L.pair_wide)
                 sort_pass<RADIX_BITS, SORT_ITEMS, false, WW>(pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u,
                                                              L.rank_bits, L.pair_blocks, L, ws, order, so, plist,
-                                                             spl, rmask, s);
+                                                             spl, rmask, s, ranges);
             else
                 sort_pass<RADIX_BITS, SORT_ITEMS, false, WN>(pa, nullptr, nullptr, nullptr, spk, nd, sf, 0u,
                                                              L.rank_bits, L.pair_blocks, L, ws, order, so, plist,
-                                                             spl, rmask, s);
+                                                             spl, rmask, s, ranges);
         } else {
             // 1024 digits: blocks of TILE_PASS_ITEMS (TILE_PASS_WIDE_ITEMS)
             // keys per thread keep the digit-by-block count matrix small
             if (L.pair_wide)
                 sort_pass<TILE_PASS_MAX_BITS, TILE_PASS_WIDE_ITEMS, false, WW>(pa, nullptr, nullptr, nullptr, spk, nd,
                                                                           sf, 0u, L.rank_bits, L.tile_blocks, L, ws,
-                                                                          order, so, plist, spl, rmask, s);
+                                                                          order, so, plist, spl, rmask, s, ranges);
             else
                 sort_pass<TILE_PASS_MAX_BITS, TILE_PASS_ITEMS, false, WN>(pa, nullptr, nullptr, nullptr, spk, nd,
                                                                           sf, 0u, L.rank_bits, L.tile_blocks, L, ws,
-                                                                          order, so, plist, spl, rmask, s);
+                                                                          order, so, plist, spl, rmask, s, ranges);
         }
-        const uint32_t* totals = (const uint32_t*)(ws + L.totals);
-        const size_t st = L.s_totals / 4;
-        hipLaunchKernelGGL(k_tile_ranges, dim3(L.nq), dim3(256), 0, s, totals, st, ranges,
-                           L.s_ranges / sizeof(uint2), L.T);
+        // (the scatter's block 0 wrote the tile ranges: the digit ranges)
         return;
     }
     const int which = radix_sort(pa, pb, nullptr, nullptr, spk, flags + FL_PUSED, sf, 0, L.rank_bits,
