@@ -37,11 +37,14 @@ const Lanes* side_lanes(hipStream_t s)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= LANES_MAX_DEVICES) return nullptr;
-    if (!g_lanes[dev].ready) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-        if (lanes_init(dev) != GS_OK) return nullptr;
+    {
+        // (a device's lanes never change once ready)
+        std::lock_guard<std::mutex> lk(g_lanes_mu);
+        if (g_lanes[dev].ready) return &g_lanes[dev];
     }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    if (lanes_init(dev) != GS_OK) return nullptr;
     return &g_lanes[dev];
 }
 
