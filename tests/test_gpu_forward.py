@@ -105,6 +105,17 @@ def test_wide_depth_sort_bit_exact():
     _check_order_and_lists(sc, rx, ws, n, 90, 360, (16, 16), (0, 25, nq - 1))
 
 
+def test_depth_sort_with_a_separate_scan_bit_exact():
+    # 140000 Gaussians, one receiver: ceil(140000 / 2048) = 69 blocks > 64,
+    # so the depth sort's passes take the count / scan / scatter launches
+    # (at most 64 blocks the scatter scans the counts itself: the tests above)
+    n = 140_000
+    sc = synth.scene(n, seed=5)
+    rx = np.zeros((1, 3), np.float32)
+    _, ws = gpu_forward(sc, synth.rss_attrs(n), rx)
+    _check_order_and_lists(sc, rx, ws, n, 90, 360, (16, 16), (0,))
+
+
 @pytest.mark.parametrize("n,seed,rx", [(2048, 0, (0.0, 0.0, 0.0)), (777, 5, (0.5, -0.5, 1.0)),
                                        (1, 3, (0.0, 0.0, 0.0)), (10_001, 7, (2.0, 2.0, 0.2))])
 def test_pixels_match_oracle_real_f1(n, seed, rx):
