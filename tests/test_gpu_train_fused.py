@@ -11,7 +11,7 @@ kernels, without the spectra or their gradient in memory.
   counts, groups whose walks fall in each band of the fused kernels'
   variants (up to 64, 128 and 256 entries) and beyond (those take the
   unfused kernels inside the call), a mix, the 100k-Gaussian training
-  shape.
+  shape and the 300k-Gaussian 180x720 one (attribute gradients sampled).
 * Against the oracles: the FP64 dense autograd renderer with the loss
   oracle (Eq. (2) means, Eq. (4) channel term, pixel term) for loss, h_hat
   and every gradient.
@@ -165,6 +165,50 @@ def test_training_shape_100k_matches_unfused_path():
     tgt = _targets(S, F, 90, 360, 41)
     fused, ref, _ = _run_both(sc, attrs, [0.0, 0.0, 0.0], tgt, gs.Grid(), gs.Params())
     _check_against_unfused(fused, ref, S)
+
+
+def test_training_at_scale_shape_matches_unfused_path():
+    # the at-scale training configuration: 300k Gaussians, 180x720, 32
+    # complex subcarriers, 64 transmitter sets (the bench's train_300k
+    # launch configuration); attributes and targets drawn on the device.
+    # Loss, means and scene gradients in full; the attribute gradients of
+    # sampled Gaussians in every seventh set.
+    n, S, F, H, W = 300_000, 64, 32, 180, 720
+    sc = synth.scene(n, seed=90)
+    dev = to_dev(sc)
+    gen = torch.Generator(device="cuda").manual_seed(91)
+    a = torch.randn(S, n, F, 2, device="cuda", generator=gen) * 0.5
+    z = torch.randn(S, F, H, W, 2, device="cuda", generator=gen) * 0.02
+    grid = gs.Grid(H, W)
+    rx_t = torch.zeros(1, 3, device="cuda")
+    ws = gs.prepare(dev, rx_t, grid=grid)
+    assert ws.flags()[0]["overflow"] == 0
+    lst, cnt = gs.live(ws)
+    h = gs.spatial_mean(z, True)
+    loss_f, hh_f, g_f, _ = gs.train_pass(ws, dev, a, rx_t, lst, cnt, z, h, 1.0)
+    torch.cuda.synchronize()
+    spec = gs.blend(ws, a, n_sets=S, is_complex=True)
+    part = torch.empty_like(spec)
+    loss, hhat, mgrad, scale = gs.loss_stats(spec, z, True, 1.0, partial=part)
+    g = gs.backward_l2(ws, dev, a, rx_t, spec, None, mgrad, scale, partial=part, is_complex=True, n_sets=S)
+    torch.cuda.synchronize()
+    _close_rel(loss_f.cpu().numpy(), loss.cpu().numpy(), "loss", 1e-5)
+    _close_rel(hh_f.cpu().numpy(), hhat.cpu().numpy(), "h_hat", 1e-5)
+    for k in NAMES:
+        compare(g_f["d_" + k].cpu().numpy(), g["d_" + k].cpu().numpy(), k)
+    # rows from the live list (the Gaussians with a nonzero attribute
+    # gradient: about a hundred here, the scene being dense around the
+    # receiver) and 2048 sampled from all Gaussians
+    rng = np.random.default_rng(92)
+    n_live = int(cnt[0])
+    assert n_live > 0
+    live_rows = lst[0, torch.from_numpy(rng.choice(n_live, min(n_live, 2048), replace=False)).cuda()].long()
+    rows = torch.unique(torch.cat([live_rows, torch.from_numpy(rng.choice(n, 2048, replace=False)).cuda()]))
+    sets = torch.arange(0, S, 7, device="cuda")
+    got = g_f["d_attr"][sets][:, rows].cpu().numpy()
+    want = g["d_attr"][sets][:, rows].cpu().numpy()
+    for i, s_ in enumerate(sets.tolist()):
+        compare(got[i], want[i], "d_attr set %d" % s_)
 
 
 def test_fused_pass_matches_oracle_loss_and_gradients():
