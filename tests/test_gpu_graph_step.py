@@ -2,7 +2,10 @@
 (torch.cuda.CUDAGraph around the library's launches) replay what the eager
 calls compute.
 
-Every replay is checked against an eager call from the same state: the model
+Training cases: 4000 Gaussians with 4 transmitters at 90x360, and the
+at-scale shape (300k Gaussians, 180x720, 32 complex subcarriers, 64
+transmitters) that the benchmark replays.  Every replay is checked against
+an eager call from the same state: the model
 state is snapshotted, one eager step runs, the state is restored, unrelated
 eager work and a synchronisation follow, then the graph replays.  Losses and
 every gradient agree to FP32 summation order (float atomics), the updated
@@ -75,6 +78,25 @@ def test_training_step_graph_replays_match_eager_steps():
                                total_steps=total)
     tx = torch.from_numpy(synth.points(B, seed=54)).cuda()
     target = torch.from_numpy(synth.normal((B, F, 90, 360, 2), 0.05, seed=55)).cuda()
+    _replays_match_eager(model, tx, target, total)
+
+
+def test_training_step_graph_replays_match_eager_steps_at_scale():
+    # the at-scale training shape: 300k Gaussians, 180x720, 32 complex
+    # subcarriers, 64 transmitters (targets drawn on the device)
+    n, B, F = 300_000, 64, 32
+    total = 1000
+    sc = synth.scene(n, seed=56)
+    model = train.LearnedScene(sc, synth.embeddings(n, seed=57), train.init_weights(58, n_chan=F), [0, 0, 0], B,
+                               list(synth.BOX_LO), list(synth.BOX_HI), grid=train.Grid(180, 720),
+                               total_steps=total)
+    tx = torch.from_numpy(synth.points(B, seed=59)).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(60)
+    target = torch.randn(B, F, 180, 720, 2, device="cuda", generator=gen) * 0.05
+    _replays_match_eager(model, tx, target, total)
+
+
+def _replays_match_eager(model, tx, target, total):
     tmean = train.spatial_mean(target, True)
 
     def step():
